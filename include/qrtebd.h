@@ -1,0 +1,204 @@
+/*
+ * qrtebd.h -- C ABI of the MI355X QR-TEBD bond-update library (libqrtebd.so).
+ *
+ * Implements the QR-based truncation of a two-site TEBD update from
+ * J. Unfried, J. Hauschild, F. Pollmann, "Fast Time-Evolution of
+ * Matrix-Product States using the QR decomposition" (arXiv:2212.09782):
+ * Sec. II steps (i)-(iii) (plain QR truncation and Hastings' form of the new
+ * left tensor), the heuristic bond growth at the end of Sec. II, and
+ * controlled bond expansion, Sec. III steps (i)-(v).
+ *
+ * Conventions
+ *  - Every tensor argument is a device pointer to contiguous row-major,
+ *    interleaved complex data (complex128 = 2 doubles, complex64 = 2 floats).
+ *    The caller allocates all of them; the library allocates only its own
+ *    workspace inside an mps_ctx.
+ *  - Site tensor B[chi_l][d][chi_r] in right-isometric form
+ *    (sum_{i,b} B[a][i][b] conj(B[a'][i][b]) = delta(a,a'), Sec. II).
+ *  - Bond matrix Xi^[m] (the bond LEFT of site m, Sec. II): either a real
+ *    vector of chi_l doubles (diagonal, e.g. Schmidt values) or a dense
+ *    chi_l x chi_l complex128 matrix.  Xi is always FP64.
+ *  - Two-site gate U: (d*d) x (d*d) complex128 acting on |i>|j>, row index
+ *    i*d + j with i the left site (the gate sum of Sec. II step (i)).
+ *  - Precision: MPS_C128 keeps site tensors in complex128 and computes in
+ *    FP64; MPS_MIXED_C64 keeps them in complex64, runs the contractions and
+ *    trailing updates on FP32 matrix cores and keeps FP64 for Householder
+ *    panel arithmetic, the eigen-decomposition, the re-orthogonalisation of
+ *    the new right tensor and the normalisation of Xi.
+ *  - All calls are asynchronous on the given HIP stream (hipStream_t passed
+ *    as mps_stream).  Outputs are valid once the stream is synchronised.
+ *  - Return value: MPS_OK (0) or a negative status; mps_last_error() gives a
+ *    thread-local message.  Argument errors are found on the host before any
+ *    launch.  Numeric trouble found on the device (non-finite norms, a zero
+ *    wave function, a stalled grid barrier) is latched in the context and
+ *    reported by the next mps_sync().
+ *  - One mps_ctx per host thread; a context is not thread-safe.
+ */
+#ifndef QRTEBD_H
+#define QRTEBD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* mps_stream; /* a hipStream_t; NULL = default stream */
+
+enum {
+  MPS_OK = 0,
+  MPS_ERR_ARG = -1,      /* bad argument (shape, mode, null pointer) */
+  MPS_ERR_CAPACITY = -2, /* a size exceeds what the kernels support */
+  MPS_ERR_OOM = -3,      /* workspace allocation failed */
+  MPS_ERR_HIP = -4,      /* a HIP runtime call failed */
+  MPS_ERR_NUMERIC = -5,  /* latched device-side numeric error (see mps_sync) */
+  MPS_ERR_STATE = -6     /* object used in a wrong state */
+};
+
+typedef enum { MPS_C128 = 0, MPS_MIXED_C64 = 1 } mps_precision;
+
+/* Truncation scheme.  PLAIN: Sec. II with Y0 = B^[n] (eta = chi_m, no
+ * truncation beyond the QR projection).  GROW: Sec. II bond growth, Y0 = the
+ * first eta rows of theta~.  CBE: Sec. III, Y0 = the first eta rows of
+ * theta~, then the eigen-decomposition of L^dag L and truncation. */
+typedef enum { MPS_TRUNC_PLAIN = 0, MPS_TRUNC_GROW = 1, MPS_TRUNC_CBE = 2 } mps_trunc;
+
+typedef struct mps_ctx_s* mps_ctx;
+
+/* One bond update (m, n = m+1).
+ *  d               physical dimension
+ *  chi_l, chi_m, chi_r  dimensions of the bond left of m, between m and n,
+ *                  right of n
+ *  eta             dimension of the QR / LQ step: PLAIN requires
+ *                  eta == chi_m; GROW and CBE require
+ *                  1 <= eta <= min(d chi_l, d chi_r) (Sec. III: eta = chi + dchi)
+ *  chi_max         CBE only: keep at most chi_max Schmidt values
+ *  svd_min         CBE only: drop Schmidt values below svd_min (absolute;
+ *                  the paper uses 1e-14); at least one value is kept
+ *  xi_is_diag      1: xi_m is a real vector of chi_l doubles; 0: dense
+ *  mode, prec      see above */
+typedef struct {
+  int d, chi_l, chi_m, chi_r;
+  int eta;
+  int chi_max;
+  double svd_min;
+  int xi_is_diag;
+  int mode;
+  int prec;
+} mps_bond_desc;
+
+/* Create / destroy a context on HIP device `device`.  Workspace grows on
+ * demand and is kept until destruction. */
+int mps_ctx_create(int device, mps_ctx* out);
+int mps_ctx_destroy(mps_ctx ctx);
+
+/* Thread-local text of the last error. */
+const char* mps_last_error(void);
+
+/* Wait for `stream` and report (then clear) latched device errors:
+ * MPS_ERR_NUMERIC if any kernel latched one since the last call. */
+int mps_sync(mps_ctx ctx, mps_stream stream);
+
+/* Capacity of the new bond: eta for PLAIN / GROW, min(eta, chi_max) for CBE.
+ * Output buffers of mps_bond_update must hold this many columns / rows. */
+int mps_bond_capacity(const mps_bond_desc* desc);
+
+/* Bytes of workspace a bond of this shape needs (for budgeting). */
+int mps_workspace_query(mps_ctx ctx, const mps_bond_desc* desc, size_t* bytes);
+
+/* The two-site update of Sec. II / III: from Xi^[m], B^[m], B^[n] and U
+ * compute B~^[m], Xi~^[n] (the new bond between m and n) and B~^[n].
+ *  xi_m      chi_l doubles (diag) or chi_l x chi_l complex128
+ *  b_m, b_n  [chi_l][d][chi_m], [chi_m][d][chi_r]  (complex128 or complex64)
+ *  u         (d*d) x (d*d) complex128
+ *  b_m_out   [chi_l][d][chi~]   written compactly with the live chi~
+ *  xi_n_out  CBE: chi~ doubles (normalised Schmidt values, descending);
+ *            PLAIN / GROW: eta x eta complex128 lower-triangular L / |L|_F
+ *  b_n_out   [chi~][d][chi_r]
+ *  chi_new_dev  device int: chi~ (== eta for PLAIN / GROW)
+ *  trunc_err_dev device double: |theta~ - approx|^2 / |theta~|^2 (end of Sec. IV)
+ * Inputs are read only; outputs must not alias inputs.  Output buffers must
+ * hold mps_bond_capacity(desc) along the new bond. */
+int mps_bond_update(mps_ctx ctx, const mps_bond_desc* desc, const void* xi_m, const void* b_m,
+                    const void* b_n, const void* u, void* b_m_out, void* xi_n_out, void* b_n_out,
+                    int* chi_new_dev, double* trunc_err_dev, mps_stream stream);
+
+/* Two-site Trotter gate of the d-state clock model (Sec. IV):
+ * U = expm(-i tau h), h = -(Z (x) Z^dag + h.c.) - g (wl (X+X^dag) (x) 1 +
+ * wr 1 (x) (X+X^dag)), Z = diag(w^k), w = exp(2 pi i/d), X the cyclic shift.
+ * wl / wr: share of each site's transverse field carried by this bond.
+ * Host computation (FP64); u_out: host array of (d*d)^2 complex128. */
+int mps_clock_gate(int d, double g, double tau, double wl, double wr, double* u_out);
+
+/* ---- device-resident MPS and the even/odd sweep (Fig. 2a) ---------------- */
+
+typedef struct mps_state_s* mps_state;
+
+/* geometry: 0 finite chain of L sites (bond b joins sites b, b+1; Xi^[0] = 1),
+ *           1 uniform cell of L = 2 sites (bonds (A,B) and (B,A)).
+ * b_ptrs[m]: device buffer of site m with room for chi_cap*d*chi_cap elements;
+ * xi_ptrs[m]: device buffer of the bond left of site m, chi_cap doubles.
+ * chi_host[m]: current dimension of the bond left of site m (chi_host[L] is
+ * the right end of a finite chain, 1).  The state starts in CBE form (every
+ * Xi diagonal).  Buffers stay owned by the caller and are updated in place. */
+int mps_state_create(mps_ctx ctx, int geometry, int L, int d, int chi_cap, int prec,
+                     void* const* b_ptrs, void* const* xi_ptrs, const int* chi_host, mps_state* out);
+int mps_state_destroy(mps_state st);
+/* Current bond dimensions (L + 1 entries, host copy kept by the library). */
+int mps_state_chis(mps_state st, int* chi_out);
+
+/* Sweep policy shared by all states of one call. */
+typedef struct {
+  int mode;         /* mps_trunc; PLAIN keeps chi fixed */
+  int chi_max;
+  double svd_min;
+  int dchi_min;     /* eta = min(chi + max(dchi_min, ceil(dchi_frac*chi)), d chi_l, d chi_r) */
+  double dchi_frac;
+} mps_sweep_policy;
+
+/* nsteps Trotter steps on every state.  gates[s] points to the device gates
+ * of state s: [nbonds][2][(d*d)^2] complex128, index 0 for tau = dt/2 and 1
+ * for tau = dt, bond b = the bond starting at site b.  order 2: even(dt/2)
+ * odd(dt) even(dt/2); order 1: even(dt) odd(dt).  All even bonds of all states
+ * form one batch, then all odd bonds.  trunc_err_dev (nullable): per state,
+ * the summed truncation error is added to trunc_err_dev[s]. */
+int mps_sweep(mps_ctx ctx, mps_state* states, int nstates, const void* const* gates, int nsteps,
+              int order, const mps_sweep_policy* policy, double* trunc_err_dev, mps_stream stream);
+
+/* Observables from the isometric form (Fig. 1c):
+ *  site_vals  [L][2] doubles: <op1> at every site from M = Xi^[m] B^[m],
+ *             as complex (re, im), divided by |M|^2
+ *  norms      [L] doubles: |M|^2 (1 for an exact right-isometric state)
+ *  bond_vals  [nbonds][2] doubles: <op2> on every bond from theta = Xi B B,
+ *             divided by |theta|^2 (op2 (d*d)^2 complex128, nullable)
+ *  entropies  [L] doubles: von Neumann entropy of every bond left of a site
+ *             from Xi (-sum p ln p, p = s^2 / sum s^2)
+ * op1, op2 are device complex128 matrices; outputs are device buffers
+ * (each nullable).  For a finite chain nbonds = L-1, for the cell 2. */
+int mps_measure(mps_ctx ctx, mps_state st, const void* op1, const void* op2, double* site_vals,
+                double* norms, double* bond_vals, double* entropies, mps_stream stream);
+
+/* ---- building blocks of the update, exported for checking and reuse ------
+ * dt: 0 complex64, 1 complex128.  All matrices row-major device buffers. */
+
+/* C = alpha op(A) op(B) + beta C (op: 0 none, 1 transpose, 2 conjugate
+ * transpose; op(A) M x K, op(B) K x N) on the matrix cores; alpha, beta real. */
+int mps_zgemm(mps_ctx ctx, int dt, int opA, int opB, int M, int N, int K, const void* A, long long lda,
+              const void* B, long long ldb, void* C, long long ldc, double alpha, double beta, mps_stream stream);
+
+/* Thin Householder QR of the m x n matrix A (n <= m, ld n): on return A
+ * holds R in its upper triangle (below it: the reflectors) and Q (m x n,
+ * ld n) the explicit orthonormal factor, A_in = Q R.  Used for both QR steps
+ * of Sec. II (the LQ of Y is the QR of Y^dag). */
+int mps_qr(mps_ctx ctx, int dt, int m, int n, void* A, void* Q, mps_stream stream);
+
+/* The k largest eigenpairs of the Hermitian n x n complex128 matrix G
+ * (destroyed): lam (k doubles, descending) and E (n x k complex128, ld k,
+ * orthonormal columns).  The FP64 eigensolver of Sec. III step (iv). */
+int mps_heig(mps_ctx ctx, int n, int k, void* G, double* lam, void* E, mps_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QRTEBD_H */

@@ -1,0 +1,486 @@
+// C ABI of libqrtebd: contexts, errors, the clock-model gate builder, bond
+// updates, device-resident MPS, the even/odd Trotter sweep and measurements.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/qrtebd.h"
+#include "bond.h"
+#include "gemm.h"
+#include "measure.h"
+
+namespace qrtebd {
+
+static thread_local char g_err[1024] = "";
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int set_hip_error(hipError_t e, const char* expr, const char* file, int line) {
+  snprintf(g_err, sizeof g_err, "HIP error %s (%d) in %s at %s:%d", hipGetErrorString(e), (int)e, expr, file, line);
+  return MPS_ERR_HIP;
+}
+
+}  // namespace qrtebd
+
+using namespace qrtebd;
+
+struct mps_ctx_s {
+  int device = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int* status = nullptr;     // device error word
+  int* chi_host = nullptr;   // pinned scratch for chi read-back
+  double* eps_host = nullptr;
+  // per-bond scratch outputs of the sweep (device)
+  void* tmp_out = nullptr;
+  size_t tmp_bytes = 0;
+};
+
+struct mps_state_s {
+  mps_ctx ctx = nullptr;
+  int geometry = 0, L = 0, d = 0, chi_cap = 0, prec = 0;
+  std::vector<void*> B, Xi;
+  std::vector<int> chi;  // bond left of site m, m = 0..L (finite: chi[L] = 1)
+};
+
+namespace {
+
+int ensure(void** p, size_t* have, size_t need, hipStream_t s) {
+  if (*have >= need) return 0;
+  QT_HIP_CHECK(hipStreamSynchronize(s));
+  if (*p) QT_HIP_CHECK(hipFree(*p));
+  *p = nullptr;
+  *have = 0;
+  const size_t bytes = need + (need >> 3) + (1 << 20);
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return set_error(MPS_ERR_OOM, "workspace allocation of %zu bytes failed", bytes);
+  }
+  *have = bytes;
+  return 0;
+}
+
+int check_desc(const mps_bond_desc* D) {
+  if (!D) return set_error(MPS_ERR_ARG, "null descriptor");
+  if (D->d < 1 || D->chi_l < 1 || D->chi_m < 1 || D->chi_r < 1)
+    return set_error(MPS_ERR_ARG, "dimensions must be >= 1 (d=%d chi=%d,%d,%d)", D->d, D->chi_l, D->chi_m, D->chi_r);
+  if (D->mode < 0 || D->mode > 2) return set_error(MPS_ERR_ARG, "unknown truncation mode %d", D->mode);
+  if (D->prec < 0 || D->prec > 1) return set_error(MPS_ERR_ARG, "unknown precision %d", D->prec);
+  const int mL = D->d * D->chi_l, mR = D->d * D->chi_r;
+  if (D->mode == MPS_TRUNC_PLAIN && D->eta != D->chi_m)
+    return set_error(MPS_ERR_ARG, "plain mode needs eta == chi_m (eta=%d chi_m=%d)", D->eta, D->chi_m);
+  if (D->eta < 1 || D->eta > std::min(mL, mR))
+    return set_error(MPS_ERR_ARG, "eta=%d outside [1, min(d chi_l, d chi_r)=%d]", D->eta, std::min(mL, mR));
+  if (D->mode == MPS_TRUNC_CBE && D->chi_max < 1) return set_error(MPS_ERR_ARG, "chi_max must be >= 1");
+  if (D->mode == MPS_TRUNC_CBE && !(D->svd_min >= 0)) return set_error(MPS_ERR_ARG, "svd_min must be >= 0");
+  if (D->d * D->d > 160) return set_error(MPS_ERR_CAPACITY, "d=%d too large (d^2 <= 160)", D->d);
+  if (std::max(mL, mR) > kMaxPanelBlocks * 256)
+    return set_error(MPS_ERR_CAPACITY, "d chi=%d too large", std::max(mL, mR));
+  if (D->mode == MPS_TRUNC_CBE && D->eta > 2048) return set_error(MPS_ERR_CAPACITY, "eta=%d > 2048", D->eta);
+  return 0;
+}
+
+BondShape shape_of(const mps_bond_desc* D) {
+  BondShape b{};
+  b.d = D->d; b.chi_l = D->chi_l; b.chi_m = D->chi_m; b.chi_r = D->chi_r;
+  b.eta = D->eta; b.chi_max = D->chi_max; b.svd_min = D->svd_min;
+  b.xi_is_diag = D->xi_is_diag; b.mode = D->mode; b.prec = D->prec;
+  return b;
+}
+
+__global__ void add_eps_kernel(const double* eps, double* acc) { *acc += *eps; }
+
+using cd = std::complex<double>;
+
+// expm by scaling and squaring of a Taylor series (n x n, row-major).
+void expm_host(std::vector<cd>& A, int n) {
+  double nrm = 0;
+  for (int j = 0; j < n; ++j) {
+    double c = 0;
+    for (int i = 0; i < n; ++i) c += std::abs(A[i * n + j]);
+    nrm = std::max(nrm, c);
+  }
+  int sq = 0;
+  while (nrm > 0.25) { nrm *= 0.5; ++sq; }
+  const double f = std::ldexp(1.0, -sq);
+  for (auto& x : A) x *= f;
+  std::vector<cd> E(n * n, 0.0), term(n * n, 0.0), tmp(n * n);
+  for (int i = 0; i < n; ++i) E[i * n + i] = term[i * n + i] = 1.0;
+  for (int k = 1; k <= 24; ++k) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        cd s = 0;
+        for (int l = 0; l < n; ++l) s += term[i * n + l] * A[l * n + j];
+        tmp[i * n + j] = s / (double)k;
+      }
+    term.swap(tmp);
+    for (int i = 0; i < n * n; ++i) E[i] += term[i];
+  }
+  for (int r = 0; r < sq; ++r) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        cd s = 0;
+        for (int l = 0; l < n; ++l) s += E[i * n + l] * E[l * n + j];
+        tmp[i * n + j] = s;
+      }
+    E.swap(tmp);
+  }
+  A.swap(E);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mps_last_error(void) { return g_err; }
+
+int mps_ctx_create(int device, mps_ctx* out) {
+  if (!out) return set_error(MPS_ERR_ARG, "null output");
+  *out = nullptr;
+  QT_HIP_CHECK(hipSetDevice(device));
+  mps_ctx c = new mps_ctx_s();
+  c->device = device;
+  if (hipMalloc(&c->status, 256) != hipSuccess || hipMemset(c->status, 0, 256) != hipSuccess ||
+      hipHostMalloc(&c->chi_host, 4096 * sizeof(int)) != hipSuccess ||
+      hipHostMalloc(&c->eps_host, 64 * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return set_error(MPS_ERR_HIP, "context allocation failed");
+  }
+  *out = c;
+  return MPS_OK;
+}
+
+int mps_ctx_destroy(mps_ctx c) {
+  if (!c) return MPS_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->tmp_out) (void)hipFree(c->tmp_out);
+  if (c->status) (void)hipFree(c->status);
+  if (c->chi_host) (void)hipHostFree(c->chi_host);
+  if (c->eps_host) (void)hipHostFree(c->eps_host);
+  delete c;
+  return MPS_OK;
+}
+
+int mps_sync(mps_ctx c, mps_stream stream) {
+  if (!c) return set_error(MPS_ERR_ARG, "null context");
+  QT_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
+  int st = 0;
+  QT_HIP_CHECK(hipMemcpy(&st, c->status, sizeof(int), hipMemcpyDeviceToHost));
+  if (st) {
+    QT_HIP_CHECK(hipMemset(c->status, 0, sizeof(int)));
+    return set_error(MPS_ERR_NUMERIC, "device reported numeric error bits 0x%x (1 barrier stall, 2 non-finite, "
+                                      "4 zero norm, 8 capacity)", st);
+  }
+  return MPS_OK;
+}
+
+int mps_bond_capacity(const mps_bond_desc* D) {
+  if (!D) return set_error(MPS_ERR_ARG, "null descriptor");
+  return shape_of(D).cap();
+}
+
+int mps_workspace_query(mps_ctx c, const mps_bond_desc* D, size_t* bytes) {
+  (void)c;
+  int rc = check_desc(D);
+  if (rc) return rc;
+  if (bytes) *bytes = bond_work_bytes(shape_of(D));
+  return MPS_OK;
+}
+
+int mps_bond_update(mps_ctx c, const mps_bond_desc* D, const void* xi_m, const void* b_m, const void* b_n,
+                    const void* u, void* b_m_out, void* xi_n_out, void* b_n_out, int* chi_new_dev,
+                    double* trunc_err_dev, mps_stream stream) {
+  if (!c) return set_error(MPS_ERR_ARG, "null context");
+  int rc = check_desc(D);
+  if (rc) return rc;
+  if (!xi_m || !b_m || !b_n || !u || !b_m_out || !xi_n_out || !b_n_out || !chi_new_dev || !trunc_err_dev)
+    return set_error(MPS_ERR_ARG, "null tensor pointer");
+  const BondShape b = shape_of(D);
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = ensure(&c->ws, &c->ws_bytes, bond_work_bytes(b), s))) return rc;
+  return bond_update_run(b, c->ws, c->status, xi_m, b_m, b_n, (const c128*)u, b_m_out, xi_n_out, b_n_out,
+                         chi_new_dev, trunc_err_dev, s);
+}
+
+int mps_clock_gate(int d, double g, double tau, double wl, double wr, double* u_out) {
+  if (d < 1 || !u_out) return set_error(MPS_ERR_ARG, "bad gate arguments");
+  const int n = d * d;
+  const cd w = std::exp(cd(0, 2 * M_PI / d));
+  std::vector<cd> Z(d * d, 0.0), X(d * d, 0.0), xs(d * d);
+  for (int k = 0; k < d; ++k) {
+    Z[k * d + k] = std::pow(w, k);
+    X[k * d + (k + 1) % d] = 1.0;
+  }
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) xs[i * d + j] = X[i * d + j] + std::conj(X[j * d + i]);
+  std::vector<cd> A(n * n, 0.0);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j)
+      for (int k = 0; k < d; ++k)
+        for (int l = 0; l < d; ++l) {
+          const int r = i * d + j, c = k * d + l;
+          // Z (x) Z^dag + h.c.
+          const cd zz = Z[i * d + k] * std::conj(Z[l * d + j]);
+          const cd zzh = std::conj(Z[k * d + i]) * Z[j * d + l];
+          cd h = -(zz + zzh);
+          h -= g * (wl * xs[i * d + k] * (j == l ? 1.0 : 0.0) + wr * (i == k ? 1.0 : 0.0) * xs[j * d + l]);
+          A[r * n + c] = cd(0, -tau) * h;
+        }
+  expm_host(A, n);
+  for (int i = 0; i < n * n; ++i) {
+    u_out[2 * i] = A[i].real();
+    u_out[2 * i + 1] = A[i].imag();
+  }
+  return MPS_OK;
+}
+
+// ---------------------------------------------------------------- states
+
+int mps_state_create(mps_ctx c, int geometry, int L, int d, int chi_cap, int prec, void* const* b_ptrs,
+                     void* const* xi_ptrs, const int* chi_host, mps_state* out) {
+  if (!c || !out || !b_ptrs || !xi_ptrs || !chi_host) return set_error(MPS_ERR_ARG, "null argument");
+  if (geometry != 0 && geometry != 1) return set_error(MPS_ERR_ARG, "geometry must be 0 or 1");
+  if (geometry == 1 && L != 2) return set_error(MPS_ERR_ARG, "the uniform cell has L = 2");
+  if (L < 2 || L > kMaxSites) return set_error(MPS_ERR_ARG, "L=%d outside [2, %d]", L, kMaxSites);
+  if (d < 1 || chi_cap < 1 || prec < 0 || prec > 1) return set_error(MPS_ERR_ARG, "bad d / chi_cap / prec");
+  mps_state st = new mps_state_s();
+  st->ctx = c;
+  st->geometry = geometry;
+  st->L = L;
+  st->d = d;
+  st->chi_cap = chi_cap;
+  st->prec = prec;
+  st->B.assign(b_ptrs, b_ptrs + L);
+  st->Xi.assign(xi_ptrs, xi_ptrs + L);
+  st->chi.assign(chi_host, chi_host + L + 1);
+  for (int m = 0; m <= L; ++m)
+    if (st->chi[m] < 1 || st->chi[m] > chi_cap) {
+      delete st;
+      return set_error(MPS_ERR_ARG, "chi[%d]=%d outside [1, chi_cap]", m, chi_host[m]);
+    }
+  if (geometry == 0 && (st->chi[0] != 1 || st->chi[L] != 1)) {
+    delete st;
+    return set_error(MPS_ERR_ARG, "a finite chain has chi = 1 at both ends");
+  }
+  if (geometry == 1) st->chi[2] = st->chi[0];
+  *out = st;
+  return MPS_OK;
+}
+
+int mps_state_destroy(mps_state st) {
+  delete st;
+  return MPS_OK;
+}
+
+int mps_state_chis(mps_state st, int* chi_out) {
+  if (!st || !chi_out) return set_error(MPS_ERR_ARG, "null argument");
+  std::copy(st->chi.begin(), st->chi.end(), chi_out);
+  return MPS_OK;
+}
+
+namespace {
+
+struct BondRef {
+  mps_state st;
+  int m, n, il, im, ir;  // sites m, n and the chi indices left / middle / right
+  const c128* gate;
+};
+
+std::vector<BondRef> layer_bonds(mps_state st, int parity, const void* gates, int gate_slot) {
+  std::vector<BondRef> out;
+  const int L = st->L, d2 = st->d * st->d;
+  const c128* g = (const c128*)gates;
+  if (st->geometry == 0) {
+    for (int m = parity; m < L - 1; m += 2)
+      out.push_back(BondRef{st, m, m + 1, m, m + 1, m + 2, g + ((size_t)m * 2 + gate_slot) * d2 * d2});
+  } else {
+    const int m = parity, n = 1 - parity;
+    out.push_back(BondRef{st, m, n, m, n, m, g + ((size_t)m * 2 + gate_slot) * d2 * d2});
+  }
+  return out;
+}
+
+int run_layer(mps_ctx c, std::vector<BondRef>& bonds, const mps_sweep_policy* pol, double* eps_acc_base,
+              const std::vector<int>& state_index, hipStream_t s) {
+  int rc;
+  for (size_t k = 0; k < bonds.size(); ++k) {
+    BondRef& br = bonds[k];
+    mps_state st = br.st;
+    const int d = st->d;
+    const int chiL = st->chi[br.il], chiM = st->chi[br.im], chiR = st->chi[br.ir];
+    mps_bond_desc D{};
+    D.d = d;
+    D.chi_l = chiL;
+    D.chi_m = chiM;
+    D.chi_r = chiR;
+    const int dchi = std::max(pol->dchi_min, (int)std::ceil(pol->dchi_frac * chiM));
+    D.eta = std::min(std::min(chiM + dchi, d * chiL), d * chiR);
+    D.chi_max = std::min(pol->chi_max, st->chi_cap);
+    D.svd_min = pol->svd_min;
+    D.xi_is_diag = 1;
+    D.mode = MPS_TRUNC_CBE;
+    D.prec = st->prec;
+    if ((rc = check_desc(&D))) return rc;
+    const BondShape b = shape_of(&D);
+    const int cap = b.cap();
+    const size_t es = st->prec ? 8 : 16;
+    const size_t bm_bytes = (size_t)chiL * d * cap * es, bn_bytes = (size_t)cap * d * chiR * es;
+    const size_t need_tmp = bm_bytes + bn_bytes + cap * 8 + 1024;
+    if ((rc = ensure(&c->tmp_out, &c->tmp_bytes, need_tmp, s))) return rc;
+    if ((rc = ensure(&c->ws, &c->ws_bytes, bond_work_bytes(b), s))) return rc;
+    char* t = (char*)c->tmp_out;
+    void* bm_out = t;
+    void* bn_out = t + ((bm_bytes + 255) & ~size_t(255));
+    double* xi_out = (double*)((char*)bn_out + ((bn_bytes + 255) & ~size_t(255)));
+    int* chi_dev = (int*)((char*)xi_out + ((cap * 8 + 255) & ~size_t(255)));
+    double* eps_dev = (double*)(chi_dev + 16);
+    if ((rc = bond_update_run(b, c->ws, c->status, st->Xi[br.m], st->B[br.m], st->B[br.n], br.gate, bm_out, xi_out,
+                              bn_out, chi_dev, eps_dev, s)))
+      return rc;
+    // the new chi decides the copy sizes: read it back
+    QT_HIP_CHECK(hipMemcpyAsync(c->chi_host, chi_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    QT_HIP_CHECK(hipStreamSynchronize(s));
+    const int chiN = c->chi_host[0];
+    if (chiN < 1 || chiN > cap) return set_error(MPS_ERR_NUMERIC, "device returned chi=%d (cap %d)", chiN, cap);
+    QT_HIP_CHECK(hipMemcpyAsync(st->B[br.m], bm_out, (size_t)chiL * d * chiN * es, hipMemcpyDeviceToDevice, s));
+    QT_HIP_CHECK(hipMemcpyAsync(st->B[br.n], bn_out, (size_t)chiN * d * chiR * es, hipMemcpyDeviceToDevice, s));
+    QT_HIP_CHECK(hipMemcpyAsync(st->Xi[br.n], xi_out, (size_t)chiN * 8, hipMemcpyDeviceToDevice, s));
+    if (eps_acc_base) {
+      hipLaunchKernelGGL(add_eps_kernel, dim3(1), dim3(1), 0, s, eps_dev, eps_acc_base + state_index[k]);
+      QT_HIP_CHECK(hipGetLastError());
+    }
+    st->chi[br.im] = chiN;
+    if (st->geometry == 1 && br.im == 0) st->chi[2] = chiN;
+  }
+  return 0;
+}
+
+}  // namespace
+
+int mps_sweep(mps_ctx c, mps_state* states, int nstates, const void* const* gates, int nsteps, int order,
+              const mps_sweep_policy* pol, double* trunc_err_dev, mps_stream stream) {
+  if (!c || !states || !gates || !pol || nstates < 1) return set_error(MPS_ERR_ARG, "null argument");
+  if (order != 1 && order != 2) return set_error(MPS_ERR_ARG, "order must be 1 or 2");
+  if (pol->mode != MPS_TRUNC_CBE)
+    return set_error(MPS_ERR_ARG, "mps_sweep keeps diagonal bond matrices: mode must be MPS_TRUNC_CBE");
+  hipStream_t s = (hipStream_t)stream;
+  struct Layer { int parity, slot; };
+  std::vector<Layer> layers;
+  if (order == 2) layers = {{0, 0}, {1, 1}, {0, 0}};
+  else layers = {{0, 1}, {1, 1}};
+  for (int step = 0; step < nsteps; ++step)
+    for (const Layer& ly : layers) {
+      std::vector<BondRef> bonds;
+      std::vector<int> idx;
+      for (int si = 0; si < nstates; ++si) {
+        auto b = layer_bonds(states[si], ly.parity, gates[si], ly.slot);
+        for (auto& x : b) {
+          bonds.push_back(x);
+          idx.push_back(si);
+        }
+      }
+      int rc = run_layer(c, bonds, pol, trunc_err_dev, idx, s);
+      if (rc) return rc;
+    }
+  return MPS_OK;
+}
+
+int mps_measure(mps_ctx c, mps_state st, const void* op1, const void* op2, double* site_vals, double* norms,
+                double* bond_vals, double* entropies, mps_stream stream) {
+  if (!c || !st) return set_error(MPS_ERR_ARG, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  const int L = st->L, d = st->d;
+  const size_t es = st->prec ? 8 : 16;
+  int rc;
+  if (op1 && (site_vals || norms)) {
+    for (int m = 0; m < L; ++m) {
+      const int chiL = st->chi[m], chiR = st->chi[m + 1];
+      const size_t need = expect_part_doubles(chiL, chiR) * 8 + 256;
+      if ((rc = ensure(&c->ws, &c->ws_bytes, need, s))) return rc;
+      if ((rc = expect_run(st->B[m], st->prec, (const double*)st->Xi[m], chiL, d, chiR, (const c128*)op1,
+                           (double*)c->ws, site_vals ? site_vals + 2 * m : nullptr, norms ? norms + m : nullptr, s)))
+        return rc;
+    }
+  }
+  if (op2 && bond_vals) {
+    const int nb = st->geometry == 0 ? L - 1 : 2;
+    for (int b = 0; b < nb; ++b) {
+      const int m = b, n = st->geometry == 0 ? b + 1 : 1 - b;
+      const int chiL = st->chi[m], chiM = st->chi[n], chiR = st->geometry == 0 ? st->chi[n + 1] : st->chi[m];
+      const size_t tb = (size_t)chiL * d * d * chiR * es;
+      const size_t need = ((tb + 255) & ~size_t(255)) + expect_part_doubles(chiL, chiR) * 8 + 256;
+      if ((rc = ensure(&c->ws, &c->ws_bytes, need, s))) return rc;
+      void* th = c->ws;
+      double* part = (double*)((char*)c->ws + ((tb + 255) & ~size_t(255)));
+      const int dt = st->prec ? DT_C64 : DT_C128;
+      GemmProb g = gemm_prob(st->B[m], chiM, OP_N, st->B[n], d * chiR, OP_N, th, d * chiR, chiL * d, d * chiR, chiM);
+      if ((rc = gemm_one(g, GemmTypes{dt, dt}, s))) return rc;
+      if ((rc = expect_run(th, st->prec, (const double*)st->Xi[m], chiL, d * d, chiR, (const c128*)op2, part,
+                           bond_vals + 2 * b, nullptr, s)))
+        return rc;
+    }
+  }
+  if (entropies) {
+    EntropyArgs ea{};
+    for (int m = 0; m < L; ++m) {
+      ea.xi[m] = (const double*)st->Xi[m];
+      ea.chi[m] = st->chi[m];
+    }
+    if ((rc = entropy_run(ea, L, entropies, s))) return rc;
+  }
+  return MPS_OK;
+}
+
+int mps_zgemm(mps_ctx c, int dt, int opA, int opB, int M, int N, int K, const void* A, long long lda, const void* B,
+              long long ldb, void* C, long long ldc, double alpha, double beta, mps_stream stream) {
+  if (!c || !A || !B || !C) return set_error(MPS_ERR_ARG, "null argument");
+  if (dt != DT_C64 && dt != DT_C128) return set_error(MPS_ERR_ARG, "dt must be 0 or 1");
+  if (opA < 0 || opA > 2 || opB < 0 || opB > 2) return set_error(MPS_ERR_ARG, "op must be 0, 1 or 2");
+  if (M < 0 || N < 0 || K < 0) return set_error(MPS_ERR_ARG, "negative size");
+  if (beta != 0.0 && beta != 1.0) return set_error(MPS_ERR_ARG, "beta must be 0 or 1");
+  GemmProb g = gemm_prob(A, lda, opA, B, ldb, opB, C, ldc, M, N, K, (float)alpha, (float)beta);
+  return gemm_one(g, GemmTypes{dt, dt}, (hipStream_t)stream);
+}
+
+int mps_qr(mps_ctx c, int dt, int m, int n, void* A, void* Q, mps_stream stream) {
+  if (!c || !A || !Q) return set_error(MPS_ERR_ARG, "null argument");
+  if (dt != DT_C64 && dt != DT_C128) return set_error(MPS_ERR_ARG, "dt must be 0 or 1");
+  if (n < 1 || n > m) return set_error(MPS_ERR_ARG, "need 1 <= n <= m");
+  if (m > kMaxPanelBlocks * 256) return set_error(MPS_ERR_CAPACITY, "m=%d too large", m);
+  const int es = dt == DT_C128 ? 16 : 8;
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if ((rc = ensure(&c->ws, &c->ws_bytes, qr_work_bytes(m, n, es, n), s))) return rc;
+  QrWork w = qr_work_carve(c->ws, m, n, es, n, c->status);
+  if ((rc = qr_factor(A, n, m, n, dt, w, s))) return rc;
+  return qr_form_q(Q, n, m, n, dt, w, s);
+}
+
+int mps_heig(mps_ctx c, int n, int k, void* G, double* lam, void* E, mps_stream stream) {
+  if (!c || !G || !lam || !E) return set_error(MPS_ERR_ARG, "null argument");
+  if (n < 1 || k < 1 || k > n) return set_error(MPS_ERR_ARG, "need 1 <= k <= n");
+  if (n > 2048) return set_error(MPS_ERR_CAPACITY, "n=%d > 2048", n);
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if ((rc = ensure(&c->ws, &c->ws_bytes, eig_work_bytes(n), s))) return rc;
+  EigWork w = eig_work_carve(c->ws, n, c->status);
+  return eig_herm_top((c128*)G, n, k, lam, (c128*)E, w, s);
+}
+
+}  // extern "C"

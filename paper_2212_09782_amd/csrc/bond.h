@@ -1,0 +1,29 @@
+// One two-site bond update on the device (internal interface).
+#pragma once
+#include "eig.h"
+
+struct mps_bond_desc_internal;
+
+namespace qrtebd {
+
+struct BondShape {
+  int d, chi_l, chi_m, chi_r, eta, chi_max;
+  double svd_min;
+  int xi_is_diag, mode, prec;
+  int cap() const;     // capacity of the new bond
+};
+
+// Workspace bytes of one bond update of this shape.
+size_t bond_work_bytes(const BondShape& b);
+
+// Run one update with workspace `ws` (bond_work_bytes(b) bytes).  status:
+// device error word.  All pointers are device pointers.
+int bond_update_run(const BondShape& b, void* ws, int* status, const void* xi_m, const void* b_m,
+                    const void* b_n, const c128* u, void* b_m_out, void* xi_n_out, void* b_n_out,
+                    int* chi_new, double* eps, hipStream_t s);
+
+// ---- small kernels shared with the measurement path
+// out[k] = sum over a partial buffer in a fixed order (one block).
+int reduce_partials(const double* part, int n, double* out, hipStream_t s);
+
+}  // namespace qrtebd

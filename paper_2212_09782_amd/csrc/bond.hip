@@ -1,0 +1,388 @@
+// The two-site bond update of Sec. II (plain QR truncation, bond growth) and
+// Sec. III (controlled bond expansion) on one GPU.
+//
+// Data flow for a bond (m, n) with theta~ viewed as the (chi_l d) x (d chi_r)
+// matrix with rows (alpha, i) and columns (j, delta):
+//   C   = B^[m] B^[n]                     GEMM   (step (i))
+//   C~  = U C,  theta~ = Xi^[m] C~        gate kernel (diagonal Xi) or GEMM (dense Xi);
+//                                         |theta~|^2 accumulated in FP64
+//   X   = theta~ Y0^dag                   GEMM, Y0 = B^[n] (plain) or theta~[:eta] (grow / CBE)
+//   X   = Q^[m] R                         Householder QR, explicit Q^[m]
+//   Y^dag = theta~^dag Q^[m]              GEMM   (step (ii))
+//   Y^dag = Q' R'  i.e. Y = L Q^[n] with L = R'^dag, Q^[n] = Q'^dag
+//   plain / grow: Xi~ = L/|L|, B~^[n] = Q^[n]                        (step (iii))
+//   CBE: L^dag L = R' R'^dag (FP64) = E diag(S^2) E^dag, keep chi~,   (Sec. III (iv), (v))
+//        Xi~ = S_kept/|S_kept|, B~^[n] = E_kept^dag Q^[n]
+//   B~^[m] = C~ B~^[n]^dag                GEMM (Hastings' form: no Xi inverse)
+//   eps = (|theta~|^2 - sum_kept S^2) / |theta~|^2
+// In the mixed path B~^[n] gets one FP64-checked re-orthogonalisation step,
+// B <- B - (B B^dag - 1) B / 2, with B B^dag accumulated in FP64.
+#include "bond.h"
+
+#include <algorithm>
+
+namespace qrtebd {
+
+int BondShape::cap() const {
+  if (mode == 2) return std::max(1, std::min(eta, chi_max));
+  return eta;
+}
+
+namespace {
+
+inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <typename S>
+__global__ __launch_bounds__(64) void gate_kernel(cpx<S>* C, cpx<S>* Th, const c128* __restrict__ U,
+                                                  const double* xi, int d, int chiR, double* partial) {
+  extern __shared__ c128 Cs[];  // d^2 x 64, one column per thread
+  const int d2 = d * d, t = threadIdx.x;
+  const int alpha = blockIdx.y, delta = blockIdx.x * 64 + t;
+  const long long base = (long long)alpha * d2 * chiR;
+  const bool live = delta < chiR;
+  for (int q = 0; q < d2; ++q)
+    Cs[q * 64 + t] = live ? ccast<double>(C[base + (long long)q * chiR + delta]) : mk<double>(0, 0);
+  const double x = xi ? xi[alpha] : 1.0;
+  double nrm = 0;
+  if (live) {
+    for (int o = 0; o < d2; ++o) {
+      c128 acc = mk<double>(0, 0);
+      for (int q = 0; q < d2; ++q) acc = cadd(acc, cmul(U[o * d2 + q], Cs[q * 64 + t]));
+      const long long off = base + (long long)o * chiR + delta;
+      C[off] = ccast<S>(acc);
+      if (Th) {
+        const cpx<S> th = ccast<S>(cscale(acc, x));
+        Th[off] = th;
+        nrm += (double)th.re * th.re + (double)th.im * th.im;
+      }
+    }
+  }
+  nrm = wave_sum(nrm);
+  if (t == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = nrm;
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void sumsq_kernel(const cpx<S>* A, long long n, double* partial) {
+  __shared__ double scr[4];
+  double s = 0;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const cpx<S> z = A[i];
+    s += (double)z.re * z.re + (double)z.im * z.im;
+  }
+  s = block_sum(s, scr);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void reduce_kernel(const double* part, int n, double* out) {
+  __shared__ double scr[4];
+  double s = 0;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  s = block_sum(s, scr);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// R (upper triangle of the first eta rows of the factored Y^dag) with zeros below.
+template <typename S>
+__global__ void extract_r_kernel(const cpx<S>* YH, int eta, cpx<S>* R) {
+  const long long n = (long long)eta * eta;
+  for (long long idx = blockIdx.x * 256ll + threadIdx.x; idx < n; idx += (long long)gridDim.x * 256) {
+    const int i = (int)(idx / eta), j = (int)(idx % eta);
+    R[idx] = j >= i ? YH[idx] : mk<S>(0, 0);
+  }
+}
+
+// plain / grow: Xi~ = L / |L|_F with L = R^dag (complex128 output, eta x eta).
+template <typename S>
+__global__ void plain_xi_kernel(const cpx<S>* R, int eta, const double* kept2, c128* xi) {
+  const double inv = 1.0 / sqrt(*kept2);
+  const long long n = (long long)eta * eta;
+  for (long long idx = blockIdx.x * 256ll + threadIdx.x; idx < n; idx += (long long)gridDim.x * 256) {
+    const int i = (int)(idx / eta), j = (int)(idx % eta);
+    c128 v = mk<double>(0, 0);
+    if (j <= i) {
+      const cpx<S> r = R[(long long)j * eta + i];
+      v = mk<double>((double)r.re * inv, -(double)r.im * inv);
+    }
+    xi[idx] = v;
+  }
+}
+
+__global__ void plain_finish_kernel(int eta, const double* norm2, const double* kept2, int* chi_new,
+                                    double* eps, int* status) {
+  const double n2 = *norm2, k2 = *kept2;
+  if (!(n2 > 0) || !isfinite(n2)) latch_error(status, n2 == 0 ? ERRBIT_ZERONORM : ERRBIT_NONFINITE);
+  *chi_new = eta;
+  *eps = n2 > 0 ? fmax(0.0, n2 - k2) / n2 : 0.0;
+}
+
+// CBE step (v): chi~ = number of leading S >= svd_min (at most kmax, at least
+// one), Xi~ = S_kept / |S_kept|, eps.
+__global__ __launch_bounds__(256) void select_kernel(const double* lam, int kmax, double svd_min,
+                                                     const double* norm2, int* chi_new, double* xi,
+                                                     double* kept2, double* eps, int* status) {
+  __shared__ int first_bad;
+  __shared__ double scr[4];
+  __shared__ double k2s;
+  if (threadIdx.x == 0) first_bad = kmax;
+  __syncthreads();
+  for (int j = threadIdx.x; j < kmax; j += 256) {
+    const double l = lam[j];
+    if (!isfinite(l)) latch_error(status, ERRBIT_NONFINITE);
+    if (!(sqrt(fmax(l, 0.0)) >= svd_min)) atomicMin(&first_bad, j);
+  }
+  __syncthreads();
+  const int k = max(1, first_bad);
+  double s = 0;
+  for (int j = threadIdx.x; j < k; j += 256) s += fmax(lam[j], 0.0);
+  s = block_sum(s, scr);
+  if (threadIdx.x == 0) k2s = s;
+  __syncthreads();
+  const double inv = k2s > 0 ? 1.0 / sqrt(k2s) : 0.0;
+  for (int j = threadIdx.x; j < k; j += 256) xi[j] = sqrt(fmax(lam[j], 0.0)) * inv;
+  if (threadIdx.x == 0) {
+    const double n2 = *norm2;
+    if (!(n2 > 0) || !isfinite(n2)) latch_error(status, n2 == 0 ? ERRBIT_ZERONORM : ERRBIT_NONFINITE);
+    *chi_new = k;
+    *kept2 = k2s;
+    *eps = n2 > 0 ? fmax(0.0, n2 - k2s) / n2 : 0.0;
+  }
+}
+
+// out (cols x rows) = conj(in (rows x cols))^T
+template <typename S>
+__global__ __launch_bounds__(256) void transpose_conj_kernel(const cpx<S>* in, int rows, int cols, cpx<S>* out) {
+  __shared__ cpx<S> tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = by + r, j = bx + tx;
+    if (i < rows && j < cols) tile[r][tx] = in[(long long)i * cols + j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int j = bx + r, i = by + tx;
+    if (i < rows && j < cols) {
+      const cpx<S> z = tile[tx][r];
+      out[(long long)j * rows + i] = mk<S>(z.re, -z.im);
+    }
+  }
+}
+
+template <typename D, typename S>
+__global__ void cast_kernel(const cpx<S>* in, long long n, cpx<D>* out) {
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256) out[i] = ccast<D>(in[i]);
+}
+
+// Dc = (G - 1)/2 on the live chi~ x chi~ block (G complex128, Dc complex64, ld cap).
+__global__ void reorth_prep_kernel(const c128* G, int cap, const int* chi_new, c64* Dc) {
+  const int k = *chi_new;
+  const long long n = (long long)k * k;
+  for (long long idx = blockIdx.x * 256ll + threadIdx.x; idx < n; idx += (long long)gridDim.x * 256) {
+    const int i = (int)(idx / k), j = (int)(idx % k);
+    const c128 g = G[(long long)i * cap + j];
+    Dc[(long long)i * cap + j] = mk<float>((float)(0.5 * (g.re - (i == j ? 1.0 : 0.0))), (float)(0.5 * g.im));
+  }
+}
+
+int grid_for(long long n) { return (int)std::max<long long>(1, std::min<long long>((n + 255) / 256, 4096)); }
+
+struct Carve {
+  char* p;
+  void* take(size_t b) {
+    void* r = p;
+    p += a256(b);
+    return r;
+  }
+};
+
+struct BondBufs {
+  void *C, *Th, *X, *YH, *R, *Ec, *XiC, *Dc, *tmp;
+  c128 *G, *E, *G2;
+  double *lam, *partial, *norm2, *kept2;
+  void* qrw;
+  void* eigw;
+  size_t total;
+};
+
+int kwant_of(const BondShape& b) { return b.cap(); }
+
+BondBufs carve(const BondShape& b, void* base) {
+  const size_t es = b.prec == 0 ? 16 : 8;
+  const size_t mL = (size_t)b.d * b.chi_l, mR = (size_t)b.d * b.chi_r, eta = b.eta;
+  const size_t kw = kwant_of(b), cap = b.cap();
+  const bool cbe = b.mode == 2, mixed = b.prec != 0;
+  Carve c{(char*)base};
+  BondBufs o{};
+  o.C = c.take(mL * mR * es);
+  o.Th = c.take(mL * mR * es);
+  o.X = c.take(mL * eta * es);
+  o.YH = c.take(mR * eta * es);
+  o.R = c.take(eta * eta * es);
+  o.G = (c128*)c.take(cbe ? eta * eta * 16 : 0);
+  o.E = (c128*)c.take(cbe ? eta * kw * 16 : 0);
+  o.Ec = c.take(cbe && mixed ? eta * kw * es : 0);
+  o.lam = (double*)c.take(cbe ? kw * 8 : 0);
+  o.XiC = c.take(!b.xi_is_diag && mixed ? (size_t)b.chi_l * b.chi_l * es : 0);
+  o.G2 = (c128*)c.take(mixed ? cap * cap * 16 : 0);
+  o.Dc = c.take(mixed ? cap * cap * 8 : 0);
+  o.tmp = c.take(mixed ? cap * mR * es : 0);
+  const size_t npart = std::max<size_t>((size_t)b.chi_l * ((b.chi_r + 63) / 64), 4096);
+  o.partial = (double*)c.take(npart * 8);
+  o.norm2 = (double*)c.take(8);
+  o.kept2 = (double*)c.take(8);
+  o.qrw = c.take(qr_work_bytes((int)std::max(mL, mR), (int)eta, (int)es, (int)eta));
+  o.eigw = c.take(cbe ? eig_work_bytes((int)eta) : 0);
+  o.total = (size_t)(c.p - (char*)base);
+  return o;
+}
+
+template <typename S>
+int run_typed(const BondShape& b, void* ws, int* status, const void* xi_m, const void* b_m, const void* b_n,
+              const c128* u, void* b_m_out, void* xi_n_out, void* b_n_out, int* chi_new, double* eps,
+              hipStream_t s) {
+  const int dt = sizeof(S) == 8 ? DT_C128 : DT_C64;
+  const GemmTypes ty{dt, dt};
+  const int d = b.d, chiL = b.chi_l, chiM = b.chi_m, chiR = b.chi_r, eta = b.eta;
+  const int mL = d * chiL, mR = d * chiR;
+  const int cap = b.cap(), kw = kwant_of(b);
+  const bool cbe = b.mode == 2, mixed = dt == DT_C64;
+  BondBufs w = carve(b, ws);
+  QrWork qw = qr_work_carve(w.qrw, std::max(mL, mR), eta, (int)sizeof(cpx<S>), eta, status);
+  int rc;
+
+  // (i) C = B^[m] B^[n]
+  if ((rc = gemm_one(gemm_prob(b_m, chiM, OP_N, b_n, mR, OP_N, w.C, mR, mL, mR, chiM), ty, s))) return rc;
+  // C~ = U C (in place) and theta~ = Xi C~
+  {
+    const dim3 grid((chiR + 63) / 64, chiL);
+    const size_t shm = (size_t)d * d * 64 * sizeof(c128);
+    static bool attr = false;
+    if (!attr) {
+      QT_HIP_CHECK(hipFuncSetAttribute((const void*)gate_kernel<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024));
+      attr = true;
+    }
+    const bool diag = b.xi_is_diag != 0;
+    hipLaunchKernelGGL(gate_kernel<S>, grid, dim3(64), shm, s, (cpx<S>*)w.C, diag ? (cpx<S>*)w.Th : nullptr, u,
+                       diag ? (const double*)xi_m : nullptr, d, chiR, w.partial);
+    QT_HIP_CHECK(hipGetLastError());
+    if (diag) {
+      if ((rc = reduce_partials(w.partial, (int)(grid.x * grid.y), w.norm2, s))) return rc;
+    } else {
+      const void* xiA = xi_m;
+      if (mixed) {
+        const long long nx = (long long)chiL * chiL;
+        hipLaunchKernelGGL((cast_kernel<float, double>), dim3(grid_for(nx)), dim3(256), 0, s, (const c128*)xi_m, nx,
+                           (c64*)w.XiC);
+        QT_HIP_CHECK(hipGetLastError());
+        xiA = w.XiC;
+      }
+      // theta~ = Xi C~ with C~ viewed as chi_l x (d d chi_r)
+      const int ncol = d * mR;
+      if ((rc = gemm_one(gemm_prob(xiA, chiL, OP_N, w.C, ncol, OP_N, w.Th, ncol, chiL, ncol, chiL), ty, s))) return rc;
+      const long long n = (long long)mL * mR;
+      hipLaunchKernelGGL(sumsq_kernel<S>, dim3(1024), dim3(256), 0, s, (const cpx<S>*)w.Th, n, w.partial);
+      QT_HIP_CHECK(hipGetLastError());
+      if ((rc = reduce_partials(w.partial, 1024, w.norm2, s))) return rc;
+    }
+  }
+  // X = theta~ Y0^dag
+  {
+    GemmProb g = b.mode == 0 ? gemm_prob(w.Th, mR, OP_N, b_n, mR, OP_C, w.X, eta, mL, eta, mR)
+                             : gemm_prob(w.Th, mR, OP_N, w.Th, mR, OP_C, w.X, eta, mL, eta, mR);
+    if ((rc = gemm_one(g, ty, s))) return rc;
+  }
+  // Q^[m]
+  if ((rc = qr_factor(w.X, eta, mL, eta, dt, qw, s))) return rc;
+  if ((rc = qr_form_q(w.X, eta, mL, eta, dt, qw, s))) return rc;
+  // Y^dag = theta~^dag Q^[m], then Y^dag = Q' R'
+  if ((rc = gemm_one(gemm_prob(w.Th, mR, OP_C, w.X, eta, OP_N, w.YH, eta, mR, eta, mL), ty, s))) return rc;
+  if ((rc = qr_factor(w.YH, eta, mR, eta, dt, qw, s))) return rc;
+  {
+    const long long n = (long long)eta * eta;
+    hipLaunchKernelGGL(extract_r_kernel<S>, dim3(grid_for(n)), dim3(256), 0, s, (const cpx<S>*)w.YH, eta,
+                       (cpx<S>*)w.R);
+    QT_HIP_CHECK(hipGetLastError());
+  }
+  if ((rc = qr_form_q(w.YH, eta, mR, eta, dt, qw, s))) return rc;
+
+  if (cbe) {
+    // L^dag L = R' R'^dag in FP64
+    if ((rc = gemm_one(gemm_prob(w.R, eta, OP_N, w.R, eta, OP_C, w.G, eta, eta, eta, eta), GemmTypes{dt, DT_C128}, s)))
+      return rc;
+    EigWork ew = eig_work_carve(w.eigw, eta, status);
+    if ((rc = eig_herm_top(w.G, eta, kw, w.lam, w.E, ew, s))) return rc;
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, s, w.lam, kw, b.svd_min, w.norm2, chi_new,
+                       (double*)xi_n_out, w.kept2, eps, status);
+    QT_HIP_CHECK(hipGetLastError());
+    const void* Eu = w.E;
+    if (mixed) {
+      const long long n = (long long)eta * kw;
+      hipLaunchKernelGGL((cast_kernel<float, double>), dim3(grid_for(n)), dim3(256), 0, s, w.E, n, (c64*)w.Ec);
+      QT_HIP_CHECK(hipGetLastError());
+      Eu = w.Ec;
+    }
+    // B~^[n] = E_kept^dag Q'^dag  (chi~ x d chi_r)
+    GemmProb g = gemm_prob(Eu, kw, OP_C, w.YH, eta, OP_C, b_n_out, mR, kw, mR, eta);
+    g.dM = chi_new;
+    if ((rc = gemm_one(g, ty, s))) return rc;
+  } else {
+    const long long n = (long long)eta * eta;
+    hipLaunchKernelGGL(sumsq_kernel<S>, dim3(1024), dim3(256), 0, s, (const cpx<S>*)w.R, n, w.partial);
+    QT_HIP_CHECK(hipGetLastError());
+    if ((rc = reduce_partials(w.partial, 1024, w.kept2, s))) return rc;
+    hipLaunchKernelGGL(plain_xi_kernel<S>, dim3(grid_for(n)), dim3(256), 0, s, (const cpx<S>*)w.R, eta, w.kept2,
+                       (c128*)xi_n_out);
+    QT_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(plain_finish_kernel, dim3(1), dim3(1), 0, s, eta, w.norm2, w.kept2, chi_new, eps, status);
+    QT_HIP_CHECK(hipGetLastError());
+    // B~^[n] = Q^[n] = Q'^dag
+    const dim3 grid((eta + 31) / 32, (mR + 31) / 32);
+    hipLaunchKernelGGL(transpose_conj_kernel<S>, grid, dim3(256), 0, s, (const cpx<S>*)w.YH, mR, eta,
+                       (cpx<S>*)b_n_out);
+    QT_HIP_CHECK(hipGetLastError());
+  }
+  if (mixed) {
+    // one re-orthogonalisation step of B~^[n] with B B^dag accumulated in FP64
+    GemmProb g2 = gemm_prob(b_n_out, mR, OP_N, b_n_out, mR, OP_C, w.G2, cap, cap, cap, mR);
+    g2.dM = chi_new;
+    g2.dN = chi_new;
+    if ((rc = gemm_one(g2, GemmTypes{DT_C64, DT_C128}, s))) return rc;
+    hipLaunchKernelGGL(reorth_prep_kernel, dim3(grid_for((long long)cap * cap)), dim3(256), 0, s, w.G2, cap, chi_new,
+                       (c64*)w.Dc);
+    QT_HIP_CHECK(hipGetLastError());
+    QT_HIP_CHECK(hipMemcpyAsync(w.tmp, b_n_out, (size_t)cap * mR * sizeof(cpx<S>), hipMemcpyDeviceToDevice, s));
+    GemmProb g3 = gemm_prob(w.Dc, cap, OP_N, w.tmp, mR, OP_N, b_n_out, mR, cap, mR, cap, -1.f, 1.f);
+    g3.dM = chi_new;
+    g3.dK = chi_new;
+    if ((rc = gemm_one(g3, ty, s))) return rc;
+  }
+  // B~^[m] = C~ B~^[n]^dag  (chi_l d x chi~, compact with the live chi~)
+  {
+    GemmProb g = gemm_prob(w.C, mR, OP_N, b_n_out, mR, OP_C, b_m_out, cap, mL, cap, mR);
+    g.dN = chi_new;
+    g.ldc_live_N = 1;
+    if ((rc = gemm_one(g, ty, s))) return rc;
+  }
+  return 0;
+}
+
+}  // namespace
+
+int reduce_partials(const double* part, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, s, part, n, out);
+  QT_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+size_t bond_work_bytes(const BondShape& b) { return carve(b, nullptr).total + 256; }
+
+int bond_update_run(const BondShape& b, void* ws, int* status, const void* xi_m, const void* b_m, const void* b_n,
+                    const c128* u, void* b_m_out, void* xi_n_out, void* b_n_out, int* chi_new, double* eps,
+                    hipStream_t s) {
+  if (b.prec == 0)
+    return run_typed<double>(b, ws, status, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, chi_new, eps, s);
+  return run_typed<float>(b, ws, status, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, chi_new, eps, s);
+}
+
+}  // namespace qrtebd

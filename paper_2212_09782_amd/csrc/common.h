@@ -1,0 +1,137 @@
+// Shared device/host helpers of the QR-TEBD library (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace qrtebd {
+
+// Interleaved complex scalar, the memory layout of complex64 / complex128.
+template <typename T> struct alignas(2 * sizeof(T)) cpx { T re, im; };
+using c64 = cpx<float>;
+using c128 = cpx<double>;
+
+template <typename T> __host__ __device__ inline cpx<T> mk(T r, T i) { cpx<T> z; z.re = r; z.im = i; return z; }
+template <typename T> __host__ __device__ inline cpx<T> cadd(cpx<T> a, cpx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+template <typename T> __host__ __device__ inline cpx<T> csub(cpx<T> a, cpx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+template <typename T> __host__ __device__ inline cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+// conj(a) * b
+template <typename T> __host__ __device__ inline cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+  return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+template <typename T> __host__ __device__ inline cpx<T> cconj(cpx<T> a) { return mk(a.re, -a.im); }
+template <typename T> __host__ __device__ inline cpx<T> cscale(cpx<T> a, T s) { return mk(a.re * s, a.im * s); }
+template <typename T> __host__ __device__ inline T cabs2(cpx<T> a) { return a.re * a.re + a.im * a.im; }
+
+template <typename D, typename S> __host__ __device__ inline cpx<D> ccast(cpx<S> a) {
+  return mk<D>((D)a.re, (D)a.im);
+}
+
+// Error bits latched in the device status word.
+enum : int {
+  ERRBIT_BARRIER = 1,    // a grid barrier spun past its limit
+  ERRBIT_NONFINITE = 2,  // NaN / Inf met in a norm or spectrum
+  ERRBIT_ZERONORM = 4,   // a two-site wave function of zero norm
+  ERRBIT_CAPACITY = 8,   // a live dimension exceeded its capacity
+};
+
+__device__ inline void latch_error(int* status, int bit) {
+  if (status) atomicOr(status, bit);
+}
+
+// ---------------------------------------------------------------- reductions
+// Wave64 sum via cross-lane shuffles.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block-wide sum of one double (all threads get the result).  scratch needs
+// blockDim.x/64 doubles of LDS.  Contains two barriers.
+__device__ inline double block_sum(double v, double* scratch) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double s = 0;
+  for (int w = 0; w < nw; ++w) s += scratch[w];
+  return s;
+}
+
+// ---------------------------------------------------------------- grid barrier
+// Flag barrier for cooperative launches: every block publishes its arrival
+// generation in its own cache line, block 0 gathers them and publishes the
+// generation word that all other blocks wait on.  Spins are bounded: on
+// timeout the error bit is latched and false is returned so the kernel can
+// leave.  base must hold 16*(nblocks+1) unsigned words, zeroed before the
+// launch; gen counts barriers from 1 within one launch.
+struct GridSync {
+  unsigned* base;
+  int* status;
+};
+
+__device__ inline bool grid_barrier(GridSync gs, unsigned gen, int nblk, int* smem_flag) {
+  constexpr long kSpinLimit = 1L << 22;
+  // every thread's earlier global writes become visible device-wide first
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  unsigned* genw = gs.base;
+  unsigned* flags = gs.base + 16;
+  if (threadIdx.x == 0) *smem_flag = 0;
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int b = 1 + (int)threadIdx.x; b < nblk; b += blockDim.x) {
+      long spins = 0;
+      while (__hip_atomic_load(flags + 16 * b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+        if (++spins > kSpinLimit) { *smem_flag = 1; break; }
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(genw, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (threadIdx.x == 0) {
+    __hip_atomic_store(flags + 16 * blockIdx.x, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    long spins = 0;
+    while (__hip_atomic_load(genw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+      if (++spins > kSpinLimit) { *smem_flag = 1; break; }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const bool ok = *smem_flag == 0;
+  if (!ok && threadIdx.x == 0) latch_error(gs.status, ERRBIT_BARRIER);
+  return ok;
+}
+
+// Words needed by grid_barrier for nblk blocks.
+inline size_t grid_sync_words(int nblk) { return 16 * (size_t)(nblk + 1); }
+
+}  // namespace qrtebd
+
+#define QT_HIP_CHECK(expr)                                                     \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess) return ::qrtebd::set_hip_error(e_, #expr, __FILE__, __LINE__); \
+  } while (0)
+
+namespace qrtebd {
+int set_hip_error(hipError_t e, const char* expr, const char* file, int line);
+int set_error(int code, const char* fmt, ...);
+}

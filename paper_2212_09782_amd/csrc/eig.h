@@ -1,0 +1,27 @@
+// FP64 Hermitian eigensolver for L^dag L (internal interface).
+#pragma once
+#include "qr.h"
+
+namespace qrtebd {
+
+struct EigWork {
+  double* d;        // n   diagonal of the tridiagonal matrix
+  double* e;        // n   off-diagonal (real, >= 0 up to sign)
+  c128* tau;        // n   reflector factors
+  double* lu;       // 4 * n * n inverse-iteration factors
+  unsigned* sync;   // grid barrier words
+  c128* red;        // cross-block partial sums: 2 * (256 + 1) + 2 * n  (p vector + row)
+  QrWork qtri;      // reflectors of the tridiagonalisation, (n-1) x (n-1) problem with n work columns
+  QrWork qz;        // re-orthogonalisation QR of the eigenvector block, n x n
+  int* status;
+};
+
+size_t eig_work_bytes(int n);
+EigWork eig_work_carve(void* base, int n, int* status);
+
+// Largest kwant eigenpairs of the Hermitian n x n matrix G (row-major, ld n,
+// destroyed).  lam: kwant eigenvalues in descending order; E: n x kwant
+// (row-major, ld kwant) with the matching orthonormal eigenvectors as columns.
+int eig_herm_top(c128* G, int n, int kwant, double* lam, c128* E, const EigWork& w, hipStream_t s);
+
+}  // namespace qrtebd

@@ -1,0 +1,498 @@
+// FP64 Hermitian eigensolver for step (iv) of controlled bond expansion
+// (Sec. III): L^dag L = V^dag S^2 V.
+//
+//  1. Householder tridiagonalisation A = Q T Q^H (LAPACK zhetd2 conventions,
+//     lower form) in one cooperative kernel.  The matrix rows live in LDS,
+//     dealt cyclically to the blocks; the reflector vector, the trailing
+//     row and the rank-2 update vector live in registers (column j of a
+//     vector belongs to thread j mod 256).  Step k needs one grid barrier:
+//     each block publishes its slice of p = tau A v and its part of p^H v,
+//     and the current row k+1; after the barrier every block rebuilds row k+1
+//     itself and derives the next reflector without further communication.
+//     T is real symmetric because every off-diagonal beta is real.
+//  2. The wanted (largest) eigenvalues of T by Sturm-count bisection, one
+//     thread per eigenvalue.
+//  3. Their eigenvectors by inverse iteration on T (tridiagonal LU with
+//     partial pivoting, three solves from a fixed pseudo-random start), one
+//     thread per vector.
+//  4. Re-orthogonalisation of that block by the Householder QR (clusters of
+//     close eigenvalues are orthogonalised in eigenvalue order).
+//  5. Back-transformation E = Q Z with the compact-WY blocks of step 1 on
+//     the MFMA GEMM.
+#include "eig.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace qrtebd {
+namespace {
+
+constexpr int NB = kQrNb;
+constexpr int QMAX = 8;            // register slots per thread: n <= 2048
+constexpr int kMaxN = 256 * QMAX;
+constexpr size_t kTriLds = 150 * 1024;
+
+__device__ inline c128 z0() { return mk<double>(0, 0); }
+
+// x - (a conj(b) + c conj(d)), written with explicit fused operations so that
+// every block evaluates it identically.
+__device__ inline c128 rank2_sub(c128 x, c128 a, c128 b, c128 c, c128 d) {
+  double re = fma(a.re, b.re, fma(a.im, b.im, fma(c.re, d.re, c.im * d.im)));
+  double im = fma(a.im, b.re, fma(-a.re, b.im, fma(c.im, d.re, -c.re * d.im)));
+  return mk<double>(x.re - re, x.im - im);
+}
+
+struct TriArgs {
+  const c128* G;
+  int n, rows_loc;
+  double* d;
+  double* e;
+  c128* tau;
+  c128* V;        // QrWork V layout of the (n-1) x (n-1) reflector problem
+  c128* pbuf;     // [2][n]
+  c128* rowbuf;   // [2][n]
+  c128* red;      // [2][nblk]
+  GridSync gs;
+};
+
+__global__ __launch_bounds__(256) void tridiag_kernel(TriArgs a) {
+  extern __shared__ c128 rows[];  // rows_loc x n, local row r = global row blk + r * P
+  __shared__ double scratch[8];
+  __shared__ c128 wred[4][16];
+  __shared__ c128 vloc[16], wloc[16], ploc[16];
+  __shared__ c128 scal[6];
+  __shared__ int flag;
+
+  const int n = a.n, P = gridDim.x, blk = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int RL = a.rows_loc;
+  const int mqr = n - 1;
+
+  for (int r = 0; r < RL; ++r) {
+    const int gi = blk + r * P;
+    if (gi < n)
+      for (int j = tid; j < n; j += 256) rows[r * n + j] = a.G[(long long)gi * n + j];
+  }
+  c128 rk[QMAX], v[QMAX], w[QMAX];
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    const int j = tid + 256 * q;
+    rk[q] = j < n ? a.G[j] : z0();
+    v[q] = z0();
+    w[q] = z0();
+  }
+  __syncthreads();
+
+  for (int k = 0; k < n - 1; ++k) {
+    const int slot = k & 1;
+    // ---- reflector from column k below the diagonal = conj(row k right of it)
+    double xn2 = 0;
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const int j = tid + 256 * q;
+      if (j >= k + 2 && j < n) xn2 += cabs2(rk[q]);
+    }
+    xn2 = block_sum(xn2, scratch);
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q)
+      if (tid + 256 * q == k + 1) scal[4] = cconj(rk[q]);
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q)
+      if (tid + 256 * q == k) scal[5] = rk[q];
+    __syncthreads();
+    if (tid == 0) {
+      const c128 alpha = scal[4];
+      c128 tau = z0(), scale = z0();
+      double beta = alpha.re;
+      if (!(xn2 == 0.0 && alpha.im == 0.0)) {
+        beta = -copysign(sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn2), alpha.re);
+        tau = mk<double>((beta - alpha.re) / beta, -alpha.im / beta);
+        const c128 den = mk<double>(alpha.re - beta, alpha.im);
+        const double dd = cabs2(den);
+        scale = mk<double>(den.re / dd, -den.im / dd);
+      }
+      scal[0] = tau;
+      scal[1] = scale;
+      if (blk == 0) {
+        a.d[k] = scal[5].re;
+        a.e[k] = beta;
+        a.tau[k] = tau;
+        if (!isfinite(beta) || !isfinite(scal[5].re)) latch_error(a.gs.status, ERRBIT_NONFINITE);
+      }
+    }
+    __syncthreads();
+    const c128 tau = scal[0], scale = scal[1];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const int j = tid + 256 * q;
+      v[q] = j == k + 1 ? mk<double>(1, 0) : (j > k + 1 && j < n ? cmul(cconj(rk[q]), scale) : z0());
+    }
+    // v_i of this block's rows, for the rank-2 update
+    for (int r = 0; r < RL; ++r) {
+      const int gi = blk + r * P;
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q)
+        if (gi < n && tid + 256 * q == gi) vloc[r] = v[q];
+    }
+    // reflector k into the QR-compatible layout: subproblem row i <-> row i+1
+    if (blk == k % P) {
+      const int p = k / NB, c = k % NB, j0 = p * NB;
+      c128* Vp = a.V + (size_t)p * mqr * NB;
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        const int g = tid + 256 * q;  // global row
+        if (g >= j0 + 1 && g < n) Vp[(long long)(g - 1 - j0) * NB + c] = g >= k + 1 ? v[q] : z0();
+      }
+    }
+    // ---- p_i = tau sum_{j>k} A[i][j] v_j for own rows i > k
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      if (r < RL) {
+        const int gi = blk + r * P;
+        c128 s = z0();
+        if (gi > k && gi < n) {
+#pragma unroll
+          for (int q = 0; q < QMAX; ++q) {
+            const int j = tid + 256 * q;
+            if (j > k && j < n) s = cadd(s, cmul(rows[r * n + j], v[q]));
+          }
+        }
+        const double sr = wave_sum(s.re), si = wave_sum(s.im);
+        if (lane == 0) wred[wid][r] = mk<double>(sr, si);
+      }
+    }
+    __syncthreads();
+    if (tid < RL) {
+      const int r = tid, gi = blk + r * P;
+      c128 s = z0();
+      for (int ww = 0; ww < 4; ++ww) s = cadd(s, wred[ww][r]);
+      const c128 pi = (gi > k && gi < n) ? cmul(tau, s) : z0();
+      ploc[r] = pi;
+      if (gi > k && gi < n) a.pbuf[(long long)slot * n + gi] = pi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      c128 s = z0();
+      for (int r = 0; r < RL; ++r) s = cadd(s, cmulc(ploc[r], vloc[r]));
+      a.red[(long long)slot * P + blk] = s;
+    }
+    if ((k + 1) % P == blk) {
+      const int r = (k + 1) / P;
+      for (int j = tid; j < n; j += 256) a.rowbuf[(long long)slot * n + j] = rows[r * n + j];
+    }
+    if (!grid_barrier(a.gs, (unsigned)(k + 1), P, &flag)) return;
+    // ---- w = p + alpha2 v,  alpha2 = -tau (p^H v) / 2
+    if (tid == 0) {
+      c128 s = z0();
+      for (int b = 0; b < P; ++b) s = cadd(s, a.red[(long long)slot * P + b]);
+      scal[2] = cscale(cmul(tau, s), -0.5);
+    }
+    __syncthreads();
+    const c128 alpha2 = scal[2];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const int j = tid + 256 * q;
+      w[q] = (j > k && j < n) ? cadd(a.pbuf[(long long)slot * n + j], cmul(alpha2, v[q])) : z0();
+      if (j == k + 1) scal[3] = w[q];
+    }
+    for (int r = 0; r < RL; ++r) {
+      const int gi = blk + r * P;
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q)
+        if (gi < n && tid + 256 * q == gi) wloc[r] = w[q];
+    }
+    __syncthreads();
+    // row k+1 (as published before the update) gets the rank-2 update
+    const c128 wk1 = scal[3];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const int j = tid + 256 * q;
+      if (j < n) {
+        const c128 x = a.rowbuf[(long long)slot * n + j];
+        rk[q] = j > k ? rank2_sub(x, mk<double>(1, 0), w[q], wk1, v[q]) : x;
+      }
+    }
+    for (int r = 0; r < RL; ++r) {
+      const int gi = blk + r * P;
+      if (gi <= k || gi >= n) continue;
+      const c128 vi = vloc[r], wi = wloc[r];
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        const int j = tid + 256 * q;
+        if (j > k && j < n) rows[r * n + j] = rank2_sub(rows[r * n + j], vi, w[q], wi, v[q]);
+      }
+    }
+    __syncthreads();
+  }
+  // d[n-1] from the thread holding column n-1 of the final row
+  if (blk == 0) {
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q)
+      if (tid + 256 * q == n - 1) {
+        a.d[n - 1] = rk[q].re;
+        a.e[n - 1] = 0.0;
+        a.tau[n - 1] = z0();
+      }
+  }
+}
+
+// Number of eigenvalues of the tridiagonal (d, e) below x (Sturm sequence).
+__device__ inline int sturm_count(const double* d, const double* e, int n, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0;
+  }
+  return cnt;
+}
+
+// lam[j] = (j+1)-th largest eigenvalue, j < kwant.
+__global__ void bisect_kernel(const double* d, const double* e, int n, int kwant, double* lam) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= kwant) return;
+  double lo = d[0], hi = d[0], emax2 = 0;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
+    lo = fmin(lo, d[i] - r);
+    hi = fmax(hi, d[i] + r);
+    if (i < n - 1) emax2 = fmax(emax2, e[i] * e[i]);
+  }
+  const double tnorm = fmax(fabs(lo), fabs(hi));
+  const double pivmin = fmax(2.2250738585072014e-308, 2.2250738585072014e-308 * emax2);
+  lo -= 2.2e-16 * tnorm + 2 * pivmin;
+  hi += 2.2e-16 * tnorm + 2 * pivmin;
+  const int idx = n - 1 - j;  // ascending index
+  double a = lo, b = hi;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (a + b);
+    if (mid <= a || mid >= b) break;
+    if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) + pivmin) break;
+    if (sturm_count(d, e, n, mid, pivmin) > idx) b = mid; else a = mid;
+  }
+  lam[j] = 0.5 * (a + b);
+}
+
+__device__ inline double hash_uniform(unsigned long long x) {
+  x += 0x9e3779b97f4a7c15ULL;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
+  x ^= x >> 31;
+  return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// Inverse iteration for eigenvalue lam[j]: E[:, j] (real, stored complex).
+// lu: [4][n][kwant] (diag, super1, super2, multiplier); the pivot choice is
+// kept in the sign bit of the multiplier slot's companion (swap flags below).
+__global__ void invit_kernel(const double* d, const double* e, int n, int kwant, const double* lam,
+                             double* lu, unsigned char* swp, c128* E) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= kwant) return;
+  const double l = lam[j];
+  double tnorm = 0;
+  for (int i = 0; i < n; ++i)
+    tnorm = fmax(tnorm, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0));
+  const double tiny = fmax(tnorm, 1e-300) * 2.2e-16;
+  double* U0 = lu;
+  double* U1 = lu + (size_t)n * kwant;
+  double* U2 = lu + 2 * (size_t)n * kwant;
+  double* ML = lu + 3 * (size_t)n * kwant;
+  auto at = [&](int i) { return (size_t)i * kwant + j; };
+  // factor T - l I with partial pivoting
+  double c0 = d[0] - l, c1 = n > 1 ? e[0] : 0.0, c2 = 0.0;
+  for (int k = 0; k < n - 1; ++k) {
+    const double n0 = e[k], n1 = d[k + 1] - l, n2 = (k + 1 < n - 1) ? e[k + 1] : 0.0;
+    double u0, u1, u2, m;
+    unsigned char sw;
+    if (fabs(c0) >= fabs(n0)) {
+      m = c0 != 0.0 ? n0 / c0 : 0.0;
+      u0 = c0; u1 = c1; u2 = c2; sw = 0;
+      c0 = n1 - m * c1; c1 = n2 - m * c2; c2 = 0.0;
+    } else {
+      m = c0 / n0;
+      u0 = n0; u1 = n1; u2 = n2; sw = 1;
+      c0 = c1 - m * n1; c1 = c2 - m * n2; c2 = 0.0;
+    }
+    if (u0 == 0.0) u0 = tiny;
+    U0[at(k)] = u0; U1[at(k)] = u1; U2[at(k)] = u2; ML[at(k)] = m; swp[at(k)] = sw;
+  }
+  U0[at(n - 1)] = c0 == 0.0 ? tiny : c0;
+  U1[at(n - 1)] = 0.0;
+  U2[at(n - 1)] = 0.0;
+  // start vector, stored in E's real parts
+  for (int i = 0; i < n; ++i) E[at(i)] = mk<double>(hash_uniform(((unsigned long long)j << 32) ^ (unsigned)i), 0.0);
+  for (int it = 0; it < 3; ++it) {
+    // forward: apply the row operations to b (in place in E.re)
+    double rc = E[at(0)].re;
+    for (int k = 0; k < n - 1; ++k) {
+      const double bk1 = E[at(k + 1)].re, m = ML[at(k)];
+      if (swp[at(k)] == 0) {
+        E[at(k)].re = rc;
+        rc = bk1 - m * rc;
+      } else {
+        E[at(k)].re = bk1;
+        rc = rc - m * bk1;
+      }
+    }
+    E[at(n - 1)].re = rc;
+    // back substitution
+    double z1 = 0.0, z2 = 0.0, nrm = 0.0;
+    for (int i = n - 1; i >= 0; --i) {
+      const double z = (E[at(i)].re - U1[at(i)] * z1 - U2[at(i)] * z2) / U0[at(i)];
+      E[at(i)].re = z;
+      z2 = z1;
+      z1 = z;
+      nrm = fmax(nrm, fabs(z));
+    }
+    // scale to unit max norm, then to unit 2-norm on the last pass
+    double s2 = 0.0;
+    const double inv = nrm > 0 ? 1.0 / nrm : 1.0;
+    for (int i = 0; i < n; ++i) {
+      const double z = E[at(i)].re * inv;
+      E[at(i)].re = z;
+      s2 += z * z;
+    }
+    if (it == 2) {
+      const double f = 1.0 / sqrt(s2);
+      for (int i = 0; i < n; ++i) E[at(i)].re *= f;
+    }
+  }
+}
+
+// T_p and V_p T_p for every panel of the tridiagonalisation reflectors.
+__global__ __launch_bounds__(256) void larft_kernel(c128* V, c128* VT, c128* T, const c128* tau, int m, int nrefl) {
+  __shared__ c128 G[NB][NB + 1];
+  __shared__ c128 Tm[NB][NB + 1];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const int j0 = p * NB, jb = min(NB, nrefl - j0), mp = m - j0;
+  const c128* Vp = V + (size_t)p * m * NB;
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int a = idx / NB, b = idx % NB;
+    c128 s = z0();
+    if (a < jb && b < jb)
+      for (int i = 0; i < mp; ++i) s = cadd(s, cmulc(Vp[(long long)i * NB + a], Vp[(long long)i * NB + b]));
+    G[a][b] = s;
+    Tm[a][b] = z0();
+  }
+  __syncthreads();
+  for (int k = 0; k < jb; ++k) {
+    const c128 tk = tau[j0 + k];
+    if (tid < k) {
+      c128 s = z0();
+      for (int q = tid; q < k; ++q) s = cadd(s, cmul(Tm[tid][q], G[q][k]));
+      Tm[tid][k] = cmul(mk<double>(-tk.re, -tk.im), s);
+    }
+    if (tid == k) Tm[k][k] = tk;
+    __syncthreads();
+  }
+  c128* VTp = VT + (size_t)p * m * NB;
+  for (int idx = tid; idx < mp * NB; idx += 256) {
+    const int i = idx / NB, c = idx % NB;
+    c128 s = z0();
+    if (c < jb)
+      for (int q = 0; q <= c; ++q) s = cadd(s, cmul(Vp[(long long)i * NB + q], Tm[q][c]));
+    VTp[idx] = s;
+  }
+  for (int idx = tid; idx < NB * NB; idx += 256) T[(size_t)p * NB * NB + idx] = Tm[idx / NB][idx % NB];
+}
+
+__global__ void eig1_kernel(const c128* G, double* lam, c128* E) {
+  lam[0] = G[0].re;
+  E[0] = mk<double>(1, 0);
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int tri_rows_loc(int n) {
+  const int rl = (int)(kTriLds / (16 * (size_t)n));
+  return std::max(1, std::min(std::min(n, 16), rl));
+}
+
+}  // namespace
+
+size_t eig_work_bytes(int n) {
+  size_t b = 0;
+  b += 3 * align256((size_t)n * 16);                 // d, e, tau
+  b += align256(4 * (size_t)n * n * 8);              // lu
+  b += align256((size_t)n * n);                      // swap flags
+  b += align256(grid_sync_words(256) * 4);
+  b += align256((2 * 257 + 4 * (size_t)n) * 16);     // red + pbuf + rowbuf
+  b += align256(qr_work_bytes(std::max(n - 1, 1), std::max(n - 1, 1), 16, n));
+  b += align256(qr_work_bytes(n, n, 16, n));
+  return b;
+}
+
+EigWork eig_work_carve(void* base, int n, int* status) {
+  char* p = (char*)base;
+  EigWork w{};
+  w.d = (double*)p; p += align256((size_t)n * 16);
+  w.e = (double*)p; p += align256((size_t)n * 16);
+  w.tau = (c128*)p; p += align256((size_t)n * 16);
+  w.lu = (double*)p; p += align256(4 * (size_t)n * n * 8);
+  p += align256((size_t)n * n);  // swap flags follow lu (see eig_herm_top)
+  w.sync = (unsigned*)p; p += align256(grid_sync_words(256) * 4);
+  w.red = (c128*)p; p += align256((2 * 257 + 4 * (size_t)n) * 16);
+  w.qtri = qr_work_carve(p, std::max(n - 1, 1), std::max(n - 1, 1), 16, n, status);
+  p += align256(qr_work_bytes(std::max(n - 1, 1), std::max(n - 1, 1), 16, n));
+  w.qz = qr_work_carve(p, n, n, 16, n, status);
+  w.status = status;
+  return w;
+}
+
+int eig_herm_top(c128* G, int n, int kwant, double* lam, c128* E, const EigWork& w, hipStream_t s) {
+  if (n < 1 || kwant < 1 || kwant > n) return set_error(-1, "eig: bad sizes n=%d kwant=%d", n, kwant);
+  if (n > kMaxN) return set_error(-2, "eig: n=%d exceeds the supported %d", n, kMaxN);
+  if (n == 1) {
+    hipLaunchKernelGGL(eig1_kernel, dim3(1), dim3(1), 0, s, G, lam, E);
+    QT_HIP_CHECK(hipGetLastError());
+    return 0;
+  }
+  const int RL = tri_rows_loc(n);
+  const int P = (n + RL - 1) / RL;
+  if (P > 256) return set_error(-2, "eig: n=%d needs %d blocks", n, P);
+  int rc = fill_zero(w.sync, grid_sync_words(P) * 4, s);
+  if (rc) return rc;
+  // reflector V must be zero where the kernel writes nothing (rows above each panel's start)
+  const int mqr = n - 1;
+  const int npan = (mqr + NB - 1) / NB;
+  if ((rc = fill_zero(w.qtri.V, (size_t)npan * mqr * NB * 16, s))) return rc;
+  TriArgs ta{};
+  ta.G = G;
+  ta.n = n;
+  ta.rows_loc = RL;
+  ta.d = w.d;
+  ta.e = w.e;
+  ta.tau = w.tau;
+  ta.V = (c128*)w.qtri.V;
+  ta.red = w.red;
+  ta.pbuf = w.red + 2 * 257;
+  ta.rowbuf = ta.pbuf + 2 * (size_t)n;
+  ta.gs = GridSync{w.sync, w.status};
+  const size_t shmem = (size_t)RL * n * sizeof(c128);
+  static bool attr = false;
+  if (!attr) {
+    QT_HIP_CHECK(hipFuncSetAttribute((const void*)tridiag_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kTriLds));
+    attr = true;
+  }
+  void* args[] = {(void*)&ta};
+  QT_HIP_CHECK(hipLaunchCooperativeKernel((const void*)tridiag_kernel, dim3(P), dim3(256), args, (unsigned)shmem, s));
+  hipLaunchKernelGGL(larft_kernel, dim3(npan), dim3(256), 0, s, (c128*)w.qtri.V, (c128*)w.qtri.VT, w.qtri.T,
+                     w.tau, mqr, mqr);
+  QT_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(bisect_kernel, dim3((kwant + 63) / 64), dim3(64), 0, s, w.d, w.e, n, kwant, lam);
+  QT_HIP_CHECK(hipGetLastError());
+  unsigned char* swp = (unsigned char*)((char*)w.lu + align256(4 * (size_t)n * n * 8));
+  hipLaunchKernelGGL(invit_kernel, dim3((kwant + 63) / 64), dim3(64), 0, s, w.d, w.e, n, kwant, lam, w.lu, swp, E);
+  QT_HIP_CHECK(hipGetLastError());
+  // orthonormalise the eigenvector block, then E = Q Z
+  if ((rc = qr_factor(E, kwant, n, kwant, DT_C128, w.qz, s))) return rc;
+  if ((rc = qr_form_q(E, kwant, n, kwant, DT_C128, w.qz, s))) return rc;
+  if ((rc = qr_apply_q(E + kwant, kwant, kwant, mqr, mqr, DT_C128, w.qtri, s))) return rc;
+  return 0;
+}
+
+}  // namespace qrtebd

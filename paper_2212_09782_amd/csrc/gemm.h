@@ -1,0 +1,73 @@
+// Grouped complex GEMM on MFMA (internal interface).
+#pragma once
+#include "common.h"
+
+namespace qrtebd {
+
+enum Op : int { OP_N = 0, OP_T = 1, OP_C = 2 };
+enum Dt : int { DT_C64 = 0, DT_C128 = 1 };
+
+// C = alpha * op(A) * op(B) + beta * C, all matrices row-major, interleaved
+// complex.  op(A) is M x K: OP_N reads A[m*lda + k], OP_T / OP_C read
+// A[k*lda + m] (OP_C conjugated).  Likewise op(B) is K x N.
+// M, N, K are capacities: they fix the launch grid.  When dM/dN/dK are set the
+// live size is min(capacity, *dX), read on the device, so a graph or a later
+// kernel can change it without the host.  ldc_live_N makes the output compact
+// with the live N as its leading dimension.
+// ksplit > 1 splits K: each split writes raw sums to work ([ksplit][Mcap][Ncap]
+// in the compute type), and gemm_splitk_reduce forms alpha*sum + beta*C.
+struct GemmProb {
+  const void* A;
+  const void* B;
+  void* C;
+  long long lda, ldb, ldc;
+  int M, N, K;
+  const int* dM;
+  const int* dN;
+  const int* dK;
+  int ldc_live_N;
+  int opA, opB;
+  float alpha, beta;
+  int ksplit;
+  void* work;
+};
+
+constexpr int kGemmMaxProb = 16;
+
+struct GemmBatch {
+  int nprob;
+  int tile_start[kGemmMaxProb + 1];
+  int tiles_m[kGemmMaxProb];
+  int tiles_n[kGemmMaxProb];
+  GemmProb p[kGemmMaxProb];
+};
+
+// Input / output element types: DT_C128 in and out computes on FP64 MFMA,
+// DT_C64 in and out on FP32 MFMA, DT_C64 in with DT_C128 out on FP64 MFMA.
+struct GemmTypes {
+  int tin;
+  int tout;
+};
+
+// Launch one grouped GEMM (all problems share the types).  Problems with
+// ksplit > 1 also launch the reduction.  Returns 0 or a negative status.
+int gemm_run(const GemmProb* probs, int nprob, GemmTypes ty, hipStream_t stream);
+inline int gemm_one(const GemmProb& p, GemmTypes ty, hipStream_t stream) {
+  return gemm_run(&p, 1, ty, stream);
+}
+
+// Convenience constructor with static sizes.
+inline GemmProb gemm_prob(const void* A, long long lda, int opA, const void* B, long long ldb,
+                          int opB, void* C, long long ldc, int M, int N, int K,
+                          float alpha = 1.f, float beta = 0.f) {
+  GemmProb p{};
+  p.A = A; p.B = B; p.C = C;
+  p.lda = lda; p.ldb = ldb; p.ldc = ldc;
+  p.M = M; p.N = N; p.K = K;
+  p.opA = opA; p.opB = opB;
+  p.alpha = alpha; p.beta = beta;
+  p.ksplit = 1;
+  return p;
+}
+
+}  // namespace qrtebd

@@ -1,0 +1,281 @@
+// Grouped complex GEMM on CDNA4 matrix cores.
+//
+// Every contraction of the bond update (theta, X, Y, L^dag L, the new tensors,
+// the compact-WY trailing updates of the Householder QR) is a complex matrix
+// product.  A complex product is four real MFMA products (the "4M" form):
+//   Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B.
+// FP64 inputs run on v_mfma_f64_16x16x4f64, FP32 inputs on
+// v_mfma_f32_16x16x4f32, both with their native accumulator.
+//
+// Tiling: a 256-thread workgroup owns a 64x64 output tile, each wave a 32x32
+// quadrant (2x2 MFMA blocks, separate real/imaginary accumulators).  Operand
+// tiles of depth 16 are staged through LDS in planar (re / im) k-major form so
+// that each MFMA operand is one conflict-light 8-byte LDS read per lane; the
+// next tile is prefetched into registers while the current one is consumed.
+#include "gemm.h"
+
+#include <algorithm>
+
+namespace qrtebd {
+namespace {
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static inline v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // output row held by (lane, item r) of a 16x16 block
+  __device__ static inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static inline v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
+
+template <typename Tin, typename Tout, typename Tc>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmBatch b) {
+  using MF = Mfma<Tc>;
+  using v4 = typename MF::v4;
+  __shared__ Tc As[2][BK][BM + PAD];
+  __shared__ Tc Bs[2][BK][BN + PAD];
+
+  const int bid = blockIdx.x;
+  int p = 0;
+  while (p + 1 < b.nprob && bid >= b.tile_start[p + 1]) ++p;
+  const GemmProb& P = b.p[p];
+  int t = bid - b.tile_start[p];
+  const int tm = b.tiles_m[p], tn = b.tiles_n[p];
+  const int split = t / (tm * tn);
+  t -= split * tm * tn;
+  const int tile_m = t % tm, tile_n = t / tm;
+
+  int M = P.M, N = P.N, K = P.K;
+  if (P.dM) M = min(M, *P.dM);
+  if (P.dN) N = min(N, *P.dN);
+  if (P.dK) K = min(K, *P.dK);
+  const int m0 = tile_m * BM, n0 = tile_n * BN;
+  if (m0 >= M || n0 >= N) return;
+  const int ks = P.ksplit > 1 ? P.ksplit : 1;
+  const int kchunk = ((K + ks - 1) / ks + BK - 1) / BK * BK;
+  const int kbeg = split * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+
+  const cpx<Tin>* __restrict__ A = (const cpx<Tin>*)P.A;
+  const cpx<Tin>* __restrict__ B = (const cpx<Tin>*)P.B;
+  const long long lda = P.lda, ldb = P.ldb;
+  const int opA = P.opA, opB = P.opB;
+  const Tc sa = opA == OP_C ? Tc(-1) : Tc(1);
+  const Tc sb = opB == OP_C ? Tc(-1) : Tc(1);
+
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = (wid & 1) * 32, wn = (wid >> 1) * 32;
+
+  v4 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc_re[i][j] = v4{0, 0, 0, 0};
+      acc_im[i][j] = v4{0, 0, 0, 0};
+    }
+
+  cpx<Tin> ra[4], rb[4];
+  // thread -> tile element mapping for the two storage orientations
+  const int rowq = tid >> 2, colq = (tid & 3) * 4;    // 64 rows x 16 cols (k contiguous)
+  const int rowk = tid >> 4, colk = (tid & 15) * 4;   // 16 k-rows x 64 cols
+
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      cpx<Tin> z = mk<Tin>(0, 0);
+      if (opA == OP_N) {
+        const int m = m0 + rowq, k = k0 + colq + e;
+        if (m < M && k < kend) z = A[(long long)m * lda + k];
+      } else {
+        const int k = k0 + rowk, m = m0 + colk + e;
+        if (m < M && k < kend) z = A[(long long)k * lda + m];
+      }
+      ra[e] = z;
+      cpx<Tin> w = mk<Tin>(0, 0);
+      if (opB == OP_N) {
+        const int k = k0 + rowk, n = n0 + colk + e;
+        if (n < N && k < kend) w = B[(long long)k * ldb + n];
+      } else {
+        const int n = n0 + rowq, k = k0 + colq + e;
+        if (n < N && k < kend) w = B[(long long)n * ldb + k];
+      }
+      rb[e] = w;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (opA == OP_N) {
+        As[0][colq + e][rowq] = (Tc)ra[e].re;
+        As[1][colq + e][rowq] = sa * (Tc)ra[e].im;
+      } else {
+        As[0][rowk][colk + e] = (Tc)ra[e].re;
+        As[1][rowk][colk + e] = sa * (Tc)ra[e].im;
+      }
+      if (opB == OP_N) {
+        Bs[0][rowk][colk + e] = (Tc)rb[e].re;
+        Bs[1][rowk][colk + e] = sb * (Tc)rb[e].im;
+      } else {
+        Bs[0][colq + e][rowq] = (Tc)rb[e].re;
+        Bs[1][colq + e][rowq] = sb * (Tc)rb[e].im;
+      }
+    }
+  };
+
+  if (kbeg < kend) load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + BK < kend) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      Tc ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = As[0][kr][wm + i * 16 + (lane & 15)];
+        ai[i] = As[1][kr][wm + i * 16 + (lane & 15)];
+        br[i] = Bs[0][kr][wn + i * 16 + (lane & 15)];
+        bi[i] = Bs[1][kr][wn + i * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc_re[i][j] = MF::op(ar[i], br[j], acc_re[i][j]);
+          acc_re[i][j] = MF::op(-ai[i], bi[j], acc_re[i][j]);
+          acc_im[i][j] = MF::op(ar[i], bi[j], acc_im[i][j]);
+          acc_im[i][j] = MF::op(ai[i], br[j], acc_im[i][j]);
+        }
+    }
+  }
+
+  // epilogue
+  if (ks > 1) {
+    cpx<Tc>* W = (cpx<Tc>*)P.work + (long long)split * P.M * P.N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm + i * 16 + MF::row(lane, r);
+          const int col = n0 + wn + j * 16 + (lane & 15);
+          if (row < M && col < N) W[(long long)row * P.N + col] = mk<Tc>(acc_re[i][j][r], acc_im[i][j][r]);
+        }
+    return;
+  }
+  cpx<Tout>* C = (cpx<Tout>*)P.C;
+  const long long ldc = P.ldc_live_N ? (long long)N : P.ldc;
+  const Tc alpha = (Tc)P.alpha, beta = (Tc)P.beta;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + MF::row(lane, r);
+        const int col = n0 + wn + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          Tc vr = alpha * acc_re[i][j][r], vi = alpha * acc_im[i][j][r];
+          cpx<Tout>* c = C + (long long)row * ldc + col;
+          if (beta != Tc(0)) {
+            const cpx<Tout> o = *c;
+            vr += beta * (Tc)o.re;
+            vi += beta * (Tc)o.im;
+          }
+          *c = mk<Tout>((Tout)vr, (Tout)vi);
+        }
+      }
+}
+
+// C = alpha * sum_s work[s] + beta * C over the live M x N.
+template <typename Tout, typename Tc>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmProb P) {
+  int M = P.M, N = P.N;
+  if (P.dM) M = min(M, *P.dM);
+  if (P.dN) N = min(N, *P.dN);
+  const long long total = (long long)M * N;
+  const long long ldc = P.ldc_live_N ? (long long)N : P.ldc;
+  const cpx<Tc>* W = (const cpx<Tc>*)P.work;
+  cpx<Tout>* C = (cpx<Tout>*)P.C;
+  const Tc alpha = (Tc)P.alpha, beta = (Tc)P.beta;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int row = (int)(idx / N), col = (int)(idx % N);
+    Tc sr = 0, si = 0;
+    for (int s = 0; s < P.ksplit; ++s) {
+      const cpx<Tc> w = W[((long long)s * P.M + row) * P.N + col];
+      sr += w.re;
+      si += w.im;
+    }
+    sr *= alpha;
+    si *= alpha;
+    cpx<Tout>* c = C + (long long)row * ldc + col;
+    if (beta != Tc(0)) {
+      const cpx<Tout> o = *c;
+      sr += beta * (Tc)o.re;
+      si += beta * (Tc)o.im;
+    }
+    *c = mk<Tout>((Tout)sr, (Tout)si);
+  }
+}
+
+template <typename Tin, typename Tout, typename Tc>
+int launch_typed(const GemmProb* probs, int nprob, hipStream_t stream) {
+  int i = 0;
+  while (i < nprob) {
+    GemmBatch b{};
+    int total = 0;
+    b.nprob = 0;
+    while (i < nprob && b.nprob < kGemmMaxProb) {
+      const GemmProb& q = probs[i++];
+      if (q.M <= 0 || q.N <= 0) continue;
+      const int tm = (q.M + BM - 1) / BM, tn = (q.N + BN - 1) / BN;
+      const int ks = q.ksplit > 1 ? q.ksplit : 1;
+      b.p[b.nprob] = q;
+      b.tiles_m[b.nprob] = tm;
+      b.tiles_n[b.nprob] = tn;
+      b.tile_start[b.nprob] = total;
+      total += tm * tn * ks;
+      b.nprob++;
+    }
+    if (b.nprob == 0) continue;
+    b.tile_start[b.nprob] = total;
+    hipLaunchKernelGGL((gemm_kernel<Tin, Tout, Tc>), dim3(total), dim3(256), 0, stream, b);
+    QT_HIP_CHECK(hipGetLastError());
+    for (int q = 0; q < b.nprob; ++q) {
+      const GemmProb& pr = b.p[q];
+      if (pr.ksplit > 1) {
+        const long long tot = (long long)pr.M * pr.N;
+        const int grid = (int)std::min<long long>((tot + 255) / 256, 4096);
+        hipLaunchKernelGGL((splitk_reduce_kernel<Tout, Tc>), dim3(grid), dim3(256), 0, stream, pr);
+        QT_HIP_CHECK(hipGetLastError());
+      }
+    }
+  }
+  return 0;
+}
+
+}  // namespace
+
+int gemm_run(const GemmProb* probs, int nprob, GemmTypes ty, hipStream_t stream) {
+  if (ty.tin == DT_C128 && ty.tout == DT_C128) return launch_typed<double, double, double>(probs, nprob, stream);
+  if (ty.tin == DT_C64 && ty.tout == DT_C64) return launch_typed<float, float, float>(probs, nprob, stream);
+  if (ty.tin == DT_C64 && ty.tout == DT_C128) return launch_typed<float, double, double>(probs, nprob, stream);
+  return set_error(-1, "gemm_run: unsupported type combination %d/%d", ty.tin, ty.tout);
+}
+
+}  // namespace qrtebd

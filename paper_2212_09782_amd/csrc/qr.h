@@ -1,0 +1,48 @@
+// Blocked Householder QR of tall matrices (internal interface).
+#pragma once
+#include "gemm.h"
+
+namespace qrtebd {
+
+constexpr int kQrNb = 32;  // panel width
+
+// Device workspace of one QR of an m x n matrix (n <= m).
+struct QrWork {
+  void* V;        // per panel p: (m - 32p) x 32 explicit reflectors, ld 32, at offset p*m*32
+  void* VT;       // same layout: V T
+  void* VTh;      // same layout: V T^H
+  c128* T;        // per panel 32 x 32 upper triangular
+  void* W;        // 32 x n product V^H A (element type of the storage)
+  void* Wsplit;   // split-K partials: kMaxSplit x 32 x n in the compute type
+  c128* red;      // panel reductions: 2 x nblk x 32 + 2 x 32
+  unsigned* sync; // grid barrier words (>= grid_sync_words(kMaxPanelBlocks))
+  int* status;
+  int wcols;      // column capacity of W / Wsplit
+};
+
+constexpr int kMaxPanelBlocks = 256;
+constexpr int kMaxSplit = 16;
+
+// Bytes of the QrWork of an m x n problem with element size es whose W can
+// hold wcols columns (wcols >= n; qr_apply_q may then act on up to wcols).
+size_t qr_work_bytes(int m, int n, int es, int wcols);
+// Carve a QrWork out of one device allocation of qr_work_bytes bytes.
+QrWork qr_work_carve(void* base, int m, int n, int es, int wcols, int* status);
+
+// In-place factorisation A = Q R (A is m x n, row-major with leading dim lda,
+// dt = DT_C128 or DT_C64).  On return the upper triangle of A holds R and the
+// reflectors are in the work buffers.
+int qr_factor(void* A, long long lda, int m, int n, int dt, const QrWork& w, hipStream_t s);
+
+// Q (m x n, ld ldq) := the first n columns of H_0 H_1 ... (explicit thin Q).
+int qr_form_q(void* Q, long long ldq, int m, int n, int dt, const QrWork& w, hipStream_t s);
+
+// Z (rows r0..r0+m-1 of a matrix with nz columns, ld ldz) := H_0 H_1 ... Z,
+// using the reflectors of a factorisation of an m x n matrix.
+int qr_apply_q(void* Z, long long ldz, int nz, int m, int n, int dt, const QrWork& w, hipStream_t s);
+
+// Helpers shared by the bond update.
+int fill_zero(void* p, size_t bytes, hipStream_t s);
+int set_identity(void* Q, long long ldq, int m, int n, int dt, hipStream_t s);
+
+}  // namespace qrtebd

@@ -1,0 +1,358 @@
+// Blocked Householder QR for the tall matrices of the bond update.
+//
+// Sec. II of the paper truncates with two QR decompositions (X = Q^[m] R and,
+// as the QR of Y^dag, Y = L Q^[n]).  Both are thin, unpivoted Householder
+// factorisations here:
+//
+//  * panel: 32 columns at a time, factored by one cooperative kernel whose
+//    blocks each keep a slab of panel rows in LDS (FP64 arithmetic whatever
+//    the storage precision).  Column k needs one grid barrier: every block
+//    contributes sum_i conj(P[i,k]) P[i,c] over its rows below the diagonal
+//    for all c, which yields at once the norm below the diagonal (c = k, no
+//    cancellation against the diagonal), the reflector's products with the
+//    panel (c > k) and the products with the earlier reflectors that build
+//    the compact-WY factor T (c < k).  Reflectors follow LAPACK's zlarfg
+//    convention: H = I - tau v v^H, v_k = 1, beta real.
+//  * trailing update: A <- (I - V T V^H)^H A as two MFMA GEMMs,
+//    W = V^H A (split over the long dimension) and A -= (V T^H) W.
+//  * explicit Q: backward accumulation of the same blocks onto [I; 0].
+#include "qr.h"
+
+#include <algorithm>
+
+namespace qrtebd {
+namespace {
+
+constexpr int NB = kQrNb;
+
+struct PanelArgs {
+  void* A;
+  long long lda;
+  int m, jb, rows_per_blk;
+  void* V;
+  void* VT;
+  void* VTh;
+  c128* T;
+  c128* red;
+  c128* rowbuf;
+  GridSync gs;
+};
+
+__device__ inline c128 cz() { return mk<double>(0, 0); }
+
+template <typename S>
+__global__ __launch_bounds__(256) void qr_panel_kernel(PanelArgs a) {
+  extern __shared__ c128 P[];  // rows_per_blk x NB
+  __shared__ c128 part[8][NB];
+  __shared__ c128 tsum[NB];
+  __shared__ c128 rowk[NB];
+  __shared__ c128 vh[NB];
+  __shared__ c128 tmpv[NB];
+  __shared__ c128 Tm[NB][NB + 1];
+  __shared__ c128 sc[3];
+  __shared__ int flag;
+
+  const int tid = threadIdx.x, nblk = gridDim.x, blk = blockIdx.x;
+  const int r0 = blk * a.rows_per_blk;
+  const int nr = max(0, min(a.m, r0 + a.rows_per_blk) - r0);
+  const int jb = a.jb;
+  cpx<S>* A = (cpx<S>*)a.A;
+
+  for (int idx = tid; idx < nr * NB; idx += 256) {
+    const int i = idx / NB, c = idx % NB;
+    P[idx] = c < jb ? ccast<double>(A[(long long)(r0 + i) * a.lda + c]) : cz();
+  }
+  for (int idx = tid; idx < NB * (NB + 1); idx += 256) (&Tm[0][0])[idx] = cz();
+  __syncthreads();
+
+  for (int k = 0; k < jb; ++k) {
+    const int slot = k & 1;
+    {  // partial sums over this block's rows strictly below the diagonal
+      const int rg = tid >> 5, c = tid & 31;
+      c128 acc = cz();
+      if (c < jb)
+        for (int i = rg; i < nr; i += 8)
+          if (r0 + i > k) acc = cadd(acc, cmulc(P[i * NB + k], P[i * NB + c]));
+      part[rg][c] = acc;
+    }
+    __syncthreads();
+    if (tid < NB) {
+      c128 s = cz();
+      for (int g = 0; g < 8; ++g) s = cadd(s, part[g][tid]);
+      a.red[((long long)slot * nblk + blk) * NB + tid] = s;
+      if (k >= r0 && k < r0 + nr) a.rowbuf[slot * NB + tid] = P[(k - r0) * NB + tid];
+    }
+    if (!grid_barrier(a.gs, (unsigned)(k + 1), nblk, &flag)) return;
+    {
+      const int bg = tid >> 5, c = tid & 31;
+      c128 acc = cz();
+      for (int w = bg; w < nblk; w += 8) acc = cadd(acc, a.red[((long long)slot * nblk + w) * NB + c]);
+      part[bg][c] = acc;
+    }
+    __syncthreads();
+    if (tid < NB) {
+      c128 s = cz();
+      for (int g = 0; g < 8; ++g) s = cadd(s, part[g][tid]);
+      tsum[tid] = s;
+      rowk[tid] = a.rowbuf[slot * NB + tid];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const c128 alpha = rowk[k];
+      const double xnorm2 = fmax(tsum[k].re, 0.0);
+      c128 tau = cz(), scale = cz();
+      double beta = alpha.re;
+      if (!(xnorm2 == 0.0 && alpha.im == 0.0)) {
+        beta = -copysign(sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xnorm2), alpha.re);
+        tau = mk<double>((beta - alpha.re) / beta, -alpha.im / beta);
+        const c128 den = mk<double>(alpha.re - beta, alpha.im);
+        const double dd = cabs2(den);
+        scale = mk<double>(den.re / dd, -den.im / dd);
+      }
+      if (!isfinite(beta)) latch_error(a.gs.status, ERRBIT_NONFINITE);
+      sc[0] = tau;
+      sc[1] = scale;
+      sc[2] = mk<double>(beta, 0.0);
+    }
+    __syncthreads();
+    const c128 tau = sc[0], scale = sc[1];
+    if (tid < NB) {
+      const int l = tid;
+      if (l > k && l < jb) vh[l] = cadd(rowk[l], cmulc(scale, tsum[l]));
+      if (l < k) tmpv[l] = cadd(cconj(rowk[l]), cmul(scale, cconj(tsum[l])));
+    }
+    __syncthreads();
+    if (tid < NB) {
+      const int j = tid;
+      if (j < k) {
+        c128 s = cz();
+        for (int q = j; q < k; ++q) s = cadd(s, cmul(Tm[j][q], tmpv[q]));
+        Tm[j][k] = cmul(mk<double>(-tau.re, -tau.im), s);
+      } else if (j == k) {
+        Tm[k][k] = tau;
+      }
+    }
+    for (int i = tid; i < nr; i += 256)
+      if (r0 + i > k) P[i * NB + k] = cmul(P[i * NB + k], scale);
+    __syncthreads();
+    const c128 ctau = cconj(tau);
+    for (int idx = tid; idx < nr * NB; idx += 256) {
+      const int i = idx / NB, l = idx % NB, gi = r0 + i;
+      if (gi >= k && l > k && l < jb) {
+        const c128 v = gi == k ? mk<double>(1, 0) : P[i * NB + k];
+        P[idx] = csub(P[idx], cmul(ctau, cmul(v, vh[l])));
+      }
+    }
+    __syncthreads();
+    if (tid == 0 && k >= r0 && k < r0 + nr) P[(k - r0) * NB + k] = sc[2];
+    __syncthreads();
+  }
+
+  // write back R / reflectors in place and the explicit V, V T, V T^H
+  for (int idx = tid; idx < nr * NB; idx += 256) {
+    const int i = idx / NB, c = idx % NB;
+    if (c < jb) A[(long long)(r0 + i) * a.lda + c] = ccast<S>(P[idx]);
+  }
+  cpx<S>* V = (cpx<S>*)a.V;
+  cpx<S>* VT = (cpx<S>*)a.VT;
+  cpx<S>* VTh = (cpx<S>*)a.VTh;
+  for (int idx = tid; idx < nr * NB; idx += 256) {
+    const int i = idx / NB, c = idx % NB, gi = r0 + i;
+    c128 vc = cz(), vt = cz(), vth = cz();
+    if (c < jb) {
+      vc = gi > c ? P[idx] : (gi == c ? mk<double>(1, 0) : cz());
+      for (int q = 0; q < jb; ++q) {
+        const c128 vq = gi > q ? P[i * NB + q] : (gi == q ? mk<double>(1, 0) : cz());
+        if (q <= c) vt = cadd(vt, cmul(vq, Tm[q][c]));
+        if (q >= c) vth = cadd(vth, cmul(vq, cconj(Tm[c][q])));
+      }
+    }
+    const long long o = (long long)(r0 + i) * NB + c;
+    V[o] = ccast<S>(vc);
+    VT[o] = ccast<S>(vt);
+    VTh[o] = ccast<S>(vth);
+  }
+  if (blk == 0)
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+      const int r = idx / NB, c = idx % NB;
+      a.T[idx] = (r < jb && c < jb) ? Tm[r][c] : cz();
+    }
+}
+
+__global__ void fill_zero_kernel(unsigned* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+template <typename S>
+__global__ void set_identity_kernel(cpx<S>* Q, long long ldq, int m, int n) {
+  const long long total = (long long)m * n;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / n), j = (int)(idx % n);
+    Q[(long long)i * ldq + j] = mk<S>(i == j ? S(1) : S(0), S(0));
+  }
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int panel_rows(int mp) {
+  int r = (mp + 39) / 40;
+  r = (r + 31) / 32 * 32;
+  return std::min(256, std::max(32, r));
+}
+
+template <typename S>
+int launch_panel(const PanelArgs& pa, int nblk, hipStream_t s) {
+  const size_t shmem = (size_t)pa.rows_per_blk * NB * sizeof(c128);
+  static bool attr_set = false;
+  if (!attr_set) {
+    QT_HIP_CHECK(hipFuncSetAttribute((const void*)qr_panel_kernel<S>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 256 * NB * sizeof(c128)));
+    attr_set = true;
+  }
+  void* args[] = {(void*)&pa};
+  QT_HIP_CHECK(hipLaunchCooperativeKernel((const void*)qr_panel_kernel<S>, dim3(nblk), dim3(256), args,
+                                          (unsigned)shmem, s));
+  return 0;
+}
+
+}  // namespace
+
+int fill_zero(void* p, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 4;
+  if (n == 0) return 0;
+  const int grid = (int)std::min<size_t>((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid), dim3(256), 0, s, (unsigned*)p, n);
+  QT_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+int set_identity(void* Q, long long ldq, int m, int n, int dt, hipStream_t s) {
+  const long long total = (long long)m * n;
+  const int grid = (int)std::min<long long>((total + 255) / 256, 4096);
+  if (total == 0) return 0;
+  if (dt == DT_C128)
+    hipLaunchKernelGGL(set_identity_kernel<double>, dim3(grid), dim3(256), 0, s, (c128*)Q, ldq, m, n);
+  else
+    hipLaunchKernelGGL(set_identity_kernel<float>, dim3(grid), dim3(256), 0, s, (c64*)Q, ldq, m, n);
+  QT_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+size_t qr_work_bytes(int m, int n, int es, int wcols) {
+  const size_t np = (size_t)(n + NB - 1) / NB;
+  if (wcols < n) wcols = n;
+  size_t b = 0;
+  b += 3 * align256(np * (size_t)m * NB * es);
+  b += align256(np * NB * NB * sizeof(c128));
+  b += align256((size_t)NB * wcols * es);
+  b += align256((size_t)kMaxSplit * NB * wcols * sizeof(c128));
+  b += align256((2 * (size_t)kMaxPanelBlocks * NB + 2 * NB) * sizeof(c128));
+  b += align256(grid_sync_words(kMaxPanelBlocks) * 4);
+  return b;
+}
+
+QrWork qr_work_carve(void* base, int m, int n, int es, int wcols, int* status) {
+  const size_t np = (size_t)(n + NB - 1) / NB;
+  if (wcols < n) wcols = n;
+  char* p = (char*)base;
+  QrWork w{};
+  const size_t vb = align256(np * (size_t)m * NB * es);
+  w.V = p; p += vb;
+  w.VT = p; p += vb;
+  w.VTh = p; p += vb;
+  w.T = (c128*)p; p += align256(np * NB * NB * sizeof(c128));
+  w.W = p; p += align256((size_t)NB * wcols * es);
+  w.Wsplit = p; p += align256((size_t)kMaxSplit * NB * wcols * sizeof(c128));
+  w.red = (c128*)p; p += align256((2 * (size_t)kMaxPanelBlocks * NB + 2 * NB) * sizeof(c128));
+  w.sync = (unsigned*)p;
+  w.status = status;
+  w.wcols = wcols;
+  return w;
+}
+
+int qr_factor(void* A, long long lda, int m, int n, int dt, const QrWork& w, hipStream_t s) {
+  if (n > m || n <= 0) return set_error(-1, "qr_factor: need 0 < n <= m (m=%d n=%d)", m, n);
+  const int es = dt == DT_C128 ? 16 : 8;
+  const GemmTypes ty{dt, dt};
+  const int np = (n + NB - 1) / NB;
+  char* Ab = (char*)A;
+  for (int p = 0; p < np; ++p) {
+    const int j0 = p * NB, jb = std::min(NB, n - j0), mp = m - j0;
+    const int rows = panel_rows(mp);
+    const int nblk = (mp + rows - 1) / rows;
+    if (nblk > kMaxPanelBlocks) return set_error(-2, "qr_factor: panel of %d rows too tall", mp);
+    int rc = fill_zero(w.sync, grid_sync_words(nblk) * 4, s);
+    if (rc) return rc;
+    PanelArgs pa{};
+    pa.A = Ab + ((long long)j0 * lda + j0) * es;
+    pa.lda = lda;
+    pa.m = mp;
+    pa.jb = jb;
+    pa.rows_per_blk = rows;
+    const size_t voff = (size_t)p * m * NB * es;
+    pa.V = (char*)w.V + voff;
+    pa.VT = (char*)w.VT + voff;
+    pa.VTh = (char*)w.VTh + voff;
+    pa.T = w.T + (size_t)p * NB * NB;
+    pa.red = w.red;
+    pa.rowbuf = w.red + 2 * (size_t)kMaxPanelBlocks * NB;
+    pa.gs = GridSync{w.sync, w.status};
+    rc = dt == DT_C128 ? launch_panel<double>(pa, nblk, s) : launch_panel<float>(pa, nblk, s);
+    if (rc) return rc;
+    const int nt = n - j0 - jb;
+    if (nt > 0) {
+      void* At = Ab + ((long long)j0 * lda + j0 + jb) * es;
+      GemmProb g1 = gemm_prob(pa.V, NB, OP_C, At, lda, OP_N, w.W, nt, jb, nt, mp);
+      g1.ksplit = std::min(kMaxSplit, std::max(1, mp / 512));
+      g1.work = w.Wsplit;
+      GemmProb g2 = gemm_prob(pa.VTh, NB, OP_N, w.W, nt, OP_N, At, lda, mp, nt, jb, -1.f, 1.f);
+      if ((rc = gemm_one(g1, ty, s))) return rc;
+      if ((rc = gemm_one(g2, ty, s))) return rc;
+    }
+  }
+  return 0;
+}
+
+int qr_apply_q(void* Z, long long ldz, int nz, int m, int n, int dt, const QrWork& w, hipStream_t s) {
+  if (nz > w.wcols) return set_error(-1, "qr_apply_q: %d columns exceed the work size %d", nz, w.wcols);
+  const int es = dt == DT_C128 ? 16 : 8;
+  const GemmTypes ty{dt, dt};
+  const int np = (n + NB - 1) / NB;
+  for (int p = np - 1; p >= 0; --p) {
+    const int j0 = p * NB, jb = std::min(NB, n - j0), mp = m - j0;
+    const size_t voff = (size_t)p * m * NB * es;
+    void* Zs = (char*)Z + (long long)j0 * ldz * es;
+    GemmProb g1 = gemm_prob((char*)w.V + voff, NB, OP_C, Zs, ldz, OP_N, w.W, nz, jb, nz, mp);
+    g1.ksplit = std::min(kMaxSplit, std::max(1, mp / 512));
+    g1.work = w.Wsplit;
+    GemmProb g2 = gemm_prob((char*)w.VT + voff, NB, OP_N, w.W, nz, OP_N, Zs, ldz, mp, nz, jb, -1.f, 1.f);
+    int rc;
+    if ((rc = gemm_one(g1, ty, s))) return rc;
+    if ((rc = gemm_one(g2, ty, s))) return rc;
+  }
+  return 0;
+}
+
+int qr_form_q(void* Q, long long ldq, int m, int n, int dt, const QrWork& w, hipStream_t s) {
+  const int es = dt == DT_C128 ? 16 : 8;
+  const GemmTypes ty{dt, dt};
+  int rc = set_identity(Q, ldq, m, n, dt, s);
+  if (rc) return rc;
+  const int np = (n + NB - 1) / NB;
+  for (int p = np - 1; p >= 0; --p) {
+    const int j0 = p * NB, jb = std::min(NB, n - j0), mp = m - j0, nq = n - j0;
+    const size_t voff = (size_t)p * m * NB * es;
+    void* Qs = (char*)Q + ((long long)j0 * ldq + j0) * es;
+    GemmProb g1 = gemm_prob((char*)w.V + voff, NB, OP_C, Qs, ldq, OP_N, w.W, nq, jb, nq, mp);
+    g1.ksplit = std::min(kMaxSplit, std::max(1, mp / 512));
+    g1.work = w.Wsplit;
+    GemmProb g2 = gemm_prob((char*)w.VT + voff, NB, OP_N, w.W, nq, OP_N, Qs, ldq, mp, nq, jb, -1.f, 1.f);
+    if ((rc = gemm_one(g1, ty, s))) return rc;
+    if ((rc = gemm_one(g2, ty, s))) return rc;
+  }
+  return 0;
+}
+
+}  // namespace qrtebd

@@ -1,0 +1,297 @@
+"""ctypes binding of libqrtebd.so with the C-ABI names (include/qrtebd.h).
+
+Argument marshalling only: torch tensors supply device memory and the HIP
+stream, every step of the bond update runs in the library's kernels.  There is
+no fallback: load() raises if the library is missing or fails to load.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqrtebd.so")
+
+MPS_OK, MPS_ERR_ARG, MPS_ERR_CAPACITY, MPS_ERR_OOM, MPS_ERR_HIP, MPS_ERR_NUMERIC, MPS_ERR_STATE = 0, -1, -2, -3, -4, -5, -6
+MPS_C128, MPS_MIXED_C64 = 0, 1
+PLAIN, GROW, CBE = 0, 1, 2
+DT_C64, DT_C128 = 0, 1
+
+# every function the header declares, for the export check
+EXPORTS = [
+    "mps_ctx_create", "mps_ctx_destroy", "mps_last_error", "mps_sync", "mps_bond_capacity",
+    "mps_workspace_query", "mps_bond_update", "mps_clock_gate", "mps_state_create",
+    "mps_state_destroy", "mps_state_chis", "mps_sweep", "mps_measure", "mps_zgemm", "mps_qr",
+    "mps_heig",
+]
+
+
+class mps_bond_desc(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("chi_l", ctypes.c_int), ("chi_m", ctypes.c_int),
+                ("chi_r", ctypes.c_int), ("eta", ctypes.c_int), ("chi_max", ctypes.c_int),
+                ("svd_min", ctypes.c_double), ("xi_is_diag", ctypes.c_int), ("mode", ctypes.c_int),
+                ("prec", ctypes.c_int)]
+
+
+class mps_sweep_policy(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("chi_max", ctypes.c_int), ("svd_min", ctypes.c_double),
+                ("dchi_min", ctypes.c_int), ("dchi_frac", ctypes.c_double)]
+
+
+class QrtebdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libqrtebd error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+P = ctypes.c_void_p
+I = ctypes.c_int
+D = ctypes.c_double
+LL = ctypes.c_longlong
+
+
+def _declare(lib):
+    sig = {
+        "mps_ctx_create": (I, [I, ctypes.POINTER(P)]),
+        "mps_ctx_destroy": (I, [P]),
+        "mps_last_error": (ctypes.c_char_p, []),
+        "mps_sync": (I, [P, P]),
+        "mps_bond_capacity": (I, [ctypes.POINTER(mps_bond_desc)]),
+        "mps_workspace_query": (I, [P, ctypes.POINTER(mps_bond_desc), ctypes.POINTER(ctypes.c_size_t)]),
+        "mps_bond_update": (I, [P, ctypes.POINTER(mps_bond_desc), P, P, P, P, P, P, P, P, P, P]),
+        "mps_clock_gate": (I, [I, D, D, D, D, P]),
+        "mps_state_create": (I, [P, I, I, I, I, I, ctypes.POINTER(P), ctypes.POINTER(P),
+                                 ctypes.POINTER(I), ctypes.POINTER(P)]),
+        "mps_state_destroy": (I, [P]),
+        "mps_state_chis": (I, [P, ctypes.POINTER(I)]),
+        "mps_sweep": (I, [P, ctypes.POINTER(P), I, ctypes.POINTER(P), I, I,
+                          ctypes.POINTER(mps_sweep_policy), P, P]),
+        "mps_measure": (I, [P, P, P, P, P, P, P, P, P]),
+        "mps_zgemm": (I, [P, I, I, I, I, I, I, P, LL, P, LL, P, LL, D, D, P]),
+        "mps_qr": (I, [P, I, I, I, P, P, P]),
+        "mps_heig": (I, [P, I, I, P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+def load():
+    """Load the library (once).  Raises if it is missing: there is no CPU path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise QrtebdError(MPS_ERR_STATE, f"{LIB_PATH} not built (run paper_2212_09782_amd.build)")
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def _check(rc):
+    if rc != MPS_OK:
+        raise QrtebdError(rc, load().mps_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return P(s.cuda_stream)
+
+
+def _ptr(t):
+    return P(t.data_ptr()) if t is not None else P(0)
+
+
+# ---------------------------------------------------------------- context
+
+class Context:
+    """Owns an mps_ctx (device workspace of the library)."""
+
+    def __init__(self, device=0):
+        self.lib = load()
+        h = P()
+        _check(self.lib.mps_ctx_create(device, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.mps_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self, stream=None):
+        _check(self.lib.mps_sync(self.h, _stream(stream)))
+
+
+def clock_gate(d, g, tau, wl=0.5, wr=0.5):
+    """mps_clock_gate: host complex128 (d^2 x d^2) gate of the clock model."""
+    out = np.zeros((d * d, d * d), np.complex128)
+    _check(load().mps_clock_gate(d, g, tau, wl, wr, out.ctypes.data_as(P)))
+    return out
+
+
+def bond_desc(d, chi_l, chi_m, chi_r, eta, chi_max, svd_min=1e-14, xi_is_diag=True, mode=CBE, prec=MPS_C128):
+    return mps_bond_desc(d, chi_l, chi_m, chi_r, eta, chi_max, svd_min, int(bool(xi_is_diag)), mode, prec)
+
+
+def bond_capacity(desc):
+    return load().mps_bond_capacity(ctypes.byref(desc))
+
+
+def mps_bond_update(ctx, desc, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, chi_new, trunc_err, stream=None):
+    """Direct C-ABI call; every argument a torch tensor on the GPU."""
+    _check(ctx.lib.mps_bond_update(ctx.h, ctypes.byref(desc), _ptr(xi_m), _ptr(b_m), _ptr(b_n), _ptr(u),
+                                   _ptr(b_m_out), _ptr(xi_n_out), _ptr(b_n_out), _ptr(chi_new),
+                                   _ptr(trunc_err), _stream(stream)))
+
+
+def bond_update(ctx, desc, xi_m, b_m, b_n, u, stream=None):
+    """Allocate capacity-sized outputs, run mps_bond_update, return device tensors.
+
+    Returns (b_m_out, xi_n_out, b_n_out, chi_new, trunc_err) where the first
+    three are flat capacity buffers (use unpack_bond for shaped views).
+    """
+    import torch
+    dev = b_m.device
+    cap = bond_capacity(desc)
+    cdt = torch.complex128 if desc.prec == MPS_C128 else torch.complex64
+    b_m_out = torch.empty(desc.chi_l * desc.d * cap, dtype=cdt, device=dev)
+    b_n_out = torch.empty(cap * desc.d * desc.chi_r, dtype=cdt, device=dev)
+    if desc.mode == CBE:
+        xi_out = torch.empty(cap, dtype=torch.float64, device=dev)
+    else:
+        xi_out = torch.empty(cap * cap, dtype=torch.complex128, device=dev)
+    chi = torch.zeros(1, dtype=torch.int32, device=dev)
+    eps = torch.zeros(1, dtype=torch.float64, device=dev)
+    mps_bond_update(ctx, desc, xi_m, b_m, b_n, u, b_m_out, xi_out, b_n_out, chi, eps, stream)
+    return b_m_out, xi_out, b_n_out, chi, eps
+
+
+def unpack_bond(desc, b_m_out, xi_out, b_n_out, chi):
+    """Host numpy views of a finished update with the live chi~ (synchronises)."""
+    k = int(chi.item())
+    bm = b_m_out[: desc.chi_l * desc.d * k].cpu().numpy().reshape(desc.chi_l, desc.d, k)
+    bn = b_n_out[: k * desc.d * desc.chi_r].cpu().numpy().reshape(k, desc.d, desc.chi_r)
+    if desc.mode == CBE:
+        xi = xi_out[:k].cpu().numpy()
+    else:
+        xi = xi_out.cpu().numpy().reshape(k, k)
+    return bm, xi, bn, k
+
+
+# ---------------------------------------------------------------- building blocks
+
+def mps_zgemm(ctx, dt, opA, opB, M, N, K, A, lda, B, ldb, C, ldc, alpha=1.0, beta=0.0, stream=None):
+    _check(ctx.lib.mps_zgemm(ctx.h, dt, opA, opB, M, N, K, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc,
+                             alpha, beta, _stream(stream)))
+
+
+def mps_qr(ctx, dt, m, n, A, Q, stream=None):
+    _check(ctx.lib.mps_qr(ctx.h, dt, m, n, _ptr(A), _ptr(Q), _stream(stream)))
+
+
+def mps_heig(ctx, n, k, G, lam, E, stream=None):
+    _check(ctx.lib.mps_heig(ctx.h, n, k, _ptr(G), _ptr(lam), _ptr(E), _stream(stream)))
+
+
+# ---------------------------------------------------------------- states / sweep / measure
+
+class State:
+    """Device-resident MPS (torch buffers) registered with the library."""
+
+    def __init__(self, ctx, B, Xi, finite=True, chi_cap=None, prec=MPS_C128):
+        """B: list of numpy [chi_l, d, chi_r]; Xi: list of 1-D numpy (bond left of each site)."""
+        import torch
+        self.ctx = ctx
+        self.L = len(B)
+        self.d = B[0].shape[1]
+        self.finite = finite
+        self.prec = prec
+        chis = [b.shape[0] for b in B] + [B[-1].shape[2]]
+        self.chi_cap = int(chi_cap or max(chis))
+        cdt = torch.complex128 if prec == MPS_C128 else torch.complex64
+        self.B = [torch.zeros(self.chi_cap * self.d * self.chi_cap, dtype=cdt, device="cuda") for _ in B]
+        self.Xi = [torch.zeros(self.chi_cap, dtype=torch.float64, device="cuda") for _ in B]
+        for m in range(self.L):
+            flat = torch.from_numpy(np.ascontiguousarray(B[m]).reshape(-1)).to(cdt)
+            self.B[m][: flat.numel()].copy_(flat)
+            x = torch.from_numpy(np.asarray(Xi[m], dtype=np.float64).reshape(-1))
+            self.Xi[m][: x.numel()].copy_(x)
+        bp = (P * self.L)(*[P(t.data_ptr()) for t in self.B])
+        xp = (P * self.L)(*[P(t.data_ptr()) for t in self.Xi])
+        ch = (I * (self.L + 1))(*chis)
+        h = P()
+        _check(ctx.lib.mps_state_create(ctx.h, 0 if finite else 1, self.L, self.d, self.chi_cap, prec,
+                                        bp, xp, ch, ctypes.byref(h)))
+        self.h = h
+
+    def chis(self):
+        out = (I * (self.L + 1))()
+        _check(self.ctx.lib.mps_state_chis(self.h, out))
+        return list(out)
+
+    def to_numpy(self):
+        """(B list, Xi list) with live dimensions (synchronises)."""
+        import torch
+        torch.cuda.synchronize()
+        ch = self.chis()
+        B, Xi = [], []
+        for m in range(self.L):
+            n = ch[m] * self.d * ch[m + 1]
+            B.append(self.B[m][:n].cpu().numpy().astype(np.complex128).reshape(ch[m], self.d, ch[m + 1]))
+            Xi.append(self.Xi[m][: ch[m]].cpu().numpy())
+        return B, Xi
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.mps_state_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sweep_policy(chi_max, svd_min=1e-14, dchi_min=100, dchi_frac=0.1, mode=CBE):
+    return mps_sweep_policy(mode, chi_max, svd_min, dchi_min, dchi_frac)
+
+
+def mps_sweep(ctx, states, gates, nsteps, order, policy, trunc_err=None, stream=None):
+    """gates: one device complex128 tensor [nbonds, 2, d^2, d^2] per state."""
+    n = len(states)
+    sp = (P * n)(*[s.h for s in states])
+    gp = (P * n)(*[P(g.data_ptr()) for g in gates])
+    _check(ctx.lib.mps_sweep(ctx.h, sp, n, gp, nsteps, order, ctypes.byref(policy), _ptr(trunc_err),
+                             _stream(stream)))
+
+
+def mps_measure(ctx, state, op1=None, op2=None, site_vals=None, norms=None, bond_vals=None, entropies=None,
+                stream=None):
+    _check(ctx.lib.mps_measure(ctx.h, state.h, _ptr(op1), _ptr(op2), _ptr(site_vals), _ptr(norms),
+                               _ptr(bond_vals), _ptr(entropies), _stream(stream)))
+
+
+def chain_gates(d, g, L, finite, dt):
+    """Device tensor [nbonds, 2, d^2, d^2]: the clock gates for tau = dt/2 and dt (library builder)."""
+    import torch
+    nb = L - 1 if finite else L
+    out = np.zeros((max(nb, 1), 2, d * d, d * d), np.complex128)
+    for b in range(nb):
+        if finite:
+            wl = 1.0 if b == 0 else 0.5
+            wr = 1.0 if b + 1 == L - 1 else 0.5
+        else:
+            wl = wr = 0.5
+        out[b, 0] = clock_gate(d, g, dt / 2, wl, wr)
+        out[b, 1] = clock_gate(d, g, dt, wl, wr)
+    return torch.from_numpy(out).to("cuda")
