@@ -178,6 +178,17 @@ int mps_sweep(mps_ctx ctx, mps_state* states, int nstates, const void* const* ga
 int mps_measure(mps_ctx ctx, mps_state st, const void* op1, const void* op2, double* site_vals,
                 double* norms, double* bond_vals, double* entropies, mps_stream stream);
 
+/* ---- profiling ------------------------------------------------------------
+ * When enabled, the context records a HIP event pair on the call's stream
+ * around every launch of the contraction GEMMs of the bond update (C = B B,
+ * X, Y^dag, B~[n], B~[m]; the dominant kernel class) together with its
+ * algorithmic flop count 8 M N K, for up to max_launches launches.
+ * mps_profile_read waits for the recorded events and returns the summed
+ * kernel time (ms), the summed flops and the number of launches since the
+ * last mps_profile_enable. */
+int mps_profile_enable(mps_ctx ctx, int on, int max_launches);
+int mps_profile_read(mps_ctx ctx, double* total_ms, double* total_flops, int* launches);
+
 /* ---- building blocks of the update, exported for checking and reuse ------
  * dt: 0 complex64, 1 complex128.  All matrices row-major device buffers. */
 

@@ -46,6 +46,7 @@ struct mps_ctx_s {
   // per-bond scratch outputs of the sweep (device)
   void* tmp_out = nullptr;
   size_t tmp_bytes = 0;
+  KernelTimer timer;
 };
 
 struct mps_state_s {
@@ -173,6 +174,11 @@ int mps_ctx_destroy(mps_ctx c) {
   if (c->status) (void)hipFree(c->status);
   if (c->chi_host) (void)hipHostFree(c->chi_host);
   if (c->eps_host) (void)hipHostFree(c->eps_host);
+  if (c->timer.ev) {
+    for (int i = 0; i < 2 * c->timer.cap; ++i) (void)hipEventDestroy(c->timer.ev[i]);
+    delete[] c->timer.ev;
+    delete[] c->timer.flops;
+  }
   delete c;
   return MPS_OK;
 }
@@ -215,7 +221,44 @@ int mps_bond_update(mps_ctx c, const mps_bond_desc* D, const void* xi_m, const v
   hipStream_t s = (hipStream_t)stream;
   if ((rc = ensure(&c->ws, &c->ws_bytes, bond_work_bytes(b), s))) return rc;
   return bond_update_run(b, c->ws, c->status, xi_m, b_m, b_n, (const c128*)u, b_m_out, xi_n_out, b_n_out,
-                         chi_new_dev, trunc_err_dev, s);
+                         chi_new_dev, trunc_err_dev, s, &c->timer);
+}
+
+int mps_profile_enable(mps_ctx c, int on, int max_launches) {
+  if (!c) return set_error(MPS_ERR_ARG, "null context");
+  KernelTimer& t = c->timer;
+  if (on && max_launches > t.cap) {
+    if (t.ev) {
+      for (int i = 0; i < 2 * t.cap; ++i) (void)hipEventDestroy(t.ev[i]);
+      delete[] t.ev;
+      delete[] t.flops;
+    }
+    t.ev = new hipEvent_t[2 * (size_t)max_launches];
+    t.flops = new double[max_launches];
+    t.cap = 0;
+    for (int i = 0; i < 2 * max_launches; ++i) QT_HIP_CHECK(hipEventCreate(&t.ev[i]));
+    t.cap = max_launches;
+  }
+  t.on = on ? 1 : 0;
+  t.n = 0;
+  return MPS_OK;
+}
+
+int mps_profile_read(mps_ctx c, double* total_ms, double* total_flops, int* launches) {
+  if (!c) return set_error(MPS_ERR_ARG, "null context");
+  KernelTimer& t = c->timer;
+  double ms = 0, fl = 0;
+  for (int i = 0; i < t.n; ++i) {
+    QT_HIP_CHECK(hipEventSynchronize(t.ev[2 * i + 1]));
+    float e = 0;
+    QT_HIP_CHECK(hipEventElapsedTime(&e, t.ev[2 * i], t.ev[2 * i + 1]));
+    ms += e;
+    fl += t.flops[i];
+  }
+  if (total_ms) *total_ms = ms;
+  if (total_flops) *total_flops = fl;
+  if (launches) *launches = t.n;
+  return MPS_OK;
 }
 
 int mps_clock_gate(int d, double g, double tau, double wl, double wr, double* u_out) {
@@ -351,7 +394,7 @@ int run_layer(mps_ctx c, std::vector<BondRef>& bonds, const mps_sweep_policy* po
     int* chi_dev = (int*)((char*)xi_out + ((cap * 8 + 255) & ~size_t(255)));
     double* eps_dev = (double*)(chi_dev + 16);
     if ((rc = bond_update_run(b, c->ws, c->status, st->Xi[br.m], st->B[br.m], st->B[br.n], br.gate, bm_out, xi_out,
-                              bn_out, chi_dev, eps_dev, s)))
+                              bn_out, chi_dev, eps_dev, s, &c->timer)))
       return rc;
     // the new chi decides the copy sizes: read it back
     QT_HIP_CHECK(hipMemcpyAsync(c->chi_host, chi_dev, sizeof(int), hipMemcpyDeviceToHost, s));

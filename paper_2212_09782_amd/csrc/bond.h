@@ -2,9 +2,20 @@
 #pragma once
 #include "eig.h"
 
-struct mps_bond_desc_internal;
-
 namespace qrtebd {
+
+// HIP-event records around the contraction GEMMs of the bond update (the
+// dominant kernel class), with the algorithmic flops (8 M N K) of each launch.
+struct KernelTimer {
+  int on = 0;
+  int n = 0;                 // recorded launches
+  int cap = 0;
+  hipEvent_t* ev = nullptr;  // 2 * cap events
+  double* flops = nullptr;   // cap
+};
+
+// gemm_one with event records when the timer is on.
+int timed_gemm(KernelTimer* t, const GemmProb& p, GemmTypes ty, hipStream_t s);
 
 struct BondShape {
   int d, chi_l, chi_m, chi_r, eta, chi_max;
@@ -20,7 +31,7 @@ size_t bond_work_bytes(const BondShape& b);
 // device error word.  All pointers are device pointers.
 int bond_update_run(const BondShape& b, void* ws, int* status, const void* xi_m, const void* b_m,
                     const void* b_n, const c128* u, void* b_m_out, void* xi_n_out, void* b_n_out,
-                    int* chi_new, double* eps, hipStream_t s);
+                    int* chi_new, double* eps, hipStream_t s, KernelTimer* timer = nullptr);
 
 // ---- small kernels shared with the measurement path
 // out[k] = sum over a partial buffer in a fixed order (one block).

@@ -239,7 +239,7 @@ BondBufs carve(const BondShape& b, void* base) {
 template <typename S>
 int run_typed(const BondShape& b, void* ws, int* status, const void* xi_m, const void* b_m, const void* b_n,
               const c128* u, void* b_m_out, void* xi_n_out, void* b_n_out, int* chi_new, double* eps,
-              hipStream_t s) {
+              hipStream_t s, KernelTimer* tm) {
   const int dt = sizeof(S) == 8 ? DT_C128 : DT_C64;
   const GemmTypes ty{dt, dt};
   const int d = b.d, chiL = b.chi_l, chiM = b.chi_m, chiR = b.chi_r, eta = b.eta;
@@ -251,7 +251,7 @@ int run_typed(const BondShape& b, void* ws, int* status, const void* xi_m, const
   int rc;
 
   // (i) C = B^[m] B^[n]
-  if ((rc = gemm_one(gemm_prob(b_m, chiM, OP_N, b_n, mR, OP_N, w.C, mR, mL, mR, chiM), ty, s))) return rc;
+  if ((rc = timed_gemm(tm, gemm_prob(b_m, chiM, OP_N, b_n, mR, OP_N, w.C, mR, mL, mR, chiM), ty, s))) return rc;
   // C~ = U C (in place) and theta~ = Xi C~
   {
     const dim3 grid((chiR + 63) / 64, chiL);
@@ -290,13 +290,13 @@ int run_typed(const BondShape& b, void* ws, int* status, const void* xi_m, const
   {
     GemmProb g = b.mode == 0 ? gemm_prob(w.Th, mR, OP_N, b_n, mR, OP_C, w.X, eta, mL, eta, mR)
                              : gemm_prob(w.Th, mR, OP_N, w.Th, mR, OP_C, w.X, eta, mL, eta, mR);
-    if ((rc = gemm_one(g, ty, s))) return rc;
+    if ((rc = timed_gemm(tm, g, ty, s))) return rc;
   }
   // Q^[m]
   if ((rc = qr_factor(w.X, eta, mL, eta, dt, qw, s))) return rc;
   if ((rc = qr_form_q(w.X, eta, mL, eta, dt, qw, s))) return rc;
   // Y^dag = theta~^dag Q^[m], then Y^dag = Q' R'
-  if ((rc = gemm_one(gemm_prob(w.Th, mR, OP_C, w.X, eta, OP_N, w.YH, eta, mR, eta, mL), ty, s))) return rc;
+  if ((rc = timed_gemm(tm, gemm_prob(w.Th, mR, OP_C, w.X, eta, OP_N, w.YH, eta, mR, eta, mL), ty, s))) return rc;
   if ((rc = qr_factor(w.YH, eta, mR, eta, dt, qw, s))) return rc;
   {
     const long long n = (long long)eta * eta;
@@ -325,7 +325,7 @@ int run_typed(const BondShape& b, void* ws, int* status, const void* xi_m, const
     // B~^[n] = E_kept^dag Q'^dag  (chi~ x d chi_r)
     GemmProb g = gemm_prob(Eu, kw, OP_C, w.YH, eta, OP_C, b_n_out, mR, kw, mR, eta);
     g.dM = chi_new;
-    if ((rc = gemm_one(g, ty, s))) return rc;
+    if ((rc = timed_gemm(tm, g, ty, s))) return rc;
   } else {
     const long long n = (long long)eta * eta;
     hipLaunchKernelGGL(sumsq_kernel<S>, dim3(1024), dim3(256), 0, s, (const cpx<S>*)w.R, n, w.partial);
@@ -362,12 +362,23 @@ int run_typed(const BondShape& b, void* ws, int* status, const void* xi_m, const
     GemmProb g = gemm_prob(w.C, mR, OP_N, b_n_out, mR, OP_C, b_m_out, cap, mL, cap, mR);
     g.dN = chi_new;
     g.ldc_live_N = 1;
-    if ((rc = gemm_one(g, ty, s))) return rc;
+    if ((rc = timed_gemm(tm, g, ty, s))) return rc;
   }
   return 0;
 }
 
 }  // namespace
+
+int timed_gemm(KernelTimer* t, const GemmProb& p, GemmTypes ty, hipStream_t s) {
+  if (!t || !t->on || t->n >= t->cap) return gemm_one(p, ty, s);
+  const int i = t->n++;
+  t->flops[i] = 8.0 * (double)p.M * (double)p.N * (double)p.K;
+  QT_HIP_CHECK(hipEventRecord(t->ev[2 * i], s));
+  int rc = gemm_one(p, ty, s);
+  if (rc) return rc;
+  QT_HIP_CHECK(hipEventRecord(t->ev[2 * i + 1], s));
+  return 0;
+}
 
 int reduce_partials(const double* part, int n, double* out, hipStream_t s) {
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, s, part, n, out);
@@ -379,10 +390,10 @@ size_t bond_work_bytes(const BondShape& b) { return carve(b, nullptr).total + 25
 
 int bond_update_run(const BondShape& b, void* ws, int* status, const void* xi_m, const void* b_m, const void* b_n,
                     const c128* u, void* b_m_out, void* xi_n_out, void* b_n_out, int* chi_new, double* eps,
-                    hipStream_t s) {
+                    hipStream_t s, KernelTimer* timer) {
   if (b.prec == 0)
-    return run_typed<double>(b, ws, status, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, chi_new, eps, s);
-  return run_typed<float>(b, ws, status, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, chi_new, eps, s);
+    return run_typed<double>(b, ws, status, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, chi_new, eps, s, timer);
+  return run_typed<float>(b, ws, status, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, chi_new, eps, s, timer);
 }
 
 }  // namespace qrtebd

@@ -79,6 +79,15 @@ __device__ inline double block_sum(double v, double* scratch) {
 // timeout the error bit is latched and false is returned so the kernel can
 // leave.  base must hold 16*(nblocks+1) unsigned words, zeroed before the
 // launch; gen counts barriers from 1 within one launch.
+//
+// smem_flag: a block-shared int the kernel zeroes once before its first
+// barrier; a stalled barrier stores its generation there.
+//
+// Publication rule: global data that other blocks read after the barrier
+// must be written by wave 0 of the block (threads 0..63).  Only wave 0 runs
+// the device-scope release fence (an L2 write-back) before arriving and the
+// acquire fence (L1/L2 invalidate) after the wait; the block-wide barrier
+// that follows orders the other waves' later loads after it.
 struct GridSync {
   unsigned* base;
   int* status;
@@ -86,18 +95,15 @@ struct GridSync {
 
 __device__ inline bool grid_barrier(GridSync gs, unsigned gen, int nblk, int* smem_flag) {
   constexpr long kSpinLimit = 1L << 22;
-  // every thread's earlier global writes become visible device-wide first
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (threadIdx.x < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   unsigned* genw = gs.base;
   unsigned* flags = gs.base + 16;
-  if (threadIdx.x == 0) *smem_flag = 0;
-  __syncthreads();
   if (blockIdx.x == 0) {
     for (int b = 1 + (int)threadIdx.x; b < nblk; b += blockDim.x) {
       long spins = 0;
       while (__hip_atomic_load(flags + 16 * b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
-        if (++spins > kSpinLimit) { *smem_flag = 1; break; }
+        if (++spins > kSpinLimit) { *smem_flag = (int)gen; break; }
       }
     }
     __syncthreads();
@@ -109,13 +115,12 @@ __device__ inline bool grid_barrier(GridSync gs, unsigned gen, int nblk, int* sm
     __hip_atomic_store(flags + 16 * blockIdx.x, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     long spins = 0;
     while (__hip_atomic_load(genw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
-      if (++spins > kSpinLimit) { *smem_flag = 1; break; }
+      if (++spins > kSpinLimit) { *smem_flag = (int)gen; break; }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
+  if (threadIdx.x < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  const bool ok = *smem_flag == 0;
+  const bool ok = *smem_flag != (int)gen;
   if (!ok && threadIdx.x == 0) latch_error(gs.status, ERRBIT_BARRIER);
   return ok;
 }

@@ -55,12 +55,26 @@ struct TriArgs {
   GridSync gs;
 };
 
+// Fixed-order block sum of a complex value (every thread gets the result).
+__device__ inline c128 block_sum_c(c128 v, c128* scr) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v.re = wave_sum(v.re);
+  v.im = wave_sum(v.im);
+  __syncthreads();
+  if (lane == 0) scr[wid] = v;
+  __syncthreads();
+  c128 s = z0();
+  for (int w = 0; w < nw; ++w) s = cadd(s, scr[w]);
+  return s;
+}
+
 __global__ __launch_bounds__(256) void tridiag_kernel(TriArgs a) {
   extern __shared__ c128 rows[];  // rows_loc x n, local row r = global row blk + r * P
   __shared__ double scratch[8];
+  __shared__ c128 cscr[8];
   __shared__ c128 wred[4][16];
-  __shared__ c128 vloc[16], wloc[16], ploc[16];
-  __shared__ c128 scal[6];
+  __shared__ c128 vloc[16], wloc[16];
+  __shared__ c128 scal[4];
   __shared__ int flag;
 
   const int n = a.n, P = gridDim.x, blk = blockIdx.x, tid = threadIdx.x;
@@ -81,60 +95,51 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriArgs a) {
     v[q] = z0();
     w[q] = z0();
   }
+  if (tid == 0) flag = 0;
   __syncthreads();
 
   for (int k = 0; k < n - 1; ++k) {
     const int slot = k & 1;
-    // ---- reflector from column k below the diagonal = conj(row k right of it)
+    // ---- reflector from column k below the diagonal = conj(row k right of it);
+    // every thread derives tau, beta, scale itself from the block sums
     double xn2 = 0;
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
       const int j = tid + 256 * q;
       if (j >= k + 2 && j < n) xn2 += cabs2(rk[q]);
+      if (j == k + 1) scal[0] = cconj(rk[q]);
+      if (j == k) scal[1] = rk[q];
     }
-    xn2 = block_sum(xn2, scratch);
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q)
-      if (tid + 256 * q == k + 1) scal[4] = cconj(rk[q]);
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q)
-      if (tid + 256 * q == k) scal[5] = rk[q];
-    __syncthreads();
-    if (tid == 0) {
-      const c128 alpha = scal[4];
-      c128 tau = z0(), scale = z0();
-      double beta = alpha.re;
-      if (!(xn2 == 0.0 && alpha.im == 0.0)) {
-        beta = -copysign(sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn2), alpha.re);
-        tau = mk<double>((beta - alpha.re) / beta, -alpha.im / beta);
-        const c128 den = mk<double>(alpha.re - beta, alpha.im);
-        const double dd = cabs2(den);
-        scale = mk<double>(den.re / dd, -den.im / dd);
-      }
-      scal[0] = tau;
-      scal[1] = scale;
-      if (blk == 0) {
-        a.d[k] = scal[5].re;
-        a.e[k] = beta;
-        a.tau[k] = tau;
-        if (!isfinite(beta) || !isfinite(scal[5].re)) latch_error(a.gs.status, ERRBIT_NONFINITE);
-      }
+    xn2 = block_sum(xn2, scratch);  // its barriers also publish scal[0], scal[1]
+    const c128 alpha = scal[0];
+    c128 tau = z0(), scale = z0();
+    double beta = alpha.re;
+    if (!(xn2 == 0.0 && alpha.im == 0.0)) {
+      beta = -copysign(sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn2), alpha.re);
+      tau = mk<double>((beta - alpha.re) / beta, -alpha.im / beta);
+      const c128 den = mk<double>(alpha.re - beta, alpha.im);
+      const double dd = cabs2(den);
+      scale = mk<double>(den.re / dd, -den.im / dd);
     }
-    __syncthreads();
-    const c128 tau = scal[0], scale = scal[1];
+    if (blk == 0 && tid == 0) {
+      a.d[k] = scal[1].re;
+      a.e[k] = beta;
+      a.tau[k] = tau;
+      if (!isfinite(beta) || !isfinite(scal[1].re)) latch_error(a.gs.status, ERRBIT_NONFINITE);
+    }
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
       const int j = tid + 256 * q;
       v[q] = j == k + 1 ? mk<double>(1, 0) : (j > k + 1 && j < n ? cmul(cconj(rk[q]), scale) : z0());
     }
     // v_i of this block's rows, for the rank-2 update
-    for (int r = 0; r < RL; ++r) {
-      const int gi = blk + r * P;
 #pragma unroll
-      for (int q = 0; q < QMAX; ++q)
-        if (gi < n && tid + 256 * q == gi) vloc[r] = v[q];
+    for (int q = 0; q < QMAX; ++q) {
+      const int j = tid + 256 * q;
+      if (j < n && j % P == blk) vloc[j / P] = v[q];
     }
     // reflector k into the QR-compatible layout: subproblem row i <-> row i+1
+    // (read only by later kernels: no publication needed)
     if (blk == k % P) {
       const int p = k / NB, c = k % NB, j0 = p * NB;
       c128* Vp = a.V + (size_t)p * mqr * NB;
@@ -149,77 +154,81 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriArgs a) {
     for (int r = 0; r < 16; ++r) {
       if (r < RL) {
         const int gi = blk + r * P;
-        c128 s = z0();
+        c128 sacc = z0();
         if (gi > k && gi < n) {
 #pragma unroll
           for (int q = 0; q < QMAX; ++q) {
             const int j = tid + 256 * q;
-            if (j > k && j < n) s = cadd(s, cmul(rows[r * n + j], v[q]));
+            if (j > k && j < n) sacc = cadd(sacc, cmul(rows[r * n + j], v[q]));
           }
         }
-        const double sr = wave_sum(s.re), si = wave_sum(s.im);
+        const double sr = wave_sum(sacc.re), si = wave_sum(sacc.im);
         if (lane == 0) wred[wid][r] = mk<double>(sr, si);
       }
     }
     __syncthreads();
-    if (tid < RL) {
-      const int r = tid, gi = blk + r * P;
-      c128 s = z0();
-      for (int ww = 0; ww < 4; ++ww) s = cadd(s, wred[ww][r]);
-      const c128 pi = (gi > k && gi < n) ? cmul(tau, s) : z0();
-      ploc[r] = pi;
-      if (gi > k && gi < n) a.pbuf[(long long)slot * n + gi] = pi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      c128 s = z0();
-      for (int r = 0; r < RL; ++r) s = cadd(s, cmulc(ploc[r], vloc[r]));
-      a.red[(long long)slot * P + blk] = s;
-    }
-    if ((k + 1) % P == blk) {
-      const int r = (k + 1) / P;
-      for (int j = tid; j < n; j += 256) a.rowbuf[(long long)slot * n + j] = rows[r * n + j];
+    if (wid == 0) {
+      // wave 0 publishes p for its rows, this block's part of p^H v, and the
+      // current row k+1 if it owns it
+      c128 part = z0();
+      if (lane < RL) {
+        const int r = lane, gi = blk + r * P;
+        c128 sacc = z0();
+        for (int ww = 0; ww < 4; ++ww) sacc = cadd(sacc, wred[ww][r]);
+        if (gi > k && gi < n) {
+          const c128 pi = cmul(tau, sacc);
+          a.pbuf[(long long)slot * n + gi] = pi;
+          part = cmulc(pi, vloc[r]);
+        }
+      }
+      part.re = wave_sum(part.re);
+      part.im = wave_sum(part.im);
+      if (lane == 0) a.red[(long long)slot * P + blk] = part;
+      if ((k + 1) % P == blk) {
+        const int r = (k + 1) / P;
+        for (int j = lane; j < n; j += 64) a.rowbuf[(long long)slot * n + j] = rows[r * n + j];
+      }
     }
     if (!grid_barrier(a.gs, (unsigned)(k + 1), P, &flag)) return;
-    // ---- w = p + alpha2 v,  alpha2 = -tau (p^H v) / 2
-    if (tid == 0) {
-      c128 s = z0();
-      for (int b = 0; b < P; ++b) s = cadd(s, a.red[(long long)slot * P + b]);
-      scal[2] = cscale(cmul(tau, s), -0.5);
-    }
-    __syncthreads();
-    const c128 alpha2 = scal[2];
+    // ---- one round of loads: block partials, p, and row k+1 as published
+    const c128 rv = tid < P ? a.red[(long long)slot * P + tid] : z0();
+    c128 pv[QMAX], xb[QMAX];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
       const int j = tid + 256 * q;
-      w[q] = (j > k && j < n) ? cadd(a.pbuf[(long long)slot * n + j], cmul(alpha2, v[q])) : z0();
-      if (j == k + 1) scal[3] = w[q];
+      pv[q] = (j > k && j < n) ? a.pbuf[(long long)slot * n + j] : z0();
+      xb[q] = j < n ? a.rowbuf[(long long)slot * n + j] : z0();
     }
-    for (int r = 0; r < RL; ++r) {
-      const int gi = blk + r * P;
+    const c128 ptv = block_sum_c(rv, cscr);   // p^H v
+    const c128 alpha2 = cscale(cmul(tau, ptv), -0.5);
+    // ---- w = p + alpha2 v
 #pragma unroll
-      for (int q = 0; q < QMAX; ++q)
-        if (gi < n && tid + 256 * q == gi) wloc[r] = w[q];
+    for (int q = 0; q < QMAX; ++q) {
+      const int j = tid + 256 * q;
+      w[q] = (j > k && j < n) ? cadd(pv[q], cmul(alpha2, v[q])) : z0();
+      if (j == k + 1) scal[2] = w[q];
+      if (j < n && j % P == blk) wloc[j / P] = w[q];
     }
     __syncthreads();
     // row k+1 (as published before the update) gets the rank-2 update
-    const c128 wk1 = scal[3];
+    const c128 wk1 = scal[2];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
       const int j = tid + 256 * q;
-      if (j < n) {
-        const c128 x = a.rowbuf[(long long)slot * n + j];
-        rk[q] = j > k ? rank2_sub(x, mk<double>(1, 0), w[q], wk1, v[q]) : x;
-      }
+      if (j < n) rk[q] = j > k ? rank2_sub(xb[q], mk<double>(1, 0), w[q], wk1, v[q]) : xb[q];
     }
-    for (int r = 0; r < RL; ++r) {
-      const int gi = blk + r * P;
-      if (gi <= k || gi >= n) continue;
-      const c128 vi = vloc[r], wi = wloc[r];
 #pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int j = tid + 256 * q;
-        if (j > k && j < n) rows[r * n + j] = rank2_sub(rows[r * n + j], vi, w[q], wi, v[q]);
+    for (int r = 0; r < 16; ++r) {
+      if (r < RL) {
+        const int gi = blk + r * P;
+        if (gi > k && gi < n) {
+          const c128 vi = vloc[r], wi = wloc[r];
+#pragma unroll
+          for (int q = 0; q < QMAX; ++q) {
+            const int j = tid + 256 * q;
+            if (j > k && j < n) rows[r * n + j] = rank2_sub(rows[r * n + j], vi, w[q], wi, v[q]);
+          }
+        }
       }
     }
     __syncthreads();
@@ -236,44 +245,88 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriArgs a) {
   }
 }
 
-// Number of eigenvalues of the tridiagonal (d, e) below x (Sturm sequence).
-__device__ inline int sturm_count(const double* d, const double* e, int n, double x, double pivmin) {
+// Number of eigenvalues of the tridiagonal (d, e^2 in LDS) below x (Sturm sequence).
+__device__ inline int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
   int cnt = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   cnt += q < 0;
   for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    q = d[i] - x - e2[i - 1] / q;
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0;
   }
   return cnt;
 }
 
-// lam[j] = (j+1)-th largest eigenvalue, j < kwant.
-__global__ void bisect_kernel(const double* d, const double* e, int n, int kwant, double* lam) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= kwant) return;
-  double lo = d[0], hi = d[0], emax2 = 0;
-  for (int i = 0; i < n; ++i) {
-    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
-    lo = fmin(lo, d[i] - r);
-    hi = fmax(hi, d[i] + r);
-    if (i < n - 1) emax2 = fmax(emax2, e[i] * e[i]);
+// Gershgorin interval and pivmin of (d, e) held in LDS; every thread gets them.
+__device__ inline void gersh(const double* d, const double* e2, int n, double* scr, double& lo, double& hi,
+                             double& pivmin) {
+  double l = 1e300, h = -1e300, em = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double r = (i > 0 ? sqrt(e2[i - 1]) : 0.0) + (i < n - 1 ? sqrt(e2[i]) : 0.0);
+    l = fmin(l, d[i] - r);
+    h = fmax(h, d[i] + r);
+    if (i < n - 1) em = fmax(em, e2[i]);
   }
-  const double tnorm = fmax(fabs(lo), fabs(hi));
-  const double pivmin = fmax(2.2250738585072014e-308, 2.2250738585072014e-308 * emax2);
-  lo -= 2.2e-16 * tnorm + 2 * pivmin;
-  hi += 2.2e-16 * tnorm + 2 * pivmin;
-  const int idx = n - 1 - j;  // ascending index
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    l = fmin(l, __shfl_xor(l, o, 64));
+    h = fmax(h, __shfl_xor(h, o, 64));
+    em = fmax(em, __shfl_xor(em, o, 64));
+  }
+  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    scr[3 * wid] = l;
+    scr[3 * wid + 1] = h;
+    scr[3 * wid + 2] = em;
+  }
+  __syncthreads();
+  l = scr[0]; h = scr[1]; em = scr[2];
+  for (int w = 1; w < nw; ++w) {
+    l = fmin(l, scr[3 * w]);
+    h = fmax(h, scr[3 * w + 1]);
+    em = fmax(em, scr[3 * w + 2]);
+  }
+  const double tnorm = fmax(fabs(l), fabs(h));
+  pivmin = fmax(2.2250738585072014e-308, 2.2250738585072014e-308 * em);
+  lo = l - 2.2e-16 * tnorm - 2 * pivmin;
+  hi = h + 2.2e-16 * tnorm + 2 * pivmin;
+}
+
+// lam[j] = (j+1)-th largest eigenvalue, j < kwant.  Multisection: the 8 lanes
+// of a group evaluate 8 interior points of the eigenvalue's interval per
+// round, shrinking it 9-fold; 22 rounds reach full FP64 resolution.
+__global__ __launch_bounds__(256) void bisect_kernel(const double* d, const double* e, int n, int kwant,
+                                                     double* lam) {
+  __shared__ double sd[kMaxN], se2[kMaxN];
+  __shared__ double scr[12];
+  for (int i = threadIdx.x; i < n; i += 256) {
+    sd[i] = d[i];
+    se2[i] = i < n - 1 ? e[i] * e[i] : 0.0;
+  }
+  __syncthreads();
+  double lo, hi, pivmin;
+  gersh(sd, se2, n, scr, lo, hi, pivmin);
+  const int lane = threadIdx.x & 63, sub = lane & 7, gbase = lane & ~7;
+  const int j = blockIdx.x * 32 + (threadIdx.x >> 3);
+  const int idx = n - 1 - min(j, kwant - 1);  // ascending index
   double a = lo, b = hi;
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (a + b);
-    if (mid <= a || mid >= b) break;
-    if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) + pivmin) break;
-    if (sturm_count(d, e, n, mid, pivmin) > idx) b = mid; else a = mid;
+  for (int it = 0; it < 22; ++it) {
+    const double x = a + (b - a) * (double)(sub + 1) * (1.0 / 9.0);
+    const int c = sturm_count(sd, se2, n, x, pivmin);
+    const unsigned long long m = __ballot(c > idx);
+    const unsigned bits = (unsigned)((m >> gbase) & 0xffull);
+    const int f = bits ? __ffs(bits) - 1 : 8;
+    const double xb = __shfl(x, gbase + min(f, 7), 64);
+    const double xa = __shfl(x, gbase + max(f - 1, 0), 64);
+    const double na = f == 0 ? a : xa;
+    const double nb = f == 8 ? b : xb;
+    a = na;
+    b = nb;
   }
-  lam[j] = 0.5 * (a + b);
+  if (j < kwant && sub == 0) lam[j] = 0.5 * (a + b);
 }
 
 __device__ inline double hash_uniform(unsigned long long x) {
@@ -285,16 +338,21 @@ __device__ inline double hash_uniform(unsigned long long x) {
 }
 
 // Inverse iteration for eigenvalue lam[j]: E[:, j] (real, stored complex).
-// lu: [4][n][kwant] (diag, super1, super2, multiplier); the pivot choice is
-// kept in the sign bit of the multiplier slot's companion (swap flags below).
-__global__ void invit_kernel(const double* d, const double* e, int n, int kwant, const double* lam,
-                             double* lu, unsigned char* swp, c128* E) {
+// lu: [4][n][kwant] (pivot row entries u0, u1, u2 and the multiplier),
+// swp: [n][kwant] row-interchange flags; T = (d, e) staged in LDS.
+__global__ __launch_bounds__(64) void invit_kernel(const double* d, const double* e, int n, int kwant,
+                                                   const double* lam, double* lu, unsigned char* swp, c128* E) {
+  __shared__ double sd[kMaxN], se[kMaxN];
+  for (int i = threadIdx.x; i < n; i += 64) {
+    sd[i] = d[i];
+    se[i] = i < n - 1 ? e[i] : 0.0;
+  }
+  __syncthreads();
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= kwant) return;
   const double l = lam[j];
   double tnorm = 0;
-  for (int i = 0; i < n; ++i)
-    tnorm = fmax(tnorm, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0));
+  for (int i = 0; i < n; ++i) tnorm = fmax(tnorm, fabs(sd[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0) + fabs(se[i]));
   const double tiny = fmax(tnorm, 1e-300) * 2.2e-16;
   double* U0 = lu;
   double* U1 = lu + (size_t)n * kwant;
@@ -302,9 +360,9 @@ __global__ void invit_kernel(const double* d, const double* e, int n, int kwant,
   double* ML = lu + 3 * (size_t)n * kwant;
   auto at = [&](int i) { return (size_t)i * kwant + j; };
   // factor T - l I with partial pivoting
-  double c0 = d[0] - l, c1 = n > 1 ? e[0] : 0.0, c2 = 0.0;
+  double c0 = sd[0] - l, c1 = n > 1 ? se[0] : 0.0, c2 = 0.0;
   for (int k = 0; k < n - 1; ++k) {
-    const double n0 = e[k], n1 = d[k + 1] - l, n2 = (k + 1 < n - 1) ? e[k + 1] : 0.0;
+    const double n0 = se[k], n1 = sd[k + 1] - l, n2 = se[k + 1];
     double u0, u1, u2, m;
     unsigned char sw;
     if (fabs(c0) >= fabs(n0)) {
@@ -324,11 +382,12 @@ __global__ void invit_kernel(const double* d, const double* e, int n, int kwant,
   U2[at(n - 1)] = 0.0;
   // start vector, stored in E's real parts
   for (int i = 0; i < n; ++i) E[at(i)] = mk<double>(hash_uniform(((unsigned long long)j << 32) ^ (unsigned)i), 0.0);
-  for (int it = 0; it < 3; ++it) {
-    // forward: apply the row operations to b (in place in E.re)
-    double rc = E[at(0)].re;
+  double scale = 1.0;
+  for (int it = 0; it < 2; ++it) {
+    // forward: the row operations of the factorisation applied to b (scaled)
+    double rc = E[at(0)].re * scale;
     for (int k = 0; k < n - 1; ++k) {
-      const double bk1 = E[at(k + 1)].re, m = ML[at(k)];
+      const double bk1 = E[at(k + 1)].re * scale, m = ML[at(k)];
       if (swp[at(k)] == 0) {
         E[at(k)].re = rc;
         rc = bk1 - m * rc;
@@ -338,8 +397,8 @@ __global__ void invit_kernel(const double* d, const double* e, int n, int kwant,
       }
     }
     E[at(n - 1)].re = rc;
-    // back substitution
-    double z1 = 0.0, z2 = 0.0, nrm = 0.0;
+    // back substitution; the max norm rescales the next pass
+    double z1 = 0.0, z2 = 0.0, nrm = 0.0, s2 = 0.0;
     for (int i = n - 1; i >= 0; --i) {
       const double z = (E[at(i)].re - U1[at(i)] * z1 - U2[at(i)] * z2) / U0[at(i)];
       E[at(i)].re = z;
@@ -347,43 +406,59 @@ __global__ void invit_kernel(const double* d, const double* e, int n, int kwant,
       z1 = z;
       nrm = fmax(nrm, fabs(z));
     }
-    // scale to unit max norm, then to unit 2-norm on the last pass
-    double s2 = 0.0;
-    const double inv = nrm > 0 ? 1.0 / nrm : 1.0;
-    for (int i = 0; i < n; ++i) {
-      const double z = E[at(i)].re * inv;
-      E[at(i)].re = z;
-      s2 += z * z;
-    }
-    if (it == 2) {
-      const double f = 1.0 / sqrt(s2);
+    scale = nrm > 0 ? 1.0 / nrm : 1.0;
+    if (it == 1) {
+      for (int i = 0; i < n; ++i) {
+        const double z = E[at(i)].re * scale;
+        s2 += z * z;
+      }
+      const double f = scale / sqrt(s2);
       for (int i = 0; i < n; ++i) E[at(i)].re *= f;
     }
   }
 }
 
-// T_p and V_p T_p for every panel of the tridiagonalisation reflectors.
+// T_p and V_p T_p for every panel of the tridiagonalisation reflectors;
+// V_p is staged through LDS in 64-row slabs.
 __global__ __launch_bounds__(256) void larft_kernel(c128* V, c128* VT, c128* T, const c128* tau, int m, int nrefl) {
-  __shared__ c128 G[NB][NB + 1];
+  __shared__ c128 slab[64][NB + 1];
   __shared__ c128 Tm[NB][NB + 1];
   const int p = blockIdx.x, tid = threadIdx.x;
   const int j0 = p * NB, jb = min(NB, nrefl - j0), mp = m - j0;
   const c128* Vp = V + (size_t)p * m * NB;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int a = idx / NB, b = idx % NB;
-    c128 s = z0();
-    if (a < jb && b < jb)
-      for (int i = 0; i < mp; ++i) s = cadd(s, cmulc(Vp[(long long)i * NB + a], Vp[(long long)i * NB + b]));
-    G[a][b] = s;
-    Tm[a][b] = z0();
+  c128 g[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) g[q] = z0();
+  for (int r0 = 0; r0 < mp; r0 += 64) {
+    __syncthreads();
+    for (int idx = tid; idx < 64 * NB; idx += 256) {
+      const int i = idx / NB, c = idx % NB;
+      slab[i][c] = (r0 + i < mp) ? Vp[(long long)(r0 + i) * NB + c] : z0();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q, aa = e / NB, bb = e % NB;
+      c128 s = g[q];
+      for (int i = 0; i < 64; ++i) s = cadd(s, cmulc(slab[i][aa], slab[i][bb]));
+      g[q] = s;
+    }
+  }
+  __syncthreads();
+  // G overwrites the slab storage (NB x NB <= 64 x (NB+1))
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + 256 * q;
+    slab[e / NB][e % NB] = g[q];
+    Tm[e / NB][e % NB] = z0();
   }
   __syncthreads();
   for (int k = 0; k < jb; ++k) {
     const c128 tk = tau[j0 + k];
     if (tid < k) {
-      c128 s = z0();
-      for (int q = tid; q < k; ++q) s = cadd(s, cmul(Tm[tid][q], G[q][k]));
-      Tm[tid][k] = cmul(mk<double>(-tk.re, -tk.im), s);
+      c128 sacc = z0();
+      for (int q = tid; q < k; ++q) sacc = cadd(sacc, cmul(Tm[tid][q], slab[q][k]));
+      Tm[tid][k] = cmul(mk<double>(-tk.re, -tk.im), sacc);
     }
     if (tid == k) Tm[k][k] = tk;
     __syncthreads();
@@ -391,10 +466,10 @@ __global__ __launch_bounds__(256) void larft_kernel(c128* V, c128* VT, c128* T, 
   c128* VTp = VT + (size_t)p * m * NB;
   for (int idx = tid; idx < mp * NB; idx += 256) {
     const int i = idx / NB, c = idx % NB;
-    c128 s = z0();
+    c128 sacc = z0();
     if (c < jb)
-      for (int q = 0; q <= c; ++q) s = cadd(s, cmul(Vp[(long long)i * NB + q], Tm[q][c]));
-    VTp[idx] = s;
+      for (int q = 0; q <= c; ++q) sacc = cadd(sacc, cmul(Vp[(long long)i * NB + q], Tm[q][c]));
+    VTp[idx] = sacc;
   }
   for (int idx = tid; idx < NB * NB; idx += 256) T[(size_t)p * NB * NB + idx] = Tm[idx / NB][idx % NB];
 }
@@ -483,7 +558,7 @@ int eig_herm_top(c128* G, int n, int kwant, double* lam, c128* E, const EigWork&
   hipLaunchKernelGGL(larft_kernel, dim3(npan), dim3(256), 0, s, (c128*)w.qtri.V, (c128*)w.qtri.VT, w.qtri.T,
                      w.tau, mqr, mqr);
   QT_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(bisect_kernel, dim3((kwant + 63) / 64), dim3(64), 0, s, w.d, w.e, n, kwant, lam);
+  hipLaunchKernelGGL(bisect_kernel, dim3((kwant + 31) / 32), dim3(256), 0, s, w.d, w.e, n, kwant, lam);
   QT_HIP_CHECK(hipGetLastError());
   unsigned char* swp = (unsigned char*)((char*)w.lu + align256(4 * (size_t)n * n * 8));
   hipLaunchKernelGGL(invit_kernel, dim3((kwant + 63) / 64), dim3(64), 0, s, w.d, w.e, n, kwant, lam, w.lu, swp, E);

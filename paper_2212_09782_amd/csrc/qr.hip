@@ -63,6 +63,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelArgs a) {
     P[idx] = c < jb ? ccast<double>(A[(long long)(r0 + i) * a.lda + c]) : cz();
   }
   for (int idx = tid; idx < NB * (NB + 1); idx += 256) (&Tm[0][0])[idx] = cz();
+  if (tid == 0) flag = 0;
   __syncthreads();
 
   for (int k = 0; k < jb; ++k) {
@@ -84,9 +85,19 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelArgs a) {
     }
     if (!grid_barrier(a.gs, (unsigned)(k + 1), nblk, &flag)) return;
     {
+      // all loads of this thread's share issued before any is summed (the
+      // partials were just invalidated out of the caches: one round trip)
       const int bg = tid >> 5, c = tid & 31;
+      constexpr int kMaxPer = kMaxPanelBlocks / 8;
+      c128 v[kMaxPer];
+#pragma unroll
+      for (int q = 0; q < kMaxPer; ++q) {
+        const int w = bg + 8 * q;
+        v[q] = w < nblk ? a.red[((long long)slot * nblk + w) * NB + c] : cz();
+      }
       c128 acc = cz();
-      for (int w = bg; w < nblk; w += 8) acc = cadd(acc, a.red[((long long)slot * nblk + w) * NB + c]);
+#pragma unroll
+      for (int q = 0; q < kMaxPer; ++q) acc = cadd(acc, v[q]);
       part[bg][c] = acc;
     }
     __syncthreads();

@@ -22,7 +22,7 @@ EXPORTS = [
     "mps_ctx_create", "mps_ctx_destroy", "mps_last_error", "mps_sync", "mps_bond_capacity",
     "mps_workspace_query", "mps_bond_update", "mps_clock_gate", "mps_state_create",
     "mps_state_destroy", "mps_state_chis", "mps_sweep", "mps_measure", "mps_zgemm", "mps_qr",
-    "mps_heig",
+    "mps_heig", "mps_profile_enable", "mps_profile_read",
 ]
 
 
@@ -71,6 +71,8 @@ def _declare(lib):
         "mps_zgemm": (I, [P, I, I, I, I, I, I, P, LL, P, LL, P, LL, D, D, P]),
         "mps_qr": (I, [P, I, I, I, P, P, P]),
         "mps_heig": (I, [P, I, I, P, P, P, P]),
+        "mps_profile_enable": (I, [P, I, I]),
+        "mps_profile_read": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -83,6 +85,9 @@ def load():
     """Load the library (once).  Raises if it is missing: there is no CPU path."""
     global _lib
     if _lib is None:
+        # torch first: the library then binds to the HIP runtime torch already
+        # loaded, so both share one runtime (and one device context)
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise QrtebdError(MPS_ERR_STATE, f"{LIB_PATH} not built (run paper_2212_09782_amd.build)")
         _lib = _declare(ctypes.CDLL(LIB_PATH))
@@ -129,6 +134,15 @@ class Context:
 
     def sync(self, stream=None):
         _check(self.lib.mps_sync(self.h, _stream(stream)))
+
+    def profile_enable(self, on=True, max_launches=100000):
+        _check(self.lib.mps_profile_enable(self.h, int(on), max_launches))
+
+    def profile_read(self):
+        """(total_ms, total_flops, launches) of the contraction GEMMs since profile_enable."""
+        ms, fl, n = D(), D(), I()
+        _check(self.lib.mps_profile_read(self.h, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n)))
+        return ms.value, fl.value, n.value
 
 
 def clock_gate(d, g, tau, wl=0.5, wr=0.5):
