@@ -162,7 +162,7 @@ def main():
         "per_precision": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                           for k, v in res.items()},
         "roofline": {
-            "kernel": "contraction GEMMs of the bond update (gemm_kernel, 5 launches per update)",
+            "kernel": "contract_gemm_kernel (the 5 contraction GEMMs of each update)",
             "bound": "mfma",
             "achieved": round(achieved / 1e12, 3),
             "peak": round(PEAK[head] / 1e12, 1),

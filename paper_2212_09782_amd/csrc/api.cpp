@@ -88,7 +88,7 @@ int check_desc(const mps_bond_desc* D) {
   if (D->mode == MPS_TRUNC_CBE && D->chi_max < 1) return set_error(MPS_ERR_ARG, "chi_max must be >= 1");
   if (D->mode == MPS_TRUNC_CBE && !(D->svd_min >= 0)) return set_error(MPS_ERR_ARG, "svd_min must be >= 0");
   if (D->d * D->d > 160) return set_error(MPS_ERR_CAPACITY, "d=%d too large (d^2 <= 160)", D->d);
-  if (std::max(mL, mR) > kMaxPanelBlocks * 256)
+  if (std::max(mL, mR) > kMaxQrRows)
     return set_error(MPS_ERR_CAPACITY, "d chi=%d too large", std::max(mL, mR));
   if (D->mode == MPS_TRUNC_CBE && D->eta > 2048) return set_error(MPS_ERR_CAPACITY, "eta=%d > 2048", D->eta);
   return 0;
@@ -505,7 +505,7 @@ int mps_qr(mps_ctx c, int dt, int m, int n, void* A, void* Q, mps_stream stream)
   if (!c || !A || !Q) return set_error(MPS_ERR_ARG, "null argument");
   if (dt != DT_C64 && dt != DT_C128) return set_error(MPS_ERR_ARG, "dt must be 0 or 1");
   if (n < 1 || n > m) return set_error(MPS_ERR_ARG, "need 1 <= n <= m");
-  if (m > kMaxPanelBlocks * 256) return set_error(MPS_ERR_CAPACITY, "m=%d too large", m);
+  if (m > kMaxQrRows) return set_error(MPS_ERR_CAPACITY, "m=%d too large", m);
   const int es = dt == DT_C128 ? 16 : 8;
   hipStream_t s = (hipStream_t)stream;
   int rc;

@@ -370,11 +370,11 @@ int run_typed(const BondShape& b, void* ws, int* status, const void* xi_m, const
 }  // namespace
 
 int timed_gemm(KernelTimer* t, const GemmProb& p, GemmTypes ty, hipStream_t s) {
-  if (!t || !t->on || t->n >= t->cap) return gemm_one(p, ty, s);
+  if (!t || !t->on || t->n >= t->cap) return gemm_one(p, ty, s, true);
   const int i = t->n++;
   t->flops[i] = 8.0 * (double)p.M * (double)p.N * (double)p.K;
   QT_HIP_CHECK(hipEventRecord(t->ev[2 * i], s));
-  int rc = gemm_one(p, ty, s);
+  int rc = gemm_one(p, ty, s, true);
   if (rc) return rc;
   QT_HIP_CHECK(hipEventRecord(t->ev[2 * i + 1], s));
   return 0;

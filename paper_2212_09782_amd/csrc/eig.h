@@ -12,7 +12,8 @@ struct EigWork {
   unsigned* sync;   // grid barrier words
   c128* red;        // cross-block partial sums: 2 * (256 + 1) + 2 * n  (p vector + row)
   QrWork qtri;      // reflectors of the tridiagonalisation, (n-1) x (n-1) problem with n work columns
-  QrWork qz;        // re-orthogonalisation QR of the eigenvector block, n x n
+  c128* gz;         // n x n Gram matrix of the eigenvector block (Newton-Schulz polish)
+  c128* ztmp;       // n x n copy of the eigenvector block
   int* status;
 };
 

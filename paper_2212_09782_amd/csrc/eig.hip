@@ -15,8 +15,12 @@
 //  3. Their eigenvectors by inverse iteration on T (tridiagonal LU with
 //     partial pivoting, three solves from a fixed pseudo-random start), one
 //     thread per vector.
-//  4. Re-orthogonalisation of that block by the Householder QR (clusters of
-//     close eigenvalues are orthogonalised in eigenvalue order).
+//  4. Re-orthogonalisation: modified Gram-Schmidt (two passes) inside each
+//     cluster of eigenvalues closer than 1e-9 |T| (where independent inverse
+//     iterations can return nearly parallel vectors), then two Newton-Schulz
+//     steps Z <- Z - Z (Z^H Z - 1)/2 on the MFMA GEMM.  Mixing two vectors by
+//     their overlap, which is ~u|T|/gap, moves their residuals by ~u|T|
+//     whatever the gap, so the polish keeps the eigenvectors accurate.
 //  5. Back-transformation E = Q Z with the compact-WY blocks of step 1 on
 //     the MFMA GEMM.
 #include "eig.h"
@@ -474,6 +478,42 @@ __global__ __launch_bounds__(256) void larft_kernel(c128* V, c128* VT, c128* T, 
   for (int idx = tid; idx < NB * NB; idx += 256) T[(size_t)p * NB * NB + idx] = Tm[idx / NB][idx % NB];
 }
 
+// Two-pass modified Gram-Schmidt over each cluster of close eigenvalues
+// (lam descending; a cluster starts where the gap to the previous value
+// exceeds rtol * max|lam|).  Block b handles the cluster starting at column b, if any.
+__global__ __launch_bounds__(256) void cluster_mgs_kernel(c128* Z, const double* lam, int n, int kw, double rtol) {
+  __shared__ double scr[8];
+  const int j = blockIdx.x;
+  const double ctol = rtol * fmax(fabs(lam[0]), fabs(lam[kw - 1]));
+  if (j > 0 && lam[j - 1] - lam[j] <= ctol) return;
+  int e = j;
+  while (e + 1 < kw && lam[e] - lam[e + 1] <= ctol) ++e;
+  if (e == j) return;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int v = j; v <= e; ++v) {
+      for (int u = j; u < v; ++u) {
+        double dot = 0;
+        for (int i = threadIdx.x; i < n; i += 256) dot += Z[(long long)i * kw + u].re * Z[(long long)i * kw + v].re;
+        dot = block_sum(dot, scr);
+        for (int i = threadIdx.x; i < n; i += 256) Z[(long long)i * kw + v].re -= dot * Z[(long long)i * kw + u].re;
+        __syncthreads();
+      }
+      double nn = 0;
+      for (int i = threadIdx.x; i < n; i += 256) nn += Z[(long long)i * kw + v].re * Z[(long long)i * kw + v].re;
+      nn = block_sum(nn, scr);
+      const double f = nn > 0 ? 1.0 / sqrt(nn) : 0.0;
+      for (int i = threadIdx.x; i < n; i += 256) Z[(long long)i * kw + v].re *= f;
+      __syncthreads();
+    }
+}
+
+// D = G - 1 on a k x k block (in place).
+__global__ void sub_identity_kernel(c128* G, int k) {
+  const long long tot = (long long)k * k;
+  for (long long idx = blockIdx.x * 256ll + threadIdx.x; idx < tot; idx += (long long)gridDim.x * 256)
+    if (idx / k == idx % k) G[idx].re -= 1.0;
+}
+
 __global__ void eig1_kernel(const c128* G, double* lam, c128* E) {
   lam[0] = G[0].re;
   E[0] = mk<double>(1, 0);
@@ -496,7 +536,7 @@ size_t eig_work_bytes(int n) {
   b += align256(grid_sync_words(256) * 4);
   b += align256((2 * 257 + 4 * (size_t)n) * 16);     // red + pbuf + rowbuf
   b += align256(qr_work_bytes(std::max(n - 1, 1), std::max(n - 1, 1), 16, n));
-  b += align256(qr_work_bytes(n, n, 16, n));
+  b += 2 * align256((size_t)n * n * 16);
   return b;
 }
 
@@ -512,7 +552,8 @@ EigWork eig_work_carve(void* base, int n, int* status) {
   w.red = (c128*)p; p += align256((2 * 257 + 4 * (size_t)n) * 16);
   w.qtri = qr_work_carve(p, std::max(n - 1, 1), std::max(n - 1, 1), 16, n, status);
   p += align256(qr_work_bytes(std::max(n - 1, 1), std::max(n - 1, 1), 16, n));
-  w.qz = qr_work_carve(p, n, n, 16, n, status);
+  w.gz = (c128*)p; p += align256((size_t)n * n * 16);
+  w.ztmp = (c128*)p; p += align256((size_t)n * n * 16);
   w.status = status;
   return w;
 }
@@ -563,9 +604,20 @@ int eig_herm_top(c128* G, int n, int kwant, double* lam, c128* E, const EigWork&
   unsigned char* swp = (unsigned char*)((char*)w.lu + align256(4 * (size_t)n * n * 8));
   hipLaunchKernelGGL(invit_kernel, dim3((kwant + 63) / 64), dim3(64), 0, s, w.d, w.e, n, kwant, lam, w.lu, swp, E);
   QT_HIP_CHECK(hipGetLastError());
-  // orthonormalise the eigenvector block, then E = Q Z
-  if ((rc = qr_factor(E, kwant, n, kwant, DT_C128, w.qz, s))) return rc;
-  if ((rc = qr_form_q(E, kwant, n, kwant, DT_C128, w.qz, s))) return rc;
+  // orthonormalise the eigenvector block (clustered MGS, Newton-Schulz), then E = Q Z
+  hipLaunchKernelGGL(cluster_mgs_kernel, dim3(kwant), dim3(256), 0, s, E, lam, n, kwant, 1e-9);
+  QT_HIP_CHECK(hipGetLastError());
+  for (int it = 0; it < 2; ++it) {
+    const GemmTypes ty{DT_C128, DT_C128};
+    if ((rc = gemm_one(gemm_prob(E, kwant, OP_C, E, kwant, OP_N, w.gz, kwant, kwant, kwant, n), ty, s))) return rc;
+    hipLaunchKernelGGL(sub_identity_kernel, dim3(std::min(4096, (kwant * kwant + 255) / 256)), dim3(256), 0, s, w.gz,
+                       kwant);
+    QT_HIP_CHECK(hipGetLastError());
+    QT_HIP_CHECK(hipMemcpyAsync(w.ztmp, E, (size_t)n * kwant * sizeof(c128), hipMemcpyDeviceToDevice, s));
+    if ((rc = gemm_one(gemm_prob(w.ztmp, kwant, OP_N, w.gz, kwant, OP_N, E, kwant, n, kwant, kwant, -0.5f, 1.f), ty,
+                       s)))
+      return rc;
+  }
   if ((rc = qr_apply_q(E + kwant, kwant, kwant, mqr, mqr, DT_C128, w.qtri, s))) return rc;
   return 0;
 }

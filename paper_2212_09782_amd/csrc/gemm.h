@@ -51,9 +51,11 @@ struct GemmTypes {
 
 // Launch one grouped GEMM (all problems share the types).  Problems with
 // ksplit > 1 also launch the reduction.  Returns 0 or a negative status.
-int gemm_run(const GemmProb* probs, int nprob, GemmTypes ty, hipStream_t stream);
-inline int gemm_one(const GemmProb& p, GemmTypes ty, hipStream_t stream) {
-  return gemm_run(&p, 1, ty, stream);
+// contract = true launches the same kernel under the name
+// contract_gemm_kernel (the bond update's contractions, profiled apart).
+int gemm_run(const GemmProb* probs, int nprob, GemmTypes ty, hipStream_t stream, bool contract = false);
+inline int gemm_one(const GemmProb& p, GemmTypes ty, hipStream_t stream, bool contract = false) {
+  return gemm_run(&p, 1, ty, stream, contract);
 }
 
 // Convenience constructor with static sizes.

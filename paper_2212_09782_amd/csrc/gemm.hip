@@ -39,7 +39,7 @@ template <> struct Mfma<float> {
 constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
 
 template <typename Tin, typename Tout, typename Tc>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmBatch b) {
+__device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   using MF = Mfma<Tc>;
   using v4 = typename MF::v4;
   __shared__ Tc As[2][BK][BM + PAD];
@@ -201,6 +201,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmBatch b) {
       }
 }
 
+// Two entry points with the same body: the contractions of the bond update
+// (the dominant kernel, reported on its own by profilers) and all other
+// products (QR trailing updates, explicit Q, Gram matrices).
+template <typename Tin, typename Tout, typename Tc>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmBatch b) { gemm_body<Tin, Tout, Tc>(b); }
+template <typename Tin, typename Tout, typename Tc>
+__global__ __launch_bounds__(256) void contract_gemm_kernel(GemmBatch b) { gemm_body<Tin, Tout, Tc>(b); }
+
 // C = alpha * sum_s work[s] + beta * C over the live M x N.
 template <typename Tout, typename Tc>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmProb P) {
@@ -234,7 +242,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmProb P) {
 }
 
 template <typename Tin, typename Tout, typename Tc>
-int launch_typed(const GemmProb* probs, int nprob, hipStream_t stream) {
+int launch_typed(const GemmProb* probs, int nprob, hipStream_t stream, bool contract) {
   int i = 0;
   while (i < nprob) {
     GemmBatch b{};
@@ -254,7 +262,10 @@ int launch_typed(const GemmProb* probs, int nprob, hipStream_t stream) {
     }
     if (b.nprob == 0) continue;
     b.tile_start[b.nprob] = total;
-    hipLaunchKernelGGL((gemm_kernel<Tin, Tout, Tc>), dim3(total), dim3(256), 0, stream, b);
+    if (contract)
+      hipLaunchKernelGGL((contract_gemm_kernel<Tin, Tout, Tc>), dim3(total), dim3(256), 0, stream, b);
+    else
+      hipLaunchKernelGGL((gemm_kernel<Tin, Tout, Tc>), dim3(total), dim3(256), 0, stream, b);
     QT_HIP_CHECK(hipGetLastError());
     for (int q = 0; q < b.nprob; ++q) {
       const GemmProb& pr = b.p[q];
@@ -271,10 +282,12 @@ int launch_typed(const GemmProb* probs, int nprob, hipStream_t stream) {
 
 }  // namespace
 
-int gemm_run(const GemmProb* probs, int nprob, GemmTypes ty, hipStream_t stream) {
-  if (ty.tin == DT_C128 && ty.tout == DT_C128) return launch_typed<double, double, double>(probs, nprob, stream);
-  if (ty.tin == DT_C64 && ty.tout == DT_C64) return launch_typed<float, float, float>(probs, nprob, stream);
-  if (ty.tin == DT_C64 && ty.tout == DT_C128) return launch_typed<float, double, double>(probs, nprob, stream);
+int gemm_run(const GemmProb* probs, int nprob, GemmTypes ty, hipStream_t stream, bool contract) {
+  if (ty.tin == DT_C128 && ty.tout == DT_C128)
+    return launch_typed<double, double, double>(probs, nprob, stream, contract);
+  if (ty.tin == DT_C64 && ty.tout == DT_C64) return launch_typed<float, float, float>(probs, nprob, stream, contract);
+  if (ty.tin == DT_C64 && ty.tout == DT_C128)
+    return launch_typed<float, double, double>(probs, nprob, stream, contract);
   return set_error(-1, "gemm_run: unsupported type combination %d/%d", ty.tin, ty.tout);
 }
 

@@ -21,7 +21,12 @@ struct QrWork {
 };
 
 constexpr int kMaxPanelBlocks = 256;
-constexpr int kMaxSplit = 16;
+constexpr int kMaxQrRows = kMaxPanelBlocks * 160;   // blocks x rows per block
+constexpr int kMaxSplit = 64;
+
+// K split for a product with a small M x N output and a long K: enough
+// workgroups to fill the GPU, chunks of at least 64.
+int splitk_for(int M, int N, int K);
 
 // Bytes of the QrWork of an m x n problem with element size es whose W can
 // hold wcols columns (wcols >= n; qr_apply_q may then act on up to wcols).

@@ -40,16 +40,17 @@ struct PanelArgs {
 
 __device__ inline c128 cz() { return mk<double>(0, 0); }
 
+constexpr int LDP = NB + 1;   // padded LDS row stride of the panel slab
+constexpr int kMaxPanelRows = 160;
+
 template <typename S>
 __global__ __launch_bounds__(256) void qr_panel_kernel(PanelArgs a) {
-  extern __shared__ c128 P[];  // rows_per_blk x NB
+  extern __shared__ c128 P[];  // rows_per_blk x LDP
   __shared__ c128 part[8][NB];
-  __shared__ c128 tsum[NB];
-  __shared__ c128 rowk[NB];
-  __shared__ c128 vh[NB];
-  __shared__ c128 tmpv[NB];
+  __shared__ c128 Sk[NB][NB + 1];   // per column k: V[:, j]^dag v_k for j < k (builds T after the loop)
   __shared__ c128 Tm[NB][NB + 1];
-  __shared__ c128 sc[3];
+  __shared__ c128 taus[NB];
+  __shared__ c128 rowk[NB];
   __shared__ int flag;
 
   const int tid = threadIdx.x, nblk = gridDim.x, blk = blockIdx.x;
@@ -60,33 +61,32 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelArgs a) {
 
   for (int idx = tid; idx < nr * NB; idx += 256) {
     const int i = idx / NB, c = idx % NB;
-    P[idx] = c < jb ? ccast<double>(A[(long long)(r0 + i) * a.lda + c]) : cz();
+    P[i * LDP + c] = c < jb ? ccast<double>(A[(long long)(r0 + i) * a.lda + c]) : cz();
   }
-  for (int idx = tid; idx < NB * (NB + 1); idx += 256) (&Tm[0][0])[idx] = cz();
   if (tid == 0) flag = 0;
   __syncthreads();
 
   for (int k = 0; k < jb; ++k) {
     const int slot = k & 1;
-    {  // partial sums over this block's rows strictly below the diagonal
+    {  // partial sums over this block's rows strictly below the diagonal:
+       // t_c = sum_i conj(P[i,k]) P[i,c] gives the norm (c = k), the products
+       // with the panel (c > k) and with earlier reflectors (c < k)
       const int rg = tid >> 5, c = tid & 31;
       c128 acc = cz();
       if (c < jb)
         for (int i = rg; i < nr; i += 8)
-          if (r0 + i > k) acc = cadd(acc, cmulc(P[i * NB + k], P[i * NB + c]));
+          if (r0 + i > k) acc = cadd(acc, cmulc(P[i * LDP + k], P[i * LDP + c]));
       part[rg][c] = acc;
     }
     __syncthreads();
-    if (tid < NB) {
+    if (tid < NB) {  // wave 0 publishes
       c128 s = cz();
       for (int g = 0; g < 8; ++g) s = cadd(s, part[g][tid]);
       a.red[((long long)slot * nblk + blk) * NB + tid] = s;
-      if (k >= r0 && k < r0 + nr) a.rowbuf[slot * NB + tid] = P[(k - r0) * NB + tid];
+      if (k >= r0 && k < r0 + nr) a.rowbuf[slot * NB + tid] = P[(k - r0) * LDP + tid];
     }
     if (!grid_barrier(a.gs, (unsigned)(k + 1), nblk, &flag)) return;
-    {
-      // all loads of this thread's share issued before any is summed (the
-      // partials were just invalidated out of the caches: one round trip)
+    {  // one round of loads: this thread's share of the block partials and row k
       const int bg = tid >> 5, c = tid & 31;
       constexpr int kMaxPer = kMaxPanelBlocks / 8;
       c128 v[kMaxPer];
@@ -95,74 +95,75 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelArgs a) {
         const int w = bg + 8 * q;
         v[q] = w < nblk ? a.red[((long long)slot * nblk + w) * NB + c] : cz();
       }
+      const c128 rk = tid < NB ? a.rowbuf[slot * NB + tid] : cz();
       c128 acc = cz();
 #pragma unroll
       for (int q = 0; q < kMaxPer; ++q) acc = cadd(acc, v[q]);
       part[bg][c] = acc;
+      if (tid < NB) rowk[tid] = rk;
     }
     __syncthreads();
-    if (tid < NB) {
-      c128 s = cz();
-      for (int g = 0; g < 8; ++g) s = cadd(s, part[g][tid]);
-      tsum[tid] = s;
-      rowk[tid] = a.rowbuf[slot * NB + tid];
+    // every thread derives the reflector (LAPACK zlarfg conventions)
+    c128 tk = cz();
+    for (int g = 0; g < 8; ++g) tk = cadd(tk, part[g][k]);
+    const c128 alpha = rowk[k];
+    const double xnorm2 = fmax(tk.re, 0.0);
+    c128 tau = cz(), scale = cz();
+    double beta = alpha.re;
+    if (!(xnorm2 == 0.0 && alpha.im == 0.0)) {
+      beta = -copysign(sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xnorm2), alpha.re);
+      tau = mk<double>((beta - alpha.re) / beta, -alpha.im / beta);
+      const c128 den = mk<double>(alpha.re - beta, alpha.im);
+      const double dd = cabs2(den);
+      scale = mk<double>(den.re / dd, -den.im / dd);
     }
-    __syncthreads();
     if (tid == 0) {
-      const c128 alpha = rowk[k];
-      const double xnorm2 = fmax(tsum[k].re, 0.0);
-      c128 tau = cz(), scale = cz();
-      double beta = alpha.re;
-      if (!(xnorm2 == 0.0 && alpha.im == 0.0)) {
-        beta = -copysign(sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xnorm2), alpha.re);
-        tau = mk<double>((beta - alpha.re) / beta, -alpha.im / beta);
-        const c128 den = mk<double>(alpha.re - beta, alpha.im);
-        const double dd = cabs2(den);
-        scale = mk<double>(den.re / dd, -den.im / dd);
-      }
+      taus[k] = tau;
       if (!isfinite(beta)) latch_error(a.gs.status, ERRBIT_NONFINITE);
-      sc[0] = tau;
-      sc[1] = scale;
-      sc[2] = mk<double>(beta, 0.0);
     }
-    __syncthreads();
-    const c128 tau = sc[0], scale = sc[1];
-    if (tid < NB) {
-      const int l = tid;
-      if (l > k && l < jb) vh[l] = cadd(rowk[l], cmulc(scale, tsum[l]));
-      if (l < k) tmpv[l] = cadd(cconj(rowk[l]), cmul(scale, cconj(tsum[l])));
+    if (tid < k) {  // V[:, j]^dag v_k = conj(V[k, j]) + scale * conj(t_j)
+      c128 tj = cz();
+      for (int g = 0; g < 8; ++g) tj = cadd(tj, part[g][tid]);
+      Sk[k][tid] = cadd(cconj(rowk[tid]), cmul(scale, cconj(tj)));
     }
-    __syncthreads();
-    if (tid < NB) {
-      const int j = tid;
-      if (j < k) {
-        c128 s = cz();
-        for (int q = j; q < k; ++q) s = cadd(s, cmul(Tm[j][q], tmpv[q]));
-        Tm[j][k] = cmul(mk<double>(-tau.re, -tau.im), s);
-      } else if (j == k) {
-        Tm[k][k] = tau;
-      }
-    }
-    for (int i = tid; i < nr; i += 256)
-      if (r0 + i > k) P[i * NB + k] = cmul(P[i * NB + k], scale);
-    __syncthreads();
-    const c128 ctau = cconj(tau);
-    for (int idx = tid; idx < nr * NB; idx += 256) {
-      const int i = idx / NB, l = idx % NB, gi = r0 + i;
-      if (gi >= k && l > k && l < jb) {
-        const c128 v = gi == k ? mk<double>(1, 0) : P[i * NB + k];
-        P[idx] = csub(P[idx], cmul(ctau, cmul(v, vh[l])));
+    // row-private update: thread i owns row i of the slab
+    if (tid < nr) {
+      const int i = tid, gi = r0 + i;
+      if (gi >= k) {
+        c128* Pi = P + i * LDP;
+        const c128 v = gi == k ? mk<double>(1, 0) : cmul(Pi[k], scale);
+        const c128 cv = cmul(cconj(tau), v);
+        for (int l = k + 1; l < jb; ++l) {
+          c128 tl = cz();
+          for (int g = 0; g < 8; ++g) tl = cadd(tl, part[g][l]);
+          const c128 vhl = cadd(rowk[l], cmulc(scale, tl));   // v^H P[:, l]
+          Pi[l] = csub(Pi[l], cmul(cv, vhl));
+        }
+        Pi[k] = gi == k ? mk<double>(beta, 0.0) : v;
       }
     }
     __syncthreads();
-    if (tid == 0 && k >= r0 && k < r0 + nr) P[(k - r0) * NB + k] = sc[2];
+  }
+
+  // T of the compact-WY form: T[k][k] = tau_k, T[0:k, k] = -tau_k T[0:k, 0:k] S_k
+  for (int idx = tid; idx < NB * (NB + 1); idx += 256) (&Tm[0][0])[idx] = cz();
+  __syncthreads();
+  for (int k = 0; k < jb; ++k) {
+    const c128 tk = taus[k];
+    if (tid < k) {
+      c128 sacc = cz();
+      for (int q = tid; q < k; ++q) sacc = cadd(sacc, cmul(Tm[tid][q], Sk[k][q]));
+      Tm[tid][k] = cmul(mk<double>(-tk.re, -tk.im), sacc);
+    } else if (tid == k) {
+      Tm[k][k] = tk;
+    }
     __syncthreads();
   }
 
   // write back R / reflectors in place and the explicit V, V T, V T^H
   for (int idx = tid; idx < nr * NB; idx += 256) {
     const int i = idx / NB, c = idx % NB;
-    if (c < jb) A[(long long)(r0 + i) * a.lda + c] = ccast<S>(P[idx]);
+    if (c < jb) A[(long long)(r0 + i) * a.lda + c] = ccast<S>(P[i * LDP + c]);
   }
   cpx<S>* V = (cpx<S>*)a.V;
   cpx<S>* VT = (cpx<S>*)a.VT;
@@ -171,9 +172,9 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelArgs a) {
     const int i = idx / NB, c = idx % NB, gi = r0 + i;
     c128 vc = cz(), vt = cz(), vth = cz();
     if (c < jb) {
-      vc = gi > c ? P[idx] : (gi == c ? mk<double>(1, 0) : cz());
+      vc = gi > c ? P[i * LDP + c] : (gi == c ? mk<double>(1, 0) : cz());
       for (int q = 0; q < jb; ++q) {
-        const c128 vq = gi > q ? P[i * NB + q] : (gi == q ? mk<double>(1, 0) : cz());
+        const c128 vq = gi > q ? P[i * LDP + q] : (gi == q ? mk<double>(1, 0) : cz());
         if (q <= c) vt = cadd(vt, cmul(vq, Tm[q][c]));
         if (q >= c) vth = cadd(vth, cmul(vq, cconj(Tm[c][q])));
       }
@@ -208,18 +209,18 @@ __global__ void set_identity_kernel(cpx<S>* Q, long long ldq, int m, int n) {
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int panel_rows(int mp) {
-  int r = (mp + 39) / 40;
+  int r = (mp + 31) / 32;
   r = (r + 31) / 32 * 32;
-  return std::min(256, std::max(32, r));
+  return std::min(kMaxPanelRows, std::max(32, r));
 }
 
 template <typename S>
 int launch_panel(const PanelArgs& pa, int nblk, hipStream_t s) {
-  const size_t shmem = (size_t)pa.rows_per_blk * NB * sizeof(c128);
+  const size_t shmem = (size_t)pa.rows_per_blk * LDP * sizeof(c128);
   static bool attr_set = false;
   if (!attr_set) {
     QT_HIP_CHECK(hipFuncSetAttribute((const void*)qr_panel_kernel<S>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 256 * NB * sizeof(c128)));
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kMaxPanelRows * LDP * sizeof(c128)));
     attr_set = true;
   }
   void* args[] = {(void*)&pa};
@@ -229,6 +230,13 @@ int launch_panel(const PanelArgs& pa, int nblk, hipStream_t s) {
 }
 
 }  // namespace
+
+int splitk_for(int M, int N, int K) {
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  int ks = (512 + tiles - 1) / tiles;
+  ks = std::min(ks, std::max(1, K / 64));
+  return std::max(1, std::min(ks, kMaxSplit));
+}
 
 int fill_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t n = bytes / 4;
@@ -316,7 +324,7 @@ int qr_factor(void* A, long long lda, int m, int n, int dt, const QrWork& w, hip
     if (nt > 0) {
       void* At = Ab + ((long long)j0 * lda + j0 + jb) * es;
       GemmProb g1 = gemm_prob(pa.V, NB, OP_C, At, lda, OP_N, w.W, nt, jb, nt, mp);
-      g1.ksplit = std::min(kMaxSplit, std::max(1, mp / 512));
+      g1.ksplit = splitk_for(jb, nt, mp);
       g1.work = w.Wsplit;
       GemmProb g2 = gemm_prob(pa.VTh, NB, OP_N, w.W, nt, OP_N, At, lda, mp, nt, jb, -1.f, 1.f);
       if ((rc = gemm_one(g1, ty, s))) return rc;
@@ -336,7 +344,7 @@ int qr_apply_q(void* Z, long long ldz, int nz, int m, int n, int dt, const QrWor
     const size_t voff = (size_t)p * m * NB * es;
     void* Zs = (char*)Z + (long long)j0 * ldz * es;
     GemmProb g1 = gemm_prob((char*)w.V + voff, NB, OP_C, Zs, ldz, OP_N, w.W, nz, jb, nz, mp);
-    g1.ksplit = std::min(kMaxSplit, std::max(1, mp / 512));
+    g1.ksplit = splitk_for(jb, nz, mp);
     g1.work = w.Wsplit;
     GemmProb g2 = gemm_prob((char*)w.VT + voff, NB, OP_N, w.W, nz, OP_N, Zs, ldz, mp, nz, jb, -1.f, 1.f);
     int rc;
@@ -357,7 +365,7 @@ int qr_form_q(void* Q, long long ldq, int m, int n, int dt, const QrWork& w, hip
     const size_t voff = (size_t)p * m * NB * es;
     void* Qs = (char*)Q + ((long long)j0 * ldq + j0) * es;
     GemmProb g1 = gemm_prob((char*)w.V + voff, NB, OP_C, Qs, ldq, OP_N, w.W, nq, jb, nq, mp);
-    g1.ksplit = std::min(kMaxSplit, std::max(1, mp / 512));
+    g1.ksplit = splitk_for(jb, nq, mp);
     g1.work = w.Wsplit;
     GemmProb g2 = gemm_prob((char*)w.VT + voff, NB, OP_N, w.W, nq, OP_N, Qs, ldq, mp, nq, jb, -1.f, 1.f);
     if ((rc = gemm_one(g1, ty, s))) return rc;

@@ -1,0 +1,239 @@
+"""Serving loop for quench simulations: continuous batching on one GPU.
+
+Requests (d, g, chi_max, geometry, nsteps, dt) arrive over time.  The engine
+keeps every admitted request's MPS resident in HBM and advances requests in
+batches: a slot owns a batch of requests and repeatedly calls mps_sweep for
+one Trotter step on all of them together (their even layers form one layer,
+then their odd layers).  Between steps, finished requests leave the batch
+and newly admitted ones join it ("continuous batching").  Several slots run
+at once, each with its own library context and HIP stream, so their work
+overlaps on the device.  Admission is by an HBM budget: a request is admitted
+only when its state buffers plus its share of workspace fit.
+
+Metrics: per-request step latency (gap between consecutive step completions
+of one request; the first step counts from admission) with p50/p99, and
+aggregate bond updates/s (all bond updates / makespan).
+
+The engine logic is independent of the executor: `Executor` runs the real
+library; tests may plug a stub executor in to check admission and batching
+on the CPU (never a product path).
+"""
+import heapq
+import math
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float
+    d: int
+    g: float
+    chi_max: int
+    finite: bool
+    L: int
+    nsteps: int = 50
+    dt: float = 0.05
+    prec: int = 0
+    # filled by the engine
+    admitted_at: float = None
+    step_times: list = field(default_factory=list)
+    done_at: float = None
+    bond_updates: int = 0
+    result: dict = None
+
+    def bonds_per_step(self):
+        """Bond updates of one second-order step: even(1/2), odd, even(1/2)."""
+        if not self.finite:
+            return 3
+        nb = self.L - 1
+        return 2 * math.ceil(nb / 2) + nb // 2
+
+
+def state_bytes(req):
+    es = 16 if req.prec == 0 else 8
+    return req.L * (req.chi_max * req.d * req.chi_max * es + req.chi_max * 8)
+
+
+class Executor:
+    """Runs requests on the GPU through the C-ABI (one instance per slot)."""
+
+    def __init__(self, device=0):
+        import torch
+        from . import lib
+        self.torch = torch
+        self.lib = lib
+        self.ctx = lib.Context(device)
+        self.stream = torch.cuda.Stream(device=device)
+        self.states = {}
+
+    def workspace_bytes(self, req):
+        lib = self.lib
+        eta = min(req.chi_max + max(100, math.ceil(0.1 * req.chi_max)), req.d * req.chi_max)
+        desc = lib.bond_desc(req.d, req.chi_max, req.chi_max, req.chi_max, eta, req.chi_max, prec=req.prec)
+        import ctypes
+        n = ctypes.c_size_t()
+        lib._check(lib.load().mps_workspace_query(self.ctx.h, ctypes.byref(desc), ctypes.byref(n)))
+        return int(n.value)
+
+    def admit(self, req):
+        lib, torch = self.lib, self.torch
+        with torch.cuda.stream(self.stream):
+            e = np.zeros((1, req.d, 1), np.complex128)
+            e[0, 0, 0] = 1
+            st = lib.State(self.ctx, [e] * req.L, [np.ones(1)] * req.L, finite=req.finite,
+                           chi_cap=req.chi_max, prec=req.prec)
+            gates = lib.chain_gates(req.d, req.g, req.L, req.finite, req.dt)
+        Z = np.diag(np.exp(2j * np.pi * np.arange(req.d) / req.d))
+        zz = torch.from_numpy((Z + Z.conj().T).reshape(-1)).to("cuda")
+        self.states[req.rid] = (st, gates, zz)
+
+    def step(self, reqs):
+        """One Trotter step of every request in reqs as one mps_sweep call."""
+        lib = self.lib
+        sts = [self.states[r.rid][0] for r in reqs]
+        gts = [self.states[r.rid][1] for r in reqs]
+        pol = lib.sweep_policy(max(r.chi_max for r in reqs), 1e-14 if reqs[0].prec == 0 else 1e-6)
+        # one policy per call: requests of one batch share chi_max caps through their states
+        lib.mps_sweep(self.ctx, sts, gts, 1, 2, pol, stream=self.stream)
+        self.stream.synchronize()
+
+    def finish(self, req):
+        torch, lib = self.torch, self.lib
+        st, gates, zz = self.states.pop(req.rid)
+        vals = torch.zeros(2 * req.L, dtype=torch.float64, device="cuda")
+        lib.mps_measure(self.ctx, st, op1=zz, site_vals=vals, stream=self.stream)
+        self.stream.synchronize()
+        req.result = {"zz": vals.cpu().numpy().reshape(req.L, 2)[:, 0].copy(), "chis": st.chis()}
+        st.close()
+
+    def close(self):
+        self.ctx.close()
+
+
+class Engine:
+    """Continuous-batching scheduler over `nslots` executors and an HBM budget."""
+
+    def __init__(self, executors, hbm_budget, max_batch=8, clock=time.perf_counter):
+        self.execs = executors
+        self.budget = hbm_budget
+        self.max_batch = max_batch
+        self.clock = clock
+        self.lock = threading.Lock()
+        self.used = 0
+        self.peak_used = 0
+        self.waiting = []          # (arrival, rid, req) heap of arrived, not yet admitted
+        self.pending = []          # not yet arrived (sorted by arrival)
+        self.batches = [[] for _ in executors]
+        self.finished = []
+        self.t0 = None
+
+    def _cost(self, req, ex):
+        # resident state plus the largest bond's workspace (conservative: the
+        # slot's workspace is shared by its batch)
+        return state_bytes(req) + ex.workspace_bytes(req)
+
+    def _try_admit(self, slot):
+        """Move arrived requests into this slot's batch while budget and batch size allow."""
+        ex = self.execs[slot]
+        with self.lock:
+            now = self.clock() - self.t0
+            while self.pending and self.pending[0].arrival <= now:
+                r = self.pending.pop(0)
+                heapq.heappush(self.waiting, (r.arrival, r.rid, r))
+            joined = []
+            while self.waiting and len(self.batches[slot]) + len(joined) < self.max_batch:
+                _, _, r = self.waiting[0]
+                c = self._cost(r, ex)
+                if self.used + c > self.budget:
+                    if self.used == 0:       # never admittable: reject rather than stall
+                        heapq.heappop(self.waiting)
+                        r.result = {"rejected": True}
+                        self.finished.append(r)
+                        continue
+                    break
+                heapq.heappop(self.waiting)
+                self.used += c
+                self.peak_used = max(self.peak_used, self.used)
+                r._cost = c
+                r.admitted_at = now
+                joined.append(r)
+        for r in joined:
+            ex.admit(r)
+            self.batches[slot].append(r)
+
+    def _worker(self, slot):
+        ex = self.execs[slot]
+        while True:
+            self._try_admit(slot)
+            batch = self.batches[slot]
+            if not batch:
+                with self.lock:
+                    idle = not self.pending and not self.waiting
+                if idle:
+                    return
+                time.sleep(0.002)
+                continue
+            ex.step(batch)
+            now = self.clock() - self.t0
+            keep = []
+            for r in batch:
+                r.step_times.append(now)
+                r.bond_updates += r.bonds_per_step()
+                if len(r.step_times) >= r.nsteps:
+                    ex.finish(r)
+                    r.done_at = now
+                    with self.lock:
+                        self.used -= r._cost
+                        self.finished.append(r)
+                else:
+                    keep.append(r)
+            self.batches[slot] = keep
+
+    def run(self, requests):
+        self.pending = sorted(requests, key=lambda r: r.arrival)
+        self.t0 = self.clock()
+        threads = [threading.Thread(target=self._worker, args=(s,)) for s in range(len(self.execs))]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        makespan = self.clock() - self.t0
+        return self.report(makespan)
+
+    def report(self, makespan):
+        lat = []
+        total = 0
+        for r in self.finished:
+            if r.result and r.result.get("rejected"):
+                continue
+            prev = r.admitted_at
+            for t in r.step_times:
+                lat.append(t - prev)
+                prev = t
+            total += r.bond_updates
+        lat = np.array(lat) if lat else np.zeros(1)
+        return {
+            "requests": len(self.finished),
+            "rejected": sum(1 for r in self.finished if r.result and r.result.get("rejected")),
+            "makespan_s": makespan,
+            "bond_updates": total,
+            "bond_updates_per_s": total / makespan if makespan > 0 else 0.0,
+            "p50_step_ms": 1e3 * float(np.percentile(lat, 50)),
+            "p99_step_ms": 1e3 * float(np.percentile(lat, 99)),
+            "peak_hbm_bytes": self.peak_used,
+        }
+
+
+def requests_from_stream(specs, nsteps=50, dt=0.05, prec=0, chi_cap=None, time_scale=1.0):
+    """Requests from inputs.serving_requests() dicts (optionally capping chi_max)."""
+    out = []
+    for k, s in enumerate(specs):
+        chi = s["chi_max"] if chi_cap is None else min(s["chi_max"], chi_cap)
+        out.append(Request(rid=k, arrival=s["arrival"] * time_scale, d=s["d"], g=s["g"], chi_max=chi,
+                           finite=s["finite"], L=s["L"], nsteps=nsteps, dt=dt, prec=prec))
+    return out
