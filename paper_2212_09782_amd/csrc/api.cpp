@@ -102,7 +102,6 @@ BondShape shape_of(const mps_bond_desc* D) {
   return b;
 }
 
-__global__ void add_eps_kernel(const double* eps, double* acc) { *acc += *eps; }
 
 using cd = std::complex<double>;
 
@@ -359,10 +358,27 @@ std::vector<BondRef> layer_bonds(mps_state st, int parity, const void* gates, in
   return out;
 }
 
+struct EpsMap {
+  int n;
+  int state[512];
+};
+
+__global__ void add_eps_batch_kernel(const double* eps, EpsMap map, double* acc) {
+  for (int k = 0; k < map.n; ++k) acc[map.state[k]] += eps[k];
+}
+
+// One layer: every bond of every state in one batched update (per precision),
+// written in place into the state buffers, then one read-back of the new chis.
 int run_layer(mps_ctx c, std::vector<BondRef>& bonds, const mps_sweep_policy* pol, double* eps_acc_base,
               const std::vector<int>& state_index, hipStream_t s) {
   int rc;
-  for (size_t k = 0; k < bonds.size(); ++k) {
+  const int nb = (int)bonds.size();
+  if (nb == 0) return 0;
+  if (nb > 512) return set_error(MPS_ERR_CAPACITY, "a layer of %d bonds exceeds 512", nb);
+  std::vector<BondShape> shapes(nb);
+  std::vector<size_t> off(nb);
+  size_t total = ((size_t)nb * (sizeof(int) + sizeof(double)) + 4096 + 255) & ~size_t(255);
+  for (int k = 0; k < nb; ++k) {
     BondRef& br = bonds[k];
     mps_state st = br.st;
     const int d = st->d;
@@ -380,36 +396,42 @@ int run_layer(mps_ctx c, std::vector<BondRef>& bonds, const mps_sweep_policy* po
     D.mode = MPS_TRUNC_CBE;
     D.prec = st->prec;
     if ((rc = check_desc(&D))) return rc;
-    const BondShape b = shape_of(&D);
-    const int cap = b.cap();
-    const size_t es = st->prec ? 8 : 16;
-    const size_t bm_bytes = (size_t)chiL * d * cap * es, bn_bytes = (size_t)cap * d * chiR * es;
-    const size_t need_tmp = bm_bytes + bn_bytes + cap * 8 + 1024;
-    if ((rc = ensure(&c->tmp_out, &c->tmp_bytes, need_tmp, s))) return rc;
-    if ((rc = ensure(&c->ws, &c->ws_bytes, bond_work_bytes(b), s))) return rc;
-    char* t = (char*)c->tmp_out;
-    void* bm_out = t;
-    void* bn_out = t + ((bm_bytes + 255) & ~size_t(255));
-    double* xi_out = (double*)((char*)bn_out + ((bn_bytes + 255) & ~size_t(255)));
-    int* chi_dev = (int*)((char*)xi_out + ((cap * 8 + 255) & ~size_t(255)));
-    double* eps_dev = (double*)(chi_dev + 16);
-    if ((rc = bond_update_run(b, c->ws, c->status, st->Xi[br.m], st->B[br.m], st->B[br.n], br.gate, bm_out, xi_out,
-                              bn_out, chi_dev, eps_dev, s, &c->timer)))
-      return rc;
-    // the new chi decides the copy sizes: read it back
-    QT_HIP_CHECK(hipMemcpyAsync(c->chi_host, chi_dev, sizeof(int), hipMemcpyDeviceToHost, s));
-    QT_HIP_CHECK(hipStreamSynchronize(s));
-    const int chiN = c->chi_host[0];
-    if (chiN < 1 || chiN > cap) return set_error(MPS_ERR_NUMERIC, "device returned chi=%d (cap %d)", chiN, cap);
-    QT_HIP_CHECK(hipMemcpyAsync(st->B[br.m], bm_out, (size_t)chiL * d * chiN * es, hipMemcpyDeviceToDevice, s));
-    QT_HIP_CHECK(hipMemcpyAsync(st->B[br.n], bn_out, (size_t)chiN * d * chiR * es, hipMemcpyDeviceToDevice, s));
-    QT_HIP_CHECK(hipMemcpyAsync(st->Xi[br.n], xi_out, (size_t)chiN * 8, hipMemcpyDeviceToDevice, s));
-    if (eps_acc_base) {
-      hipLaunchKernelGGL(add_eps_kernel, dim3(1), dim3(1), 0, s, eps_dev, eps_acc_base + state_index[k]);
-      QT_HIP_CHECK(hipGetLastError());
-    }
-    st->chi[br.im] = chiN;
-    if (st->geometry == 1 && br.im == 0) st->chi[2] = chiN;
+    shapes[k] = shape_of(&D);
+    off[k] = total;
+    total += (bond_work_bytes(shapes[k]) + 255) & ~size_t(255);
+  }
+  if ((rc = ensure(&c->ws, &c->ws_bytes, total, s))) return rc;
+  char* base = (char*)c->ws;
+  int* chi_dev = (int*)base;
+  double* eps_dev = (double*)(base + (((size_t)nb * sizeof(int) + 255) & ~size_t(255)));
+  std::vector<BondCall> calls[2];
+  std::vector<int> order[2];
+  for (int k = 0; k < nb; ++k) {
+    BondRef& br = bonds[k];
+    mps_state st = br.st;
+    BondCall bc{shapes[k], base + off[k], c->status, st->Xi[br.m], st->B[br.m], st->B[br.n], br.gate,
+                st->B[br.m], st->Xi[br.n], st->B[br.n], chi_dev + k, eps_dev + k};
+    calls[st->prec].push_back(bc);
+    order[st->prec].push_back(k);
+  }
+  for (int p = 0; p < 2; ++p)
+    if (!calls[p].empty() && (rc = bond_update_batch(calls[p].data(), (int)calls[p].size(), s, &c->timer))) return rc;
+  if (eps_acc_base) {
+    EpsMap map{};
+    map.n = nb;
+    for (int k = 0; k < nb; ++k) map.state[k] = state_index[k];
+    hipLaunchKernelGGL(add_eps_batch_kernel, dim3(1), dim3(1), 0, s, eps_dev, map, eps_acc_base);
+    QT_HIP_CHECK(hipGetLastError());
+  }
+  QT_HIP_CHECK(hipMemcpyAsync(c->chi_host, chi_dev, (size_t)nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  QT_HIP_CHECK(hipStreamSynchronize(s));
+  for (int k = 0; k < nb; ++k) {
+    BondRef& br = bonds[k];
+    const int chiN = c->chi_host[k];
+    if (chiN < 1 || chiN > shapes[k].cap())
+      return set_error(MPS_ERR_NUMERIC, "device returned chi=%d (cap %d)", chiN, shapes[k].cap());
+    br.st->chi[br.im] = chiN;
+    if (br.st->geometry == 1 && br.im == 0) br.st->chi[2] = chiN;
   }
   return 0;
 }

@@ -27,6 +27,27 @@ struct BondShape {
 // Workspace bytes of one bond update of this shape.
 size_t bond_work_bytes(const BondShape& b);
 
+// One bond of a batched update: shape, its own workspace (bond_work_bytes)
+// and device pointers.  For CBE the outputs may alias the inputs B^[m],
+// B^[n] (they are read only before the outputs are written).
+struct BondCall {
+  BondShape b;
+  void* ws;
+  int* status;
+  const void* xi_m;
+  const void* b_m;
+  const void* b_n;
+  const c128* u;
+  void* b_m_out;
+  void* xi_n_out;
+  void* b_n_out;
+  int* chi_new;
+  double* eps;
+};
+// All bonds of a batch must share the precision; modes and shapes may differ.
+int bond_update_batch(const BondCall* calls, int n, hipStream_t s, KernelTimer* timer = nullptr);
+int timed_gemm_batch(KernelTimer* t, const GemmProb* p, int n, GemmTypes ty, hipStream_t s);
+
 // Run one update with workspace `ws` (bond_work_bytes(b) bytes).  status:
 // device error word.  All pointers are device pointers.
 int bond_update_run(const BondShape& b, void* ws, int* status, const void* xi_m, const void* b_m,

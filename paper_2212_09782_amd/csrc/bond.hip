@@ -20,6 +20,7 @@
 #include "bond.h"
 
 #include <algorithm>
+#include <vector>
 
 namespace qrtebd {
 
@@ -237,23 +238,34 @@ BondBufs carve(const BondShape& b, void* base) {
 }
 
 template <typename S>
-int run_typed(const BondShape& b, void* ws, int* status, const void* xi_m, const void* b_m, const void* b_n,
-              const c128* u, void* b_m_out, void* xi_n_out, void* b_n_out, int* chi_new, double* eps,
-              hipStream_t s, KernelTimer* tm) {
+int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm) {
   const int dt = sizeof(S) == 8 ? DT_C128 : DT_C64;
   const GemmTypes ty{dt, dt};
-  const int d = b.d, chiL = b.chi_l, chiM = b.chi_m, chiR = b.chi_r, eta = b.eta;
-  const int mL = d * chiL, mR = d * chiR;
-  const int cap = b.cap(), kw = kwant_of(b);
-  const bool cbe = b.mode == 2, mixed = dt == DT_C64;
-  BondBufs w = carve(b, ws);
-  QrWork qw = qr_work_carve(w.qrw, std::max(mL, mR), eta, (int)sizeof(cpx<S>), eta, status);
+  const bool mixed = dt == DT_C64;
   int rc;
-
+  std::vector<BondBufs> W(nc);
+  std::vector<QrWork> QW(nc);
+  std::vector<GemmProb> g;
+  for (int i = 0; i < nc; ++i) {
+    const BondShape& b = calls[i].b;
+    W[i] = carve(b, calls[i].ws);
+    QW[i] = qr_work_carve(W[i].qrw, std::max(b.d * b.chi_l, b.d * b.chi_r), b.eta, (int)sizeof(cpx<S>), b.eta,
+                          calls[i].status);
+  }
   // (i) C = B^[m] B^[n]
-  if ((rc = timed_gemm(tm, gemm_prob(b_m, chiM, OP_N, b_n, mR, OP_N, w.C, mR, mL, mR, chiM), ty, s))) return rc;
-  // C~ = U C (in place) and theta~ = Xi C~
-  {
+  g.clear();
+  for (int i = 0; i < nc; ++i) {
+    const BondShape& b = calls[i].b;
+    const int mL = b.d * b.chi_l, mR = b.d * b.chi_r;
+    g.push_back(gemm_prob(calls[i].b_m, b.chi_m, OP_N, calls[i].b_n, mR, OP_N, W[i].C, mR, mL, mR, b.chi_m));
+  }
+  if ((rc = timed_gemm_batch(tm, g.data(), nc, ty, s))) return rc;
+  // C~ = U C (in place) and theta~ = Xi C~, |theta~|^2
+  for (int i = 0; i < nc; ++i) {
+    const BondCall& c = calls[i];
+    const BondShape& b = c.b;
+    BondBufs& w = W[i];
+    const int d = b.d, chiL = b.chi_l, chiR = b.chi_r, mL = d * chiL, mR = d * chiR;
     const dim3 grid((chiR + 63) / 64, chiL);
     const size_t shm = (size_t)d * d * 64 * sizeof(c128);
     static bool attr = false;
@@ -263,22 +275,21 @@ int run_typed(const BondShape& b, void* ws, int* status, const void* xi_m, const
       attr = true;
     }
     const bool diag = b.xi_is_diag != 0;
-    hipLaunchKernelGGL(gate_kernel<S>, grid, dim3(64), shm, s, (cpx<S>*)w.C, diag ? (cpx<S>*)w.Th : nullptr, u,
-                       diag ? (const double*)xi_m : nullptr, d, chiR, w.partial);
+    hipLaunchKernelGGL(gate_kernel<S>, grid, dim3(64), shm, s, (cpx<S>*)w.C, diag ? (cpx<S>*)w.Th : nullptr, c.u,
+                       diag ? (const double*)c.xi_m : nullptr, d, chiR, w.partial);
     QT_HIP_CHECK(hipGetLastError());
     if (diag) {
       if ((rc = reduce_partials(w.partial, (int)(grid.x * grid.y), w.norm2, s))) return rc;
     } else {
-      const void* xiA = xi_m;
+      const void* xiA = c.xi_m;
       if (mixed) {
         const long long nx = (long long)chiL * chiL;
-        hipLaunchKernelGGL((cast_kernel<float, double>), dim3(grid_for(nx)), dim3(256), 0, s, (const c128*)xi_m, nx,
+        hipLaunchKernelGGL((cast_kernel<float, double>), dim3(grid_for(nx)), dim3(256), 0, s, (const c128*)c.xi_m, nx,
                            (c64*)w.XiC);
         QT_HIP_CHECK(hipGetLastError());
         xiA = w.XiC;
       }
-      // theta~ = Xi C~ with C~ viewed as chi_l x (d d chi_r)
-      const int ncol = d * mR;
+      const int ncol = d * mR;   // C~ viewed as chi_l x (d d chi_r)
       if ((rc = gemm_one(gemm_prob(xiA, chiL, OP_N, w.C, ncol, OP_N, w.Th, ncol, chiL, ncol, chiL), ty, s))) return rc;
       const long long n = (long long)mL * mR;
       hipLaunchKernelGGL(sumsq_kernel<S>, dim3(1024), dim3(256), 0, s, (const cpx<S>*)w.Th, n, w.partial);
@@ -287,87 +298,155 @@ int run_typed(const BondShape& b, void* ws, int* status, const void* xi_m, const
     }
   }
   // X = theta~ Y0^dag
-  {
-    GemmProb g = b.mode == 0 ? gemm_prob(w.Th, mR, OP_N, b_n, mR, OP_C, w.X, eta, mL, eta, mR)
-                             : gemm_prob(w.Th, mR, OP_N, w.Th, mR, OP_C, w.X, eta, mL, eta, mR);
-    if ((rc = timed_gemm(tm, g, ty, s))) return rc;
+  g.clear();
+  for (int i = 0; i < nc; ++i) {
+    const BondShape& b = calls[i].b;
+    const int mL = b.d * b.chi_l, mR = b.d * b.chi_r, eta = b.eta;
+    g.push_back(b.mode == 0 ? gemm_prob(W[i].Th, mR, OP_N, calls[i].b_n, mR, OP_C, W[i].X, eta, mL, eta, mR)
+                            : gemm_prob(W[i].Th, mR, OP_N, W[i].Th, mR, OP_C, W[i].X, eta, mL, eta, mR));
   }
+  if ((rc = timed_gemm_batch(tm, g.data(), nc, ty, s))) return rc;
   // Q^[m]
-  if ((rc = qr_factor(w.X, eta, mL, eta, dt, qw, s))) return rc;
-  if ((rc = qr_form_q(w.X, eta, mL, eta, dt, qw, s))) return rc;
+  std::vector<QrJob> qj(nc);
+  for (int i = 0; i < nc; ++i) {
+    const BondShape& b = calls[i].b;
+    qj[i] = QrJob{W[i].X, b.eta, b.d * b.chi_l, b.eta, W[i].X, b.eta, b.eta, &QW[i]};
+  }
+  if ((rc = qr_factor_batch(qj.data(), nc, dt, s))) return rc;
+  if ((rc = qr_form_q_batch(qj.data(), nc, dt, s))) return rc;
   // Y^dag = theta~^dag Q^[m], then Y^dag = Q' R'
-  if ((rc = timed_gemm(tm, gemm_prob(w.Th, mR, OP_C, w.X, eta, OP_N, w.YH, eta, mR, eta, mL), ty, s))) return rc;
-  if ((rc = qr_factor(w.YH, eta, mR, eta, dt, qw, s))) return rc;
-  {
+  g.clear();
+  for (int i = 0; i < nc; ++i) {
+    const BondShape& b = calls[i].b;
+    const int mL = b.d * b.chi_l, mR = b.d * b.chi_r, eta = b.eta;
+    g.push_back(gemm_prob(W[i].Th, mR, OP_C, W[i].X, eta, OP_N, W[i].YH, eta, mR, eta, mL));
+  }
+  if ((rc = timed_gemm_batch(tm, g.data(), nc, ty, s))) return rc;
+  for (int i = 0; i < nc; ++i) {
+    const BondShape& b = calls[i].b;
+    qj[i] = QrJob{W[i].YH, b.eta, b.d * b.chi_r, b.eta, W[i].YH, b.eta, b.eta, &QW[i]};
+  }
+  if ((rc = qr_factor_batch(qj.data(), nc, dt, s))) return rc;
+  for (int i = 0; i < nc; ++i) {
+    const int eta = calls[i].b.eta;
     const long long n = (long long)eta * eta;
-    hipLaunchKernelGGL(extract_r_kernel<S>, dim3(grid_for(n)), dim3(256), 0, s, (const cpx<S>*)w.YH, eta,
-                       (cpx<S>*)w.R);
+    hipLaunchKernelGGL(extract_r_kernel<S>, dim3(grid_for(n)), dim3(256), 0, s, (const cpx<S>*)W[i].YH, eta,
+                       (cpx<S>*)W[i].R);
     QT_HIP_CHECK(hipGetLastError());
   }
-  if ((rc = qr_form_q(w.YH, eta, mR, eta, dt, qw, s))) return rc;
+  if ((rc = qr_form_q_batch(qj.data(), nc, dt, s))) return rc;
 
-  if (cbe) {
-    // L^dag L = R' R'^dag in FP64
-    if ((rc = gemm_one(gemm_prob(w.R, eta, OP_N, w.R, eta, OP_C, w.G, eta, eta, eta, eta), GemmTypes{dt, DT_C128}, s)))
-      return rc;
-    EigWork ew = eig_work_carve(w.eigw, eta, status);
-    if ((rc = eig_herm_top(w.G, eta, kw, w.lam, w.E, ew, s))) return rc;
-    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, s, w.lam, kw, b.svd_min, w.norm2, chi_new,
-                       (double*)xi_n_out, w.kept2, eps, status);
-    QT_HIP_CHECK(hipGetLastError());
-    const void* Eu = w.E;
-    if (mixed) {
-      const long long n = (long long)eta * kw;
-      hipLaunchKernelGGL((cast_kernel<float, double>), dim3(grid_for(n)), dim3(256), 0, s, w.E, n, (c64*)w.Ec);
-      QT_HIP_CHECK(hipGetLastError());
-      Eu = w.Ec;
+  // CBE: L^dag L = R' R'^dag in FP64, eigen-decomposition, selection
+  std::vector<int> cb;
+  for (int i = 0; i < nc; ++i)
+    if (calls[i].b.mode == 2) cb.push_back(i);
+  if (!cb.empty()) {
+    g.clear();
+    std::vector<EigJob> ej;
+    std::vector<EigWork> ew(nc);
+    for (int i : cb) {
+      const int eta = calls[i].b.eta;
+      g.push_back(gemm_prob(W[i].R, eta, OP_N, W[i].R, eta, OP_C, W[i].G, eta, eta, eta, eta));
+      ew[i] = eig_work_carve(W[i].eigw, eta, calls[i].status);
     }
-    // B~^[n] = E_kept^dag Q'^dag  (chi~ x d chi_r)
-    GemmProb g = gemm_prob(Eu, kw, OP_C, w.YH, eta, OP_C, b_n_out, mR, kw, mR, eta);
-    g.dM = chi_new;
-    if ((rc = timed_gemm(tm, g, ty, s))) return rc;
-  } else {
+    if ((rc = gemm_run(g.data(), (int)g.size(), GemmTypes{dt, DT_C128}, s))) return rc;
+    for (int i : cb) ej.push_back(EigJob{W[i].G, calls[i].b.eta, kwant_of(calls[i].b), W[i].lam, W[i].E, &ew[i]});
+    if ((rc = eig_herm_top_batch(ej.data(), (int)ej.size(), s))) return rc;
+    g.clear();
+    for (int i : cb) {
+      const BondCall& c = calls[i];
+      const int kw = kwant_of(c.b), eta = c.b.eta, mR = c.b.d * c.b.chi_r;
+      hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, s, W[i].lam, kw, c.b.svd_min, W[i].norm2, c.chi_new,
+                         (double*)c.xi_n_out, W[i].kept2, c.eps, c.status);
+      QT_HIP_CHECK(hipGetLastError());
+      const void* Eu = W[i].E;
+      if (mixed) {
+        const long long n = (long long)eta * kw;
+        hipLaunchKernelGGL((cast_kernel<float, double>), dim3(grid_for(n)), dim3(256), 0, s, W[i].E, n, (c64*)W[i].Ec);
+        QT_HIP_CHECK(hipGetLastError());
+        Eu = W[i].Ec;
+      }
+      // B~^[n] = E_kept^dag Q'^dag  (chi~ x d chi_r)
+      GemmProb gp = gemm_prob(Eu, kw, OP_C, W[i].YH, eta, OP_C, c.b_n_out, mR, kw, mR, eta);
+      gp.dM = c.chi_new;
+      g.push_back(gp);
+    }
+    if ((rc = timed_gemm_batch(tm, g.data(), (int)g.size(), ty, s))) return rc;
+  }
+  // plain / grow: Xi~ = L/|L|, B~^[n] = Q'^dag
+  for (int i = 0; i < nc; ++i) {
+    const BondCall& c = calls[i];
+    if (c.b.mode == 2) continue;
+    const int eta = c.b.eta, mR = c.b.d * c.b.chi_r;
     const long long n = (long long)eta * eta;
-    hipLaunchKernelGGL(sumsq_kernel<S>, dim3(1024), dim3(256), 0, s, (const cpx<S>*)w.R, n, w.partial);
+    hipLaunchKernelGGL(sumsq_kernel<S>, dim3(1024), dim3(256), 0, s, (const cpx<S>*)W[i].R, n, W[i].partial);
     QT_HIP_CHECK(hipGetLastError());
-    if ((rc = reduce_partials(w.partial, 1024, w.kept2, s))) return rc;
-    hipLaunchKernelGGL(plain_xi_kernel<S>, dim3(grid_for(n)), dim3(256), 0, s, (const cpx<S>*)w.R, eta, w.kept2,
-                       (c128*)xi_n_out);
+    if ((rc = reduce_partials(W[i].partial, 1024, W[i].kept2, s))) return rc;
+    hipLaunchKernelGGL(plain_xi_kernel<S>, dim3(grid_for(n)), dim3(256), 0, s, (const cpx<S>*)W[i].R, eta, W[i].kept2,
+                       (c128*)c.xi_n_out);
     QT_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(plain_finish_kernel, dim3(1), dim3(1), 0, s, eta, w.norm2, w.kept2, chi_new, eps, status);
+    hipLaunchKernelGGL(plain_finish_kernel, dim3(1), dim3(1), 0, s, eta, W[i].norm2, W[i].kept2, c.chi_new, c.eps,
+                       c.status);
     QT_HIP_CHECK(hipGetLastError());
-    // B~^[n] = Q^[n] = Q'^dag
     const dim3 grid((eta + 31) / 32, (mR + 31) / 32);
-    hipLaunchKernelGGL(transpose_conj_kernel<S>, grid, dim3(256), 0, s, (const cpx<S>*)w.YH, mR, eta,
-                       (cpx<S>*)b_n_out);
+    hipLaunchKernelGGL(transpose_conj_kernel<S>, grid, dim3(256), 0, s, (const cpx<S>*)W[i].YH, mR, eta,
+                       (cpx<S>*)c.b_n_out);
     QT_HIP_CHECK(hipGetLastError());
   }
   if (mixed) {
     // one re-orthogonalisation step of B~^[n] with B B^dag accumulated in FP64
-    GemmProb g2 = gemm_prob(b_n_out, mR, OP_N, b_n_out, mR, OP_C, w.G2, cap, cap, cap, mR);
-    g2.dM = chi_new;
-    g2.dN = chi_new;
-    if ((rc = gemm_one(g2, GemmTypes{DT_C64, DT_C128}, s))) return rc;
-    hipLaunchKernelGGL(reorth_prep_kernel, dim3(grid_for((long long)cap * cap)), dim3(256), 0, s, w.G2, cap, chi_new,
-                       (c64*)w.Dc);
-    QT_HIP_CHECK(hipGetLastError());
-    QT_HIP_CHECK(hipMemcpyAsync(w.tmp, b_n_out, (size_t)cap * mR * sizeof(cpx<S>), hipMemcpyDeviceToDevice, s));
-    GemmProb g3 = gemm_prob(w.Dc, cap, OP_N, w.tmp, mR, OP_N, b_n_out, mR, cap, mR, cap, -1.f, 1.f);
-    g3.dM = chi_new;
-    g3.dK = chi_new;
-    if ((rc = gemm_one(g3, ty, s))) return rc;
+    g.clear();
+    for (int i = 0; i < nc; ++i) {
+      const BondCall& c = calls[i];
+      const int cap = c.b.cap(), mR = c.b.d * c.b.chi_r;
+      GemmProb g2 = gemm_prob(c.b_n_out, mR, OP_N, c.b_n_out, mR, OP_C, W[i].G2, cap, cap, cap, mR);
+      g2.dM = c.chi_new;
+      g2.dN = c.chi_new;
+      g.push_back(g2);
+    }
+    if ((rc = gemm_run(g.data(), nc, GemmTypes{DT_C64, DT_C128}, s))) return rc;
+    g.clear();
+    for (int i = 0; i < nc; ++i) {
+      const BondCall& c = calls[i];
+      const int cap = c.b.cap(), mR = c.b.d * c.b.chi_r;
+      hipLaunchKernelGGL(reorth_prep_kernel, dim3(grid_for((long long)cap * cap)), dim3(256), 0, s, W[i].G2, cap,
+                         c.chi_new, (c64*)W[i].Dc);
+      QT_HIP_CHECK(hipGetLastError());
+      QT_HIP_CHECK(hipMemcpyAsync(W[i].tmp, c.b_n_out, (size_t)cap * mR * sizeof(cpx<S>), hipMemcpyDeviceToDevice, s));
+      GemmProb g3 = gemm_prob(W[i].Dc, cap, OP_N, W[i].tmp, mR, OP_N, c.b_n_out, mR, cap, mR, cap, -1.f, 1.f);
+      g3.dM = c.chi_new;
+      g3.dK = c.chi_new;
+      g.push_back(g3);
+    }
+    if ((rc = gemm_run(g.data(), nc, ty, s))) return rc;
   }
   // B~^[m] = C~ B~^[n]^dag  (chi_l d x chi~, compact with the live chi~)
-  {
-    GemmProb g = gemm_prob(w.C, mR, OP_N, b_n_out, mR, OP_C, b_m_out, cap, mL, cap, mR);
-    g.dN = chi_new;
-    g.ldc_live_N = 1;
-    if ((rc = timed_gemm(tm, g, ty, s))) return rc;
+  g.clear();
+  for (int i = 0; i < nc; ++i) {
+    const BondCall& c = calls[i];
+    const int cap = c.b.cap(), mL = c.b.d * c.b.chi_l, mR = c.b.d * c.b.chi_r;
+    GemmProb gp = gemm_prob(W[i].C, mR, OP_N, c.b_n_out, mR, OP_C, c.b_m_out, cap, mL, cap, mR);
+    gp.dN = c.chi_new;
+    gp.ldc_live_N = 1;
+    g.push_back(gp);
   }
-  return 0;
+  return timed_gemm_batch(tm, g.data(), nc, ty, s);
 }
 
 }  // namespace
+
+int timed_gemm_batch(KernelTimer* t, const GemmProb* p, int n, GemmTypes ty, hipStream_t s) {
+  if (!t || !t->on || t->n >= t->cap) return gemm_run(p, n, ty, s, true);
+  const int i = t->n++;
+  double fl = 0;
+  for (int k = 0; k < n; ++k) fl += 8.0 * (double)p[k].M * (double)p[k].N * (double)p[k].K;
+  t->flops[i] = fl;
+  QT_HIP_CHECK(hipEventRecord(t->ev[2 * i], s));
+  int rc = gemm_run(p, n, ty, s, true);
+  if (rc) return rc;
+  QT_HIP_CHECK(hipEventRecord(t->ev[2 * i + 1], s));
+  return 0;
+}
 
 int timed_gemm(KernelTimer* t, const GemmProb& p, GemmTypes ty, hipStream_t s) {
   if (!t || !t->on || t->n >= t->cap) return gemm_one(p, ty, s, true);
@@ -388,12 +467,19 @@ int reduce_partials(const double* part, int n, double* out, hipStream_t s) {
 
 size_t bond_work_bytes(const BondShape& b) { return carve(b, nullptr).total + 256; }
 
+int bond_update_batch(const BondCall* calls, int n, hipStream_t s, KernelTimer* timer) {
+  if (n <= 0) return 0;
+  const int prec = calls[0].b.prec;
+  for (int i = 1; i < n; ++i)
+    if (calls[i].b.prec != prec) return set_error(-1, "bond_update_batch: mixed precisions in one batch");
+  return prec == 0 ? run_batch<double>(calls, n, s, timer) : run_batch<float>(calls, n, s, timer);
+}
+
 int bond_update_run(const BondShape& b, void* ws, int* status, const void* xi_m, const void* b_m, const void* b_n,
                     const c128* u, void* b_m_out, void* xi_n_out, void* b_n_out, int* chi_new, double* eps,
                     hipStream_t s, KernelTimer* timer) {
-  if (b.prec == 0)
-    return run_typed<double>(b, ws, status, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, chi_new, eps, s, timer);
-  return run_typed<float>(b, ws, status, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, chi_new, eps, s, timer);
+  BondCall c{b, ws, status, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, chi_new, eps};
+  return bond_update_batch(&c, 1, s, timer);
 }
 
 }  // namespace qrtebd

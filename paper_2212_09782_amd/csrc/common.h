@@ -93,13 +93,15 @@ struct GridSync {
   int* status;
 };
 
-__device__ inline bool grid_barrier(GridSync gs, unsigned gen, int nblk, int* smem_flag) {
+// blk / nblk: this block's index in its group and the group size (a launch
+// may host several independent groups, each with its own GridSync words).
+__device__ inline bool grid_barrier(GridSync gs, unsigned gen, int blk, int nblk, int* smem_flag) {
   constexpr long kSpinLimit = 1L << 22;
   if (threadIdx.x < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   unsigned* genw = gs.base;
   unsigned* flags = gs.base + 16;
-  if (blockIdx.x == 0) {
+  if (blk == 0) {
     for (int b = 1 + (int)threadIdx.x; b < nblk; b += blockDim.x) {
       long spins = 0;
       while (__hip_atomic_load(flags + 16 * b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
@@ -112,7 +114,7 @@ __device__ inline bool grid_barrier(GridSync gs, unsigned gen, int nblk, int* sm
       __hip_atomic_store(genw, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
   } else if (threadIdx.x == 0) {
-    __hip_atomic_store(flags + 16 * blockIdx.x, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(flags + 16 * blk, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     long spins = 0;
     while (__hip_atomic_load(genw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
       if (++spins > kSpinLimit) { *smem_flag = (int)gen; break; }

@@ -25,4 +25,15 @@ EigWork eig_work_carve(void* base, int n, int* status);
 // (row-major, ld kwant) with the matching orthonormal eigenvectors as columns.
 int eig_herm_top(c128* G, int n, int kwant, double* lam, c128* E, const EigWork& w, hipStream_t s);
 
+// The same for several matrices at once (tridiagonalisations share
+// cooperative launches, the small kernels and GEMMs are batched).
+struct EigJob {
+  c128* G;
+  int n, kwant;
+  double* lam;
+  c128* E;
+  const EigWork* w;
+};
+int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s);
+
 }  // namespace qrtebd

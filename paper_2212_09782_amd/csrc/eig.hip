@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 namespace qrtebd {
 namespace {
@@ -46,9 +47,10 @@ __device__ inline c128 rank2_sub(c128 x, c128 a, c128 b, c128 c, c128 d) {
   return mk<double>(x.re - re, x.im - im);
 }
 
-struct TriArgs {
+// One matrix of a batched tridiagonalisation launch: its blocks are
+// [blk0, blk0 + nblk) of the grid and synchronise among themselves only.
+struct TriProb {
   const c128* G;
-  int n, rows_loc;
   double* d;
   double* e;
   c128* tau;
@@ -56,7 +58,14 @@ struct TriArgs {
   c128* pbuf;     // [2][n]
   c128* rowbuf;   // [2][n]
   c128* red;      // [2][nblk]
-  GridSync gs;
+  unsigned* sync;
+  int n, rows_loc, nblk, blk0;
+};
+constexpr int kMaxTriProbs = 16;
+struct TriBatch {
+  int nprob;
+  int* status;
+  TriProb p[kMaxTriProbs];
 };
 
 // Fixed-order block sum of a complex value (every thread gets the result).
@@ -72,7 +81,7 @@ __device__ inline c128 block_sum_c(c128 v, c128* scr) {
   return s;
 }
 
-__global__ __launch_bounds__(256) void tridiag_kernel(TriArgs a) {
+__global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
   extern __shared__ c128 rows[];  // rows_loc x n, local row r = global row blk + r * P
   __shared__ double scratch[8];
   __shared__ c128 cscr[8];
@@ -81,7 +90,11 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriArgs a) {
   __shared__ c128 scal[4];
   __shared__ int flag;
 
-  const int n = a.n, P = gridDim.x, blk = blockIdx.x, tid = threadIdx.x;
+  int pi = 0;
+  while (pi + 1 < batch.nprob && (int)blockIdx.x >= batch.p[pi + 1].blk0) ++pi;
+  const TriProb& a = batch.p[pi];
+  const GridSync gs{a.sync, batch.status};
+  const int n = a.n, P = a.nblk, blk = (int)blockIdx.x - a.blk0, tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int RL = a.rows_loc;
   const int mqr = n - 1;
@@ -101,6 +114,12 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriArgs a) {
   }
   if (tid == 0) flag = 0;
   __syncthreads();
+  // row k+1 is published by its owner's wave 0 as soon as it is final for
+  // step k (here for k = 0), long before step k's barrier
+  if (n > 1 && 1 % P == blk && wid == 0) {
+    const int r = 1 / P;
+    for (int j = lane; j < n; j += 64) a.rowbuf[j] = rows[r * n + j];
+  }
 
   for (int k = 0; k < n - 1; ++k) {
     const int slot = k & 1;
@@ -129,7 +148,7 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriArgs a) {
       a.d[k] = scal[1].re;
       a.e[k] = beta;
       a.tau[k] = tau;
-      if (!isfinite(beta) || !isfinite(scal[1].re)) latch_error(a.gs.status, ERRBIT_NONFINITE);
+      if (!isfinite(beta) || !isfinite(scal[1].re)) latch_error(batch.status, ERRBIT_NONFINITE);
     }
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
@@ -142,15 +161,15 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriArgs a) {
       const int j = tid + 256 * q;
       if (j < n && j % P == blk) vloc[j / P] = v[q];
     }
-    // reflector k into the QR-compatible layout: subproblem row i <-> row i+1
-    // (read only by later kernels: no publication needed)
-    if (blk == k % P) {
+    // reflector k into the QR-compatible layout (subproblem row i <-> row i+1):
+    // each block writes the rows it owns; read only by later kernels
+    {
       const int p = k / NB, c = k % NB, j0 = p * NB;
       c128* Vp = a.V + (size_t)p * mqr * NB;
 #pragma unroll
       for (int q = 0; q < QMAX; ++q) {
         const int g = tid + 256 * q;  // global row
-        if (g >= j0 + 1 && g < n) Vp[(long long)(g - 1 - j0) * NB + c] = g >= k + 1 ? v[q] : z0();
+        if (g >= j0 + 1 && g < n && g % P == blk) Vp[(long long)(g - 1 - j0) * NB + c] = g >= k + 1 ? v[q] : z0();
       }
     }
     // ---- p_i = tau sum_{j>k} A[i][j] v_j for own rows i > k
@@ -188,12 +207,8 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriArgs a) {
       part.re = wave_sum(part.re);
       part.im = wave_sum(part.im);
       if (lane == 0) a.red[(long long)slot * P + blk] = part;
-      if ((k + 1) % P == blk) {
-        const int r = (k + 1) / P;
-        for (int j = lane; j < n; j += 64) a.rowbuf[(long long)slot * n + j] = rows[r * n + j];
-      }
     }
-    if (!grid_barrier(a.gs, (unsigned)(k + 1), P, &flag)) return;
+    if (!grid_barrier(gs, (unsigned)(k + 1), blk, P, &flag)) return;
     // ---- one round of loads: block partials, p, and row k+1 as published
     const c128 rv = tid < P ? a.red[(long long)slot * P + tid] : z0();
     c128 pv[QMAX], xb[QMAX];
@@ -236,6 +251,11 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriArgs a) {
       }
     }
     __syncthreads();
+    // publish row k+2 (final for step k+1) into the other slot
+    if (k + 2 < n && (k + 2) % P == blk && wid == 0) {
+      const int r = (k + 2) / P;
+      for (int j = lane; j < n; j += 64) a.rowbuf[(long long)((k + 1) & 1) * n + j] = rows[r * n + j];
+    }
   }
   // d[n-1] from the thread holding column n-1 of the final row
   if (blk == 0) {
@@ -302,8 +322,32 @@ __device__ inline void gersh(const double* d, const double* e2, int n, double* s
 // lam[j] = (j+1)-th largest eigenvalue, j < kwant.  Multisection: the 8 lanes
 // of a group evaluate 8 interior points of the eigenvalue's interval per
 // round, shrinking it 9-fold; 22 rounds reach full FP64 resolution.
-__global__ __launch_bounds__(256) void bisect_kernel(const double* d, const double* e, int n, int kwant,
-                                                     double* lam) {
+struct SmallJob {
+  const double* d;
+  const double* e;
+  double* lam;
+  double* lu;
+  unsigned char* swp;
+  c128* E;
+  c128* V;
+  c128* VT;
+  c128* T;
+  const c128* tau;
+  int n, kwant;
+};
+constexpr int kMaxSmallJobs = 24;
+struct SmallBatch {
+  int njobs;
+  SmallJob j[kMaxSmallJobs];
+};
+
+__global__ __launch_bounds__(256) void bisect_kernel(SmallBatch sb) {
+  const SmallJob& J = sb.j[blockIdx.y];
+  const double* d = J.d;
+  const double* e = J.e;
+  const int n = J.n, kwant = J.kwant;
+  double* lam = J.lam;
+  if ((int)blockIdx.x * 32 >= kwant) return;
   __shared__ double sd[kMaxN], se2[kMaxN];
   __shared__ double scr[12];
   for (int i = threadIdx.x; i < n; i += 256) {
@@ -344,8 +388,16 @@ __device__ inline double hash_uniform(unsigned long long x) {
 // Inverse iteration for eigenvalue lam[j]: E[:, j] (real, stored complex).
 // lu: [4][n][kwant] (pivot row entries u0, u1, u2 and the multiplier),
 // swp: [n][kwant] row-interchange flags; T = (d, e) staged in LDS.
-__global__ __launch_bounds__(64) void invit_kernel(const double* d, const double* e, int n, int kwant,
-                                                   const double* lam, double* lu, unsigned char* swp, c128* E) {
+__global__ __launch_bounds__(64) void invit_kernel(SmallBatch sb) {
+  const SmallJob& J = sb.j[blockIdx.y];
+  const double* d = J.d;
+  const double* e = J.e;
+  const int n = J.n, kwant = J.kwant;
+  const double* lam = J.lam;
+  double* lu = J.lu;
+  unsigned char* swp = J.swp;
+  c128* E = J.E;
+  if ((int)blockIdx.x * 64 >= kwant) return;
   __shared__ double sd[kMaxN], se[kMaxN];
   for (int i = threadIdx.x; i < n; i += 64) {
     sd[i] = d[i];
@@ -424,10 +476,17 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
 
 // T_p and V_p T_p for every panel of the tridiagonalisation reflectors;
 // V_p is staged through LDS in 64-row slabs.
-__global__ __launch_bounds__(256) void larft_kernel(c128* V, c128* VT, c128* T, const c128* tau, int m, int nrefl) {
+__global__ __launch_bounds__(256) void larft_kernel(SmallBatch sb) {
   __shared__ c128 slab[64][NB + 1];
   __shared__ c128 Tm[NB][NB + 1];
+  const SmallJob& J = sb.j[blockIdx.y];
+  c128* V = J.V;
+  c128* VT = J.VT;
+  c128* T = J.T;
+  const c128* tau = J.tau;
+  const int m = J.n - 1, nrefl = J.n - 1;
   const int p = blockIdx.x, tid = threadIdx.x;
+  if (p * NB >= nrefl) return;
   const int j0 = p * NB, jb = min(NB, nrefl - j0), mp = m - j0;
   const c128* Vp = V + (size_t)p * m * NB;
   c128 g[4];
@@ -481,9 +540,14 @@ __global__ __launch_bounds__(256) void larft_kernel(c128* V, c128* VT, c128* T, 
 // Two-pass modified Gram-Schmidt over each cluster of close eigenvalues
 // (lam descending; a cluster starts where the gap to the previous value
 // exceeds rtol * max|lam|).  Block b handles the cluster starting at column b, if any.
-__global__ __launch_bounds__(256) void cluster_mgs_kernel(c128* Z, const double* lam, int n, int kw, double rtol) {
+__global__ __launch_bounds__(256) void cluster_mgs_kernel(SmallBatch sb, double rtol) {
   __shared__ double scr[8];
+  const SmallJob& J = sb.j[blockIdx.y];
+  c128* Z = J.E;
+  const double* lam = J.lam;
+  const int n = J.n, kw = J.kwant;
   const int j = blockIdx.x;
+  if (j >= kw) return;
   const double ctol = rtol * fmax(fabs(lam[0]), fabs(lam[kw - 1]));
   if (j > 0 && lam[j - 1] - lam[j] <= ctol) return;
   int e = j;
@@ -558,68 +622,139 @@ EigWork eig_work_carve(void* base, int n, int* status) {
   return w;
 }
 
-int eig_herm_top(c128* G, int n, int kwant, double* lam, c128* E, const EigWork& w, hipStream_t s) {
-  if (n < 1 || kwant < 1 || kwant > n) return set_error(-1, "eig: bad sizes n=%d kwant=%d", n, kwant);
-  if (n > kMaxN) return set_error(-2, "eig: n=%d exceeds the supported %d", n, kMaxN);
-  if (n == 1) {
-    hipLaunchKernelGGL(eig1_kernel, dim3(1), dim3(1), 0, s, G, lam, E);
-    QT_HIP_CHECK(hipGetLastError());
-    return 0;
-  }
-  const int RL = tri_rows_loc(n);
-  const int P = (n + RL - 1) / RL;
-  if (P > 256) return set_error(-2, "eig: n=%d needs %d blocks", n, P);
-  int rc = fill_zero(w.sync, grid_sync_words(P) * 4, s);
-  if (rc) return rc;
-  // reflector V must be zero where the kernel writes nothing (rows above each panel's start)
-  const int mqr = n - 1;
-  const int npan = (mqr + NB - 1) / NB;
-  if ((rc = fill_zero(w.qtri.V, (size_t)npan * mqr * NB * 16, s))) return rc;
-  TriArgs ta{};
-  ta.G = G;
-  ta.n = n;
-  ta.rows_loc = RL;
-  ta.d = w.d;
-  ta.e = w.e;
-  ta.tau = w.tau;
-  ta.V = (c128*)w.qtri.V;
-  ta.red = w.red;
-  ta.pbuf = w.red + 2 * 257;
-  ta.rowbuf = ta.pbuf + 2 * (size_t)n;
-  ta.gs = GridSync{w.sync, w.status};
-  const size_t shmem = (size_t)RL * n * sizeof(c128);
+int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
+  int rc;
   static bool attr = false;
   if (!attr) {
     QT_HIP_CHECK(hipFuncSetAttribute((const void*)tridiag_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)kTriLds));
     attr = true;
   }
-  void* args[] = {(void*)&ta};
-  QT_HIP_CHECK(hipLaunchCooperativeKernel((const void*)tridiag_kernel, dim3(P), dim3(256), args, (unsigned)shmem, s));
-  hipLaunchKernelGGL(larft_kernel, dim3(npan), dim3(256), 0, s, (c128*)w.qtri.V, (c128*)w.qtri.VT, w.qtri.T,
-                     w.tau, mqr, mqr);
-  QT_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(bisect_kernel, dim3((kwant + 31) / 32), dim3(256), 0, s, w.d, w.e, n, kwant, lam);
-  QT_HIP_CHECK(hipGetLastError());
-  unsigned char* swp = (unsigned char*)((char*)w.lu + align256(4 * (size_t)n * n * 8));
-  hipLaunchKernelGGL(invit_kernel, dim3((kwant + 63) / 64), dim3(64), 0, s, w.d, w.e, n, kwant, lam, w.lu, swp, E);
-  QT_HIP_CHECK(hipGetLastError());
-  // orthonormalise the eigenvector block (clustered MGS, Newton-Schulz), then E = Q Z
-  hipLaunchKernelGGL(cluster_mgs_kernel, dim3(kwant), dim3(256), 0, s, E, lam, n, kwant, 1e-9);
-  QT_HIP_CHECK(hipGetLastError());
-  for (int it = 0; it < 2; ++it) {
-    const GemmTypes ty{DT_C128, DT_C128};
-    if ((rc = gemm_one(gemm_prob(E, kwant, OP_C, E, kwant, OP_N, w.gz, kwant, kwant, kwant, n), ty, s))) return rc;
-    hipLaunchKernelGGL(sub_identity_kernel, dim3(std::min(4096, (kwant * kwant + 255) / 256)), dim3(256), 0, s, w.gz,
-                       kwant);
-    QT_HIP_CHECK(hipGetLastError());
-    QT_HIP_CHECK(hipMemcpyAsync(w.ztmp, E, (size_t)n * kwant * sizeof(c128), hipMemcpyDeviceToDevice, s));
-    if ((rc = gemm_one(gemm_prob(w.ztmp, kwant, OP_N, w.gz, kwant, OP_N, E, kwant, n, kwant, kwant, -0.5f, 1.f), ty,
-                       s)))
-      return rc;
+  // validation, 1 x 1 problems, barrier words and reflector buffers
+  std::vector<int> big;
+  for (int j = 0; j < njobs; ++j) {
+    const EigJob& J = jobs[j];
+    if (J.n < 1 || J.kwant < 1 || J.kwant > J.n) return set_error(-1, "eig: bad sizes n=%d kwant=%d", J.n, J.kwant);
+    if (J.n > kMaxN) return set_error(-2, "eig: n=%d exceeds the supported %d", J.n, kMaxN);
+    if (J.n == 1) {
+      hipLaunchKernelGGL(eig1_kernel, dim3(1), dim3(1), 0, s, J.G, J.lam, J.E);
+      QT_HIP_CHECK(hipGetLastError());
+      continue;
+    }
+    const int RL = tri_rows_loc(J.n), P = (J.n + RL - 1) / RL;
+    if (P > 256) return set_error(-2, "eig: n=%d needs %d blocks", J.n, P);
+    if ((rc = fill_zero(J.w->sync, grid_sync_words(P) * 4, s))) return rc;
+    const int mqr = J.n - 1, npan = (mqr + NB - 1) / NB;
+    if ((rc = fill_zero(J.w->qtri.V, (size_t)npan * mqr * NB * 16, s))) return rc;
+    big.push_back(j);
   }
-  if ((rc = qr_apply_q(E + kwant, kwant, kwant, mqr, mqr, DT_C128, w.qtri, s))) return rc;
-  return 0;
+  if (big.empty()) return 0;
+  // 1. tridiagonalisations, packed into cooperative launches of <= 256 blocks
+  {
+    TriBatch tb{};
+    int used = 0;
+    size_t shmem = 0;
+    auto flush = [&]() -> int {
+      if (tb.nprob == 0) return 0;
+      void* args[] = {(void*)&tb};
+      QT_HIP_CHECK(hipLaunchCooperativeKernel((const void*)tridiag_kernel, dim3(used), dim3(256), args,
+                                              (unsigned)shmem, s));
+      tb = TriBatch{};
+      used = 0;
+      shmem = 0;
+      return 0;
+    };
+    for (int j : big) {
+      const EigJob& J = jobs[j];
+      const int RL = tri_rows_loc(J.n), P = (J.n + RL - 1) / RL;
+      if (used + P > 256 || tb.nprob == kMaxTriProbs)
+        if ((rc = flush())) return rc;
+      TriProb& t = tb.p[tb.nprob++];
+      tb.status = J.w->status;
+      t.G = J.G;
+      t.n = J.n;
+      t.rows_loc = RL;
+      t.nblk = P;
+      t.blk0 = used;
+      t.d = J.w->d;
+      t.e = J.w->e;
+      t.tau = J.w->tau;
+      t.V = (c128*)J.w->qtri.V;
+      t.red = J.w->red;
+      t.pbuf = J.w->red + 2 * 257;
+      t.rowbuf = t.pbuf + 2 * (size_t)J.n;
+      t.sync = J.w->sync;
+      used += P;
+      shmem = std::max(shmem, (size_t)RL * J.n * sizeof(c128));
+    }
+    if ((rc = flush())) return rc;
+  }
+  // 2-5. larft, bisection, inverse iteration, clustered MGS (batched small kernels)
+  for (size_t j0 = 0; j0 < big.size(); j0 += kMaxSmallJobs) {
+    SmallBatch sb{};
+    int maxn = 0, maxk = 0;
+    for (size_t q = j0; q < std::min(big.size(), j0 + kMaxSmallJobs); ++q) {
+      const EigJob& J = jobs[big[q]];
+      SmallJob& S = sb.j[sb.njobs++];
+      S.d = J.w->d;
+      S.e = J.w->e;
+      S.lam = J.lam;
+      S.lu = J.w->lu;
+      S.swp = (unsigned char*)((char*)J.w->lu + align256(4 * (size_t)J.n * J.n * 8));
+      S.E = J.E;
+      S.V = (c128*)J.w->qtri.V;
+      S.VT = (c128*)J.w->qtri.VT;
+      S.T = J.w->qtri.T;
+      S.tau = J.w->tau;
+      S.n = J.n;
+      S.kwant = J.kwant;
+      maxn = std::max(maxn, J.n);
+      maxk = std::max(maxk, J.kwant);
+    }
+    const int npan = (maxn - 1 + NB - 1) / NB;
+    hipLaunchKernelGGL(larft_kernel, dim3(npan, sb.njobs), dim3(256), 0, s, sb);
+    QT_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(bisect_kernel, dim3((maxk + 31) / 32, sb.njobs), dim3(256), 0, s, sb);
+    QT_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(invit_kernel, dim3((maxk + 63) / 64, sb.njobs), dim3(64), 0, s, sb);
+    QT_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(cluster_mgs_kernel, dim3(maxk, sb.njobs), dim3(256), 0, s, sb, 1e-9);
+    QT_HIP_CHECK(hipGetLastError());
+  }
+  // 6. two Newton-Schulz steps Z <- Z - Z (Z^H Z - 1)/2, grouped over the jobs
+  const GemmTypes ty{DT_C128, DT_C128};
+  std::vector<GemmProb> gs;
+  for (int it = 0; it < 2; ++it) {
+    gs.clear();
+    for (int j : big) {
+      const EigJob& J = jobs[j];
+      gs.push_back(gemm_prob(J.E, J.kwant, OP_C, J.E, J.kwant, OP_N, J.w->gz, J.kwant, J.kwant, J.kwant, J.n));
+    }
+    if ((rc = gemm_run(gs.data(), (int)gs.size(), ty, s))) return rc;
+    gs.clear();
+    for (int j : big) {
+      const EigJob& J = jobs[j];
+      hipLaunchKernelGGL(sub_identity_kernel, dim3(std::min(4096, (J.kwant * J.kwant + 255) / 256)), dim3(256), 0, s,
+                         J.w->gz, J.kwant);
+      QT_HIP_CHECK(hipGetLastError());
+      QT_HIP_CHECK(hipMemcpyAsync(J.w->ztmp, J.E, (size_t)J.n * J.kwant * sizeof(c128), hipMemcpyDeviceToDevice, s));
+      gs.push_back(gemm_prob(J.w->ztmp, J.kwant, OP_N, J.w->gz, J.kwant, OP_N, J.E, J.kwant, J.n, J.kwant, J.kwant,
+                             -0.5f, 1.f));
+    }
+    if ((rc = gemm_run(gs.data(), (int)gs.size(), ty, s))) return rc;
+  }
+  // 7. back-transformation E = Q Z (rows 1.. of each E)
+  std::vector<QrJob> qj;
+  for (int j : big) {
+    const EigJob& J = jobs[j];
+    qj.push_back(QrJob{nullptr, 0, J.n - 1, J.n - 1, J.E + J.kwant, J.kwant, J.kwant, &J.w->qtri});
+  }
+  return qr_apply_q_batch(qj.data(), (int)qj.size(), DT_C128, s);
+}
+
+int eig_herm_top(c128* G, int n, int kwant, double* lam, c128* E, const EigWork& w, hipStream_t s) {
+  EigJob J{G, n, kwant, lam, E, &w};
+  return eig_herm_top_batch(&J, 1, s);
 }
 
 }  // namespace qrtebd

@@ -10,8 +10,12 @@
 // Tiling: a 256-thread workgroup owns a 64x64 output tile, each wave a 32x32
 // quadrant (2x2 MFMA blocks, separate real/imaginary accumulators).  Operand
 // tiles of depth 16 are staged through LDS in planar (re / im) k-major form so
-// that each MFMA operand is one conflict-light 8-byte LDS read per lane; the
-// next tile is prefetched into registers while the current one is consumed.
+// that each MFMA operand is one conflict-light LDS read per lane.  LDS is
+// double-buffered: the next tile is loaded from global memory into registers
+// and stored into the other buffer while the current one is consumed, so each
+// K stage needs one workgroup barrier.  Workgroup ids are remapped so that the
+// 8 XCDs (which take workgroups round-robin) each work on a contiguous range
+// of tiles and share operands in their own L2.
 #include "gemm.h"
 
 #include <algorithm>
@@ -42,10 +46,18 @@ template <typename Tin, typename Tout, typename Tc>
 __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   using MF = Mfma<Tc>;
   using v4 = typename MF::v4;
-  __shared__ Tc As[2][BK][BM + PAD];
-  __shared__ Tc Bs[2][BK][BN + PAD];
+  __shared__ Tc As[2][2][BK][BM + PAD];   // [buffer][re/im][k][m]
+  __shared__ Tc Bs[2][2][BK][BN + PAD];
 
-  const int bid = blockIdx.x;
+  // XCD-aware remap: hardware workgroup g runs on XCD g % 8; give XCD x the
+  // contiguous logical range [start_x, start_x + count_x)
+  int bid;
+  {
+    const int total = b.tile_start[b.nprob];
+    const int g = blockIdx.x, x = g & 7, loc = g >> 3;
+    const int q = total >> 3, r = total & 7;
+    bid = x < r ? x * (q + 1) + loc : r * (q + 1) + (x - r) * q + loc;
+  }
   int p = 0;
   while (p + 1 < b.nprob && bid >= b.tile_start[p + 1]) ++p;
   const GemmProb& P = b.p[p];
@@ -113,42 +125,45 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
       rb[e] = w;
     }
   };
-  auto store = [&]() {
+  auto store = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       if (opA == OP_N) {
-        As[0][colq + e][rowq] = (Tc)ra[e].re;
-        As[1][colq + e][rowq] = sa * (Tc)ra[e].im;
+        As[buf][0][colq + e][rowq] = (Tc)ra[e].re;
+        As[buf][1][colq + e][rowq] = sa * (Tc)ra[e].im;
       } else {
-        As[0][rowk][colk + e] = (Tc)ra[e].re;
-        As[1][rowk][colk + e] = sa * (Tc)ra[e].im;
+        As[buf][0][rowk][colk + e] = (Tc)ra[e].re;
+        As[buf][1][rowk][colk + e] = sa * (Tc)ra[e].im;
       }
       if (opB == OP_N) {
-        Bs[0][rowk][colk + e] = (Tc)rb[e].re;
-        Bs[1][rowk][colk + e] = sb * (Tc)rb[e].im;
+        Bs[buf][0][rowk][colk + e] = (Tc)rb[e].re;
+        Bs[buf][1][rowk][colk + e] = sb * (Tc)rb[e].im;
       } else {
-        Bs[0][colq + e][rowq] = (Tc)rb[e].re;
-        Bs[1][colq + e][rowq] = sb * (Tc)rb[e].im;
+        Bs[buf][0][colq + e][rowq] = (Tc)rb[e].re;
+        Bs[buf][1][colq + e][rowq] = sb * (Tc)rb[e].im;
       }
     }
   };
 
-  if (kbeg < kend) load(kbeg);
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  int buf = 0;
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    __syncthreads();
-    store();
-    __syncthreads();
-    if (k0 + BK < kend) load(k0 + BK);
+    const bool more = k0 + BK < kend;
+    if (more) load(k0 + BK);     // global -> registers, overlapping the MFMAs below
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
       Tc ar[2], ai[2], br[2], bi[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        ar[i] = As[0][kr][wm + i * 16 + (lane & 15)];
-        ai[i] = As[1][kr][wm + i * 16 + (lane & 15)];
-        br[i] = Bs[0][kr][wn + i * 16 + (lane & 15)];
-        bi[i] = Bs[1][kr][wn + i * 16 + (lane & 15)];
+        ar[i] = As[buf][0][kr][wm + i * 16 + (lane & 15)];
+        ai[i] = As[buf][1][kr][wm + i * 16 + (lane & 15)];
+        br[i] = Bs[buf][0][kr][wn + i * 16 + (lane & 15)];
+        bi[i] = Bs[buf][1][kr][wn + i * 16 + (lane & 15)];
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -160,6 +175,9 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
           acc_im[i][j] = MF::op(ai[i], br[j], acc_im[i][j]);
         }
     }
+    if (more) store(buf ^ 1);    // the other buffer was released by the previous barrier
+    __syncthreads();
+    buf ^= 1;
   }
 
   // epilogue

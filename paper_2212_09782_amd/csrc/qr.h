@@ -46,6 +46,22 @@ int qr_form_q(void* Q, long long ldq, int m, int n, int dt, const QrWork& w, hip
 // using the reflectors of a factorisation of an m x n matrix.
 int qr_apply_q(void* Z, long long ldz, int nz, int m, int n, int dt, const QrWork& w, hipStream_t s);
 
+// Batched forms: one job per matrix (all of type dt).  Panels of all jobs
+// share cooperative launches and their trailing updates share grouped GEMMs.
+//   factor: A (m x n, ld lda) in place;  form_q / apply_q: Z (m x nz, ld ldz).
+struct QrJob {
+  void* A;
+  long long lda;
+  int m, n;
+  void* Z;
+  long long ldz;
+  int nz;
+  const QrWork* w;
+};
+int qr_factor_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s);
+int qr_form_q_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s);
+int qr_apply_q_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s);
+
 // Helpers shared by the bond update.
 int fill_zero(void* p, size_t bytes, hipStream_t s);
 int set_identity(void* Q, long long ldq, int m, int n, int dt, hipStream_t s);

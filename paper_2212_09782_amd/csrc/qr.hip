@@ -19,23 +19,32 @@
 #include "qr.h"
 
 #include <algorithm>
+#include <vector>
 
 namespace qrtebd {
 namespace {
 
 constexpr int NB = kQrNb;
 
-struct PanelArgs {
+// One panel problem of a batched panel launch: its blocks are
+// [blk0, blk0 + nblk) of the grid and synchronise among themselves only.
+struct PanelProb {
   void* A;
   long long lda;
-  int m, jb, rows_per_blk;
   void* V;
   void* VT;
   void* VTh;
   c128* T;
   c128* red;
   c128* rowbuf;
-  GridSync gs;
+  unsigned* sync;
+  int m, jb, rows_per_blk, nblk, blk0, gen0;
+};
+constexpr int kMaxPanelProbs = 24;
+struct PanelBatch {
+  int nprob;
+  int* status;
+  PanelProb p[kMaxPanelProbs];
 };
 
 __device__ inline c128 cz() { return mk<double>(0, 0); }
@@ -44,7 +53,7 @@ constexpr int LDP = NB + 1;   // padded LDS row stride of the panel slab
 constexpr int kMaxPanelRows = 160;
 
 template <typename S>
-__global__ __launch_bounds__(256) void qr_panel_kernel(PanelArgs a) {
+__global__ __launch_bounds__(256) void qr_panel_kernel(PanelBatch batch) {
   extern __shared__ c128 P[];  // rows_per_blk x LDP
   __shared__ c128 part[8][NB];
   __shared__ c128 Sk[NB][NB + 1];   // per column k: V[:, j]^dag v_k for j < k (builds T after the loop)
@@ -53,7 +62,11 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelArgs a) {
   __shared__ c128 rowk[NB];
   __shared__ int flag;
 
-  const int tid = threadIdx.x, nblk = gridDim.x, blk = blockIdx.x;
+  int pi = 0;
+  while (pi + 1 < batch.nprob && (int)blockIdx.x >= batch.p[pi + 1].blk0) ++pi;
+  const PanelProb& a = batch.p[pi];
+  const GridSync gs{a.sync, batch.status};
+  const int tid = threadIdx.x, nblk = a.nblk, blk = (int)blockIdx.x - a.blk0;
   const int r0 = blk * a.rows_per_blk;
   const int nr = max(0, min(a.m, r0 + a.rows_per_blk) - r0);
   const int jb = a.jb;
@@ -85,7 +98,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelArgs a) {
       a.red[((long long)slot * nblk + blk) * NB + tid] = s;
       if (k >= r0 && k < r0 + nr) a.rowbuf[slot * NB + tid] = P[(k - r0) * LDP + tid];
     }
-    if (!grid_barrier(a.gs, (unsigned)(k + 1), nblk, &flag)) return;
+    if (!grid_barrier(gs, (unsigned)(a.gen0 + k + 1), blk, nblk, &flag)) return;
     {  // one round of loads: this thread's share of the block partials and row k
       const int bg = tid >> 5, c = tid & 31;
       constexpr int kMaxPer = kMaxPanelBlocks / 8;
@@ -119,7 +132,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelArgs a) {
     }
     if (tid == 0) {
       taus[k] = tau;
-      if (!isfinite(beta)) latch_error(a.gs.status, ERRBIT_NONFINITE);
+      if (!isfinite(beta)) latch_error(batch.status, ERRBIT_NONFINITE);
     }
     if (tid < k) {  // V[:, j]^dag v_k = conj(V[k, j]) + scale * conj(t_j)
       c128 tj = cz();
@@ -215,16 +228,16 @@ int panel_rows(int mp) {
 }
 
 template <typename S>
-int launch_panel(const PanelArgs& pa, int nblk, hipStream_t s) {
-  const size_t shmem = (size_t)pa.rows_per_blk * LDP * sizeof(c128);
+int launch_panel(const PanelBatch& pb, int nblk_total, int max_rows, hipStream_t s) {
+  const size_t shmem = (size_t)max_rows * LDP * sizeof(c128);
   static bool attr_set = false;
   if (!attr_set) {
     QT_HIP_CHECK(hipFuncSetAttribute((const void*)qr_panel_kernel<S>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, kMaxPanelRows * LDP * sizeof(c128)));
     attr_set = true;
   }
-  void* args[] = {(void*)&pa};
-  QT_HIP_CHECK(hipLaunchCooperativeKernel((const void*)qr_panel_kernel<S>, dim3(nblk), dim3(256), args,
+  void* args[] = {(void*)&pb};
+  QT_HIP_CHECK(hipLaunchCooperativeKernel((const void*)qr_panel_kernel<S>, dim3(nblk_total), dim3(256), args,
                                           (unsigned)shmem, s));
   return 0;
 }
@@ -291,87 +304,141 @@ QrWork qr_work_carve(void* base, int m, int n, int es, int wcols, int* status) {
   return w;
 }
 
-int qr_factor(void* A, long long lda, int m, int n, int dt, const QrWork& w, hipStream_t s) {
-  if (n > m || n <= 0) return set_error(-1, "qr_factor: need 0 < n <= m (m=%d n=%d)", m, n);
+// One panel step p of a batch of factorisations: the panel kernels (packed
+// into cooperative launches of at most kMaxPanelBlocks blocks) and then the
+// grouped trailing-update GEMMs of all jobs.
+static int factor_panel_step(const QrJob* jobs, int njobs, int p, int dt, hipStream_t s) {
   const int es = dt == DT_C128 ? 16 : 8;
-  const GemmTypes ty{dt, dt};
-  const int np = (n + NB - 1) / NB;
-  char* Ab = (char*)A;
-  for (int p = 0; p < np; ++p) {
-    const int j0 = p * NB, jb = std::min(NB, n - j0), mp = m - j0;
+  PanelBatch pb{};
+  int used = 0, max_rows = 0;
+  int rc;
+  auto flush = [&]() -> int {
+    if (pb.nprob == 0) return 0;
+    int r = dt == DT_C128 ? launch_panel<double>(pb, used, max_rows, s) : launch_panel<float>(pb, used, max_rows, s);
+    pb = PanelBatch{};
+    used = 0;
+    max_rows = 0;
+    return r;
+  };
+  std::vector<GemmProb> g1s, g2s;
+  for (int j = 0; j < njobs; ++j) {
+    const QrJob& J = jobs[j];
+    const int j0 = p * NB;
+    if (j0 >= J.n) continue;
+    const int jb = std::min(NB, J.n - j0), mp = J.m - j0;
     const int rows = panel_rows(mp);
     const int nblk = (mp + rows - 1) / rows;
     if (nblk > kMaxPanelBlocks) return set_error(-2, "qr_factor: panel of %d rows too tall", mp);
-    int rc = fill_zero(w.sync, grid_sync_words(nblk) * 4, s);
-    if (rc) return rc;
-    PanelArgs pa{};
-    pa.A = Ab + ((long long)j0 * lda + j0) * es;
-    pa.lda = lda;
-    pa.m = mp;
-    pa.jb = jb;
-    pa.rows_per_blk = rows;
-    const size_t voff = (size_t)p * m * NB * es;
-    pa.V = (char*)w.V + voff;
-    pa.VT = (char*)w.VT + voff;
-    pa.VTh = (char*)w.VTh + voff;
-    pa.T = w.T + (size_t)p * NB * NB;
-    pa.red = w.red;
-    pa.rowbuf = w.red + 2 * (size_t)kMaxPanelBlocks * NB;
-    pa.gs = GridSync{w.sync, w.status};
-    rc = dt == DT_C128 ? launch_panel<double>(pa, nblk, s) : launch_panel<float>(pa, nblk, s);
-    if (rc) return rc;
-    const int nt = n - j0 - jb;
+    if (used + nblk > kMaxPanelBlocks || pb.nprob == kMaxPanelProbs)
+      if ((rc = flush())) return rc;
+    const QrWork& w = *J.w;
+    PanelProb& pp = pb.p[pb.nprob++];
+    pb.status = w.status;
+    char* Ab = (char*)J.A;
+    pp.A = Ab + ((long long)j0 * J.lda + j0) * es;
+    pp.lda = J.lda;
+    const size_t voff = (size_t)p * J.m * NB * es;
+    pp.V = (char*)w.V + voff;
+    pp.VT = (char*)w.VT + voff;
+    pp.VTh = (char*)w.VTh + voff;
+    pp.T = w.T + (size_t)p * NB * NB;
+    pp.red = w.red;
+    pp.rowbuf = w.red + 2 * (size_t)kMaxPanelBlocks * NB;
+    pp.sync = w.sync;
+    pp.m = mp;
+    pp.jb = jb;
+    pp.rows_per_blk = rows;
+    pp.nblk = nblk;
+    pp.blk0 = used;
+    pp.gen0 = j0;   // generations keep increasing over the panels of one factorisation
+    used += nblk;
+    max_rows = std::max(max_rows, rows);
+    const int nt = J.n - j0 - jb;
     if (nt > 0) {
-      void* At = Ab + ((long long)j0 * lda + j0 + jb) * es;
-      GemmProb g1 = gemm_prob(pa.V, NB, OP_C, At, lda, OP_N, w.W, nt, jb, nt, mp);
+      void* At = Ab + ((long long)j0 * J.lda + j0 + jb) * es;
+      GemmProb g1 = gemm_prob(pp.V, NB, OP_C, At, J.lda, OP_N, w.W, nt, jb, nt, mp);
       g1.ksplit = splitk_for(jb, nt, mp);
       g1.work = w.Wsplit;
-      GemmProb g2 = gemm_prob(pa.VTh, NB, OP_N, w.W, nt, OP_N, At, lda, mp, nt, jb, -1.f, 1.f);
-      if ((rc = gemm_one(g1, ty, s))) return rc;
-      if ((rc = gemm_one(g2, ty, s))) return rc;
+      g1s.push_back(g1);
+      g2s.push_back(gemm_prob(pp.VTh, NB, OP_N, w.W, nt, OP_N, At, J.lda, mp, nt, jb, -1.f, 1.f));
     }
   }
+  if ((rc = flush())) return rc;
+  const GemmTypes ty{dt, dt};
+  if (!g1s.empty() && (rc = gemm_run(g1s.data(), (int)g1s.size(), ty, s))) return rc;
+  if (!g2s.empty() && (rc = gemm_run(g2s.data(), (int)g2s.size(), ty, s))) return rc;
   return 0;
+}
+
+int qr_factor_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s) {
+  int maxp = 0, rc;
+  for (int j = 0; j < njobs; ++j) {
+    const QrJob& J = jobs[j];
+    if (J.n > J.m || J.n <= 0) return set_error(-1, "qr_factor: need 0 < n <= m (m=%d n=%d)", J.m, J.n);
+    if (J.m > kMaxQrRows) return set_error(-2, "qr_factor: m=%d too large", J.m);
+    // barrier words are zeroed once per factorisation; generations increase over its panels
+    if ((rc = fill_zero(J.w->sync, grid_sync_words(kMaxPanelBlocks) * 4, s))) return rc;
+    maxp = std::max(maxp, (J.n + NB - 1) / NB);
+  }
+  for (int p = 0; p < maxp; ++p)
+    if ((rc = factor_panel_step(jobs, njobs, p, dt, s))) return rc;
+  return 0;
+}
+
+// Z_j := H_0 H_1 ... Z_j for every job (Z rows j0.. of each panel); set_id
+// first overwrites Z_j with [I; 0] (explicit Q).
+static int apply_batch(const QrJob* jobs, int njobs, int dt, bool set_id, hipStream_t s) {
+  const int es = dt == DT_C128 ? 16 : 8;
+  const GemmTypes ty{dt, dt};
+  int maxp = 0, rc;
+  for (int j = 0; j < njobs; ++j) {
+    const QrJob& J = jobs[j];
+    maxp = std::max(maxp, (J.n + NB - 1) / NB);
+    if (set_id && (rc = set_identity(J.Z, J.ldz, J.m, J.nz, dt, s))) return rc;
+    if (J.nz > J.w->wcols) return set_error(-1, "qr_apply_q: %d columns exceed the work size %d", J.nz, J.w->wcols);
+  }
+  std::vector<GemmProb> g1s, g2s;
+  for (int p = maxp - 1; p >= 0; --p) {
+    g1s.clear();
+    g2s.clear();
+    for (int j = 0; j < njobs; ++j) {
+      const QrJob& J = jobs[j];
+      const int j0 = p * NB;
+      if (j0 >= J.n) continue;
+      const int jb = std::min(NB, J.n - j0), mp = J.m - j0;
+      const int c0 = set_id ? j0 : 0;        // explicit Q: columns < j0 are still e_j
+      const int nz = J.nz - c0;
+      if (nz <= 0) continue;
+      const size_t voff = (size_t)p * J.m * NB * es;
+      void* Zs = (char*)J.Z + ((long long)j0 * J.ldz + c0) * es;
+      GemmProb g1 = gemm_prob((char*)J.w->V + voff, NB, OP_C, Zs, J.ldz, OP_N, J.w->W, nz, jb, nz, mp);
+      g1.ksplit = splitk_for(jb, nz, mp);
+      g1.work = J.w->Wsplit;
+      g1s.push_back(g1);
+      g2s.push_back(gemm_prob((char*)J.w->VT + voff, NB, OP_N, J.w->W, nz, OP_N, Zs, J.ldz, mp, nz, jb, -1.f, 1.f));
+    }
+    if (!g1s.empty() && (rc = gemm_run(g1s.data(), (int)g1s.size(), ty, s))) return rc;
+    if (!g2s.empty() && (rc = gemm_run(g2s.data(), (int)g2s.size(), ty, s))) return rc;
+  }
+  return 0;
+}
+
+int qr_form_q_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s) { return apply_batch(jobs, njobs, dt, true, s); }
+int qr_apply_q_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s) { return apply_batch(jobs, njobs, dt, false, s); }
+
+int qr_factor(void* A, long long lda, int m, int n, int dt, const QrWork& w, hipStream_t s) {
+  QrJob J{A, lda, m, n, A, lda, n, &w};
+  return qr_factor_batch(&J, 1, dt, s);
 }
 
 int qr_apply_q(void* Z, long long ldz, int nz, int m, int n, int dt, const QrWork& w, hipStream_t s) {
-  if (nz > w.wcols) return set_error(-1, "qr_apply_q: %d columns exceed the work size %d", nz, w.wcols);
-  const int es = dt == DT_C128 ? 16 : 8;
-  const GemmTypes ty{dt, dt};
-  const int np = (n + NB - 1) / NB;
-  for (int p = np - 1; p >= 0; --p) {
-    const int j0 = p * NB, jb = std::min(NB, n - j0), mp = m - j0;
-    const size_t voff = (size_t)p * m * NB * es;
-    void* Zs = (char*)Z + (long long)j0 * ldz * es;
-    GemmProb g1 = gemm_prob((char*)w.V + voff, NB, OP_C, Zs, ldz, OP_N, w.W, nz, jb, nz, mp);
-    g1.ksplit = splitk_for(jb, nz, mp);
-    g1.work = w.Wsplit;
-    GemmProb g2 = gemm_prob((char*)w.VT + voff, NB, OP_N, w.W, nz, OP_N, Zs, ldz, mp, nz, jb, -1.f, 1.f);
-    int rc;
-    if ((rc = gemm_one(g1, ty, s))) return rc;
-    if ((rc = gemm_one(g2, ty, s))) return rc;
-  }
-  return 0;
+  QrJob J{nullptr, 0, m, n, Z, ldz, nz, &w};
+  return qr_apply_q_batch(&J, 1, dt, s);
 }
 
 int qr_form_q(void* Q, long long ldq, int m, int n, int dt, const QrWork& w, hipStream_t s) {
-  const int es = dt == DT_C128 ? 16 : 8;
-  const GemmTypes ty{dt, dt};
-  int rc = set_identity(Q, ldq, m, n, dt, s);
-  if (rc) return rc;
-  const int np = (n + NB - 1) / NB;
-  for (int p = np - 1; p >= 0; --p) {
-    const int j0 = p * NB, jb = std::min(NB, n - j0), mp = m - j0, nq = n - j0;
-    const size_t voff = (size_t)p * m * NB * es;
-    void* Qs = (char*)Q + ((long long)j0 * ldq + j0) * es;
-    GemmProb g1 = gemm_prob((char*)w.V + voff, NB, OP_C, Qs, ldq, OP_N, w.W, nq, jb, nq, mp);
-    g1.ksplit = splitk_for(jb, nq, mp);
-    g1.work = w.Wsplit;
-    GemmProb g2 = gemm_prob((char*)w.VT + voff, NB, OP_N, w.W, nq, OP_N, Qs, ldq, mp, nq, jb, -1.f, 1.f);
-    if ((rc = gemm_one(g1, ty, s))) return rc;
-    if ((rc = gemm_one(g2, ty, s))) return rc;
-  }
-  return 0;
+  QrJob J{nullptr, 0, m, n, Q, ldq, n, &w};
+  return qr_form_q_batch(&J, 1, dt, s);
 }
 
 }  // namespace qrtebd
