@@ -73,54 +73,49 @@ __device__ inline double block_sum(double v, double* scratch) {
 }
 
 // ---------------------------------------------------------------- grid barrier
-// Flag barrier for cooperative launches: every block publishes its arrival
-// generation in its own cache line, block 0 gathers them and publishes the
-// generation word that all other blocks wait on.  Spins are bounded: on
-// timeout the error bit is latched and false is returned so the kernel can
-// leave.  base must hold 16*(nblocks+1) unsigned words, zeroed before the
-// launch; gen counts barriers from 1 within one launch.
-//
-// smem_flag: a block-shared int the kernel zeroes once before its first
-// barrier; a stalled barrier stores its generation there.
-//
-// Publication rule: global data that other blocks read after the barrier
-// must be written by wave 0 of the block (threads 0..63).  Only wave 0 runs
-// the device-scope release fence (an L2 write-back) before arriving and the
-// acquire fence (L1/L2 invalidate) after the wait; the block-wide barrier
-// that follows orders the other waves' later loads after it.
+// Barrier among the blocks of one group of a cooperative launch, without
+// cache write-back / invalidate fences:
+//  * data that other blocks read after the barrier is written with
+//    pub_store and read with pub_load (device-scope atomic accesses, which
+//    bypass the non-coherent caches), from any wave;
+//  * every wave waits until its own stores have completed, the block
+//    synchronises, thread 0 publishes its arrival generation in its own cache
+//    line, and the threads of every block poll all flags of the group.
+// Spins are bounded: on timeout the block's smem_flag records the generation,
+// the error bit is latched and false is returned so the kernel can leave.
+// base holds 16*(nblk+1) words zeroed before the first barrier; generations
+// must increase from one barrier to the next (they may continue across
+// launches that use the same words).  smem_flag: a block-shared int the
+// kernel zeroes once before its first barrier.
 struct GridSync {
   unsigned* base;
   int* status;
 };
 
-// blk / nblk: this block's index in its group and the group size (a launch
-// may host several independent groups, each with its own GridSync words).
+__device__ inline void pub_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double pub_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void pub_store(c128* p, c128 v) {
+  pub_store(&p->re, v.re);
+  pub_store(&p->im, v.im);
+}
+__device__ inline c128 pub_load(const c128* p) { return mk<double>(pub_load(&p->re), pub_load(&p->im)); }
+
 __device__ inline bool grid_barrier(GridSync gs, unsigned gen, int blk, int nblk, int* smem_flag) {
   constexpr long kSpinLimit = 1L << 22;
-  if (threadIdx.x < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  unsigned* genw = gs.base;
   unsigned* flags = gs.base + 16;
-  if (blk == 0) {
-    for (int b = 1 + (int)threadIdx.x; b < nblk; b += blockDim.x) {
-      long spins = 0;
-      while (__hip_atomic_load(flags + 16 * b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
-        if (++spins > kSpinLimit) { *smem_flag = (int)gen; break; }
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      __hip_atomic_store(genw, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  } else if (threadIdx.x == 0) {
-    __hip_atomic_store(flags + 16 * blk, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);   // this wave's published stores are complete
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flags + 16 * blk, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int b = (int)threadIdx.x; b < nblk; b += blockDim.x) {
     long spins = 0;
-    while (__hip_atomic_load(genw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+    while (__hip_atomic_load(flags + 16 * b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
       if (++spins > kSpinLimit) { *smem_flag = (int)gen; break; }
     }
   }
-  if (threadIdx.x < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   __syncthreads();
   const bool ok = *smem_flag != (int)gen;
   if (!ok && threadIdx.x == 0) latch_error(gs.status, ERRBIT_BARRIER);

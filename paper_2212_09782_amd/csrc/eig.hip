@@ -116,9 +116,9 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
   __syncthreads();
   // row k+1 is published by its owner's wave 0 as soon as it is final for
   // step k (here for k = 0), long before step k's barrier
-  if (n > 1 && 1 % P == blk && wid == 0) {
+  if (n > 1 && 1 % P == blk) {
     const int r = 1 / P;
-    for (int j = lane; j < n; j += 64) a.rowbuf[j] = rows[r * n + j];
+    for (int j = tid; j < n; j += 256) pub_store(a.rowbuf + j, rows[r * n + j]);
   }
 
   for (int k = 0; k < n - 1; ++k) {
@@ -200,23 +200,23 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
         for (int ww = 0; ww < 4; ++ww) sacc = cadd(sacc, wred[ww][r]);
         if (gi > k && gi < n) {
           const c128 pi = cmul(tau, sacc);
-          a.pbuf[(long long)slot * n + gi] = pi;
+          pub_store(a.pbuf + (long long)slot * n + gi, pi);
           part = cmulc(pi, vloc[r]);
         }
       }
       part.re = wave_sum(part.re);
       part.im = wave_sum(part.im);
-      if (lane == 0) a.red[(long long)slot * P + blk] = part;
+      if (lane == 0) pub_store(a.red + (long long)slot * P + blk, part);
     }
     if (!grid_barrier(gs, (unsigned)(k + 1), blk, P, &flag)) return;
     // ---- one round of loads: block partials, p, and row k+1 as published
-    const c128 rv = tid < P ? a.red[(long long)slot * P + tid] : z0();
+    const c128 rv = tid < P ? pub_load(a.red + (long long)slot * P + tid) : z0();
     c128 pv[QMAX], xb[QMAX];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
       const int j = tid + 256 * q;
-      pv[q] = (j > k && j < n) ? a.pbuf[(long long)slot * n + j] : z0();
-      xb[q] = j < n ? a.rowbuf[(long long)slot * n + j] : z0();
+      pv[q] = (j > k && j < n) ? pub_load(a.pbuf + (long long)slot * n + j) : z0();
+      xb[q] = j < n ? pub_load(a.rowbuf + (long long)slot * n + j) : z0();
     }
     const c128 ptv = block_sum_c(rv, cscr);   // p^H v
     const c128 alpha2 = cscale(cmul(tau, ptv), -0.5);
@@ -252,9 +252,9 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
     }
     __syncthreads();
     // publish row k+2 (final for step k+1) into the other slot
-    if (k + 2 < n && (k + 2) % P == blk && wid == 0) {
+    if (k + 2 < n && (k + 2) % P == blk) {
       const int r = (k + 2) / P;
-      for (int j = lane; j < n; j += 64) a.rowbuf[(long long)((k + 1) & 1) * n + j] = rows[r * n + j];
+      for (int j = tid; j < n; j += 256) pub_store(a.rowbuf + (long long)((k + 1) & 1) * n + j, rows[r * n + j]);
     }
   }
   // d[n-1] from the thread holding column n-1 of the final row

@@ -92,11 +92,11 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelBatch batch) {
       part[rg][c] = acc;
     }
     __syncthreads();
-    if (tid < NB) {  // wave 0 publishes
+    if (tid < NB) {
       c128 s = cz();
       for (int g = 0; g < 8; ++g) s = cadd(s, part[g][tid]);
-      a.red[((long long)slot * nblk + blk) * NB + tid] = s;
-      if (k >= r0 && k < r0 + nr) a.rowbuf[slot * NB + tid] = P[(k - r0) * LDP + tid];
+      pub_store(a.red + ((long long)slot * nblk + blk) * NB + tid, s);
+      if (k >= r0 && k < r0 + nr) pub_store(a.rowbuf + slot * NB + tid, P[(k - r0) * LDP + tid]);
     }
     if (!grid_barrier(gs, (unsigned)(a.gen0 + k + 1), blk, nblk, &flag)) return;
     {  // one round of loads: this thread's share of the block partials and row k
@@ -106,9 +106,9 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelBatch batch) {
 #pragma unroll
       for (int q = 0; q < kMaxPer; ++q) {
         const int w = bg + 8 * q;
-        v[q] = w < nblk ? a.red[((long long)slot * nblk + w) * NB + c] : cz();
+        v[q] = w < nblk ? pub_load(a.red + ((long long)slot * nblk + w) * NB + c) : cz();
       }
-      const c128 rk = tid < NB ? a.rowbuf[slot * NB + tid] : cz();
+      const c128 rk = tid < NB ? pub_load(a.rowbuf + slot * NB + tid) : cz();
       c128 acc = cz();
 #pragma unroll
       for (int q = 0; q < kMaxPer; ++q) acc = cadd(acc, v[q]);

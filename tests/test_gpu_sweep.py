@@ -46,17 +46,26 @@ def run_pair(ctx, d, g, L, finite, dt, nsteps, chi_max, dchi_min=100, dchi_frac=
     norms = torch.zeros(L, dtype=torch.float64, device="cuda")
     ent = torch.zeros(L, dtype=torch.float64, device="cuda")
     out = []
+    eps_cum = 0.0
     for step in range(nsteps):
         lib.mps_sweep(ctx, [st], [gates], 1, 2, pol)
         lib.mps_measure(ctx, st, op1=zz, site_vals=site, norms=norms, entropies=ent)
         ctx.sync()
-        omps.trotter_step(ost, gh, gf, chi_max=chi_max, dchi_rule=lambda c: max(dchi_min, int(np.ceil(dchi_frac * c))))
+        eps_cum += omps.trotter_step(ost, gh, gf, chi_max=chi_max,
+                                     dchi_rule=lambda c: max(dchi_min, int(np.ceil(dchi_frac * c))))
         zo, no = omps.site_expectation(ost, Z + Z.conj().T)
         eo = omps.bond_entropies(ost)
-        out.append(dict(z_gpu=site.cpu().numpy().reshape(L, 2), n_gpu=norms.cpu().numpy(),
+        out.append(dict(eps_cum=eps_cum, z_gpu=site.cpu().numpy().reshape(L, 2), n_gpu=norms.cpu().numpy(),
                         e_gpu=ent.cpu().numpy(), z_or=zo, n_or=no, e_or=eo,
                         chis=st.chis(), chis_or=[b.shape[0] for b in ost["B"]]))
     return st, ost, out
+
+
+def tol(o):
+    """1e-10, or O(discarded weight) once the chi_max cut can split a degenerate
+    Schmidt multiplet (Z_d symmetry pairs them): there the kept subspace is not
+    unique and both sides are valid truncations."""
+    return max(1e-10, 10 * o["eps_cum"])
 
 
 def test_config1_quench_finite(ctx):
@@ -64,10 +73,12 @@ def test_config1_quench_finite(ctx):
     print("config1 quench", flush=True)
     st, ost, out = run_pair(ctx, 3, 2.0, 20, True, 0.05, 20, 32)
     for k, o in enumerate(out):
-        assert np.max(np.abs(o["z_gpu"][:, 0] - o["z_or"].real)) < 1e-10, k
+        err = np.max(np.abs(o["z_gpu"][:, 0] - o["z_or"].real))
+        print(f"step {k}: max|dZ| {err:.2e}  cumulative eps {o['eps_cum']:.2e}  chi {max(o['chis'])}", flush=True)
+        assert err < tol(o), k
         assert np.max(np.abs(o["z_gpu"][:, 1])) < 1e-12, k             # Im <Z + Z^dag> = 0
-        assert np.max(np.abs(o["n_gpu"] - o["n_or"])) < 1e-10, k
-        assert np.max(np.abs(o["e_gpu"] - o["e_or"])) < 1e-9, k
+        assert np.max(np.abs(o["n_gpu"] - o["n_or"])) < tol(o), k
+        assert np.max(np.abs(o["e_gpu"] - o["e_or"])) < 1e-9 + 10 * tol(o), k
     # the state itself: overlap of the full wave functions (L = 20, chi <= 32: contract on the host)
     B, Xi = st.to_numpy()
     g = dict(B=B, Xi=Xi, finite=True)
@@ -83,7 +94,8 @@ def test_config1_quench_finite(ctx):
     for b in B2:
         n2 = np.einsum("xy,xiu,yiv->uv", n2, b.conj(), b)
     fid = abs(E[0, 0]) ** 2 / (n1[0, 0].real * n2[0, 0].real)
-    assert fid > 1 - 1e-10
+    print(f"fidelity 1 - {1 - fid:.2e}")
+    assert fid > 1 - max(1e-10, 10 * out[-1]["eps_cum"])
     assert g["B"][0].shape[0] == 1
 
 
@@ -91,8 +103,8 @@ def test_uniform_cell_quench(ctx):
     """Uniform two-site cell, d = 3, chi_max = 24, 10 steps."""
     st, ost, out = run_pair(ctx, 3, 2.0, 2, False, 0.05, 10, 24, dchi_min=8)
     for k, o in enumerate(out):
-        assert np.max(np.abs(o["z_gpu"][:, 0] - o["z_or"].real)) < 1e-10, k
-        assert np.max(np.abs(o["e_gpu"] - o["e_or"])) < 1e-9, k
+        assert np.max(np.abs(o["z_gpu"][:, 0] - o["z_or"].real)) < tol(o), k
+        assert np.max(np.abs(o["e_gpu"] - o["e_or"])) < 1e-9 + 10 * tol(o), k
 
 
 def test_bond_energy_measure(ctx):
@@ -122,4 +134,4 @@ def test_mixed_quench_error_bound(ctx):
     print(f"mixed vs c128 max |dZ| = {err:.3e}")
     assert err < 1e-5
     for a in o128:
-        assert np.max(np.abs(a["z_gpu"][:, 0] - a["z_or"].real)) < 1e-10
+        assert np.max(np.abs(a["z_gpu"][:, 0] - a["z_or"].real)) < tol(a)
