@@ -55,7 +55,8 @@ constexpr int kMaxPanelRows = 160;
 template <typename S>
 __global__ __launch_bounds__(256) void qr_panel_kernel(PanelBatch batch) {
   extern __shared__ c128 P[];  // rows_per_blk x LDP
-  __shared__ c128 part[8][NB];
+  __shared__ c128 part[4][NB];
+  __shared__ c128 tsum[NB];
   __shared__ c128 Sk[NB][NB + 1];   // per column k: V[:, j]^dag v_k for j < k (builds T after the loop)
   __shared__ c128 Tm[NB][NB + 1];
   __shared__ c128 taus[NB];
@@ -79,48 +80,54 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelBatch batch) {
   if (tid == 0) flag = 0;
   __syncthreads();
 
+  // Thread (rg, c) owns column c of the slab rows rg, rg + 8, ...  Its running
+  // partial t_c = sum_i conj(P[i,k]) P[i,c] over its rows strictly below the
+  // diagonal is formed for column 0 here and for column k + 1 during the
+  // update by reflector k (the new column k + 1 is read back right after the
+  // lanes of the same wave wrote it).
+  const int rg = tid >> 5, c = tid & 31;
+  c128 acc = cz();
+  for (int i = rg; i < nr; i += 8)
+    if (r0 + i > 0) acc = cadd(acc, cmulc(P[i * LDP], P[i * LDP + c]));
+
   for (int k = 0; k < jb; ++k) {
     const int slot = k & 1;
-    {  // partial sums over this block's rows strictly below the diagonal:
-       // t_c = sum_i conj(P[i,k]) P[i,c] gives the norm (c = k), the products
-       // with the panel (c > k) and with earlier reflectors (c < k)
-      const int rg = tid >> 5, c = tid & 31;
-      c128 acc = cz();
-      if (c < jb)
-        for (int i = rg; i < nr; i += 8)
-          if (r0 + i > k) acc = cadd(acc, cmulc(P[i * LDP + k], P[i * LDP + c]));
-      part[rg][c] = acc;
-    }
+    // block partial: lanes c and c + 32 of a wave hold rows of equal parity
+    acc.re += __shfl_xor(acc.re, 32, 64);
+    acc.im += __shfl_xor(acc.im, 32, 64);
+    if ((tid & 63) < 32) part[tid >> 6][c] = acc;
     __syncthreads();
     if (tid < NB) {
-      c128 s = cz();
-      for (int g = 0; g < 8; ++g) s = cadd(s, part[g][tid]);
-      pub_store(a.red + ((long long)slot * nblk + blk) * NB + tid, s);
+      const c128 sblk = cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid]));
+      pub_store(a.red + ((long long)slot * nblk + blk) * NB + tid, sblk);
       if (k >= r0 && k < r0 + nr) pub_store(a.rowbuf + slot * NB + tid, P[(k - r0) * LDP + tid]);
     }
     if (!grid_barrier(gs, (unsigned)(a.gen0 + k + 1), blk, nblk, &flag)) return;
-    {  // one round of loads: this thread's share of the block partials and row k
-      const int bg = tid >> 5, c = tid & 31;
+    {  // one round of loads: 8 lanes per column share the block partials
+      const int cl = tid >> 3, bg = tid & 7;
       constexpr int kMaxPer = kMaxPanelBlocks / 8;
       c128 v[kMaxPer];
 #pragma unroll
       for (int q = 0; q < kMaxPer; ++q) {
         const int w = bg + 8 * q;
-        v[q] = w < nblk ? pub_load(a.red + ((long long)slot * nblk + w) * NB + c) : cz();
+        v[q] = w < nblk ? pub_load(a.red + ((long long)slot * nblk + w) * NB + cl) : cz();
       }
       const c128 rk = tid < NB ? pub_load(a.rowbuf + slot * NB + tid) : cz();
-      c128 acc = cz();
+      c128 t = cz();
 #pragma unroll
-      for (int q = 0; q < kMaxPer; ++q) acc = cadd(acc, v[q]);
-      part[bg][c] = acc;
+      for (int q = 0; q < kMaxPer; ++q) t = cadd(t, v[q]);
+#pragma unroll
+      for (int o = 1; o < 8; o <<= 1) {
+        t.re += __shfl_xor(t.re, o, 64);
+        t.im += __shfl_xor(t.im, o, 64);
+      }
+      if (bg == 0) tsum[cl] = t;
       if (tid < NB) rowk[tid] = rk;
     }
     __syncthreads();
     // every thread derives the reflector (LAPACK zlarfg conventions)
-    c128 tk = cz();
-    for (int g = 0; g < 8; ++g) tk = cadd(tk, part[g][k]);
     const c128 alpha = rowk[k];
-    const double xnorm2 = fmax(tk.re, 0.0);
+    const double xnorm2 = fmax(tsum[k].re, 0.0);
     c128 tau = cz(), scale = cz();
     double beta = alpha.re;
     if (!(xnorm2 == 0.0 && alpha.im == 0.0)) {
@@ -134,28 +141,29 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelBatch batch) {
       taus[k] = tau;
       if (!isfinite(beta)) latch_error(batch.status, ERRBIT_NONFINITE);
     }
-    if (tid < k) {  // V[:, j]^dag v_k = conj(V[k, j]) + scale * conj(t_j)
-      c128 tj = cz();
-      for (int g = 0; g < 8; ++g) tj = cadd(tj, part[g][tid]);
-      Sk[k][tid] = cadd(cconj(rowk[tid]), cmul(scale, cconj(tj)));
+    if (tid < k)  // V[:, j]^dag v_k = conj(V[k, j]) + scale * conj(t_j)
+      Sk[k][tid] = cadd(cconj(rowk[tid]), cmul(scale, cconj(tsum[tid])));
+    // apply H_k^H to this thread's column: P[i,c] -= conj(tau) v_i (v^H P[:,c])
+    const c128 cvh = cmul(cconj(tau), cadd(rowk[c], cmulc(scale, tsum[c])));
+    const int kn = k + 1;
+    acc = cz();
+    for (int i = rg; i < nr; i += 8) {
+      const int gi = r0 + i;
+      if (gi < k) continue;
+      // Row i belongs to one half-wave, whose lane k rewrites P[i,k] while the
+      // other lanes need its old value: both reads precede every write of the
+      // pass (compiler barriers; LDS operations of a wave complete in order).
+      c128* Pi = P + i * LDP;
+      const c128 pk = Pi[k];
+      c128 b = Pi[c];
+      asm volatile("" ::: "memory");
+      const c128 v = gi == k ? mk<double>(1, 0) : cmul(pk, scale);
+      if (c > k) b = csub(b, cmul(v, cvh));
+      else if (c == k) b = gi == k ? mk<double>(beta, 0.0) : v;
+      if (c >= k) Pi[c] = b;
+      asm volatile("" ::: "memory");
+      if (kn < jb && gi > kn) acc = cadd(acc, cmulc(Pi[kn], b));
     }
-    // row-private update: thread i owns row i of the slab
-    if (tid < nr) {
-      const int i = tid, gi = r0 + i;
-      if (gi >= k) {
-        c128* Pi = P + i * LDP;
-        const c128 v = gi == k ? mk<double>(1, 0) : cmul(Pi[k], scale);
-        const c128 cv = cmul(cconj(tau), v);
-        for (int l = k + 1; l < jb; ++l) {
-          c128 tl = cz();
-          for (int g = 0; g < 8; ++g) tl = cadd(tl, part[g][l]);
-          const c128 vhl = cadd(rowk[l], cmulc(scale, tl));   // v^H P[:, l]
-          Pi[l] = csub(Pi[l], cmul(cv, vhl));
-        }
-        Pi[k] = gi == k ? mk<double>(beta, 0.0) : v;
-      }
-    }
-    __syncthreads();
   }
 
   // T of the compact-WY form: T[k][k] = tau_k, T[0:k, k] = -tau_k T[0:k, 0:k] S_k
