@@ -162,7 +162,8 @@ def main():
         "per_precision": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                           for k, v in res.items()},
         "roofline": {
-            "kernel": "contract_gemm_kernel (the 5 contraction GEMMs of each update)",
+            "kernel": ("contract_gemm_kernel<float, float, float>" if head == "c64" else "contract_gemm_kernel<double, double, double>")
+                      + " (the 5 contraction GEMMs of each update)",
             "bound": "mfma",
             "achieved": round(achieved / 1e12, 3),
             "peak": round(PEAK[head] / 1e12, 1),

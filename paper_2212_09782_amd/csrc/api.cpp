@@ -47,6 +47,7 @@ struct mps_ctx_s {
   void* tmp_out = nullptr;
   size_t tmp_bytes = 0;
   KernelTimer timer;
+  QrAsync qa{};              // auxiliary stream + events of the QR look-ahead
 };
 
 struct mps_state_s {
@@ -160,6 +161,13 @@ int mps_ctx_create(int device, mps_ctx* out) {
     delete c;
     return set_error(MPS_ERR_HIP, "context allocation failed");
   }
+  if (hipStreamCreateWithFlags(&c->qa.aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->qa.ev_panel, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->qa.ev_trail, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    mps_ctx_destroy(c);
+    return set_error(MPS_ERR_HIP, "context stream creation failed");
+  }
   *out = c;
   return MPS_OK;
 }
@@ -173,6 +181,9 @@ int mps_ctx_destroy(mps_ctx c) {
   if (c->status) (void)hipFree(c->status);
   if (c->chi_host) (void)hipHostFree(c->chi_host);
   if (c->eps_host) (void)hipHostFree(c->eps_host);
+  if (c->qa.ev_panel) (void)hipEventDestroy(c->qa.ev_panel);
+  if (c->qa.ev_trail) (void)hipEventDestroy(c->qa.ev_trail);
+  if (c->qa.aux) (void)hipStreamDestroy(c->qa.aux);
   if (c->timer.ev) {
     for (int i = 0; i < 2 * c->timer.cap; ++i) (void)hipEventDestroy(c->timer.ev[i]);
     delete[] c->timer.ev;
@@ -220,7 +231,7 @@ int mps_bond_update(mps_ctx c, const mps_bond_desc* D, const void* xi_m, const v
   hipStream_t s = (hipStream_t)stream;
   if ((rc = ensure(&c->ws, &c->ws_bytes, bond_work_bytes(b), s))) return rc;
   return bond_update_run(b, c->ws, c->status, xi_m, b_m, b_n, (const c128*)u, b_m_out, xi_n_out, b_n_out,
-                         chi_new_dev, trunc_err_dev, s, &c->timer);
+                         chi_new_dev, trunc_err_dev, s, &c->timer, &c->qa);
 }
 
 int mps_profile_enable(mps_ctx c, int on, int max_launches) {
@@ -415,7 +426,7 @@ int run_layer(mps_ctx c, std::vector<BondRef>& bonds, const mps_sweep_policy* po
     order[st->prec].push_back(k);
   }
   for (int p = 0; p < 2; ++p)
-    if (!calls[p].empty() && (rc = bond_update_batch(calls[p].data(), (int)calls[p].size(), s, &c->timer))) return rc;
+    if (!calls[p].empty() && (rc = bond_update_batch(calls[p].data(), (int)calls[p].size(), s, &c->timer, &c->qa))) return rc;
   if (eps_acc_base) {
     EpsMap map{};
     map.n = nb;
@@ -533,7 +544,8 @@ int mps_qr(mps_ctx c, int dt, int m, int n, void* A, void* Q, mps_stream stream)
   int rc;
   if ((rc = ensure(&c->ws, &c->ws_bytes, qr_work_bytes(m, n, es, n), s))) return rc;
   QrWork w = qr_work_carve(c->ws, m, n, es, n, c->status);
-  if ((rc = qr_factor(A, n, m, n, dt, w, s))) return rc;
+  QrJob J{A, n, m, n, A, n, n, &w};
+  if ((rc = qr_factor_batch(&J, 1, dt, s, &c->qa))) return rc;
   return qr_form_q(Q, n, m, n, dt, w, s);
 }
 

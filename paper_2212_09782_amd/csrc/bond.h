@@ -45,14 +45,17 @@ struct BondCall {
   double* eps;
 };
 // All bonds of a batch must share the precision; modes and shapes may differ.
-int bond_update_batch(const BondCall* calls, int n, hipStream_t s, KernelTimer* timer = nullptr);
+// as: optional look-ahead resources for the QR factorisations.
+int bond_update_batch(const BondCall* calls, int n, hipStream_t s, KernelTimer* timer = nullptr,
+                      const QrAsync* as = nullptr);
 int timed_gemm_batch(KernelTimer* t, const GemmProb* p, int n, GemmTypes ty, hipStream_t s);
 
 // Run one update with workspace `ws` (bond_work_bytes(b) bytes).  status:
 // device error word.  All pointers are device pointers.
 int bond_update_run(const BondShape& b, void* ws, int* status, const void* xi_m, const void* b_m,
                     const void* b_n, const c128* u, void* b_m_out, void* xi_n_out, void* b_n_out,
-                    int* chi_new, double* eps, hipStream_t s, KernelTimer* timer = nullptr);
+                    int* chi_new, double* eps, hipStream_t s, KernelTimer* timer = nullptr,
+                    const QrAsync* as = nullptr);
 
 // ---- small kernels shared with the measurement path
 // out[k] = sum over a partial buffer in a fixed order (one block).

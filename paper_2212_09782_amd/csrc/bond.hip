@@ -238,7 +238,7 @@ BondBufs carve(const BondShape& b, void* base) {
 }
 
 template <typename S>
-int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm) {
+int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, const QrAsync* as) {
   const int dt = sizeof(S) == 8 ? DT_C128 : DT_C64;
   const GemmTypes ty{dt, dt};
   const bool mixed = dt == DT_C64;
@@ -312,7 +312,7 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm) {
     const BondShape& b = calls[i].b;
     qj[i] = QrJob{W[i].X, b.eta, b.d * b.chi_l, b.eta, W[i].X, b.eta, b.eta, &QW[i]};
   }
-  if ((rc = qr_factor_batch(qj.data(), nc, dt, s))) return rc;
+  if ((rc = qr_factor_batch(qj.data(), nc, dt, s, as))) return rc;
   if ((rc = qr_form_q_batch(qj.data(), nc, dt, s))) return rc;
   // Y^dag = theta~^dag Q^[m], then Y^dag = Q' R'
   g.clear();
@@ -326,7 +326,7 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm) {
     const BondShape& b = calls[i].b;
     qj[i] = QrJob{W[i].YH, b.eta, b.d * b.chi_r, b.eta, W[i].YH, b.eta, b.eta, &QW[i]};
   }
-  if ((rc = qr_factor_batch(qj.data(), nc, dt, s))) return rc;
+  if ((rc = qr_factor_batch(qj.data(), nc, dt, s, as))) return rc;
   for (int i = 0; i < nc; ++i) {
     const int eta = calls[i].b.eta;
     const long long n = (long long)eta * eta;
@@ -467,19 +467,19 @@ int reduce_partials(const double* part, int n, double* out, hipStream_t s) {
 
 size_t bond_work_bytes(const BondShape& b) { return carve(b, nullptr).total + 256; }
 
-int bond_update_batch(const BondCall* calls, int n, hipStream_t s, KernelTimer* timer) {
+int bond_update_batch(const BondCall* calls, int n, hipStream_t s, KernelTimer* timer, const QrAsync* as) {
   if (n <= 0) return 0;
   const int prec = calls[0].b.prec;
   for (int i = 1; i < n; ++i)
     if (calls[i].b.prec != prec) return set_error(-1, "bond_update_batch: mixed precisions in one batch");
-  return prec == 0 ? run_batch<double>(calls, n, s, timer) : run_batch<float>(calls, n, s, timer);
+  return prec == 0 ? run_batch<double>(calls, n, s, timer, as) : run_batch<float>(calls, n, s, timer, as);
 }
 
 int bond_update_run(const BondShape& b, void* ws, int* status, const void* xi_m, const void* b_m, const void* b_n,
                     const c128* u, void* b_m_out, void* xi_n_out, void* b_n_out, int* chi_new, double* eps,
-                    hipStream_t s, KernelTimer* timer) {
+                    hipStream_t s, KernelTimer* timer, const QrAsync* as) {
   BondCall c{b, ws, status, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, chi_new, eps};
-  return bond_update_batch(&c, 1, s, timer);
+  return bond_update_batch(&c, 1, s, timer, as);
 }
 
 }  // namespace qrtebd

@@ -36,6 +36,7 @@ constexpr int NB = kQrNb;
 constexpr int QMAX = 8;            // register slots per thread: n <= 2048
 constexpr int kMaxN = 256 * QMAX;
 constexpr size_t kTriLds = 150 * 1024;
+constexpr int kTriRows = 8;           // rows per block at most (register partials of A v)
 
 __device__ inline c128 z0() { return mk<double>(0, 0); }
 
@@ -81,12 +82,39 @@ __device__ inline c128 block_sum_c(c128 v, c128* scr) {
   return s;
 }
 
+// Sum over the 64 lanes of x[0..15] (reduce-scatter butterfly, 17 shuffles):
+// on return every lane l holds the total of entry (l >> 2) & 15.
+__device__ inline double wave_reduce_scatter16(double (&x)[16]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 32, h = 8; o >= 4; o >>= 1, h >>= 1) {
+    const bool hi = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const double keep = hi ? x[i + h] : x[i];
+      const double send = hi ? x[i] : x[i + h];
+      x[i] = keep + __shfl_xor(send, o, 64);
+    }
+  }
+  const double t = x[0] + __shfl_xor(x[0], 1, 64);
+  return t + __shfl_xor(t, 2, 64);
+}
+
+// Householder tridiagonalisation of one Hermitian matrix per block group.
+// Rows are distributed cyclically (global row blk + r P in local row r, kept
+// in LDS); every block also holds the current row k+1 and the vectors v, w
+// of the step in registers (element j = tid + 256 q).  Step k: the reflector
+// of row k (every block derives it from the same data), p = tau A v over the
+// own rows, one grid barrier to exchange p and p^H v, w = p - tau/2 (p^H v) v,
+// the rank-2 update A -= v w^H + w v^H.  The update of step k and the product
+// A v of step k+1 share one pass over LDS: the reflector of row k+1 is formed
+// first from the updated row k+1 (published by its owner before the barrier).
 __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
   extern __shared__ c128 rows[];  // rows_loc x n, local row r = global row blk + r * P
   __shared__ double scratch[8];
   __shared__ c128 cscr[8];
-  __shared__ c128 wred[4][16];
-  __shared__ c128 vloc[16], wloc[16];
+  __shared__ double wred[4][16];
+  __shared__ c128 vloc[2][kTriRows], wloc[kTriRows];
   __shared__ c128 scal[4];
   __shared__ int flag;
 
@@ -104,38 +132,40 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
     if (gi < n)
       for (int j = tid; j < n; j += 256) rows[r * n + j] = a.G[(long long)gi * n + j];
   }
+  // own[q]: local row of global row j = tid + 256 q if this block owns it, else -1
+  int own[QMAX];
   c128 rk[QMAX], v[QMAX], w[QMAX];
 #pragma unroll
   for (int q = 0; q < QMAX; ++q) {
     const int j = tid + 256 * q;
+    own[q] = (j < n && j % P == blk) ? j / P : -1;
     rk[q] = j < n ? a.G[j] : z0();
     v[q] = z0();
     w[q] = z0();
   }
   if (tid == 0) flag = 0;
   __syncthreads();
-  // row k+1 is published by its owner's wave 0 as soon as it is final for
-  // step k (here for k = 0), long before step k's barrier
-  if (n > 1 && 1 % P == blk) {
+  if (n > 1 && 1 % P == blk) {   // row 1, final for step 0
     const int r = 1 / P;
     for (int j = tid; j < n; j += 256) pub_store(a.rowbuf + j, rows[r * n + j]);
   }
 
-  for (int k = 0; k < n - 1; ++k) {
-    const int slot = k & 1;
-    // ---- reflector from column k below the diagonal = conj(row k right of it);
-    // every thread derives tau, beta, scale itself from the block sums
+  // Reflector of row kk (held in rk): tau, the vector v (registers, vloc[vb]
+  // for the own rows), d[kk], e[kk], tau[kk] and column kk of the QR layout.
+  c128 tau = z0();
+  auto reflector = [&](int kk, int vb) {
     double xn2 = 0;
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
       const int j = tid + 256 * q;
-      if (j >= k + 2 && j < n) xn2 += cabs2(rk[q]);
-      if (j == k + 1) scal[0] = cconj(rk[q]);
-      if (j == k) scal[1] = rk[q];
+      if (j >= kk + 2 && j < n) xn2 += cabs2(rk[q]);
+      if (j == kk + 1) scal[0] = cconj(rk[q]);
+      if (j == kk) scal[1] = rk[q];
     }
     xn2 = block_sum(xn2, scratch);  // its barriers also publish scal[0], scal[1]
     const c128 alpha = scal[0];
-    c128 tau = z0(), scale = z0();
+    c128 scale = z0();
+    tau = z0();
     double beta = alpha.re;
     if (!(xn2 == 0.0 && alpha.im == 0.0)) {
       beta = -copysign(sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn2), alpha.re);
@@ -145,71 +175,78 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
       scale = mk<double>(den.re / dd, -den.im / dd);
     }
     if (blk == 0 && tid == 0) {
-      a.d[k] = scal[1].re;
-      a.e[k] = beta;
-      a.tau[k] = tau;
+      a.d[kk] = scal[1].re;
+      a.e[kk] = beta;
+      a.tau[kk] = tau;
       if (!isfinite(beta) || !isfinite(scal[1].re)) latch_error(batch.status, ERRBIT_NONFINITE);
     }
+    const int p = kk / NB, c = kk % NB, j0 = p * NB;
+    c128* Vp = a.V + (size_t)p * mqr * NB;
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
       const int j = tid + 256 * q;
-      v[q] = j == k + 1 ? mk<double>(1, 0) : (j > k + 1 && j < n ? cmul(cconj(rk[q]), scale) : z0());
-    }
-    // v_i of this block's rows, for the rank-2 update
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-      const int j = tid + 256 * q;
-      if (j < n && j % P == blk) vloc[j / P] = v[q];
-    }
-    // reflector k into the QR-compatible layout (subproblem row i <-> row i+1):
-    // each block writes the rows it owns; read only by later kernels
-    {
-      const int p = k / NB, c = k % NB, j0 = p * NB;
-      c128* Vp = a.V + (size_t)p * mqr * NB;
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int g = tid + 256 * q;  // global row
-        if (g >= j0 + 1 && g < n && g % P == blk) Vp[(long long)(g - 1 - j0) * NB + c] = g >= k + 1 ? v[q] : z0();
+      v[q] = j == kk + 1 ? mk<double>(1, 0) : (j > kk + 1 && j < n ? cmul(cconj(rk[q]), scale) : z0());
+      if (own[q] >= 0) {
+        vloc[vb][own[q]] = v[q];
+        if (j >= j0 + 1) Vp[(long long)(j - 1 - j0) * NB + c] = j >= kk + 1 ? v[q] : z0();
       }
     }
-    // ---- p_i = tau sum_{j>k} A[i][j] v_j for own rows i > k
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      if (r < RL) {
-        const int gi = blk + r * P;
-        c128 sacc = z0();
-        if (gi > k && gi < n) {
-#pragma unroll
-          for (int q = 0; q < QMAX; ++q) {
-            const int j = tid + 256 * q;
-            if (j > k && j < n) sacc = cadd(sacc, cmul(rows[r * n + j], v[q]));
-          }
-        }
-        const double sr = wave_sum(sacc.re), si = wave_sum(sacc.im);
-        if (lane == 0) wred[wid][r] = mk<double>(sr, si);
-      }
-    }
+  };
+
+  // p = tau A v over the own rows i > kk from the partial sums acc[2r], acc[2r+1]
+  // of this thread; publishes p, this block's p^H v (slot sl) and returns.
+  auto publish_p = [&](double (&acc)[16], int kk, int sl, int vb) {
+    const double tot = wave_reduce_scatter16(acc);
+    if ((lane & 3) == 0) wred[wid][(lane >> 2) & 15] = tot;
     __syncthreads();
     if (wid == 0) {
-      // wave 0 publishes p for its rows, this block's part of p^H v, and the
-      // current row k+1 if it owns it
       c128 part = z0();
       if (lane < RL) {
         const int r = lane, gi = blk + r * P;
-        c128 sacc = z0();
-        for (int ww = 0; ww < 4; ++ww) sacc = cadd(sacc, wred[ww][r]);
-        if (gi > k && gi < n) {
-          const c128 pi = cmul(tau, sacc);
-          pub_store(a.pbuf + (long long)slot * n + gi, pi);
-          part = cmulc(pi, vloc[r]);
+        const c128 s = mk<double>(wred[0][2 * r] + wred[1][2 * r] + wred[2][2 * r] + wred[3][2 * r],
+                                  wred[0][2 * r + 1] + wred[1][2 * r + 1] + wred[2][2 * r + 1] + wred[3][2 * r + 1]);
+        if (gi > kk && gi < n) {
+          const c128 pv = cmul(tau, s);
+          pub_store(a.pbuf + (long long)sl * n + gi, pv);
+          part = cmulc(pv, vloc[vb][r]);
         }
       }
       part.re = wave_sum(part.re);
       part.im = wave_sum(part.im);
-      if (lane == 0) pub_store(a.red + (long long)slot * P + blk, part);
+      if (lane == 0) pub_store(a.red + (long long)sl * P + blk, part);
     }
-    if (!grid_barrier(gs, (unsigned)(k + 1), blk, P, &flag)) return;
-    // ---- one round of loads: block partials, p, and row k+1 as published
+  };
+
+  // ---- step 0: reflector and product from the original rows
+  int vb = 0;
+  if (n > 1) {
+    reflector(0, vb);
+    double acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int r = 0; r < kTriRows; ++r) {
+      if (r < RL) {
+        const int gi = blk + r * P;
+        if (gi > 0 && gi < n) {
+          c128 s = z0();
+#pragma unroll
+          for (int q = 0; q < QMAX; ++q) {
+            const int j = tid + 256 * q;
+            if (j > 0 && j < n) s = cadd(s, cmul(rows[r * n + j], v[q]));
+          }
+          acc[2 * r] = s.re;
+          acc[2 * r + 1] = s.im;
+        }
+      }
+    }
+    publish_p(acc, 0, 0, vb);
+    if (!grid_barrier(gs, 1u, blk, P, &flag)) return;
+  }
+
+  for (int k = 0; k < n - 1; ++k) {
+    const int slot = k & 1;
+    // ---- one round of loads: block partials of p^H v, p, and row k+1
     const c128 rv = tid < P ? pub_load(a.red + (long long)slot * P + tid) : z0();
     c128 pv[QMAX], xb[QMAX];
 #pragma unroll
@@ -226,36 +263,57 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
       const int j = tid + 256 * q;
       w[q] = (j > k && j < n) ? cadd(pv[q], cmul(alpha2, v[q])) : z0();
       if (j == k + 1) scal[2] = w[q];
-      if (j < n && j % P == blk) wloc[j / P] = w[q];
+      if (own[q] >= 0) wloc[own[q]] = w[q];
     }
     __syncthreads();
-    // row k+1 (as published before the update) gets the rank-2 update
+    // row k+1 after the update of step k (v_{k+1} = 1)
     const c128 wk1 = scal[2];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
       const int j = tid + 256 * q;
-      if (j < n) rk[q] = j > k ? rank2_sub(xb[q], mk<double>(1, 0), w[q], wk1, v[q]) : xb[q];
+      rk[q] = j < n ? (j > k ? rank2_sub(xb[q], mk<double>(1, 0), w[q], wk1, v[q]) : xb[q]) : z0();
     }
+    if (k + 1 >= n - 1) break;   // no reflector left: rk is the last row
+
+    // ---- reflector k+1 from the updated row k+1; v of step k stays in vk
+    c128 vk[QMAX];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int q = 0; q < QMAX; ++q) vk[q] = v[q];
+    reflector(k + 1, vb ^ 1);   // ends with v = v_{k+1}; its block sum orders the LDS writes above
+    // ---- one pass over the own rows i > k+1: rank-2 update of step k and
+    // the partial sums of A v_{k+1} for step k+1
+    double acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int r = 0; r < kTriRows; ++r) {
       if (r < RL) {
         const int gi = blk + r * P;
-        if (gi > k && gi < n) {
-          const c128 vi = vloc[r], wi = wloc[r];
+        if (gi > k + 1 && gi < n) {
+          const c128 vi = vloc[vb][r], wi = wloc[r];
+          c128 s = z0();
 #pragma unroll
           for (int q = 0; q < QMAX; ++q) {
             const int j = tid + 256 * q;
-            if (j > k && j < n) rows[r * n + j] = rank2_sub(rows[r * n + j], vi, w[q], wi, v[q]);
+            if (j > k && j < n) {
+              const c128 x = rank2_sub(rows[r * n + j], vi, w[q], wi, vk[q]);
+              rows[r * n + j] = x;
+              s = cadd(s, cmul(x, v[q]));
+            }
           }
+          acc[2 * r] = s.re;
+          acc[2 * r + 1] = s.im;
         }
       }
     }
-    __syncthreads();
-    // publish row k+2 (final for step k+1) into the other slot
-    if (k + 2 < n && (k + 2) % P == blk) {
+    vb ^= 1;
+    publish_p(acc, k + 1, slot ^ 1, vb);   // its block barrier orders the row writes above
+    // row k+2, final for step k+1, from its owner
+    if ((k + 2) % P == blk) {
       const int r = (k + 2) / P;
-      for (int j = tid; j < n; j += 256) pub_store(a.rowbuf + (long long)((k + 1) & 1) * n + j, rows[r * n + j]);
+      for (int j = tid; j < n; j += 256) pub_store(a.rowbuf + (long long)(slot ^ 1) * n + j, rows[r * n + j]);
     }
+    if (!grid_barrier(gs, (unsigned)(k + 2), blk, P, &flag)) return;
   }
   // d[n-1] from the thread holding column n-1 of the final row
   if (blk == 0) {
@@ -267,20 +325,6 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
         a.tau[n - 1] = z0();
       }
   }
-}
-
-// Number of eigenvalues of the tridiagonal (d, e^2 in LDS) below x (Sturm sequence).
-__device__ inline int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
-  int cnt = 0;
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  cnt += q < 0;
-  for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0;
-  }
-  return cnt;
 }
 
 // Gershgorin interval and pivmin of (d, e) held in LDS; every thread gets them.
@@ -319,9 +363,6 @@ __device__ inline void gersh(const double* d, const double* e2, int n, double* s
   hi = h + 2.2e-16 * tnorm + 2 * pivmin;
 }
 
-// lam[j] = (j+1)-th largest eigenvalue, j < kwant.  Multisection: the 8 lanes
-// of a group evaluate 8 interior points of the eigenvalue's interval per
-// round, shrinking it 9-fold; 22 rounds reach full FP64 resolution.
 struct SmallJob {
   const double* d;
   const double* e;
@@ -330,7 +371,6 @@ struct SmallJob {
   unsigned char* swp;
   c128* E;
   c128* V;
-  c128* VT;
   c128* T;
   const c128* tau;
   int n, kwant;
@@ -341,13 +381,22 @@ struct SmallBatch {
   SmallJob j[kMaxSmallJobs];
 };
 
+// lam[j] = (j+1)-th largest eigenvalue, j < kwant.  Multisection with one
+// wave per eigenvalue: each lane evaluates one of the 64 interior points of
+// the current interval per round, shrinking it 65-fold; the points whose
+// count does not exceed the target index form a prefix, so the new interval
+// follows from one ballot.  10 rounds shrink the Gershgorin interval by 2^60,
+// past FP64 resolution.
+constexpr int kBisectPts = 1;
+constexpr int kBisectRounds = 10;
+
 __global__ __launch_bounds__(256) void bisect_kernel(SmallBatch sb) {
   const SmallJob& J = sb.j[blockIdx.y];
   const double* d = J.d;
   const double* e = J.e;
   const int n = J.n, kwant = J.kwant;
   double* lam = J.lam;
-  if ((int)blockIdx.x * 32 >= kwant) return;
+  if ((int)blockIdx.x * 4 >= kwant) return;
   __shared__ double sd[kMaxN], se2[kMaxN];
   __shared__ double scr[12];
   for (int i = threadIdx.x; i < n; i += 256) {
@@ -357,24 +406,43 @@ __global__ __launch_bounds__(256) void bisect_kernel(SmallBatch sb) {
   __syncthreads();
   double lo, hi, pivmin;
   gersh(sd, se2, n, scr, lo, hi, pivmin);
-  const int lane = threadIdx.x & 63, sub = lane & 7, gbase = lane & ~7;
-  const int j = blockIdx.x * 32 + (threadIdx.x >> 3);
-  const int idx = n - 1 - min(j, kwant - 1);  // ascending index
+  const int lane = threadIdx.x & 63;
+  const int j = min((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6), kwant - 1);
+  const int idx = n - 1 - j;  // ascending index
+  constexpr int npts = 64 * kBisectPts;
+  constexpr double inv = 1.0 / (npts + 1);
   double a = lo, b = hi;
-  for (int it = 0; it < 22; ++it) {
-    const double x = a + (b - a) * (double)(sub + 1) * (1.0 / 9.0);
-    const int c = sturm_count(sd, se2, n, x, pivmin);
-    const unsigned long long m = __ballot(c > idx);
-    const unsigned bits = (unsigned)((m >> gbase) & 0xffull);
-    const int f = bits ? __ffs(bits) - 1 : 8;
-    const double xb = __shfl(x, gbase + min(f, 7), 64);
-    const double xa = __shfl(x, gbase + max(f - 1, 0), 64);
-    const double na = f == 0 ? a : xa;
-    const double nb = f == 8 ? b : xb;
+  for (int it = 0; it < kBisectRounds; ++it) {
+    const double w = b - a;
+    double x[kBisectPts], q[kBisectPts];
+    int cnt[kBisectPts];
+#pragma unroll
+    for (int c = 0; c < kBisectPts; ++c) {
+      x[c] = a + w * (double)(kBisectPts * lane + c + 1) * inv;
+      q[c] = sd[0] - x[c];
+      if (fabs(q[c]) < pivmin) q[c] = -pivmin;
+      cnt[c] = q[c] < 0;
+    }
+    for (int i = 1; i < n; ++i) {
+      const double di = sd[i], ei = se2[i - 1];
+#pragma unroll
+      for (int c = 0; c < kBisectPts; ++c) {
+        double t = di - x[c] - ei / q[c];
+        if (fabs(t) < pivmin) t = -pivmin;
+        q[c] = t;
+        cnt[c] += t < 0;
+      }
+    }
+    // f = number of points (in increasing order) whose count is <= idx
+    int f = 0;
+#pragma unroll
+    for (int c = 0; c < kBisectPts; ++c) f += __popcll(~__ballot(cnt[c] > idx));
+    const double na = f == 0 ? a : a + w * (double)f * inv;
+    const double nb = f == npts ? b : a + w * (double)(f + 1) * inv;
     a = na;
     b = nb;
   }
-  if (j < kwant && sub == 0) lam[j] = 0.5 * (a + b);
+  if (lane == 0 && (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6) < kwant) lam[j] = 0.5 * (a + b);
 }
 
 __device__ inline double hash_uniform(unsigned long long x) {
@@ -386,8 +454,12 @@ __device__ inline double hash_uniform(unsigned long long x) {
 }
 
 // Inverse iteration for eigenvalue lam[j]: E[:, j] (real, stored complex).
-// lu: [4][n][kwant] (pivot row entries u0, u1, u2 and the multiplier),
-// swp: [n][kwant] row-interchange flags; T = (d, e) staged in LDS.
+// lu: [4][n][kwant] (reciprocal pivot, the two further entries of the pivot
+// row, the multiplier), swp: [n][kwant] row-interchange flags; T = (d, e)
+// staged in LDS.  One thread per eigenvalue; every pass over the stored
+// factors loads kPf steps ahead so the recurrences do not wait on memory.
+constexpr int kPf = 16;
+
 __global__ __launch_bounds__(64) void invit_kernel(SmallBatch sb) {
   const SmallJob& J = sb.j[blockIdx.y];
   const double* d = J.d;
@@ -410,78 +482,137 @@ __global__ __launch_bounds__(64) void invit_kernel(SmallBatch sb) {
   double tnorm = 0;
   for (int i = 0; i < n; ++i) tnorm = fmax(tnorm, fabs(sd[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0) + fabs(se[i]));
   const double tiny = fmax(tnorm, 1e-300) * 2.2e-16;
-  double* U0 = lu;
+  double* R0 = lu;
   double* U1 = lu + (size_t)n * kwant;
   double* U2 = lu + 2 * (size_t)n * kwant;
   double* ML = lu + 3 * (size_t)n * kwant;
   auto at = [&](int i) { return (size_t)i * kwant + j; };
-  // factor T - l I with partial pivoting
+  // factor T - l I with partial pivoting (row k+1 enters at step k); the
+  // first right-hand side, a hashed uniform start vector, is eliminated on
+  // the fly and stored in E's real parts
   double c0 = sd[0] - l, c1 = n > 1 ? se[0] : 0.0, c2 = 0.0;
+  auto start = [&](int i) { return hash_uniform(((unsigned long long)j << 32) ^ (unsigned)i); };
+  double rc = start(0);
   for (int k = 0; k < n - 1; ++k) {
     const double n0 = se[k], n1 = sd[k + 1] - l, n2 = se[k + 1];
+    const double bk1 = start(k + 1);
     double u0, u1, u2, m;
     unsigned char sw;
     if (fabs(c0) >= fabs(n0)) {
       m = c0 != 0.0 ? n0 / c0 : 0.0;
       u0 = c0; u1 = c1; u2 = c2; sw = 0;
       c0 = n1 - m * c1; c1 = n2 - m * c2; c2 = 0.0;
+      E[at(k)] = mk<double>(rc, 0.0);
+      rc = bk1 - m * rc;
     } else {
       m = c0 / n0;
       u0 = n0; u1 = n1; u2 = n2; sw = 1;
       c0 = c1 - m * n1; c1 = c2 - m * n2; c2 = 0.0;
+      E[at(k)] = mk<double>(bk1, 0.0);
+      rc = rc - m * bk1;
     }
     if (u0 == 0.0) u0 = tiny;
-    U0[at(k)] = u0; U1[at(k)] = u1; U2[at(k)] = u2; ML[at(k)] = m; swp[at(k)] = sw;
+    R0[at(k)] = 1.0 / u0; U1[at(k)] = u1; U2[at(k)] = u2; ML[at(k)] = m; swp[at(k)] = sw;
   }
-  U0[at(n - 1)] = c0 == 0.0 ? tiny : c0;
+  R0[at(n - 1)] = 1.0 / (c0 == 0.0 ? tiny : c0);
   U1[at(n - 1)] = 0.0;
   U2[at(n - 1)] = 0.0;
-  // start vector, stored in E's real parts
-  for (int i = 0; i < n; ++i) E[at(i)] = mk<double>(hash_uniform(((unsigned long long)j << 32) ^ (unsigned)i), 0.0);
+  E[at(n - 1)] = mk<double>(rc, 0.0);
+
   double scale = 1.0;
   for (int it = 0; it < 2; ++it) {
-    // forward: the row operations of the factorisation applied to b (scaled)
-    double rc = E[at(0)].re * scale;
-    for (int k = 0; k < n - 1; ++k) {
-      const double bk1 = E[at(k + 1)].re * scale, m = ML[at(k)];
-      if (swp[at(k)] == 0) {
-        E[at(k)].re = rc;
-        rc = bk1 - m * rc;
-      } else {
-        E[at(k)].re = bk1;
-        rc = rc - m * bk1;
-      }
-    }
-    E[at(n - 1)].re = rc;
-    // back substitution; the max norm rescales the next pass
-    double z1 = 0.0, z2 = 0.0, nrm = 0.0, s2 = 0.0;
-    for (int i = n - 1; i >= 0; --i) {
-      const double z = (E[at(i)].re - U1[at(i)] * z1 - U2[at(i)] * z2) / U0[at(i)];
-      E[at(i)].re = z;
-      z2 = z1;
-      z1 = z;
-      nrm = fmax(nrm, fabs(z));
-    }
-    scale = nrm > 0 ? 1.0 / nrm : 1.0;
     if (it == 1) {
-      for (int i = 0; i < n; ++i) {
-        const double z = E[at(i)].re * scale;
-        s2 += z * z;
+      // forward: the row operations of the factorisation applied to b (scaled)
+      double r = E[at(0)].re * scale;
+      for (int k0 = 0; k0 < n - 1; k0 += kPf) {
+        double bb[kPf], mm[kPf];
+        unsigned char ss[kPf];
+#pragma unroll
+        for (int t = 0; t < kPf; ++t) {
+          const int k = k0 + t;
+          if (k < n - 1) {
+            bb[t] = E[at(k + 1)].re;
+            mm[t] = ML[at(k)];
+            ss[t] = swp[at(k)];
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < kPf; ++t) {
+          const int k = k0 + t;
+          if (k < n - 1) {
+            const double bk1 = bb[t] * scale;
+            if (ss[t] == 0) {
+              E[at(k)].re = r;
+              r = bk1 - mm[t] * r;
+            } else {
+              E[at(k)].re = bk1;
+              r = r - mm[t] * bk1;
+            }
+          }
+        }
       }
-      const double f = scale / sqrt(s2);
-      for (int i = 0; i < n; ++i) E[at(i)].re *= f;
+      E[at(n - 1)].re = r;
+    }
+    // back substitution; the first pass's max norm rescales the second, the
+    // second accumulates the 2-norm
+    double z1 = 0.0, z2 = 0.0, nrm = 0.0, s2 = 0.0;
+    for (int i0 = n - 1; i0 >= 0; i0 -= kPf) {
+      double bb[kPf], r0[kPf], u1[kPf], u2[kPf];
+#pragma unroll
+      for (int t = 0; t < kPf; ++t) {
+        const int i = i0 - t;
+        if (i >= 0) {
+          bb[t] = E[at(i)].re;
+          r0[t] = R0[at(i)];
+          u1[t] = U1[at(i)];
+          u2[t] = U2[at(i)];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < kPf; ++t) {
+        const int i = i0 - t;
+        if (i >= 0) {
+          const double z = (bb[t] - u1[t] * z1 - u2[t] * z2) * r0[t];
+          E[at(i)].re = z;
+          z2 = z1;
+          z1 = z;
+          nrm = fmax(nrm, fabs(z));
+          s2 += z * z;
+        }
+      }
+    }
+    if (it == 0) {
+      scale = nrm > 0 ? 1.0 / nrm : 1.0;
+    } else {
+      double f = s2 > 0 ? 1.0 / sqrt(s2) : 0.0;
+      if (nrm > 1e150 || (nrm > 0 && nrm < 1e-150)) {   // sum of squares out of range: rescale by the max
+        double t2 = 0.0;
+        for (int i = 0; i < n; ++i) {
+          const double z = E[at(i)].re / nrm;
+          t2 += z * z;
+        }
+        f = 1.0 / (nrm * sqrt(t2));
+      }
+      for (int i0 = 0; i0 < n; i0 += kPf) {
+        double zz[kPf];
+#pragma unroll
+        for (int t = 0; t < kPf; ++t)
+          if (i0 + t < n) zz[t] = E[at(i0 + t)].re;
+#pragma unroll
+        for (int t = 0; t < kPf; ++t)
+          if (i0 + t < n) E[at(i0 + t)].re = zz[t] * f;
+      }
     }
   }
 }
 
-// T_p and V_p T_p for every panel of the tridiagonalisation reflectors;
-// V_p is staged through LDS in 64-row slabs.
+// T_p for every panel of the tridiagonalisation reflectors (from the Gram
+// matrix V_p^H V_p; V_p is staged through LDS in 64-row slabs).
 __global__ __launch_bounds__(256) void larft_kernel(SmallBatch sb) {
   __shared__ c128 slab[64][NB + 1];
   __shared__ c128 Tm[NB][NB + 1];
   const SmallJob& J = sb.j[blockIdx.y];
   c128* V = J.V;
-  c128* VT = J.VT;
   c128* T = J.T;
   const c128* tau = J.tau;
   const int m = J.n - 1, nrefl = J.n - 1;
@@ -525,14 +656,6 @@ __global__ __launch_bounds__(256) void larft_kernel(SmallBatch sb) {
     }
     if (tid == k) Tm[k][k] = tk;
     __syncthreads();
-  }
-  c128* VTp = VT + (size_t)p * m * NB;
-  for (int idx = tid; idx < mp * NB; idx += 256) {
-    const int i = idx / NB, c = idx % NB;
-    c128 sacc = z0();
-    if (c < jb)
-      for (int q = 0; q <= c; ++q) sacc = cadd(sacc, cmul(Vp[(long long)i * NB + q], Tm[q][c]));
-    VTp[idx] = sacc;
   }
   for (int idx = tid; idx < NB * NB; idx += 256) T[(size_t)p * NB * NB + idx] = Tm[idx / NB][idx % NB];
 }
@@ -587,7 +710,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int tri_rows_loc(int n) {
   const int rl = (int)(kTriLds / (16 * (size_t)n));
-  return std::max(1, std::min(std::min(n, 16), rl));
+  return std::max(1, std::min(std::min(n, kTriRows), rl));
 }
 
 }  // namespace
@@ -703,7 +826,6 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
       S.swp = (unsigned char*)((char*)J.w->lu + align256(4 * (size_t)J.n * J.n * 8));
       S.E = J.E;
       S.V = (c128*)J.w->qtri.V;
-      S.VT = (c128*)J.w->qtri.VT;
       S.T = J.w->qtri.T;
       S.tau = J.w->tau;
       S.n = J.n;
@@ -714,7 +836,7 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
     const int npan = (maxn - 1 + NB - 1) / NB;
     hipLaunchKernelGGL(larft_kernel, dim3(npan, sb.njobs), dim3(256), 0, s, sb);
     QT_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(bisect_kernel, dim3((maxk + 31) / 32, sb.njobs), dim3(256), 0, s, sb);
+    hipLaunchKernelGGL(bisect_kernel, dim3((maxk + 3) / 4, sb.njobs), dim3(256), 0, s, sb);
     QT_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(invit_kernel, dim3((maxk + 63) / 64, sb.njobs), dim3(64), 0, s, sb);
     QT_HIP_CHECK(hipGetLastError());

@@ -15,7 +15,8 @@ enum Dt : int { DT_C64 = 0, DT_C128 = 1 };
 // kernel can change it without the host.  ldc_live_N makes the output compact
 // with the live N as its leading dimension.
 // ksplit > 1 splits K: each split writes raw sums to work ([ksplit][Mcap][Ncap]
-// in the compute type), and gemm_splitk_reduce forms alpha*sum + beta*C.
+// in the compute type), and a reduction kernel forms alpha*sum + beta*C
+// unless skip_reduce is set.
 struct GemmProb {
   const void* A;
   const void* B;
@@ -30,6 +31,7 @@ struct GemmProb {
   float alpha, beta;
   int ksplit;
   void* work;
+  int skip_reduce;   // ksplit > 1: leave the partials in work (the caller reduces them)
 };
 
 constexpr int kGemmMaxProb = 16;

@@ -9,11 +9,11 @@ constexpr int kQrNb = 32;  // panel width
 // Device workspace of one QR of an m x n matrix (n <= m).
 struct QrWork {
   void* V;        // per panel p: (m - 32p) x 32 explicit reflectors, ld 32, at offset p*m*32
-  void* VT;       // same layout: V T
-  void* VTh;      // same layout: V T^H
-  c128* T;        // per panel 32 x 32 upper triangular
+  c128* T;        // per panel 32 x 32 upper triangular (compact-WY factor)
   void* W;        // 32 x n product V^H A (element type of the storage)
   void* Wsplit;   // split-K partials: kMaxSplit x 32 x n in the compute type
+  void* Wn;       // 32 x 32 product for the next panel's columns (look-ahead)
+  void* Wnsplit;  // its split-K partials: kMaxSplit x 32 x 32
   c128* red;      // panel reductions: 2 x nblk x 32 + 2 x 32
   unsigned* sync; // grid barrier words (>= grid_sync_words(kMaxPanelBlocks))
   int* status;
@@ -58,7 +58,14 @@ struct QrJob {
   int nz;
   const QrWork* w;
 };
-int qr_factor_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s);
+// Optional look-ahead: with an auxiliary stream (default priority) and two
+// events, the update of the columns beyond the next panel runs on aux while
+// the next panel is factored on s; the call returns with s joined to aux.
+struct QrAsync {
+  hipStream_t aux;
+  hipEvent_t ev_panel, ev_trail;
+};
+int qr_factor_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s, const QrAsync* as = nullptr);
 int qr_form_q_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s);
 int qr_apply_q_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s);
 

@@ -13,9 +13,11 @@
 //    panel (c > k) and the products with the earlier reflectors that build
 //    the compact-WY factor T (c < k).  Reflectors follow LAPACK's zlarfg
 //    convention: H = I - tau v v^H, v_k = 1, beta real.
-//  * trailing update: A <- (I - V T V^H)^H A as two MFMA GEMMs,
-//    W = V^H A (split over the long dimension) and A -= (V T^H) W.
-//  * explicit Q: backward accumulation of the same blocks onto [I; 0].
+//  * trailing update: A <- (I - V T V^H)^H A as W = V^H A (an MFMA GEMM
+//    split over the long dimension), W <- T^H W folded into the reduction of
+//    the split partials (FP64), and A -= V W (MFMA GEMM).
+//  * explicit Q: backward accumulation of the same blocks onto [I; 0], with
+//    T in place of T^H.
 #include "qr.h"
 
 #include <algorithm>
@@ -32,8 +34,6 @@ struct PanelProb {
   void* A;
   long long lda;
   void* V;
-  void* VT;
-  void* VTh;
   c128* T;
   c128* red;
   c128* rowbuf;
@@ -52,10 +52,13 @@ __device__ inline c128 cz() { return mk<double>(0, 0); }
 constexpr int LDP = NB + 1;   // padded LDS row stride of the panel slab
 constexpr int kMaxPanelRows = 160;
 
+constexpr int kPanelThreads = 512;   // 16 row groups x 32 columns: two waves per SIMD
+constexpr int kRowGroups = kPanelThreads / 32;
+
 template <typename S>
-__global__ __launch_bounds__(256) void qr_panel_kernel(PanelBatch batch) {
+__global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batch) {
   extern __shared__ c128 P[];  // rows_per_blk x LDP
-  __shared__ c128 part[4][NB];
+  __shared__ c128 part[kPanelThreads / 64][NB];
   __shared__ c128 tsum[NB];
   __shared__ c128 Sk[NB][NB + 1];   // per column k: V[:, j]^dag v_k for j < k (builds T after the loop)
   __shared__ c128 Tm[NB][NB + 1];
@@ -73,21 +76,21 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelBatch batch) {
   const int jb = a.jb;
   cpx<S>* A = (cpx<S>*)a.A;
 
-  for (int idx = tid; idx < nr * NB; idx += 256) {
+  for (int idx = tid; idx < nr * NB; idx += kPanelThreads) {
     const int i = idx / NB, c = idx % NB;
     P[i * LDP + c] = c < jb ? ccast<double>(A[(long long)(r0 + i) * a.lda + c]) : cz();
   }
   if (tid == 0) flag = 0;
   __syncthreads();
 
-  // Thread (rg, c) owns column c of the slab rows rg, rg + 8, ...  Its running
+  // Thread (rg, c) owns column c of the slab rows rg, rg + 16, ...  Its running
   // partial t_c = sum_i conj(P[i,k]) P[i,c] over its rows strictly below the
   // diagonal is formed for column 0 here and for column k + 1 during the
   // update by reflector k (the new column k + 1 is read back right after the
   // lanes of the same wave wrote it).
   const int rg = tid >> 5, c = tid & 31;
   c128 acc = cz();
-  for (int i = rg; i < nr; i += 8)
+  for (int i = rg; i < nr; i += kRowGroups)
     if (r0 + i > 0) acc = cadd(acc, cmulc(P[i * LDP], P[i * LDP + c]));
 
   for (int k = 0; k < jb; ++k) {
@@ -98,18 +101,20 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelBatch batch) {
     if ((tid & 63) < 32) part[tid >> 6][c] = acc;
     __syncthreads();
     if (tid < NB) {
-      const c128 sblk = cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid]));
+      c128 sblk = cz();
+#pragma unroll
+      for (int g = 0; g < kPanelThreads / 64; ++g) sblk = cadd(sblk, part[g][tid]);
       pub_store(a.red + ((long long)slot * nblk + blk) * NB + tid, sblk);
       if (k >= r0 && k < r0 + nr) pub_store(a.rowbuf + slot * NB + tid, P[(k - r0) * LDP + tid]);
     }
     if (!grid_barrier(gs, (unsigned)(a.gen0 + k + 1), blk, nblk, &flag)) return;
     {  // one round of loads: 8 lanes per column share the block partials
-      const int cl = tid >> 3, bg = tid & 7;
-      constexpr int kMaxPer = kMaxPanelBlocks / 8;
+      const int cl = tid >> 4, bg = tid & 15;
+      constexpr int kMaxPer = kMaxPanelBlocks / 16;
       c128 v[kMaxPer];
 #pragma unroll
       for (int q = 0; q < kMaxPer; ++q) {
-        const int w = bg + 8 * q;
+        const int w = bg + 16 * q;
         v[q] = w < nblk ? pub_load(a.red + ((long long)slot * nblk + w) * NB + cl) : cz();
       }
       const c128 rk = tid < NB ? pub_load(a.rowbuf + slot * NB + tid) : cz();
@@ -117,7 +122,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelBatch batch) {
 #pragma unroll
       for (int q = 0; q < kMaxPer; ++q) t = cadd(t, v[q]);
 #pragma unroll
-      for (int o = 1; o < 8; o <<= 1) {
+      for (int o = 1; o < 16; o <<= 1) {
         t.re += __shfl_xor(t.re, o, 64);
         t.im += __shfl_xor(t.im, o, 64);
       }
@@ -146,69 +151,69 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(PanelBatch batch) {
     // apply H_k^H to this thread's column: P[i,c] -= conj(tau) v_i (v^H P[:,c])
     const c128 cvh = cmul(cconj(tau), cadd(rowk[c], cmulc(scale, tsum[c])));
     const int kn = k + 1;
+    // v^H P[:, k+1] scaled, for the new P[i, k+1] every lane forms itself
+    const c128 cvhn = kn < jb ? cmul(cconj(tau), cadd(rowk[kn], cmulc(scale, tsum[kn]))) : cz();
     acc = cz();
-    for (int i = rg; i < nr; i += 8) {
-      const int gi = r0 + i;
-      if (gi < k) continue;
-      // Row i belongs to one half-wave, whose lane k rewrites P[i,k] while the
-      // other lanes need its old value: both reads precede every write of the
-      // pass (compiler barriers; LDS operations of a wave complete in order).
-      c128* Pi = P + i * LDP;
-      const c128 pk = Pi[k];
-      c128 b = Pi[c];
-      asm volatile("" ::: "memory");
-      const c128 v = gi == k ? mk<double>(1, 0) : cmul(pk, scale);
-      if (c > k) b = csub(b, cmul(v, cvh));
-      else if (c == k) b = gi == k ? mk<double>(beta, 0.0) : v;
-      if (c >= k) Pi[c] = b;
-      asm volatile("" ::: "memory");
-      if (kn < jb && gi > kn) acc = cadd(acc, cmulc(Pi[kn], b));
-    }
-  }
-
-  // T of the compact-WY form: T[k][k] = tau_k, T[0:k, k] = -tau_k T[0:k, 0:k] S_k
-  for (int idx = tid; idx < NB * (NB + 1); idx += 256) (&Tm[0][0])[idx] = cz();
-  __syncthreads();
-  for (int k = 0; k < jb; ++k) {
-    const c128 tk = taus[k];
-    if (tid < k) {
-      c128 sacc = cz();
-      for (int q = tid; q < k; ++q) sacc = cadd(sacc, cmul(Tm[tid][q], Sk[k][q]));
-      Tm[tid][k] = cmul(mk<double>(-tk.re, -tk.im), sacc);
-    } else if (tid == k) {
-      Tm[k][k] = tk;
-    }
-    __syncthreads();
-  }
-
-  // write back R / reflectors in place and the explicit V, V T, V T^H
-  for (int idx = tid; idx < nr * NB; idx += 256) {
-    const int i = idx / NB, c = idx % NB;
-    if (c < jb) A[(long long)(r0 + i) * a.lda + c] = ccast<S>(P[i * LDP + c]);
-  }
-  cpx<S>* V = (cpx<S>*)a.V;
-  cpx<S>* VT = (cpx<S>*)a.VT;
-  cpx<S>* VTh = (cpx<S>*)a.VTh;
-  for (int idx = tid; idx < nr * NB; idx += 256) {
-    const int i = idx / NB, c = idx % NB, gi = r0 + i;
-    c128 vc = cz(), vt = cz(), vth = cz();
-    if (c < jb) {
-      vc = gi > c ? P[i * LDP + c] : (gi == c ? mk<double>(1, 0) : cz());
-      for (int q = 0; q < jb; ++q) {
-        const c128 vq = gi > q ? P[i * LDP + q] : (gi == q ? mk<double>(1, 0) : cz());
-        if (q <= c) vt = cadd(vt, cmul(vq, Tm[q][c]));
-        if (q >= c) vth = cadd(vth, cmul(vq, cconj(Tm[c][q])));
+    // Every lane reads the old P[i,k] and P[i,k+1] of its row (broadcast) and
+    // its own P[i,c] before it writes P[i,c]; rows go in unrolled chunks so
+    // their loads are in flight together.
+    constexpr int RU = 4;
+    for (int i0 = rg; i0 < nr; i0 += kRowGroups * RU) {
+      c128 pk[RU], pn[RU], b[RU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int i = i0 + kRowGroups * u < nr ? i0 + kRowGroups * u : i0;   // past the slab: dummy read of an own row
+        const c128* Pi = P + i * LDP;
+        pk[u] = Pi[k];
+        pn[u] = Pi[kn < NB ? kn : k];
+        b[u] = Pi[c];
+      }
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int i = i0 + kRowGroups * u, gi = r0 + i;
+        const bool act = i < nr && gi >= k;
+        const c128 v = gi == k ? mk<double>(1, 0) : cmul(pk[u], scale);
+        const c128 bn = c > k ? csub(b[u], cmul(v, cvh)) : (c == k ? (gi == k ? mk<double>(beta, 0.0) : v) : b[u]);
+        if (act && c >= k) P[i * LDP + c] = bn;
+        if (act && kn < jb && gi > kn) acc = cadd(acc, cmulc(csub(pn[u], cmul(v, cvhn)), bn));
       }
     }
-    const long long o = (long long)(r0 + i) * NB + c;
-    V[o] = ccast<S>(vc);
-    VT[o] = ccast<S>(vt);
-    VTh[o] = ccast<S>(vth);
+  }
+
+  // T of the compact-WY form: T[k][k] = tau_k, T[r][k] = -tau_k sum_q T[r][q] S_k[q]
+  // (q = r..k-1).  Row r depends only on its own earlier entries: the 8 lanes
+  // r*8 .. r*8+7 (one wave) build it, each summing every 8th term.
+  __syncthreads();
+  if (tid < 8 * NB) {
+    const int r = tid >> 3, part = tid & 7;
+    for (int q = part; q < NB; q += 8) Tm[r][q] = (q == r && r < jb) ? taus[r] : cz();
+    for (int k = 1; k < jb; ++k) {
+      c128 sacc = cz();
+      if (r < k)
+        for (int q = r + ((part - r) & 7); q < k; q += 8) sacc = cadd(sacc, cmul(Tm[r][q], Sk[k][q]));
+#pragma unroll
+      for (int o = 1; o < 8; o <<= 1) {
+        sacc.re += __shfl_xor(sacc.re, o, 64);
+        sacc.im += __shfl_xor(sacc.im, o, 64);
+      }
+      if (part == (k & 7) && r < k) Tm[r][k] = cmul(mk<double>(-taus[k].re, -taus[k].im), sacc);
+    }
+  }
+  __syncthreads();
+
+  // write back R / reflectors in place, the explicit V and (block 0) T
+  cpx<S>* V = (cpx<S>*)a.V;
+  for (int idx = tid; idx < nr * NB; idx += kPanelThreads) {
+    const int i = idx / NB, cc = idx % NB, gi = r0 + i;
+    const c128 pv = P[i * LDP + cc];
+    if (cc < jb) A[(long long)(r0 + i) * a.lda + cc] = ccast<S>(pv);
+    const c128 vc = cc < jb ? (gi > cc ? pv : (gi == cc ? mk<double>(1, 0) : cz())) : cz();
+    V[(long long)(r0 + i) * NB + cc] = ccast<S>(vc);
   }
   if (blk == 0)
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-      const int r = idx / NB, c = idx % NB;
-      a.T[idx] = (r < jb && c < jb) ? Tm[r][c] : cz();
+    for (int idx = tid; idx < NB * NB; idx += kPanelThreads) {
+      const int r = idx / NB, cc = idx % NB;
+      a.T[idx] = (r < jb && cc < jb) ? Tm[r][cc] : cz();
     }
 }
 
@@ -245,7 +250,7 @@ int launch_panel(const PanelBatch& pb, int nblk_total, int max_rows, hipStream_t
     attr_set = true;
   }
   void* args[] = {(void*)&pb};
-  QT_HIP_CHECK(hipLaunchCooperativeKernel((const void*)qr_panel_kernel<S>, dim3(nblk_total), dim3(256), args,
+  QT_HIP_CHECK(hipLaunchCooperativeKernel((const void*)qr_panel_kernel<S>, dim3(nblk_total), dim3(kPanelThreads), args,
                                           (unsigned)shmem, s));
   return 0;
 }
@@ -284,10 +289,12 @@ size_t qr_work_bytes(int m, int n, int es, int wcols) {
   const size_t np = (size_t)(n + NB - 1) / NB;
   if (wcols < n) wcols = n;
   size_t b = 0;
-  b += 3 * align256(np * (size_t)m * NB * es);
+  b += align256(np * (size_t)m * NB * es);
   b += align256(np * NB * NB * sizeof(c128));
   b += align256((size_t)NB * wcols * es);
   b += align256((size_t)kMaxSplit * NB * wcols * sizeof(c128));
+  b += align256((size_t)NB * NB * es);
+  b += align256((size_t)kMaxSplit * NB * NB * sizeof(c128));
   b += align256((2 * (size_t)kMaxPanelBlocks * NB + 2 * NB) * sizeof(c128));
   b += align256(grid_sync_words(kMaxPanelBlocks) * 4);
   return b;
@@ -300,11 +307,11 @@ QrWork qr_work_carve(void* base, int m, int n, int es, int wcols, int* status) {
   QrWork w{};
   const size_t vb = align256(np * (size_t)m * NB * es);
   w.V = p; p += vb;
-  w.VT = p; p += vb;
-  w.VTh = p; p += vb;
   w.T = (c128*)p; p += align256(np * NB * NB * sizeof(c128));
   w.W = p; p += align256((size_t)NB * wcols * es);
   w.Wsplit = p; p += align256((size_t)kMaxSplit * NB * wcols * sizeof(c128));
+  w.Wn = p; p += align256((size_t)NB * NB * es);
+  w.Wnsplit = p; p += align256((size_t)kMaxSplit * NB * NB * sizeof(c128));
   w.red = (c128*)p; p += align256((2 * (size_t)kMaxPanelBlocks * NB + 2 * NB) * sizeof(c128));
   w.sync = (unsigned*)p;
   w.status = status;
@@ -312,10 +319,82 @@ QrWork qr_work_carve(void* base, int m, int n, int es, int wcols, int* status) {
   return w;
 }
 
-// One panel step p of a batch of factorisations: the panel kernels (packed
-// into cooperative launches of at most kMaxPanelBlocks blocks) and then the
-// grouped trailing-update GEMMs of all jobs.
-static int factor_panel_step(const QrJob* jobs, int njobs, int p, int dt, hipStream_t s) {
+// W := op(T) sum_s src[s] for the 32 x nt block products W = V^H X of a batch
+// of jobs (one column per thread, FP64 arithmetic; in place when the product
+// was not split).  op = T (explicit Q, Z := H Z) or T^H (factorisation).
+struct TwJob {
+  const void* src;   // ks x jb x nt partials (compute type = storage type here)
+  int ks, jb, nt;
+  const c128* T;     // 32 x 32
+  void* W;           // jb x nt, ld nt
+};
+constexpr int kMaxTwJobs = 24;
+struct TwBatch {
+  int n, herm;
+  TwJob j[kMaxTwJobs];
+};
+
+// Block: 8 columns of one job, one element (row r, column nn) per thread:
+// the split partials are summed with eight loads in flight, the sums go to
+// LDS and the same elements of op(T) S are formed.
+constexpr int kTwCols = 8;
+
+template <typename S>
+__global__ __launch_bounds__(256) void reduce_tw_kernel(TwBatch b) {
+  __shared__ c128 Ts[NB][NB + 1];
+  __shared__ c128 Sm[NB][kTwCols];
+  const TwJob& J = b.j[blockIdx.y];
+  const int n0 = blockIdx.x * kTwCols;
+  if (n0 >= J.nt) return;
+  for (int idx = threadIdx.x; idx < NB * NB; idx += 256) {
+    const int r = idx / NB, q = idx % NB;
+    Ts[r][q] = b.herm ? cconj(J.T[q * NB + r]) : J.T[r * NB + q];
+  }
+  const int r = threadIdx.x / kTwCols, nn = threadIdx.x % kTwCols, n = n0 + nn;
+  const cpx<S>* src = (const cpx<S>*)J.src + (long long)r * J.nt + n;
+  const long long stride = (long long)J.jb * J.nt;
+  c128 acc = cz();
+  if (n < J.nt && r < J.jb) {
+    int k = 0;
+    for (; k + 8 <= J.ks; k += 8) {
+      cpx<S> t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = src[(k + u) * stride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = cadd(acc, ccast<double>(t[u]));
+    }
+    for (; k < J.ks; ++k) acc = cadd(acc, ccast<double>(src[k * stride]));
+  }
+  Sm[r][nn] = acc;
+  __syncthreads();
+  if (n >= J.nt || r >= J.jb) return;
+  c128 o = cz();
+  for (int q = 0; q < J.jb; ++q) o = cadd(o, cmul(Ts[r][q], Sm[q][nn]));
+  ((cpx<S>*)J.W)[(long long)r * J.nt + n] = ccast<S>(o);
+}
+
+static int launch_tw(const std::vector<TwJob>& jobs, bool herm, int dt, hipStream_t s) {
+  for (size_t i0 = 0; i0 < jobs.size(); i0 += kMaxTwJobs) {
+    TwBatch b{};
+    b.herm = herm ? 1 : 0;
+    int maxn = 0;
+    for (size_t i = i0; i < jobs.size() && b.n < kMaxTwJobs; ++i) {
+      b.j[b.n++] = jobs[i];
+      maxn = std::max(maxn, jobs[i].nt);
+    }
+    const dim3 grid((maxn + kTwCols - 1) / kTwCols, b.n);
+    if (dt == DT_C128)
+      hipLaunchKernelGGL(reduce_tw_kernel<double>, grid, dim3(256), 0, s, b);
+    else
+      hipLaunchKernelGGL(reduce_tw_kernel<float>, grid, dim3(256), 0, s, b);
+    QT_HIP_CHECK(hipGetLastError());
+  }
+  return 0;
+}
+
+// The cooperative panel kernels of step p for all jobs, packed into launches
+// of at most kMaxPanelBlocks blocks.
+static int launch_panels(const QrJob* jobs, int njobs, int p, int dt, hipStream_t s) {
   const int es = dt == DT_C128 ? 16 : 8;
   PanelBatch pb{};
   int used = 0, max_rows = 0;
@@ -328,7 +407,6 @@ static int factor_panel_step(const QrJob* jobs, int njobs, int p, int dt, hipStr
     max_rows = 0;
     return r;
   };
-  std::vector<GemmProb> g1s, g2s;
   for (int j = 0; j < njobs; ++j) {
     const QrJob& J = jobs[j];
     const int j0 = p * NB;
@@ -342,13 +420,10 @@ static int factor_panel_step(const QrJob* jobs, int njobs, int p, int dt, hipStr
     const QrWork& w = *J.w;
     PanelProb& pp = pb.p[pb.nprob++];
     pb.status = w.status;
-    char* Ab = (char*)J.A;
-    pp.A = Ab + ((long long)j0 * J.lda + j0) * es;
+    pp.A = (char*)J.A + ((long long)j0 * J.lda + j0) * es;
     pp.lda = J.lda;
     const size_t voff = (size_t)p * J.m * NB * es;
     pp.V = (char*)w.V + voff;
-    pp.VT = (char*)w.VT + voff;
-    pp.VTh = (char*)w.VTh + voff;
     pp.T = w.T + (size_t)p * NB * NB;
     pp.red = w.red;
     pp.rowbuf = w.red + 2 * (size_t)kMaxPanelBlocks * NB;
@@ -361,24 +436,46 @@ static int factor_panel_step(const QrJob* jobs, int njobs, int p, int dt, hipStr
     pp.gen0 = j0;   // generations keep increasing over the panels of one factorisation
     used += nblk;
     max_rows = std::max(max_rows, rows);
-    const int nt = J.n - j0 - jb;
-    if (nt > 0) {
-      void* At = Ab + ((long long)j0 * J.lda + j0 + jb) * es;
-      GemmProb g1 = gemm_prob(pp.V, NB, OP_C, At, J.lda, OP_N, w.W, nt, jb, nt, mp);
-      g1.ksplit = splitk_for(jb, nt, mp);
-      g1.work = w.Wsplit;
-      g1s.push_back(g1);
-      g2s.push_back(gemm_prob(pp.VTh, NB, OP_N, w.W, nt, OP_N, At, J.lda, mp, nt, jb, -1.f, 1.f));
-    }
   }
-  if ((rc = flush())) return rc;
+  return flush();
+}
+
+// Apply the reflectors of panel p (as H^H) to the column blocks [b0, b1) of
+// every job (clipped to its n): W = V^H A (split over the rows), A -= V T^H W.
+// next = true uses the small W buffers (the next panel's columns).
+static int update_columns(const QrJob* jobs, int njobs, int p, int dt, int b0, int b1, bool next, hipStream_t s) {
+  const int es = dt == DT_C128 ? 16 : 8;
+  std::vector<GemmProb> g1s, g2s;
+  std::vector<TwJob> tw;
+  for (int j = 0; j < njobs; ++j) {
+    const QrJob& J = jobs[j];
+    const int j0 = p * NB;
+    if (j0 >= J.n) continue;
+    const int jb = std::min(NB, J.n - j0), mp = J.m - j0;
+    const int c0 = b0 * NB, c1 = (int)std::min<long long>(J.n, (long long)b1 * NB);
+    const int nt = c1 - c0;
+    if (nt <= 0) continue;
+    const QrWork& w = *J.w;
+    const size_t voff = (size_t)p * J.m * NB * es;
+    void* At = (char*)J.A + ((long long)j0 * J.lda + c0) * es;
+    void* W = next ? w.Wn : w.W;
+    GemmProb g1 = gemm_prob((char*)w.V + voff, NB, OP_C, At, J.lda, OP_N, W, nt, jb, nt, mp);
+    g1.ksplit = splitk_for(jb, nt, mp);
+    g1.work = next ? w.Wnsplit : w.Wsplit;
+    g1.skip_reduce = 1;
+    g1s.push_back(g1);
+    tw.push_back(TwJob{g1.ksplit > 1 ? g1.work : W, g1.ksplit, jb, nt, w.T + (size_t)p * NB * NB, W});
+    g2s.push_back(gemm_prob((char*)w.V + voff, NB, OP_N, W, nt, OP_N, At, J.lda, mp, nt, jb, -1.f, 1.f));
+  }
   const GemmTypes ty{dt, dt};
+  int rc;
   if (!g1s.empty() && (rc = gemm_run(g1s.data(), (int)g1s.size(), ty, s))) return rc;
+  if (!tw.empty() && (rc = launch_tw(tw, true, dt, s))) return rc;
   if (!g2s.empty() && (rc = gemm_run(g2s.data(), (int)g2s.size(), ty, s))) return rc;
   return 0;
 }
 
-int qr_factor_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s) {
+int qr_factor_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s, const QrAsync* as) {
   int maxp = 0, rc;
   for (int j = 0; j < njobs; ++j) {
     const QrJob& J = jobs[j];
@@ -388,10 +485,36 @@ int qr_factor_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s) {
     if ((rc = fill_zero(J.w->sync, grid_sync_words(kMaxPanelBlocks) * 4, s))) return rc;
     maxp = std::max(maxp, (J.n + NB - 1) / NB);
   }
-  for (int p = 0; p < maxp; ++p)
-    if ((rc = factor_panel_step(jobs, njobs, p, dt, s))) return rc;
+  if (!as || !as->aux) {
+    // in order on one stream: panel p, then every column right of it
+    for (int p = 0; p < maxp; ++p) {
+      if ((rc = launch_panels(jobs, njobs, p, dt, s))) return rc;
+      if ((rc = update_columns(jobs, njobs, p, dt, p + 1, 1 << 20, false, s))) return rc;
+    }
+    return 0;
+  }
+  // Look-ahead: after panel p-1 only the next panel's columns are updated on
+  // s (once the trailing update of panel p-2 has reached them) and panel p
+  // starts at once; the update of the remaining columns by panel p-1 runs on
+  // the auxiliary stream meanwhile.  The cooperative panels occupy a fraction
+  // of the CUs, so the two overlap.
+  for (int p = 0; p <= maxp; ++p) {
+    if (p >= 1) {
+      if (p >= 2) QT_HIP_CHECK(hipStreamWaitEvent(s, as->ev_trail, 0));
+      if ((rc = update_columns(jobs, njobs, p - 1, dt, p, p + 1, true, s))) return rc;
+      QT_HIP_CHECK(hipStreamWaitEvent(as->aux, as->ev_panel, 0));
+      if ((rc = update_columns(jobs, njobs, p - 1, dt, p + 1, 1 << 20, false, as->aux))) return rc;
+      QT_HIP_CHECK(hipEventRecord(as->ev_trail, as->aux));
+    }
+    if (p < maxp) {
+      if ((rc = launch_panels(jobs, njobs, p, dt, s))) return rc;
+      QT_HIP_CHECK(hipEventRecord(as->ev_panel, s));
+    }
+  }
+  if (maxp >= 1) QT_HIP_CHECK(hipStreamWaitEvent(s, as->ev_trail, 0));
   return 0;
 }
+
 
 // Z_j := H_0 H_1 ... Z_j for every job (Z rows j0.. of each panel); set_id
 // first overwrites Z_j with [I; 0] (explicit Q).
@@ -406,9 +529,11 @@ static int apply_batch(const QrJob* jobs, int njobs, int dt, bool set_id, hipStr
     if (J.nz > J.w->wcols) return set_error(-1, "qr_apply_q: %d columns exceed the work size %d", J.nz, J.w->wcols);
   }
   std::vector<GemmProb> g1s, g2s;
+  std::vector<TwJob> tw;
   for (int p = maxp - 1; p >= 0; --p) {
     g1s.clear();
     g2s.clear();
+    tw.clear();
     for (int j = 0; j < njobs; ++j) {
       const QrJob& J = jobs[j];
       const int j0 = p * NB;
@@ -422,10 +547,13 @@ static int apply_batch(const QrJob* jobs, int njobs, int dt, bool set_id, hipStr
       GemmProb g1 = gemm_prob((char*)J.w->V + voff, NB, OP_C, Zs, J.ldz, OP_N, J.w->W, nz, jb, nz, mp);
       g1.ksplit = splitk_for(jb, nz, mp);
       g1.work = J.w->Wsplit;
+      g1.skip_reduce = 1;
       g1s.push_back(g1);
-      g2s.push_back(gemm_prob((char*)J.w->VT + voff, NB, OP_N, J.w->W, nz, OP_N, Zs, J.ldz, mp, nz, jb, -1.f, 1.f));
+      tw.push_back(TwJob{g1.ksplit > 1 ? g1.work : J.w->W, g1.ksplit, jb, nz, J.w->T + (size_t)p * NB * NB, J.w->W});
+      g2s.push_back(gemm_prob((char*)J.w->V + voff, NB, OP_N, J.w->W, nz, OP_N, Zs, J.ldz, mp, nz, jb, -1.f, 1.f));
     }
     if (!g1s.empty() && (rc = gemm_run(g1s.data(), (int)g1s.size(), ty, s))) return rc;
+    if (!tw.empty() && (rc = launch_tw(tw, false, dt, s))) return rc;
     if (!g2s.empty() && (rc = gemm_run(g2s.data(), (int)g2s.size(), ty, s))) return rc;
   }
   return 0;

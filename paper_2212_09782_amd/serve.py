@@ -88,8 +88,8 @@ class Executor:
             st = lib.State(self.ctx, [e] * req.L, [np.ones(1)] * req.L, finite=req.finite,
                            chi_cap=req.chi_max, prec=req.prec)
             gates = lib.chain_gates(req.d, req.g, req.L, req.finite, req.dt)
-        Z = np.diag(np.exp(2j * np.pi * np.arange(req.d) / req.d))
-        zz = torch.from_numpy((Z + Z.conj().T).reshape(-1)).to("cuda")
+            Z = np.diag(np.exp(2j * np.pi * np.arange(req.d) / req.d))
+            zz = torch.from_numpy((Z + Z.conj().T).reshape(-1)).to("cuda")
         self.states[req.rid] = (st, gates, zz)
 
     def step(self, reqs):
@@ -105,8 +105,11 @@ class Executor:
     def finish(self, req):
         torch, lib = self.torch, self.lib
         st, gates, zz = self.states.pop(req.rid)
-        vals = torch.zeros(2 * req.L, dtype=torch.float64, device="cuda")
-        lib.mps_measure(self.ctx, st, op1=zz, site_vals=vals, stream=self.stream)
+        # every device tensor of this executor lives on its stream: a zero fill
+        # queued on another stream would be unordered with the measurement
+        with torch.cuda.stream(self.stream):
+            vals = torch.zeros(2 * req.L, dtype=torch.float64, device="cuda")
+            lib.mps_measure(self.ctx, st, op1=zz, site_vals=vals, stream=self.stream)
         self.stream.synchronize()
         req.result = {"zz": vals.cpu().numpy().reshape(req.L, 2)[:, 0].copy(), "chis": st.chis()}
         st.close()

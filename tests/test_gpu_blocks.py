@@ -26,7 +26,8 @@ def op(a, o):
     return a if o == 0 else (a.T if o == 1 else a.conj().T)
 
 
-GEMM_SHAPES = [(1, 1, 1), (17, 33, 5), (64, 64, 16), (130, 70, 200), (5, 300, 1000), (257, 129, 65)]
+GEMM_SHAPES = [(1, 1, 1), (17, 33, 5), (64, 64, 16), (130, 70, 200), (5, 300, 1000), (257, 129, 65),
+               (128, 128, 16), (300, 260, 47), (513, 640, 300)]
 
 
 @pytest.mark.parametrize("dt", [lib.DT_C128, lib.DT_C64])

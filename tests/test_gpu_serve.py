@@ -35,5 +35,8 @@ def test_alone_equals_mix():
         ex.close()
     assert rep["requests"] == 4 and rep["rejected"] == 0
     for r in reqs:
+        print(f"request {r.rid}: alone {np.round(alone[r.rid], 6)} mix {np.round(r.result['zz'], 6)} "
+              f"chis {r.result['chis']}", flush=True)
+    for r in reqs:
         assert np.max(np.abs(r.result["zz"] - alone[r.rid])) < 1e-12, r.rid
     print(rep)
