@@ -42,17 +42,47 @@ __device__ inline void latch_error(int* status, int bit) {
 }
 
 // ---------------------------------------------------------------- reductions
-// Wave64 sum via cross-lane shuffles.
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Lane moves inside the VALU (DPP), no LDS traffic.  Lanes whose source is
+// outside the row, or whose row is masked off, receive 0.
+template <int CTRL, int ROW_MASK = 0xf, bool BOUND = false>
+__device__ inline double dpp_mov(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xf, BOUND);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xf, BOUND);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROW_MASK = 0xf, bool BOUND = false>
+__device__ inline float dpp_mov(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, BOUND));
+}
+__device__ inline double lane_read(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+__device__ inline float lane_read(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// Sum over each row of 16 lanes: lane 16 r + 15 ends with row r's total
+// (quad swaps, then shifts by 4 and 8 within the row).
+template <typename T>
+__device__ inline T row16_sum(T v) {
+  v += dpp_mov<0xb1>(v);              // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4e>(v);              // quad_perm [2,3,0,1]
+  v += dpp_mov<0x114, 0xf, true>(v);  // row_shr:4
+  v += dpp_mov<0x118, 0xf, true>(v);  // row_shr:8
   return v;
 }
-__device__ inline float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Sum over the wave left in lane 63 (row totals combined by row broadcasts).
+template <typename T>
+__device__ inline T wave_sum_to63(T v) {
+  v = row16_sum(v);
+  v += dpp_mov<0x142, 0xa>(v);        // row_bcast:15 into rows 1 and 3
+  v += dpp_mov<0x143, 0xc>(v);        // row_bcast:31 into rows 2 and 3
   return v;
 }
+// Wave64 sum, every lane gets it (fixed order).
+__device__ inline double wave_sum(double v) { return lane_read(wave_sum_to63(v), 63); }
+__device__ inline float wave_sum(float v) { return lane_read(wave_sum_to63(v), 63); }
 __device__ inline double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));

@@ -5,15 +5,15 @@
 //     lower form) in one cooperative kernel.  The matrix rows live in LDS,
 //     dealt cyclically to the blocks; the reflector vector, the trailing
 //     row and the rank-2 update vector live in registers (column j of a
-//     vector belongs to thread j mod 256).  Step k needs one grid barrier:
+//     vector belongs to thread j mod 512).  Step k needs one grid barrier:
 //     each block publishes its slice of p = tau A v and its part of p^H v,
 //     and the current row k+1; after the barrier every block rebuilds row k+1
 //     itself and derives the next reflector without further communication.
 //     T is real symmetric because every off-diagonal beta is real.
-//  2. The wanted (largest) eigenvalues of T by Sturm-count bisection, one
-//     thread per eigenvalue.
+//  2. The wanted (largest) eigenvalues of T by Sturm-count multisection, one
+//     wave per eigenvalue (64 points per round).
 //  3. Their eigenvectors by inverse iteration on T (tridiagonal LU with
-//     partial pivoting, three solves from a fixed pseudo-random start), one
+//     partial pivoting, two solves from a fixed pseudo-random start), one
 //     thread per vector.
 //  4. Re-orthogonalisation: modified Gram-Schmidt (two passes) inside each
 //     cluster of eigenvalues closer than 1e-9 |T| (where independent inverse
@@ -33,8 +33,9 @@ namespace qrtebd {
 namespace {
 
 constexpr int NB = kQrNb;
-constexpr int QMAX = 8;            // register slots per thread: n <= 2048
-constexpr int kMaxN = 256 * QMAX;
+constexpr int kMaxN = 2048;         // largest matrix
+constexpr int kTriThreads = 512;    // threads of a tridiagonalisation block (two waves per SIMD)
+constexpr int QMAX = kMaxN / kTriThreads;   // register slots per thread
 constexpr size_t kTriLds = 150 * 1024;
 constexpr int kTriRows = 8;           // rows per block at most (register partials of A v)
 
@@ -82,38 +83,20 @@ __device__ inline c128 block_sum_c(c128 v, c128* scr) {
   return s;
 }
 
-// Sum over the 64 lanes of x[0..15] (reduce-scatter butterfly, 17 shuffles):
-// on return every lane l holds the total of entry (l >> 2) & 15.
-__device__ inline double wave_reduce_scatter16(double (&x)[16]) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 32, h = 8; o >= 4; o >>= 1, h >>= 1) {
-    const bool hi = (lane & o) != 0;
-#pragma unroll
-    for (int i = 0; i < h; ++i) {
-      const double keep = hi ? x[i + h] : x[i];
-      const double send = hi ? x[i] : x[i + h];
-      x[i] = keep + __shfl_xor(send, o, 64);
-    }
-  }
-  const double t = x[0] + __shfl_xor(x[0], 1, 64);
-  return t + __shfl_xor(t, 2, 64);
-}
-
 // Householder tridiagonalisation of one Hermitian matrix per block group.
 // Rows are distributed cyclically (global row blk + r P in local row r, kept
 // in LDS); every block also holds the current row k+1 and the vectors v, w
-// of the step in registers (element j = tid + 256 q).  Step k: the reflector
+// of the step in registers (element j = tid + 512 q).  Step k: the reflector
 // of row k (every block derives it from the same data), p = tau A v over the
 // own rows, one grid barrier to exchange p and p^H v, w = p - tau/2 (p^H v) v,
 // the rank-2 update A -= v w^H + w v^H.  The update of step k and the product
 // A v of step k+1 share one pass over LDS: the reflector of row k+1 is formed
 // first from the updated row k+1 (published by its owner before the barrier).
-__global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
+__global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriBatch batch) {
   extern __shared__ c128 rows[];  // rows_loc x n, local row r = global row blk + r * P
   __shared__ double scratch[8];
   __shared__ c128 cscr[8];
-  __shared__ double wred[4][16];
+  __shared__ double wred[kTriThreads / 64][16];
   __shared__ c128 vloc[2][kTriRows], wloc[kTriRows];
   __shared__ c128 scal[4];
   __shared__ int flag;
@@ -130,14 +113,14 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
   for (int r = 0; r < RL; ++r) {
     const int gi = blk + r * P;
     if (gi < n)
-      for (int j = tid; j < n; j += 256) rows[r * n + j] = a.G[(long long)gi * n + j];
+      for (int j = tid; j < n; j += kTriThreads) rows[r * n + j] = a.G[(long long)gi * n + j];
   }
-  // own[q]: local row of global row j = tid + 256 q if this block owns it, else -1
+  // own[q]: local row of global row j = tid + 512 q if this block owns it, else -1
   int own[QMAX];
   c128 rk[QMAX], v[QMAX], w[QMAX];
 #pragma unroll
   for (int q = 0; q < QMAX; ++q) {
-    const int j = tid + 256 * q;
+    const int j = tid + kTriThreads * q;
     own[q] = (j < n && j % P == blk) ? j / P : -1;
     rk[q] = j < n ? a.G[j] : z0();
     v[q] = z0();
@@ -147,7 +130,7 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
   __syncthreads();
   if (n > 1 && 1 % P == blk) {   // row 1, final for step 0
     const int r = 1 / P;
-    for (int j = tid; j < n; j += 256) pub_store(a.rowbuf + j, rows[r * n + j]);
+    for (int j = tid; j < n; j += kTriThreads) pub_store(a.rowbuf + j, rows[r * n + j]);
   }
 
   // Reflector of row kk (held in rk): tau, the vector v (registers, vloc[vb]
@@ -157,7 +140,7 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
     double xn2 = 0;
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      const int j = tid + 256 * q;
+      const int j = tid + kTriThreads * q;
       if (j >= kk + 2 && j < n) xn2 += cabs2(rk[q]);
       if (j == kk + 1) scal[0] = cconj(rk[q]);
       if (j == kk) scal[1] = rk[q];
@@ -184,7 +167,7 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
     c128* Vp = a.V + (size_t)p * mqr * NB;
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      const int j = tid + 256 * q;
+      const int j = tid + kTriThreads * q;
       v[q] = j == kk + 1 ? mk<double>(1, 0) : (j > kk + 1 && j < n ? cmul(cconj(rk[q]), scale) : z0());
       if (own[q] >= 0) {
         vloc[vb][own[q]] = v[q];
@@ -196,15 +179,19 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
   // p = tau A v over the own rows i > kk from the partial sums acc[2r], acc[2r+1]
   // of this thread; publishes p, this block's p^H v (slot sl) and returns.
   auto publish_p = [&](double (&acc)[16], int kk, int sl, int vb) {
-    const double tot = wave_reduce_scatter16(acc);
-    if ((lane & 3) == 0) wred[wid][(lane >> 2) & 15] = tot;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = wave_sum_to63(acc[e]);
+    if (lane == 63)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) wred[wid][e] = acc[e];
     __syncthreads();
     if (wid == 0) {
       c128 part = z0();
       if (lane < RL) {
         const int r = lane, gi = blk + r * P;
-        const c128 s = mk<double>(wred[0][2 * r] + wred[1][2 * r] + wred[2][2 * r] + wred[3][2 * r],
-                                  wred[0][2 * r + 1] + wred[1][2 * r + 1] + wred[2][2 * r + 1] + wred[3][2 * r + 1]);
+        c128 s = z0();
+#pragma unroll
+        for (int g = 0; g < kTriThreads / 64; ++g) s = cadd(s, mk<double>(wred[g][2 * r], wred[g][2 * r + 1]));
         if (gi > kk && gi < n) {
           const c128 pv = cmul(tau, s);
           pub_store(a.pbuf + (long long)sl * n + gi, pv);
@@ -232,7 +219,7 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
           c128 s = z0();
 #pragma unroll
           for (int q = 0; q < QMAX; ++q) {
-            const int j = tid + 256 * q;
+            const int j = tid + kTriThreads * q;
             if (j > 0 && j < n) s = cadd(s, cmul(rows[r * n + j], v[q]));
           }
           acc[2 * r] = s.re;
@@ -251,7 +238,7 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
     c128 pv[QMAX], xb[QMAX];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      const int j = tid + 256 * q;
+      const int j = tid + kTriThreads * q;
       pv[q] = (j > k && j < n) ? pub_load(a.pbuf + (long long)slot * n + j) : z0();
       xb[q] = j < n ? pub_load(a.rowbuf + (long long)slot * n + j) : z0();
     }
@@ -260,7 +247,7 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
     // ---- w = p + alpha2 v
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      const int j = tid + 256 * q;
+      const int j = tid + kTriThreads * q;
       w[q] = (j > k && j < n) ? cadd(pv[q], cmul(alpha2, v[q])) : z0();
       if (j == k + 1) scal[2] = w[q];
       if (own[q] >= 0) wloc[own[q]] = w[q];
@@ -270,7 +257,7 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
     const c128 wk1 = scal[2];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      const int j = tid + 256 * q;
+      const int j = tid + kTriThreads * q;
       rk[q] = j < n ? (j > k ? rank2_sub(xb[q], mk<double>(1, 0), w[q], wk1, v[q]) : xb[q]) : z0();
     }
     if (k + 1 >= n - 1) break;   // no reflector left: rk is the last row
@@ -294,7 +281,7 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
           c128 s = z0();
 #pragma unroll
           for (int q = 0; q < QMAX; ++q) {
-            const int j = tid + 256 * q;
+            const int j = tid + kTriThreads * q;
             if (j > k && j < n) {
               const c128 x = rank2_sub(rows[r * n + j], vi, w[q], wi, vk[q]);
               rows[r * n + j] = x;
@@ -311,7 +298,7 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
     // row k+2, final for step k+1, from its owner
     if ((k + 2) % P == blk) {
       const int r = (k + 2) / P;
-      for (int j = tid; j < n; j += 256) pub_store(a.rowbuf + (long long)(slot ^ 1) * n + j, rows[r * n + j]);
+      for (int j = tid; j < n; j += kTriThreads) pub_store(a.rowbuf + (long long)(slot ^ 1) * n + j, rows[r * n + j]);
     }
     if (!grid_barrier(gs, (unsigned)(k + 2), blk, P, &flag)) return;
   }
@@ -319,7 +306,7 @@ __global__ __launch_bounds__(256) void tridiag_kernel(TriBatch batch) {
   if (blk == 0) {
 #pragma unroll
     for (int q = 0; q < QMAX; ++q)
-      if (tid + 256 * q == n - 1) {
+      if (tid + kTriThreads * q == n - 1) {
         a.d[n - 1] = rk[q].re;
         a.e[n - 1] = 0.0;
         a.tau[n - 1] = z0();
@@ -780,7 +767,7 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
     auto flush = [&]() -> int {
       if (tb.nprob == 0) return 0;
       void* args[] = {(void*)&tb};
-      QT_HIP_CHECK(hipLaunchCooperativeKernel((const void*)tridiag_kernel, dim3(used), dim3(256), args,
+      QT_HIP_CHECK(hipLaunchCooperativeKernel((const void*)tridiag_kernel, dim3(used), dim3(kTriThreads), args,
                                               (unsigned)shmem, s));
       tb = TriBatch{};
       used = 0;

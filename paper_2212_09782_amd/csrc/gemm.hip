@@ -102,10 +102,13 @@ __device__ __forceinline__ void gemm_body_l(const GemmBatch& b) {
       acc_im[i][j] = v4{0, 0, 0, 0};
     }
 
-  // staging: 8 elements of each operand per thread and stage
+  // staging: 8 elements of each operand per thread and stage.  k-contiguous
+  // source (128 rows x 16 k): 8 consecutive k of one row.  Row-contiguous
+  // source (16 k x 128 columns): 4 consecutive k of 2 adjacent columns, so
+  // that LDS receives 16-byte k-contiguous chunks in both cases.
   c64 ra[8], rb[8];
-  const int r_row = tid >> 1, r_k = (tid & 1) * 8;     // k-contiguous source: 128 rows x 16 k
-  const int c_k = tid >> 4, c_col = (tid & 15) * 8;    // row-contiguous source: 16 k x 128 columns
+  const int r_row = tid >> 1, r_k = (tid & 1) * 8;
+  const int c_kq = (tid & 3) * 4, c_col = (tid >> 2) * 2;
   auto load = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -113,14 +116,14 @@ __device__ __forceinline__ void gemm_body_l(const GemmBatch& b) {
       if (opA == OP_N) {
         const int m = m0 + r_row, k = k0 + r_k + e;
         if (m < M && k < kend) z = A[(long long)m * lda + k];
-      } else {
-        const int k = k0 + c_k, m = m0 + c_col + e;
+      } else {   // element e: column c_col + (e & 1), k = c_kq + (e >> 1)
+        const int k = k0 + c_kq + (e >> 1), m = m0 + c_col + (e & 1);
         if (m < M && k < kend) z = A[(long long)k * lda + m];
       }
       ra[e] = z;
       c64 w = mk<float>(0, 0);
       if (opB == OP_N) {
-        const int k = k0 + c_k, n = n0 + c_col + e;
+        const int k = k0 + c_kq + (e >> 1), n = n0 + c_col + (e & 1);
         if (n < N && k < kend) w = B[(long long)k * ldb + n];
       } else {
         const int n = n0 + r_row, k = k0 + r_k + e;
@@ -140,9 +143,10 @@ __device__ __forceinline__ void gemm_body_l(const GemmBatch& b) {
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        As[buf][0][c_col + e][c_k] = ra[e].re;
-        As[buf][1][c_col + e][c_k] = sa * ra[e].im;
+      for (int h = 0; h < 2; ++h) {
+        *(v4*)&As[buf][0][c_col + h][c_kq] = v4{ra[h].re, ra[2 + h].re, ra[4 + h].re, ra[6 + h].re};
+        *(v4*)&As[buf][1][c_col + h][c_kq] =
+            v4{sa * ra[h].im, sa * ra[2 + h].im, sa * ra[4 + h].im, sa * ra[6 + h].im};
       }
     }
     if (opB != OP_N) {
@@ -155,9 +159,10 @@ __device__ __forceinline__ void gemm_body_l(const GemmBatch& b) {
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        Bs[buf][0][c_col + e][c_k] = rb[e].re;
-        Bs[buf][1][c_col + e][c_k] = sb * rb[e].im;
+      for (int h = 0; h < 2; ++h) {
+        *(v4*)&Bs[buf][0][c_col + h][c_kq] = v4{rb[h].re, rb[2 + h].re, rb[4 + h].re, rb[6 + h].re};
+        *(v4*)&Bs[buf][1][c_col + h][c_kq] =
+            v4{sb * rb[h].im, sb * rb[2 + h].im, sb * rb[4 + h].im, sb * rb[6 + h].im};
       }
     }
   };

@@ -58,7 +58,7 @@ constexpr int kRowGroups = kPanelThreads / 32;
 template <typename S>
 __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batch) {
   extern __shared__ c128 P[];  // rows_per_blk x LDP
-  __shared__ c128 part[kPanelThreads / 64][NB];
+  __shared__ c128 part[kRowGroups][NB];
   __shared__ c128 tsum[NB];
   __shared__ c128 Sk[NB][NB + 1];   // per column k: V[:, j]^dag v_k for j < k (builds T after the loop)
   __shared__ c128 Tm[NB][NB + 1];
@@ -95,15 +95,13 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
 
   for (int k = 0; k < jb; ++k) {
     const int slot = k & 1;
-    // block partial: lanes c and c + 32 of a wave hold rows of equal parity
-    acc.re += __shfl_xor(acc.re, 32, 64);
-    acc.im += __shfl_xor(acc.im, 32, 64);
-    if ((tid & 63) < 32) part[tid >> 6][c] = acc;
+    // block partial over the row groups
+    part[rg][c] = acc;
     __syncthreads();
     if (tid < NB) {
       c128 sblk = cz();
 #pragma unroll
-      for (int g = 0; g < kPanelThreads / 64; ++g) sblk = cadd(sblk, part[g][tid]);
+      for (int g = 0; g < kRowGroups; ++g) sblk = cadd(sblk, part[g][tid]);
       pub_store(a.red + ((long long)slot * nblk + blk) * NB + tid, sblk);
       if (k >= r0 && k < r0 + nr) pub_store(a.rowbuf + slot * NB + tid, P[(k - r0) * LDP + tid]);
     }
@@ -121,12 +119,9 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
       c128 t = cz();
 #pragma unroll
       for (int q = 0; q < kMaxPer; ++q) t = cadd(t, v[q]);
-#pragma unroll
-      for (int o = 1; o < 16; o <<= 1) {
-        t.re += __shfl_xor(t.re, o, 64);
-        t.im += __shfl_xor(t.im, o, 64);
-      }
-      if (bg == 0) tsum[cl] = t;
+      t.re = row16_sum(t.re);   // the 16 lanes of column cl form one DPP row
+      t.im = row16_sum(t.im);
+      if (bg == 15) tsum[cl] = t;
       if (tid < NB) rowk[tid] = rk;
     }
     __syncthreads();
@@ -191,12 +186,15 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
       c128 sacc = cz();
       if (r < k)
         for (int q = r + ((part - r) & 7); q < k; q += 8) sacc = cadd(sacc, cmul(Tm[r][q], Sk[k][q]));
-#pragma unroll
-      for (int o = 1; o < 8; o <<= 1) {
-        sacc.re += __shfl_xor(sacc.re, o, 64);
-        sacc.im += __shfl_xor(sacc.im, o, 64);
-      }
-      if (part == (k & 7) && r < k) Tm[r][k] = cmul(mk<double>(-taus[k].re, -taus[k].im), sacc);
+      // sum over the 8 lanes of the row (DPP): quad sums, then lanes 4..7 of
+      // each 8-lane group add the quad below, so lane 7 holds the total
+      sacc.re += dpp_mov<0xb1>(sacc.re);
+      sacc.im += dpp_mov<0xb1>(sacc.im);
+      sacc.re += dpp_mov<0x4e>(sacc.re);
+      sacc.im += dpp_mov<0x4e>(sacc.im);
+      sacc.re += dpp_mov<0x114, 0xf, true>(sacc.re);
+      sacc.im += dpp_mov<0x114, 0xf, true>(sacc.im);
+      if (part == 7 && r < k) Tm[r][k] = cmul(mk<double>(-taus[k].re, -taus[k].im), sacc);
     }
   }
   __syncthreads();
