@@ -1,6 +1,7 @@
 // C ABI of libqrtebd: contexts, errors, the clock-model gate builder, bond
 // updates, device-resident MPS, the even/odd Trotter sweep and measurements.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -161,7 +162,21 @@ int mps_ctx_create(int device, mps_ctx* out) {
     delete c;
     return set_error(MPS_ERR_HIP, "context allocation failed");
   }
-  if (hipStreamCreateWithFlags(&c->qa.aux, hipStreamNonBlocking) != hipSuccess ||
+  // The auxiliary stream (trailing updates of the QR look-ahead) leaves one
+  // CU in eight to the cooperative panel kernels that run beside it, so the
+  // two really overlap; a plain stream if the masked one is unavailable.
+  {
+    int ncu = 0;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+    std::vector<uint32_t> mask((std::max(ncu, 1) + 31) / 32, 0u);
+    for (int cu = 0; cu < ncu; ++cu)
+      if (cu % 8 != 0) mask[cu / 32] |= 1u << (cu % 32);
+    if (ncu < 64 || hipExtStreamCreateWithCUMask(&c->qa.aux, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+      (void)hipGetLastError();
+      c->qa.aux = nullptr;
+    }
+  }
+  if ((!c->qa.aux && hipStreamCreateWithFlags(&c->qa.aux, hipStreamNonBlocking) != hipSuccess) ||
       hipEventCreateWithFlags(&c->qa.ev_panel, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->qa.ev_trail, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();

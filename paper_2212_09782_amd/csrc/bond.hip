@@ -345,8 +345,14 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
     std::vector<EigJob> ej;
     std::vector<EigWork> ew(nc);
     for (int i : cb) {
-      const int eta = calls[i].b.eta;
-      g.push_back(gemm_prob(W[i].R, eta, OP_N, W[i].R, eta, OP_C, W[i].G, eta, eta, eta, eta));
+      const BondShape& b = calls[i].b;
+      const int eta = b.eta;
+      // theta~ is no longer needed: its buffer holds the split-K partials
+      const size_t th_bytes = (size_t)b.d * b.chi_l * b.d * b.chi_r * sizeof(cpx<S>);
+      GemmProb gg = gemm_prob(W[i].R, eta, OP_N, W[i].R, eta, OP_C, W[i].G, eta, eta, eta, eta);
+      gg.ksplit = splitk_auto(eta, eta, eta, th_bytes, sizeof(c128));
+      gg.work = W[i].Th;
+      g.push_back(gg);
       ew[i] = eig_work_carve(W[i].eigw, eta, calls[i].status);
     }
     if ((rc = gemm_run(g.data(), (int)g.size(), GemmTypes{dt, DT_C128}, s))) return rc;
@@ -402,6 +408,8 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
       GemmProb g2 = gemm_prob(c.b_n_out, mR, OP_N, c.b_n_out, mR, OP_C, W[i].G2, cap, cap, cap, mR);
       g2.dM = c.chi_new;
       g2.dN = c.chi_new;
+      g2.ksplit = splitk_auto(cap, cap, mR, (size_t)c.b.d * c.b.chi_l * mR * sizeof(cpx<S>), sizeof(c128));
+      g2.work = W[i].Th;
       g.push_back(g2);
     }
     if ((rc = gemm_run(g.data(), nc, GemmTypes{DT_C64, DT_C128}, s))) return rc;

@@ -837,7 +837,11 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
     gs.clear();
     for (int j : big) {
       const EigJob& J = jobs[j];
-      gs.push_back(gemm_prob(J.E, J.kwant, OP_C, J.E, J.kwant, OP_N, J.w->gz, J.kwant, J.kwant, J.kwant, J.n));
+      // the inverse-iteration factors are dead: their buffer holds split-K partials
+      GemmProb g1 = gemm_prob(J.E, J.kwant, OP_C, J.E, J.kwant, OP_N, J.w->gz, J.kwant, J.kwant, J.kwant, J.n);
+      g1.ksplit = splitk_auto(J.kwant, J.kwant, J.n, 4 * (size_t)J.n * J.n * 8, sizeof(c128));
+      g1.work = J.w->lu;
+      gs.push_back(g1);
     }
     if ((rc = gemm_run(gs.data(), (int)gs.size(), ty, s))) return rc;
     gs.clear();
@@ -847,8 +851,11 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
                          J.w->gz, J.kwant);
       QT_HIP_CHECK(hipGetLastError());
       QT_HIP_CHECK(hipMemcpyAsync(J.w->ztmp, J.E, (size_t)J.n * J.kwant * sizeof(c128), hipMemcpyDeviceToDevice, s));
-      gs.push_back(gemm_prob(J.w->ztmp, J.kwant, OP_N, J.w->gz, J.kwant, OP_N, J.E, J.kwant, J.n, J.kwant, J.kwant,
-                             -0.5f, 1.f));
+      GemmProb g2 = gemm_prob(J.w->ztmp, J.kwant, OP_N, J.w->gz, J.kwant, OP_N, J.E, J.kwant, J.n, J.kwant, J.kwant,
+                              -0.5f, 1.f);
+      g2.ksplit = splitk_auto(J.n, J.kwant, J.kwant, 4 * (size_t)J.n * J.n * 8, sizeof(c128));
+      g2.work = J.w->lu;
+      gs.push_back(g2);
     }
     if ((rc = gemm_run(gs.data(), (int)gs.size(), ty, s))) return rc;
   }

@@ -2,6 +2,8 @@
 #pragma once
 #include "common.h"
 
+#include <algorithm>
+
 namespace qrtebd {
 
 enum Op : int { OP_N = 0, OP_T = 1, OP_C = 2 };
@@ -58,6 +60,18 @@ struct GemmTypes {
 int gemm_run(const GemmProb* probs, int nprob, GemmTypes ty, hipStream_t stream, bool contract = false);
 inline int gemm_one(const GemmProb& p, GemmTypes ty, hipStream_t stream, bool contract = false) {
   return gemm_run(&p, 1, ty, stream, contract);
+}
+
+// Split of K for a product whose output has few 64x64 tiles: enough
+// workgroups (about 1024) to fill the GPU, chunks of at least 128, and no
+// more partials ([ks][M][N] of elem bytes) than work_bytes holds.
+inline int splitk_auto(int M, int N, int K, size_t work_bytes, size_t elem) {
+  const long long tiles = (long long)((M + 63) / 64) * ((N + 63) / 64);
+  long long ks = (1024 + tiles - 1) / tiles;
+  ks = std::min<long long>(ks, std::max(1, K / 128));
+  ks = std::min<long long>(ks, (long long)(work_bytes / ((size_t)M * N * elem)));
+  ks = std::min<long long>(ks, 64);
+  return (int)std::max<long long>(1, ks);
 }
 
 // Convenience constructor with static sizes.

@@ -296,26 +296,29 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
       acc_im[i][j] = v4{0, 0, 0, 0};
     }
 
-  cpx<Tin> ra[4], rb[4];
-  // thread -> tile element mapping for the two storage orientations
-  const int rowq = tid >> 2, colq = (tid & 3) * 4;    // 64 rows x 16 cols (k contiguous)
-  const int rowk = tid >> 4, colk = (tid & 15) * 4;   // 16 k-rows x 64 cols
+  // thread -> tile element mapping for the two storage orientations; each
+  // thread stages EPT elements of each operand per stage in groups of 4
+  constexpr int EPT = BM * BK / 256, KG = BK / 16;
+  cpx<Tin> ra[EPT], rb[EPT];
+  const int rowq = tid >> 2, colq = (tid & 3) * (BK / 4);   // 64 rows x BK cols (k contiguous)
+  const int rowk = tid >> 4, colk = (tid & 15) * 4;         // BK k-rows (16 per group) x 64 cols
 
   auto load = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < EPT; ++e) {
+      const int g = e >> 2, e4 = e & 3;
       cpx<Tin> z = mk<Tin>(0, 0);
       if (opA == OP_N) {
         const int m = m0 + rowq, k = k0 + colq + e;
         if (m < M && k < kend) z = A[(long long)m * lda + k];
       } else {
-        const int k = k0 + rowk, m = m0 + colk + e;
+        const int k = k0 + rowk + 16 * g, m = m0 + colk + e4;
         if (m < M && k < kend) z = A[(long long)k * lda + m];
       }
       ra[e] = z;
       cpx<Tin> w = mk<Tin>(0, 0);
       if (opB == OP_N) {
-        const int k = k0 + rowk, n = n0 + colk + e;
+        const int k = k0 + rowk + 16 * g, n = n0 + colk + e4;
         if (n < N && k < kend) w = B[(long long)k * ldb + n];
       } else {
         const int n = n0 + rowq, k = k0 + colq + e;
@@ -326,17 +329,18 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < EPT; ++e) {
+      const int g = e >> 2, e4 = e & 3;
       if (opA == OP_N) {
         As[buf][0][colq + e][rowq] = (Tc)ra[e].re;
         As[buf][1][colq + e][rowq] = sa * (Tc)ra[e].im;
       } else {
-        As[buf][0][rowk][colk + e] = (Tc)ra[e].re;
-        As[buf][1][rowk][colk + e] = sa * (Tc)ra[e].im;
+        As[buf][0][rowk + 16 * g][colk + e4] = (Tc)ra[e].re;
+        As[buf][1][rowk + 16 * g][colk + e4] = sa * (Tc)ra[e].im;
       }
       if (opB == OP_N) {
-        Bs[buf][0][rowk][colk + e] = (Tc)rb[e].re;
-        Bs[buf][1][rowk][colk + e] = sb * (Tc)rb[e].im;
+        Bs[buf][0][rowk + 16 * g][colk + e4] = (Tc)rb[e].re;
+        Bs[buf][1][rowk + 16 * g][colk + e4] = sb * (Tc)rb[e].im;
       } else {
         Bs[buf][0][colq + e][rowq] = (Tc)rb[e].re;
         Bs[buf][1][colq + e][rowq] = sb * (Tc)rb[e].im;

@@ -12,8 +12,7 @@ struct QrWork {
   c128* T;        // per panel 32 x 32 upper triangular (compact-WY factor)
   void* W;        // 32 x n product V^H A (element type of the storage)
   void* Wsplit;   // split-K partials: kMaxSplit x 32 x n in the compute type
-  void* Wn;       // 32 x 32 product for the next panel's columns (look-ahead)
-  void* Wnsplit;  // its split-K partials: kMaxSplit x 32 x 32
+  c128* wx;       // panel blocks x 32 x 32: partial products of the previous panel's reflectors
   c128* red;      // panel reductions: 2 x nblk x 32 + 2 x 32
   unsigned* sync; // grid barrier words (>= grid_sync_words(kMaxPanelBlocks))
   int* status;

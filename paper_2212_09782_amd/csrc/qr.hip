@@ -35,6 +35,13 @@ struct PanelProb {
   long long lda;
   void* V;
   c128* T;
+  // reflectors of the previous panel, applied to this panel's columns first
+  // (null for the first panel): V from the row 32 above this panel, its T,
+  // the 32 rows of A above the panel (entries of R) and the exchange buffer
+  const void* Vprev;
+  const c128* Tprev;
+  void* Atop;
+  c128* wx;
   c128* red;
   c128* rowbuf;
   unsigned* sync;
@@ -54,6 +61,7 @@ constexpr int kMaxPanelRows = 160;
 
 constexpr int kPanelThreads = 512;   // 16 row groups x 32 columns: two waves per SIMD
 constexpr int kRowGroups = kPanelThreads / 32;
+__device__ inline int rg_of(int tid) { return tid >> 5; }
 
 template <typename S>
 __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batch) {
@@ -83,6 +91,149 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
   if (tid == 0) flag = 0;
   __syncthreads();
 
+  if (a.Vprev) {
+    // The previous panel's reflectors on this panel's columns (rows from 32
+    // above the panel): W = V^H A over all rows (block partials exchanged
+    // through one barrier), W <- T^H W, A -= V W on the slab in LDS and, in
+    // block 0, on the 32 rows above (written back: they belong to R).
+    const cpx<S>* Vp = (const cpx<S>*)a.Vprev;
+    cpx<S>* At = (cpx<S>*)a.Atop;
+    const int cc = tid & 31, q0 = tid >> 5;   // outputs (q0, cc) and (q0 + 16, cc)
+    // V rows in 32-row chunks through Sk (free until the column loop).  Chunk
+    // 0 of block 0 is the 32 rows above the panel (their A rows go through Tm);
+    // the slab's chunks follow.  Each thread loads elements tid and tid + 512
+    // of a chunk, one chunk ahead of its use.
+    const int top = blk == 0 ? 1 : 0;
+    const int nch = (nr + NB - 1) / NB + top;
+    auto chunk_rows = [&](int ch) { return ch < top ? NB : min(NB, nr - (ch - top) * NB); };
+    auto load_v = [&](int ch, int e) -> c128 {
+      const int idx = tid + kPanelThreads * e, t = idx / NB;
+      if (t >= chunk_rows(ch)) return cz();
+      const long long v0 = ch < top ? 0 : (long long)(NB + r0 + (ch - top) * NB) * NB;
+      return ccast<double>(Vp[v0 + idx]);
+    };
+    c128 vn[2], at[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      vn[e] = load_v(0, e);
+      const int idx = tid + kPanelThreads * e, t = idx / NB, q = idx % NB;
+      at[e] = (top && q < jb) ? ccast<double>(At[(long long)t * a.lda + q]) : cz();
+    }
+    c128 w0[4] = {cz(), cz(), cz(), cz()}, w1[4] = {cz(), cz(), cz(), cz()};
+    for (int ch = 0; ch < nch; ++ch) {
+      {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int idx = tid + kPanelThreads * e;
+          Sk[idx / NB][idx % NB] = vn[e];
+          if (ch < top) Tm[idx / NB][idx % NB] = at[e];
+        }
+        if (ch + 1 < nch)
+#pragma unroll
+          for (int e = 0; e < 2; ++e) vn[e] = load_v(ch + 1, e);
+        __syncthreads();
+        const int rows = chunk_rows(ch);
+        for (int t0 = 0; t0 < rows; t0 += 4)   // four independent accumulation chains
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u;
+            if (t < rows) {
+              const c128 x = ch < top ? Tm[t][cc] : P[((ch - top) * NB + t) * LDP + cc];
+              w0[u] = cadd(w0[u], cmulc(Sk[t][q0], x));
+              w1[u] = cadd(w1[u], cmulc(Sk[t][q0 + 16], x));
+            }
+          }
+      }
+    }
+    pub_store(a.wx + ((long long)blk * NB + q0) * NB + cc, cadd(cadd(w0[0], w0[1]), cadd(w0[2], w0[3])));
+    pub_store(a.wx + ((long long)blk * NB + q0 + 16) * NB + cc, cadd(cadd(w1[0], w1[1]), cadd(w1[2], w1[3])));
+    if (!grid_barrier(gs, (unsigned)(a.gen0 + 1), blk, nblk, &flag)) return;
+    // Block b reduces columns b, b + nblk, ...: W[:, c] = sum of the block
+    // partials, then (T^H W)[:, c], published for everyone.
+    c128* w2 = a.wx + (long long)nblk * NB * NB;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = tid + kPanelThreads * e;
+      Sk[idx / NB][idx % NB] = a.Tprev[idx];
+    }
+    for (int c = blk; c < NB; c += nblk) {
+      const int r = tid & 31, g = tid >> 5;   // 16 groups of blocks
+      c128 acc = cz();
+      for (int b0 = g; b0 < nblk; b0 += 64) {
+        c128 l[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int b = b0 + 16 * u;
+          l[u] = b < nblk ? pub_load(a.wx + ((long long)b * NB + r) * NB + c) : cz();
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = cadd(acc, l[u]);
+      }
+      part[g][r] = acc;
+      __syncthreads();
+      if (tid < NB) {
+        c128 wr = cz();
+#pragma unroll
+        for (int gg = 0; gg < kRowGroups; ++gg) wr = cadd(wr, part[gg][tid]);
+        Tm[tid][0] = wr;
+      }
+      __syncthreads();
+      if (tid < NB) {   // (T^H W)[q][c] = sum_r conj(T[r][q]) W[r][c], q = tid
+        c128 u4[4] = {cz(), cz(), cz(), cz()};
+#pragma unroll
+        for (int r0 = 0; r0 < NB; r0 += 4)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) u4[u] = cadd(u4[u], cmulc(Sk[r0 + u][tid], Tm[r0 + u][0]));
+        pub_store(w2 + (long long)tid * NB + c, cadd(cadd(u4[0], u4[1]), cadd(u4[2], u4[3])));
+      }
+      __syncthreads();
+    }
+    if (!grid_barrier(gs, (unsigned)(a.gen0 + 2), blk, nblk, &flag)) return;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int idx = tid + kPanelThreads * e;
+      Tm[idx / NB][idx % NB] = pub_load(w2 + idx);
+    }
+    // A -= V W: thread (row t of the chunk, column cc), 16 row groups per chunk
+#pragma unroll
+    for (int e = 0; e < 2; ++e) vn[e] = load_v(0, e);
+    for (int ch = 0; ch < nch; ++ch) {
+      {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int idx = tid + kPanelThreads * e;
+          Sk[idx / NB][idx % NB] = vn[e];
+        }
+        if (ch + 1 < nch)
+#pragma unroll
+          for (int e = 0; e < 2; ++e) vn[e] = load_v(ch + 1, e);
+        __syncthreads();
+        const int rows = chunk_rows(ch);
+        for (int t = rg_of(tid); t < rows; t += kRowGroups) {
+          c128 d4[4] = {cz(), cz(), cz(), cz()};
+#pragma unroll
+          for (int q0b = 0; q0b < NB; q0b += 4)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) d4[u] = cadd(d4[u], cmul(Sk[t][q0b + u], Tm[q0b + u][cc]));
+          const c128 d = cadd(cadd(d4[0], d4[1]), cadd(d4[2], d4[3]));
+          if (ch < top) {
+            if (cc < jb) {
+              const long long o = (long long)t * a.lda + cc;
+              At[o] = ccast<S>(csub(ccast<double>(At[o]), d));
+            }
+          } else {
+            c128* x = P + ((ch - top) * NB + t) * LDP + cc;
+            *x = csub(*x, d);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
   // Thread (rg, c) owns column c of the slab rows rg, rg + 16, ...  Its running
   // partial t_c = sum_i conj(P[i,k]) P[i,c] over its rows strictly below the
   // diagonal is formed for column 0 here and for column k + 1 during the
@@ -105,7 +256,7 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
       pub_store(a.red + ((long long)slot * nblk + blk) * NB + tid, sblk);
       if (k >= r0 && k < r0 + nr) pub_store(a.rowbuf + slot * NB + tid, P[(k - r0) * LDP + tid]);
     }
-    if (!grid_barrier(gs, (unsigned)(a.gen0 + k + 1), blk, nblk, &flag)) return;
+    if (!grid_barrier(gs, (unsigned)(a.gen0 + k + 3), blk, nblk, &flag)) return;
     {  // one round of loads: 8 lanes per column share the block partials
       const int cl = tid >> 4, bg = tid & 15;
       constexpr int kMaxPer = kMaxPanelBlocks / 16;
@@ -232,10 +383,19 @@ __global__ void set_identity_kernel(cpx<S>* Q, long long ldq, int m, int n) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Rows per block of a panel with mp rows: about 64 blocks (rows a multiple
+// of 16, at least 32; at most kMaxPanelRows, which fits the slab in LDS).
 int panel_rows(int mp) {
-  int r = (mp + 31) / 32;
-  r = (r + 31) / 32 * 32;
+  int r = (mp + 63) / 64;
+  r = (r + 15) / 16 * 16;
   return std::min(kMaxPanelRows, std::max(32, r));
+}
+
+// Most blocks any panel of an m-row factorisation uses.
+int panel_blocks_max(int m) {
+  int mx = 1;
+  for (int mp = m; mp > 0; mp -= NB) mx = std::max(mx, (mp + panel_rows(mp) - 1) / panel_rows(mp));
+  return mx;
 }
 
 template <typename S>
@@ -291,8 +451,7 @@ size_t qr_work_bytes(int m, int n, int es, int wcols) {
   b += align256(np * NB * NB * sizeof(c128));
   b += align256((size_t)NB * wcols * es);
   b += align256((size_t)kMaxSplit * NB * wcols * sizeof(c128));
-  b += align256((size_t)NB * NB * es);
-  b += align256((size_t)kMaxSplit * NB * NB * sizeof(c128));
+  b += align256((size_t)(panel_blocks_max(m) + 1) * NB * NB * sizeof(c128));
   b += align256((2 * (size_t)kMaxPanelBlocks * NB + 2 * NB) * sizeof(c128));
   b += align256(grid_sync_words(kMaxPanelBlocks) * 4);
   return b;
@@ -308,8 +467,7 @@ QrWork qr_work_carve(void* base, int m, int n, int es, int wcols, int* status) {
   w.T = (c128*)p; p += align256(np * NB * NB * sizeof(c128));
   w.W = p; p += align256((size_t)NB * wcols * es);
   w.Wsplit = p; p += align256((size_t)kMaxSplit * NB * wcols * sizeof(c128));
-  w.Wn = p; p += align256((size_t)NB * NB * es);
-  w.Wnsplit = p; p += align256((size_t)kMaxSplit * NB * NB * sizeof(c128));
+  w.wx = (c128*)p; p += align256((size_t)(panel_blocks_max(m) + 1) * NB * NB * sizeof(c128));
   w.red = (c128*)p; p += align256((2 * (size_t)kMaxPanelBlocks * NB + 2 * NB) * sizeof(c128));
   w.sync = (unsigned*)p;
   w.status = status;
@@ -423,6 +581,12 @@ static int launch_panels(const QrJob* jobs, int njobs, int p, int dt, hipStream_
     const size_t voff = (size_t)p * J.m * NB * es;
     pp.V = (char*)w.V + voff;
     pp.T = w.T + (size_t)p * NB * NB;
+    if (p >= 1) {
+      pp.Vprev = (const char*)w.V + (size_t)(p - 1) * J.m * NB * es;
+      pp.Tprev = w.T + (size_t)(p - 1) * NB * NB;
+      pp.Atop = (char*)J.A + ((long long)(j0 - NB) * J.lda + j0) * es;
+      pp.wx = w.wx;
+    }
     pp.red = w.red;
     pp.rowbuf = w.red + 2 * (size_t)kMaxPanelBlocks * NB;
     pp.sync = w.sync;
@@ -431,7 +595,7 @@ static int launch_panels(const QrJob* jobs, int njobs, int p, int dt, hipStream_
     pp.rows_per_blk = rows;
     pp.nblk = nblk;
     pp.blk0 = used;
-    pp.gen0 = j0;   // generations keep increasing over the panels of one factorisation
+    pp.gen0 = p * (NB + 2);   // two barriers before the columns, one per column; increasing over the panels
     used += nblk;
     max_rows = std::max(max_rows, rows);
   }
@@ -439,9 +603,9 @@ static int launch_panels(const QrJob* jobs, int njobs, int p, int dt, hipStream_
 }
 
 // Apply the reflectors of panel p (as H^H) to the column blocks [b0, b1) of
-// every job (clipped to its n): W = V^H A (split over the rows), A -= V T^H W.
-// next = true uses the small W buffers (the next panel's columns).
-static int update_columns(const QrJob* jobs, int njobs, int p, int dt, int b0, int b1, bool next, hipStream_t s) {
+// every job (clipped to its n): W = V^H A (split over the rows), W <- T^H W
+// in the reduction of the split partials, A -= V W.
+static int update_columns(const QrJob* jobs, int njobs, int p, int dt, int b0, int b1, hipStream_t s) {
   const int es = dt == DT_C128 ? 16 : 8;
   std::vector<GemmProb> g1s, g2s;
   std::vector<TwJob> tw;
@@ -456,10 +620,10 @@ static int update_columns(const QrJob* jobs, int njobs, int p, int dt, int b0, i
     const QrWork& w = *J.w;
     const size_t voff = (size_t)p * J.m * NB * es;
     void* At = (char*)J.A + ((long long)j0 * J.lda + c0) * es;
-    void* W = next ? w.Wn : w.W;
+    void* W = w.W;
     GemmProb g1 = gemm_prob((char*)w.V + voff, NB, OP_C, At, J.lda, OP_N, W, nt, jb, nt, mp);
     g1.ksplit = splitk_for(jb, nt, mp);
-    g1.work = next ? w.Wnsplit : w.Wsplit;
+    g1.work = w.Wsplit;
     g1.skip_reduce = 1;
     g1s.push_back(g1);
     tw.push_back(TwJob{g1.ksplit > 1 ? g1.work : W, g1.ksplit, jb, nt, w.T + (size_t)p * NB * NB, W});
@@ -484,30 +648,30 @@ int qr_factor_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s, const Q
     maxp = std::max(maxp, (J.n + NB - 1) / NB);
   }
   if (!as || !as->aux) {
-    // in order on one stream: panel p, then every column right of it
+    // in order on one stream: panel p (which first applies panel p-1 to its
+    // own columns), then the columns from panel p+2 on
     for (int p = 0; p < maxp; ++p) {
       if ((rc = launch_panels(jobs, njobs, p, dt, s))) return rc;
-      if ((rc = update_columns(jobs, njobs, p, dt, p + 1, 1 << 20, false, s))) return rc;
+      if ((rc = update_columns(jobs, njobs, p, dt, p + 2, 1 << 20, s))) return rc;
     }
     return 0;
   }
-  // Look-ahead: after panel p-1 only the next panel's columns are updated on
-  // s (once the trailing update of panel p-2 has reached them) and panel p
-  // starts at once; the update of the remaining columns by panel p-1 runs on
-  // the auxiliary stream meanwhile.  The cooperative panels occupy a fraction
-  // of the CUs, so the two overlap.
+  // Look-ahead: panel p applies panel p-1 to its own columns itself and
+  // starts once the trailing update of panel p-2 has reached them; the update
+  // of the columns from panel p+1 on by panel p-1 runs on the auxiliary
+  // stream meanwhile.  The cooperative panels occupy a fraction of the CUs,
+  // so the two overlap.
   for (int p = 0; p <= maxp; ++p) {
     if (p >= 1) {
-      if (p >= 2) QT_HIP_CHECK(hipStreamWaitEvent(s, as->ev_trail, 0));
-      if ((rc = update_columns(jobs, njobs, p - 1, dt, p, p + 1, true, s))) return rc;
       QT_HIP_CHECK(hipStreamWaitEvent(as->aux, as->ev_panel, 0));
-      if ((rc = update_columns(jobs, njobs, p - 1, dt, p + 1, 1 << 20, false, as->aux))) return rc;
-      QT_HIP_CHECK(hipEventRecord(as->ev_trail, as->aux));
+      if ((rc = update_columns(jobs, njobs, p - 1, dt, p + 1, 1 << 20, as->aux))) return rc;
     }
     if (p < maxp) {
+      if (p >= 2) QT_HIP_CHECK(hipStreamWaitEvent(s, as->ev_trail, 0));
       if ((rc = launch_panels(jobs, njobs, p, dt, s))) return rc;
       QT_HIP_CHECK(hipEventRecord(as->ev_panel, s));
     }
+    if (p >= 1) QT_HIP_CHECK(hipEventRecord(as->ev_trail, as->aux));
   }
   if (maxp >= 1) QT_HIP_CHECK(hipStreamWaitEvent(s, as->ev_trail, 0));
   return 0;
