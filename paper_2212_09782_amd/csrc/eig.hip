@@ -164,14 +164,14 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriBatch batch) {
       if (!isfinite(beta) || !isfinite(scal[1].re)) latch_error(batch.status, ERRBIT_NONFINITE);
     }
     const int p = kk / NB, c = kk % NB, j0 = p * NB;
-    c128* Vp = a.V + (size_t)p * mqr * NB;
+    c128* Vp = a.V + qr_v_offset(p, mqr);
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
       const int j = tid + kTriThreads * q;
       v[q] = j == kk + 1 ? mk<double>(1, 0) : (j > kk + 1 && j < n ? cmul(cconj(rk[q]), scale) : z0());
       if (own[q] >= 0) {
         vloc[vb][own[q]] = v[q];
-        if (j >= j0 + 1) Vp[(long long)(j - 1 - j0) * NB + c] = j >= kk + 1 ? v[q] : z0();
+        if (j >= j0 + 1) Vp[(long long)(j - 1 - j0) * kQrLdv + c] = j >= kk + 1 ? v[q] : z0();
       }
     }
   };
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(256) void larft_kernel(SmallBatch sb) {
   const int p = blockIdx.x, tid = threadIdx.x;
   if (p * NB >= nrefl) return;
   const int j0 = p * NB, jb = min(NB, nrefl - j0), mp = m - j0;
-  const c128* Vp = V + (size_t)p * m * NB;
+  const c128* Vp = V + qr_v_offset(p, m);
   c128 g[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) g[q] = z0();
@@ -614,7 +614,7 @@ __global__ __launch_bounds__(256) void larft_kernel(SmallBatch sb) {
     __syncthreads();
     for (int idx = tid; idx < 64 * NB; idx += 256) {
       const int i = idx / NB, c = idx % NB;
-      slab[i][c] = (r0 + i < mp) ? Vp[(long long)(r0 + i) * NB + c] : z0();
+      slab[i][c] = (r0 + i < mp) ? Vp[(long long)(r0 + i) * kQrLdv + c] : z0();
     }
     __syncthreads();
 #pragma unroll
@@ -755,7 +755,7 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
     if (P > 256) return set_error(-2, "eig: n=%d needs %d blocks", J.n, P);
     if ((rc = fill_zero(J.w->sync, grid_sync_words(P) * 4, s))) return rc;
     const int mqr = J.n - 1, npan = (mqr + NB - 1) / NB;
-    if ((rc = fill_zero(J.w->qtri.V, (size_t)npan * mqr * NB * 16, s))) return rc;
+    if ((rc = fill_zero(J.w->qtri.V, (size_t)((npan + 1) / 2) * mqr * kQrLdv * 16, s))) return rc;
     big.push_back(j);
   }
   if (big.empty()) return 0;

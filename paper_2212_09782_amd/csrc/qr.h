@@ -5,13 +5,24 @@
 namespace qrtebd {
 
 constexpr int kQrNb = 32;  // panel width
+constexpr int kQrLdv = 2 * kQrNb;   // leading dimension of the stored reflectors
+
+// Element offset of panel p's reflectors (its row 0, column 0) in QrWork::V
+// of an m-row factorisation.  Panels 2g and 2g+1 share a 64-column block
+// whose rows start at row 64g; panel 2g+1 sits 32 rows and 32 columns in,
+// with zeros above it, so the pair is one m' x 64 operand.
+__host__ __device__ inline size_t qr_v_offset(int p, int m) {
+  return (size_t)(p / 2) * m * kQrLdv + (size_t)(p % 2) * (kQrNb * kQrLdv + kQrNb);
+}
 
 // Device workspace of one QR of an m x n matrix (n <= m).
 struct QrWork {
-  void* V;        // per panel p: (m - 32p) x 32 explicit reflectors, ld 32, at offset p*m*32
+  void* V;        // explicit reflectors, ld kQrLdv, panel p at qr_v_offset(p, m)
   c128* T;        // per panel 32 x 32 upper triangular (compact-WY factor)
-  void* W;        // 32 x n product V^H A (element type of the storage)
-  void* Wsplit;   // split-K partials: kMaxSplit x 32 x n in the compute type
+  c128* Tp;       // per pair of panels 64 x 64: the merged compact-WY factor
+  c128* gpart;    // per pair: partial sums of V_even^H V_odd over 64-row chunks
+  void* W;        // 64 x n product V^H A (element type of the storage)
+  void* Wsplit;   // split-K partials: kMaxSplit x 64 x n in the compute type
   c128* wx;       // panel blocks x 32 x 32: partial products of the previous panel's reflectors
   c128* red;      // panel reductions: 2 x nblk x 32 + 2 x 32
   unsigned* sync; // grid barrier words (>= grid_sync_words(kMaxPanelBlocks))

@@ -27,13 +27,14 @@ namespace qrtebd {
 namespace {
 
 constexpr int NB = kQrNb;
+constexpr int LDV = kQrLdv;
 
 // One panel problem of a batched panel launch: its blocks are
 // [blk0, blk0 + nblk) of the grid and synchronise among themselves only.
 struct PanelProb {
   void* A;
   long long lda;
-  void* V;
+  void* V;        // this panel's reflectors (ld LDV); odd panels also clear the 32 rows above
   c128* T;
   // reflectors of the previous panel, applied to this panel's columns first
   // (null for the first panel): V from the row 32 above this panel, its T,
@@ -45,7 +46,7 @@ struct PanelProb {
   c128* red;
   c128* rowbuf;
   unsigned* sync;
-  int m, jb, rows_per_blk, nblk, blk0, gen0;
+  int m, jb, rows_per_blk, nblk, blk0, gen0, odd;
 };
 constexpr int kMaxPanelProbs = 24;
 struct PanelBatch {
@@ -107,10 +108,10 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
     const int nch = (nr + NB - 1) / NB + top;
     auto chunk_rows = [&](int ch) { return ch < top ? NB : min(NB, nr - (ch - top) * NB); };
     auto load_v = [&](int ch, int e) -> c128 {
-      const int idx = tid + kPanelThreads * e, t = idx / NB;
+      const int idx = tid + kPanelThreads * e, t = idx / NB, q = idx % NB;
       if (t >= chunk_rows(ch)) return cz();
-      const long long v0 = ch < top ? 0 : (long long)(NB + r0 + (ch - top) * NB) * NB;
-      return ccast<double>(Vp[v0 + idx]);
+      const long long row = ch < top ? t : NB + r0 + (ch - top) * NB + t;
+      return ccast<double>(Vp[row * LDV + q]);
     };
     c128 vn[2], at[2];
 #pragma unroll
@@ -357,8 +358,11 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
     const c128 pv = P[i * LDP + cc];
     if (cc < jb) A[(long long)(r0 + i) * a.lda + cc] = ccast<S>(pv);
     const c128 vc = cc < jb ? (gi > cc ? pv : (gi == cc ? mk<double>(1, 0) : cz())) : cz();
-    V[(long long)(r0 + i) * NB + cc] = ccast<S>(vc);
+    V[(long long)(r0 + i) * LDV + cc] = ccast<S>(vc);
   }
+  if (blk == 0 && a.odd)   // the rows of the pair block above an odd panel
+    for (int idx = tid; idx < NB * NB; idx += kPanelThreads)
+      V[(long long)(idx / NB - NB) * LDV + idx % NB] = ccast<S>(cz());
   if (blk == 0)
     for (int idx = tid; idx < NB * NB; idx += kPanelThreads) {
       const int r = idx / NB, cc = idx % NB;
@@ -444,13 +448,15 @@ int set_identity(void* Q, long long ldq, int m, int n, int dt, hipStream_t s) {
 }
 
 size_t qr_work_bytes(int m, int n, int es, int wcols) {
-  const size_t np = (size_t)(n + NB - 1) / NB;
+  const size_t np = (size_t)(n + NB - 1) / NB, npair = (np + 1) / 2, nch = (size_t)(m + 63) / 64;
   if (wcols < n) wcols = n;
   size_t b = 0;
-  b += align256(np * (size_t)m * NB * es);
+  b += align256(npair * (size_t)m * LDV * es);
   b += align256(np * NB * NB * sizeof(c128));
-  b += align256((size_t)NB * wcols * es);
-  b += align256((size_t)kMaxSplit * NB * wcols * sizeof(c128));
+  b += align256(npair * 4 * NB * NB * sizeof(c128));
+  b += align256(npair * nch * NB * NB * sizeof(c128));
+  b += align256((size_t)2 * NB * wcols * es);
+  b += align256((size_t)kMaxSplit * 2 * NB * wcols * sizeof(c128));
   b += align256((size_t)(panel_blocks_max(m) + 1) * NB * NB * sizeof(c128));
   b += align256((2 * (size_t)kMaxPanelBlocks * NB + 2 * NB) * sizeof(c128));
   b += align256(grid_sync_words(kMaxPanelBlocks) * 4);
@@ -458,15 +464,16 @@ size_t qr_work_bytes(int m, int n, int es, int wcols) {
 }
 
 QrWork qr_work_carve(void* base, int m, int n, int es, int wcols, int* status) {
-  const size_t np = (size_t)(n + NB - 1) / NB;
+  const size_t np = (size_t)(n + NB - 1) / NB, npair = (np + 1) / 2, nch = (size_t)(m + 63) / 64;
   if (wcols < n) wcols = n;
   char* p = (char*)base;
   QrWork w{};
-  const size_t vb = align256(np * (size_t)m * NB * es);
-  w.V = p; p += vb;
+  w.V = p; p += align256(npair * (size_t)m * LDV * es);
   w.T = (c128*)p; p += align256(np * NB * NB * sizeof(c128));
-  w.W = p; p += align256((size_t)NB * wcols * es);
-  w.Wsplit = p; p += align256((size_t)kMaxSplit * NB * wcols * sizeof(c128));
+  w.Tp = (c128*)p; p += align256(npair * 4 * NB * NB * sizeof(c128));
+  w.gpart = (c128*)p; p += align256(npair * nch * NB * NB * sizeof(c128));
+  w.W = p; p += align256((size_t)2 * NB * wcols * es);
+  w.Wsplit = p; p += align256((size_t)kMaxSplit * 2 * NB * wcols * sizeof(c128));
   w.wx = (c128*)p; p += align256((size_t)(panel_blocks_max(m) + 1) * NB * NB * sizeof(c128));
   w.red = (c128*)p; p += align256((2 * (size_t)kMaxPanelBlocks * NB + 2 * NB) * sizeof(c128));
   w.sync = (unsigned*)p;
@@ -475,13 +482,15 @@ QrWork qr_work_carve(void* base, int m, int n, int es, int wcols, int* status) {
   return w;
 }
 
-// W := op(T) sum_s src[s] for the 32 x nt block products W = V^H X of a batch
-// of jobs (one column per thread, FP64 arithmetic; in place when the product
-// was not split).  op = T (explicit Q, Z := H Z) or T^H (factorisation).
+// W := op(T) sum_s src[s] for the jb x nt block products W = V^H X (jb <= 64)
+// of a batch of jobs, FP64 arithmetic, in place when the product was not
+// split.  op = T (explicit Q, Z := H Z) or T^H (factorisation).
+constexpr int kTwRows = 2 * NB;
 struct TwJob {
   const void* src;   // ks x jb x nt partials (compute type = storage type here)
   int ks, jb, nt;
-  const c128* T;     // 32 x 32
+  const c128* T;     // jb x jb, leading dimension ldt
+  int ldt;
   void* W;           // jb x nt, ld nt
 };
 constexpr int kMaxTwJobs = 24;
@@ -490,21 +499,23 @@ struct TwBatch {
   TwJob j[kMaxTwJobs];
 };
 
-// Block: 8 columns of one job, one element (row r, column nn) per thread:
+// Block: 4 columns of one job, one element (row r, column nn) per thread:
 // the split partials are summed with eight loads in flight, the sums go to
 // LDS and the same elements of op(T) S are formed.
-constexpr int kTwCols = 8;
+constexpr int kTwCols = 256 / kTwRows;
 
 template <typename S>
 __global__ __launch_bounds__(256) void reduce_tw_kernel(TwBatch b) {
-  __shared__ c128 Ts[NB][NB + 1];
-  __shared__ c128 Sm[NB][kTwCols];
+  __shared__ c128 Ts[kTwRows][kTwRows + 1];
+  __shared__ c128 Sm[kTwRows][kTwCols];
   const TwJob& J = b.j[blockIdx.y];
   const int n0 = blockIdx.x * kTwCols;
   if (n0 >= J.nt) return;
-  for (int idx = threadIdx.x; idx < NB * NB; idx += 256) {
-    const int r = idx / NB, q = idx % NB;
-    Ts[r][q] = b.herm ? cconj(J.T[q * NB + r]) : J.T[r * NB + q];
+  for (int idx = threadIdx.x; idx < kTwRows * kTwRows; idx += 256) {
+    const int r = idx / kTwRows, q = idx % kTwRows;
+    c128 t = cz();
+    if (r < J.jb && q < J.jb) t = b.herm ? cconj(J.T[q * J.ldt + r]) : J.T[r * J.ldt + q];
+    Ts[r][q] = t;
   }
   const int r = threadIdx.x / kTwCols, nn = threadIdx.x % kTwCols, n = n0 + nn;
   const cpx<S>* src = (const cpx<S>*)J.src + (long long)r * J.nt + n;
@@ -527,6 +538,90 @@ __global__ __launch_bounds__(256) void reduce_tw_kernel(TwBatch b) {
   c128 o = cz();
   for (int q = 0; q < J.jb; ++q) o = cadd(o, cmul(Ts[r][q], Sm[q][nn]));
   ((cpx<S>*)J.W)[(long long)r * J.nt + n] = ccast<S>(o);
+}
+
+// Merged compact-WY factor of a pair of panels: for H = H_e H_o with
+// H_x = I - V_x T_x V_x^H, T = [[T_e, -T_e (V_e^H V_o) T_o], [0, T_o]].
+// gpart_kernel: partial sums of G = V_e^H V_o over 64-row chunks of the pair
+// block (one block per chunk and pair); tpair_kernel: sums them and forms T.
+struct PairTask {
+  const void* V;     // pair block, ld LDV
+  int rows;          // rows of the pair block
+  int has_odd;
+  const c128* Te;    // 32 x 32
+  const c128* To;    // 32 x 32 (has_odd)
+  c128* gpart;       // nchunk x 32 x 32
+  c128* Tp;          // 64 x 64
+};
+constexpr int kMaxPairTasks = 64;
+struct PairBatch {
+  int n;
+  PairTask t[kMaxPairTasks];
+};
+
+template <typename S>
+__global__ __launch_bounds__(256) void gpart_kernel(PairBatch b) {
+  __shared__ c128 Vs[64][LDV + 1];
+  const PairTask& T = b.t[blockIdx.y];
+  const int r0 = blockIdx.x * 64;
+  if (!T.has_odd || r0 >= T.rows) return;
+  const cpx<S>* V = (const cpx<S>*)T.V;
+  const int nr = min(64, T.rows - r0);
+  for (int idx = threadIdx.x; idx < 64 * LDV; idx += 256) {
+    const int i = idx / LDV, c = idx % LDV;
+    Vs[i][c] = i < nr ? ccast<double>(V[(long long)(r0 + i) * LDV + c]) : cz();
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int q = e / NB, c = e % NB;
+    c128 acc[4] = {cz(), cz(), cz(), cz()};
+    for (int i = 0; i < 64; i += 4)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = cadd(acc[u], cmulc(Vs[i + u][q], Vs[i + u][NB + c]));
+    T.gpart[(long long)blockIdx.x * NB * NB + e] = cadd(cadd(acc[0], acc[1]), cadd(acc[2], acc[3]));
+  }
+}
+
+__global__ __launch_bounds__(256) void tpair_kernel(PairBatch b) {
+  __shared__ c128 G[NB][NB + 1], X[NB][NB + 1], Te[NB][NB + 1], To[NB][NB + 1];
+  const PairTask& T = b.t[blockIdx.x];
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int q = e / NB, c = e % NB;
+    Te[q][c] = T.Te[e];
+    To[q][c] = T.has_odd ? T.To[e] : cz();
+    c128 g = cz();
+    if (T.has_odd) {
+      const int nch = (T.rows + 63) / 64;
+      for (int k0 = 0; k0 < nch; k0 += 8) {   // eight loads in flight
+        c128 l[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) l[u] = k0 + u < nch ? T.gpart[(long long)(k0 + u) * NB * NB + e] : cz();
+#pragma unroll
+        for (int u = 0; u < 8; ++u) g = cadd(g, l[u]);
+      }
+    }
+    G[q][c] = g;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {   // X = G T_o
+    const int q = e / NB, c = e % NB;
+    c128 x = cz();
+    for (int k = 0; k < NB; ++k) x = cadd(x, cmul(G[q][k], To[k][c]));
+    X[q][c] = x;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 4 * NB * NB; e += 256) {
+    const int r = e / (2 * NB), c = e % (2 * NB);
+    c128 t = cz();
+    if (r < NB && c < NB) {
+      t = Te[r][c];
+    } else if (r >= NB && c >= NB) {
+      t = To[r - NB][c - NB];
+    } else if (r < NB && c >= NB) {   // -T_e X
+      for (int k = 0; k < NB; ++k) t = csub(t, cmul(Te[r][k], X[k][c - NB]));
+    }
+    T.Tp[e] = t;
+  }
 }
 
 static int launch_tw(const std::vector<TwJob>& jobs, bool herm, int dt, hipStream_t s) {
@@ -578,11 +673,11 @@ static int launch_panels(const QrJob* jobs, int njobs, int p, int dt, hipStream_
     pb.status = w.status;
     pp.A = (char*)J.A + ((long long)j0 * J.lda + j0) * es;
     pp.lda = J.lda;
-    const size_t voff = (size_t)p * J.m * NB * es;
-    pp.V = (char*)w.V + voff;
+    pp.V = (char*)w.V + qr_v_offset(p, J.m) * es;
+    pp.odd = p & 1;
     pp.T = w.T + (size_t)p * NB * NB;
     if (p >= 1) {
-      pp.Vprev = (const char*)w.V + (size_t)(p - 1) * J.m * NB * es;
+      pp.Vprev = (const char*)w.V + qr_v_offset(p - 1, J.m) * es;
       pp.Tprev = w.T + (size_t)(p - 1) * NB * NB;
       pp.Atop = (char*)J.A + ((long long)(j0 - NB) * J.lda + j0) * es;
       pp.wx = w.wx;
@@ -618,16 +713,16 @@ static int update_columns(const QrJob* jobs, int njobs, int p, int dt, int b0, i
     const int nt = c1 - c0;
     if (nt <= 0) continue;
     const QrWork& w = *J.w;
-    const size_t voff = (size_t)p * J.m * NB * es;
+    const char* Vp = (const char*)w.V + qr_v_offset(p, J.m) * es;
     void* At = (char*)J.A + ((long long)j0 * J.lda + c0) * es;
     void* W = w.W;
-    GemmProb g1 = gemm_prob((char*)w.V + voff, NB, OP_C, At, J.lda, OP_N, W, nt, jb, nt, mp);
+    GemmProb g1 = gemm_prob(Vp, LDV, OP_C, At, J.lda, OP_N, W, nt, jb, nt, mp);
     g1.ksplit = splitk_for(jb, nt, mp);
     g1.work = w.Wsplit;
     g1.skip_reduce = 1;
     g1s.push_back(g1);
-    tw.push_back(TwJob{g1.ksplit > 1 ? g1.work : W, g1.ksplit, jb, nt, w.T + (size_t)p * NB * NB, W});
-    g2s.push_back(gemm_prob((char*)w.V + voff, NB, OP_N, W, nt, OP_N, At, J.lda, mp, nt, jb, -1.f, 1.f));
+    tw.push_back(TwJob{g1.ksplit > 1 ? g1.work : W, g1.ksplit, jb, nt, w.T + (size_t)p * NB * NB, NB, W});
+    g2s.push_back(gemm_prob(Vp, LDV, OP_N, W, nt, OP_N, At, J.lda, mp, nt, jb, -1.f, 1.f));
   }
   const GemmTypes ty{dt, dt};
   int rc;
@@ -678,41 +773,81 @@ int qr_factor_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s, const Q
 }
 
 
-// Z_j := H_0 H_1 ... Z_j for every job (Z rows j0.. of each panel); set_id
-// first overwrites Z_j with [I; 0] (explicit Q).
+// Merged factors of every pair of panels of every job (two launches per
+// batch of tasks).
+static int build_pair_factors(const QrJob* jobs, int njobs, int dt, hipStream_t s) {
+  const int es = dt == DT_C128 ? 16 : 8;
+  std::vector<PairTask> tasks;
+  int maxch = 1;
+  for (int j = 0; j < njobs; ++j) {
+    const QrJob& J = jobs[j];
+    const QrWork& w = *J.w;
+    const int np = (J.n + NB - 1) / NB, npair = (np + 1) / 2, nch = (J.m + 63) / 64;
+    for (int g = 0; g < npair; ++g) {
+      PairTask t{};
+      t.V = (const char*)w.V + qr_v_offset(2 * g, J.m) * es;
+      t.rows = J.m - 2 * NB * g;
+      t.has_odd = 2 * g + 1 < np;
+      t.Te = w.T + (size_t)(2 * g) * NB * NB;
+      t.To = w.T + (size_t)(2 * g + 1) * NB * NB;
+      t.gpart = w.gpart + (size_t)g * nch * NB * NB;
+      t.Tp = w.Tp + (size_t)g * 4 * NB * NB;
+      tasks.push_back(t);
+      maxch = std::max(maxch, (t.rows + 63) / 64);
+    }
+  }
+  for (size_t i0 = 0; i0 < tasks.size(); i0 += kMaxPairTasks) {
+    PairBatch b{};
+    for (size_t i = i0; i < tasks.size() && b.n < kMaxPairTasks; ++i) b.t[b.n++] = tasks[i];
+    if (dt == DT_C128)
+      hipLaunchKernelGGL(gpart_kernel<double>, dim3(maxch, b.n), dim3(256), 0, s, b);
+    else
+      hipLaunchKernelGGL(gpart_kernel<float>, dim3(maxch, b.n), dim3(256), 0, s, b);
+    QT_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(tpair_kernel, dim3(b.n), dim3(256), 0, s, b);
+    QT_HIP_CHECK(hipGetLastError());
+  }
+  return 0;
+}
+
+// Z_j := H_0 H_1 ... Z_j for every job (Z rows from each pair's first row),
+// two panels at a time with their merged factor; set_id first overwrites Z_j
+// with [I; 0] (explicit Q).
 static int apply_batch(const QrJob* jobs, int njobs, int dt, bool set_id, hipStream_t s) {
   const int es = dt == DT_C128 ? 16 : 8;
   const GemmTypes ty{dt, dt};
-  int maxp = 0, rc;
+  int maxg = 0, rc;
   for (int j = 0; j < njobs; ++j) {
     const QrJob& J = jobs[j];
-    maxp = std::max(maxp, (J.n + NB - 1) / NB);
+    maxg = std::max(maxg, ((J.n + NB - 1) / NB + 1) / 2);
     if (set_id && (rc = set_identity(J.Z, J.ldz, J.m, J.nz, dt, s))) return rc;
     if (J.nz > J.w->wcols) return set_error(-1, "qr_apply_q: %d columns exceed the work size %d", J.nz, J.w->wcols);
   }
+  if ((rc = build_pair_factors(jobs, njobs, dt, s))) return rc;
   std::vector<GemmProb> g1s, g2s;
   std::vector<TwJob> tw;
-  for (int p = maxp - 1; p >= 0; --p) {
+  for (int g = maxg - 1; g >= 0; --g) {
     g1s.clear();
     g2s.clear();
     tw.clear();
     for (int j = 0; j < njobs; ++j) {
       const QrJob& J = jobs[j];
-      const int j0 = p * NB;
+      const int j0 = 2 * NB * g;
       if (j0 >= J.n) continue;
-      const int jb = std::min(NB, J.n - j0), mp = J.m - j0;
+      const int jbp = std::min(2 * NB, J.n - j0), mp = J.m - j0;
       const int c0 = set_id ? j0 : 0;        // explicit Q: columns < j0 are still e_j
       const int nz = J.nz - c0;
       if (nz <= 0) continue;
-      const size_t voff = (size_t)p * J.m * NB * es;
+      const char* Vg = (const char*)J.w->V + qr_v_offset(2 * g, J.m) * es;
       void* Zs = (char*)J.Z + ((long long)j0 * J.ldz + c0) * es;
-      GemmProb g1 = gemm_prob((char*)J.w->V + voff, NB, OP_C, Zs, J.ldz, OP_N, J.w->W, nz, jb, nz, mp);
-      g1.ksplit = splitk_for(jb, nz, mp);
+      GemmProb g1 = gemm_prob(Vg, LDV, OP_C, Zs, J.ldz, OP_N, J.w->W, nz, jbp, nz, mp);
+      g1.ksplit = splitk_for(jbp, nz, mp);
       g1.work = J.w->Wsplit;
       g1.skip_reduce = 1;
       g1s.push_back(g1);
-      tw.push_back(TwJob{g1.ksplit > 1 ? g1.work : J.w->W, g1.ksplit, jb, nz, J.w->T + (size_t)p * NB * NB, J.w->W});
-      g2s.push_back(gemm_prob((char*)J.w->V + voff, NB, OP_N, J.w->W, nz, OP_N, Zs, J.ldz, mp, nz, jb, -1.f, 1.f));
+      tw.push_back(TwJob{g1.ksplit > 1 ? g1.work : J.w->W, g1.ksplit, jbp, nz, J.w->Tp + (size_t)g * 4 * NB * NB,
+                         2 * NB, J.w->W});
+      g2s.push_back(gemm_prob(Vg, LDV, OP_N, J.w->W, nz, OP_N, Zs, J.ldz, mp, nz, jbp, -1.f, 1.f));
     }
     if (!g1s.empty() && (rc = gemm_run(g1s.data(), (int)g1s.size(), ty, s))) return rc;
     if (!tw.empty() && (rc = launch_tw(tw, false, dt, s))) return rc;
