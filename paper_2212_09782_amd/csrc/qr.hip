@@ -60,8 +60,11 @@ __device__ inline c128 cz() { return mk<double>(0, 0); }
 constexpr int LDP = NB + 1;   // padded LDS row stride of the panel slab
 constexpr int kMaxPanelRows = 160;
 
-constexpr int kPanelThreads = 512;   // 16 row groups x 32 columns: two waves per SIMD
+constexpr int kPanelThreads = 512;   // 16 row groups x 32 columns: two waves per SIMD (1024: slower)
 constexpr int kRowGroups = kPanelThreads / 32;
+constexpr int kStage = NB * NB / kPanelThreads;          // elements of a 32 x 32 tile per thread
+constexpr int kQOut = NB * NB / kPanelThreads;           // V^H A outputs per thread in the pre-phase
+constexpr int kColLanes = kPanelThreads / NB;            // lanes that share one column's partials
 __device__ inline int rg_of(int tid) { return tid >> 5; }
 
 template <typename S>
@@ -99,11 +102,11 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
     // block 0, on the 32 rows above (written back: they belong to R).
     const cpx<S>* Vp = (const cpx<S>*)a.Vprev;
     cpx<S>* At = (cpx<S>*)a.Atop;
-    const int cc = tid & 31, q0 = tid >> 5;   // outputs (q0, cc) and (q0 + 16, cc)
+    const int cc = tid & 31, q0 = tid >> 5;   // outputs (q0 + (NB / kQOut) o, cc), o < kQOut
     // V rows in 32-row chunks through Sk (free until the column loop).  Chunk
     // 0 of block 0 is the 32 rows above the panel (their A rows go through Tm);
-    // the slab's chunks follow.  Each thread loads elements tid and tid + 512
-    // of a chunk, one chunk ahead of its use.
+    // the slab's chunks follow.  Each thread loads kStage elements of a
+    // chunk, one chunk ahead of its use.
     const int top = blk == 0 ? 1 : 0;
     const int nch = (nr + NB - 1) / NB + top;
     auto chunk_rows = [&](int ch) { return ch < top ? NB : min(NB, nr - (ch - top) * NB); };
@@ -113,26 +116,30 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
       const long long row = ch < top ? t : NB + r0 + (ch - top) * NB + t;
       return ccast<double>(Vp[row * LDV + q]);
     };
-    c128 vn[2], at[2];
+    c128 vn[kStage], at[kStage];
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
+    for (int e = 0; e < kStage; ++e) {
       vn[e] = load_v(0, e);
       const int idx = tid + kPanelThreads * e, t = idx / NB, q = idx % NB;
       at[e] = (top && q < jb) ? ccast<double>(At[(long long)t * a.lda + q]) : cz();
     }
-    c128 w0[4] = {cz(), cz(), cz(), cz()}, w1[4] = {cz(), cz(), cz(), cz()};
+    c128 wacc[kQOut][4];
+#pragma unroll
+    for (int o = 0; o < kQOut; ++o)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) wacc[o][u] = cz();
     for (int ch = 0; ch < nch; ++ch) {
       {
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
+        for (int e = 0; e < kStage; ++e) {
           const int idx = tid + kPanelThreads * e;
           Sk[idx / NB][idx % NB] = vn[e];
           if (ch < top) Tm[idx / NB][idx % NB] = at[e];
         }
         if (ch + 1 < nch)
 #pragma unroll
-          for (int e = 0; e < 2; ++e) vn[e] = load_v(ch + 1, e);
+          for (int e = 0; e < kStage; ++e) vn[e] = load_v(ch + 1, e);
         __syncthreads();
         const int rows = chunk_rows(ch);
         for (int t0 = 0; t0 < rows; t0 += 4)   // four independent accumulation chains
@@ -141,32 +148,35 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
             const int t = t0 + u;
             if (t < rows) {
               const c128 x = ch < top ? Tm[t][cc] : P[((ch - top) * NB + t) * LDP + cc];
-              w0[u] = cadd(w0[u], cmulc(Sk[t][q0], x));
-              w1[u] = cadd(w1[u], cmulc(Sk[t][q0 + 16], x));
+#pragma unroll
+              for (int o = 0; o < kQOut; ++o)
+                wacc[o][u] = cadd(wacc[o][u], cmulc(Sk[t][q0 + (NB / kQOut) * o], x));
             }
           }
       }
     }
-    pub_store(a.wx + ((long long)blk * NB + q0) * NB + cc, cadd(cadd(w0[0], w0[1]), cadd(w0[2], w0[3])));
-    pub_store(a.wx + ((long long)blk * NB + q0 + 16) * NB + cc, cadd(cadd(w1[0], w1[1]), cadd(w1[2], w1[3])));
+#pragma unroll
+    for (int o = 0; o < kQOut; ++o)
+      pub_store(a.wx + ((long long)blk * NB + q0 + (NB / kQOut) * o) * NB + cc,
+                cadd(cadd(wacc[o][0], wacc[o][1]), cadd(wacc[o][2], wacc[o][3])));
     if (!grid_barrier(gs, (unsigned)(a.gen0 + 1), blk, nblk, &flag)) return;
     // Block b reduces columns b, b + nblk, ...: W[:, c] = sum of the block
     // partials, then (T^H W)[:, c], published for everyone.
     c128* w2 = a.wx + (long long)nblk * NB * NB;
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
+    for (int e = 0; e < kStage; ++e) {
       const int idx = tid + kPanelThreads * e;
       Sk[idx / NB][idx % NB] = a.Tprev[idx];
     }
     for (int c = blk; c < NB; c += nblk) {
-      const int r = tid & 31, g = tid >> 5;   // 16 groups of blocks
+      const int r = tid & 31, g = tid >> 5;   // kRowGroups groups of blocks
       c128 acc = cz();
-      for (int b0 = g; b0 < nblk; b0 += 64) {
+      for (int b0 = g; b0 < nblk; b0 += 4 * kRowGroups) {
         c128 l[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int b = b0 + 16 * u;
+          const int b = b0 + kRowGroups * u;
           l[u] = b < nblk ? pub_load(a.wx + ((long long)b * NB + r) * NB + c) : cz();
         }
 #pragma unroll
@@ -193,24 +203,24 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
     }
     if (!grid_barrier(gs, (unsigned)(a.gen0 + 2), blk, nblk, &flag)) return;
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
+    for (int e = 0; e < kStage; ++e) {
       const int idx = tid + kPanelThreads * e;
       Tm[idx / NB][idx % NB] = pub_load(w2 + idx);
     }
-    // A -= V W: thread (row t of the chunk, column cc), 16 row groups per chunk
+    // A -= V W: thread (row t of the chunk, column cc), kRowGroups rows at a time
 #pragma unroll
-    for (int e = 0; e < 2; ++e) vn[e] = load_v(0, e);
+    for (int e = 0; e < kStage; ++e) vn[e] = load_v(0, e);
     for (int ch = 0; ch < nch; ++ch) {
       {
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
+        for (int e = 0; e < kStage; ++e) {
           const int idx = tid + kPanelThreads * e;
           Sk[idx / NB][idx % NB] = vn[e];
         }
         if (ch + 1 < nch)
 #pragma unroll
-          for (int e = 0; e < 2; ++e) vn[e] = load_v(ch + 1, e);
+          for (int e = 0; e < kStage; ++e) vn[e] = load_v(ch + 1, e);
         __syncthreads();
         const int rows = chunk_rows(ch);
         for (int t = rg_of(tid); t < rows; t += kRowGroups) {
@@ -259,21 +269,27 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
     }
     if (!grid_barrier(gs, (unsigned)(a.gen0 + k + 3), blk, nblk, &flag)) return;
     {  // one round of loads: 8 lanes per column share the block partials
-      const int cl = tid >> 4, bg = tid & 15;
-      constexpr int kMaxPer = kMaxPanelBlocks / 16;
+      const int cl = tid / kColLanes, bg = tid % kColLanes;
+      constexpr int kMaxPer = kMaxPanelBlocks / kColLanes;
       c128 v[kMaxPer];
 #pragma unroll
       for (int q = 0; q < kMaxPer; ++q) {
-        const int w = bg + 16 * q;
+        const int w = bg + kColLanes * q;
         v[q] = w < nblk ? pub_load(a.red + ((long long)slot * nblk + w) * NB + cl) : cz();
       }
       const c128 rk = tid < NB ? pub_load(a.rowbuf + slot * NB + tid) : cz();
       c128 t = cz();
 #pragma unroll
       for (int q = 0; q < kMaxPer; ++q) t = cadd(t, v[q]);
-      t.re = row16_sum(t.re);   // the 16 lanes of column cl form one DPP row
+      // the kColLanes lanes of column cl: one or two DPP rows; the last lane
+      // of the group ends with the total
+      t.re = row16_sum(t.re);
       t.im = row16_sum(t.im);
-      if (bg == 15) tsum[cl] = t;
+      if (kColLanes == 32) {
+        t.re += dpp_mov<0x142, 0xa>(t.re);   // row_bcast:15 into rows 1 and 3
+        t.im += dpp_mov<0x142, 0xa>(t.im);
+      }
+      if (bg == kColLanes - 1) tsum[cl] = t;
       if (tid < NB) rowk[tid] = rk;
     }
     __syncthreads();
