@@ -414,7 +414,12 @@ __global__ __launch_bounds__(256) void bisect_kernel(SmallBatch sb) {
       const double di = sd[i], ei = se2[i - 1];
 #pragma unroll
       for (int c = 0; c < kBisectPts; ++c) {
-        double t = di - x[c] - ei / q[c];
+        // e^2 / q by the hardware reciprocal and one Newton step (within an
+        // ulp or two of the division, enough for the sign of the pivot; |q|
+        // >= pivmin keeps it finite)
+        const double r0 = __builtin_amdgcn_rcp(q[c]);
+        const double r1 = fma(r0, fma(-q[c], r0, 1.0), r0);
+        double t = di - x[c] - ei * r1;
         if (fabs(t) < pivmin) t = -pivmin;
         q[c] = t;
         cnt[c] += t < 0;

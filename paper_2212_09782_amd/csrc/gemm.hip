@@ -23,6 +23,20 @@
 namespace qrtebd {
 namespace {
 
+// Tile order within a launch: columns of kTileGroup-tall groups of tiles, so
+// that the workgroups running together on one XCD (which receives a
+// contiguous range of tiles) share A row panels and B column panels in its
+// L2 instead of streaming all of A once per tile column.
+constexpr int kTileGroup = 8;
+__device__ inline void grouped_tile(int t, int tm, int tn, int& tile_m, int& tile_n) {
+  const int per_group = kTileGroup * tn;
+  const int g = t / per_group, first_m = g * kTileGroup;
+  const int gsize = min(tm - first_m, kTileGroup);
+  const int r = t - g * per_group;
+  tile_m = first_m + r % gsize;
+  tile_n = r / gsize;
+}
+
 template <typename T> struct Mfma;
 template <> struct Mfma<double> {
   typedef double v4 __attribute__((ext_vector_type(4)));
@@ -70,7 +84,8 @@ __device__ __forceinline__ void gemm_body_l(const GemmBatch& b) {
   const int tm = b.tiles_m[p], tn = b.tiles_n[p];
   const int split = t / (tm * tn);
   t -= split * tm * tn;
-  const int tile_m = t % tm, tile_n = t / tm;
+  int tile_m, tile_n;
+  grouped_tile(t, tm, tn, tile_m, tile_n);
 
   int M = P.M, N = P.N, K = P.K;
   if (P.dM) M = min(M, *P.dM);
@@ -264,7 +279,8 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   const int tm = b.tiles_m[p], tn = b.tiles_n[p];
   const int split = t / (tm * tn);
   t -= split * tm * tn;
-  const int tile_m = t % tm, tile_n = t / tm;
+  int tile_m, tile_n;
+  grouped_tile(t, tm, tn, tile_m, tile_n);
 
   int M = P.M, N = P.N, K = P.K;
   if (P.dM) M = min(M, *P.dM);
