@@ -134,6 +134,20 @@ __device__ inline void pub_store(c128* p, c128 v) {
 }
 __device__ inline c128 pub_load(const c128* p) { return mk<double>(pub_load(&p->re), pub_load(&p->im)); }
 
+// Published data read in one 16-byte access with the cache policy of the
+// device-scope loads (past the non-coherent caches): a buffer resource over
+// base (uniform), addressed by a per-lane element index.  Reads after a
+// grid_barrier only: the access is not atomic.
+__device__ inline __amdgpu_buffer_rsrc_t coh_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, 0x00020000);
+}
+__device__ inline c128 coh_load(__amdgpu_buffer_rsrc_t r, int elem) {
+  typedef int i4 __attribute__((ext_vector_type(4)));
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2 x = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, elem * 16, 0, 16));
+  return mk<double>(x.x, x.y);
+}
+
 __device__ inline bool grid_barrier(GridSync gs, unsigned gen, int blk, int nblk, int* smem_flag) {
   constexpr long kSpinLimit = 1L << 22;
   unsigned* flags = gs.base + 16;

@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
     }
 #pragma unroll
     for (int o = 0; o < kQOut; ++o)
-      pub_store(a.wx + ((long long)blk * NB + q0 + (NB / kQOut) * o) * NB + cc,
+      pub_store(a.wx + ((long long)blk * NB + cc) * NB + q0 + (NB / kQOut) * o,
                 cadd(cadd(wacc[o][0], wacc[o][1]), cadd(wacc[o][2], wacc[o][3])));
     if (!grid_barrier(gs, (unsigned)(a.gen0 + 1), blk, nblk, &flag)) return;
     // Block b reduces columns b, b + nblk, ...: W[:, c] = sum of the block
@@ -169,6 +169,7 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
       const int idx = tid + kPanelThreads * e;
       Sk[idx / NB][idx % NB] = a.Tprev[idx];
     }
+    const auto rwx = coh_rsrc(a.wx);
     for (int c = blk; c < NB; c += nblk) {
       const int r = tid & 31, g = tid >> 5;   // kRowGroups groups of blocks
       c128 acc = cz();
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int b = b0 + kRowGroups * u;
-          l[u] = b < nblk ? pub_load(a.wx + ((long long)b * NB + r) * NB + c) : cz();
+          l[u] = b < nblk ? coh_load(rwx, (b * NB + c) * NB + r) : cz();
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc = cadd(acc, l[u]);
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
 #pragma unroll
     for (int e = 0; e < kStage; ++e) {
       const int idx = tid + kPanelThreads * e;
-      Tm[idx / NB][idx % NB] = pub_load(w2 + idx);
+      Tm[idx / NB][idx % NB] = coh_load(rwx, nblk * NB * NB + idx);
     }
     // A -= V W: thread (row t of the chunk, column cc), kRowGroups rows at a time
 #pragma unroll
@@ -272,12 +273,13 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
       const int cl = tid / kColLanes, bg = tid % kColLanes;
       constexpr int kMaxPer = kMaxPanelBlocks / kColLanes;
       c128 v[kMaxPer];
+      const auto rred = coh_rsrc(a.red), rrow = coh_rsrc(a.rowbuf);
 #pragma unroll
       for (int q = 0; q < kMaxPer; ++q) {
         const int w = bg + kColLanes * q;
-        v[q] = w < nblk ? pub_load(a.red + ((long long)slot * nblk + w) * NB + cl) : cz();
+        v[q] = w < nblk ? coh_load(rred, (slot * nblk + w) * NB + cl) : cz();
       }
-      const c128 rk = tid < NB ? pub_load(a.rowbuf + slot * NB + tid) : cz();
+      const c128 rk = tid < NB ? coh_load(rrow, slot * NB + tid) : cz();
       c128 t = cz();
 #pragma unroll
       for (int q = 0; q < kMaxPer; ++q) t = cadd(t, v[q]);
