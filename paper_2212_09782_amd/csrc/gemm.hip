@@ -2,15 +2,18 @@
 //
 // Every contraction of the bond update (theta, X, Y, L^dag L, the new tensors,
 // the compact-WY trailing updates of the Householder QR) is a complex matrix
-// product.  A complex product is four real MFMA products (the "4M" form):
-//   Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B.
-// FP64 inputs run on v_mfma_f64_16x16x4f64, FP32 inputs on
-// v_mfma_f32_16x16x4f32, both with their native accumulator.
+// product.  With FP64 arithmetic a complex product is four real MFMA
+// products (Re C += Re A Re B - Im A Im B, Im C += Re A Im B + Im A Re B); with
+// FP32 arithmetic it is three (Gauss' form: P1 = Re A Re B, P2 = Im A Im B,
+// P3 = (Re A + Im A)(Re B + Im B), Re C = P1 - P2, Im C = P3 - P1 - P2).
+// FP64 runs on v_mfma_f64_16x16x4f64, FP32 on v_mfma_f32_16x16x4f32, both with
+// their native accumulator.
 //
 // Tiling: a 256-thread workgroup owns a 64x64 output tile, each wave a 32x32
-// quadrant (2x2 MFMA blocks, separate real/imaginary accumulators).  Operand
-// tiles of depth 16 are staged through LDS in planar (re / im) k-major form so
-// that each MFMA operand is one conflict-light LDS read per lane.  LDS is
+// quadrant (2x2 MFMA blocks, one accumulator set per real product).  Operand
+// tiles of depth 16 are staged through LDS in planar k-major form (re, im and,
+// for the 3-product form, re + im) so that each MFMA operand is one
+// conflict-light LDS read per lane.  LDS is
 // double-buffered: the next tile is loaded from global memory into registers
 // and stored into the other buffer while the current one is consumed, so each
 // K stage needs one workgroup barrier.  Workgroup ids are remapped so that the
@@ -260,8 +263,14 @@ template <typename Tin, typename Tout, typename Tc>
 __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   using MF = Mfma<Tc>;
   using v4 = typename MF::v4;
-  __shared__ Tc As[2][2][BK][BM + PAD];   // [buffer][re/im][k][m]
-  __shared__ Tc Bs[2][2][BK][BN + PAD];
+  // FP32 products take the 3-product form (P1 = Re A Re B, P2 = Im A Im B,
+  // P3 = (Re A + Im A)(Re B + Im B); Re C = P1 - P2, Im C = P3 - P1 - P2),
+  // a quarter fewer MFMAs; FP64 keeps the 4-product form, whose smaller
+  // accumulator set leaves room for two waves per SIMD.
+  constexpr bool k3 = sizeof(Tc) == 4;
+  constexpr int NPL = k3 ? 3 : 2;            // LDS planes per operand
+  __shared__ Tc As[2][NPL][BK][BM + PAD];   // [buffer][re / im (/ re + im)][k][m]
+  __shared__ Tc Bs[2][NPL][BK][BN + PAD];
 
   // XCD-aware remap: hardware workgroup g runs on XCD g % 8; give XCD x the
   // contiguous logical range [start_x, start_x + count_x)
@@ -303,14 +312,14 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = (wid & 1) * 32, wn = (wid >> 1) * 32;
 
-  v4 acc_re[2][2], acc_im[2][2];
+  // 3-product form: P1, P2, P3; 4-product form: Re C in acc[0], Im C in acc[1]
+  v4 acc[NPL][2][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int pl = 0; pl < NPL; ++pl)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      acc_re[i][j] = v4{0, 0, 0, 0};
-      acc_im[i][j] = v4{0, 0, 0, 0};
-    }
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[pl][i][j] = v4{0, 0, 0, 0};
 
   // thread -> tile element mapping for the two storage orientations; each
   // thread stages EPT elements of each operand per stage in groups of 4
@@ -347,19 +356,17 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int g = e >> 2, e4 = e & 3;
-      if (opA == OP_N) {
-        As[buf][0][colq + e][rowq] = (Tc)ra[e].re;
-        As[buf][1][colq + e][rowq] = sa * (Tc)ra[e].im;
-      } else {
-        As[buf][0][rowk + 16 * g][colk + e4] = (Tc)ra[e].re;
-        As[buf][1][rowk + 16 * g][colk + e4] = sa * (Tc)ra[e].im;
-      }
-      if (opB == OP_N) {
-        Bs[buf][0][rowk + 16 * g][colk + e4] = (Tc)rb[e].re;
-        Bs[buf][1][rowk + 16 * g][colk + e4] = sb * (Tc)rb[e].im;
-      } else {
-        Bs[buf][0][colq + e][rowq] = (Tc)rb[e].re;
-        Bs[buf][1][colq + e][rowq] = sb * (Tc)rb[e].im;
+      const Tc a_r = (Tc)ra[e].re, a_i = sa * (Tc)ra[e].im;
+      const Tc b_r = (Tc)rb[e].re, b_i = sb * (Tc)rb[e].im;
+      const int ak = opA == OP_N ? colq + e : rowk + 16 * g, am = opA == OP_N ? rowq : colk + e4;
+      const int bk = opB == OP_N ? rowk + 16 * g : colq + e, bn = opB == OP_N ? colk + e4 : rowq;
+      As[buf][0][ak][am] = a_r;
+      As[buf][1][ak][am] = a_i;
+      Bs[buf][0][bk][bn] = b_r;
+      Bs[buf][1][bk][bn] = b_i;
+      if constexpr (k3) {
+        As[buf][NPL - 1][ak][am] = a_r + a_i;
+        Bs[buf][NPL - 1][bk][bn] = b_r + b_i;
       }
     }
   };
@@ -376,22 +383,27 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
-      Tc ar[2], ai[2], br[2], bi[2];
+      Tc a3[NPL][2], b3[NPL][2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        ar[i] = As[buf][0][kr][wm + i * 16 + (lane & 15)];
-        ai[i] = As[buf][1][kr][wm + i * 16 + (lane & 15)];
-        br[i] = Bs[buf][0][kr][wn + i * 16 + (lane & 15)];
-        bi[i] = Bs[buf][1][kr][wn + i * 16 + (lane & 15)];
-      }
+      for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          a3[pl][i] = As[buf][pl][kr][wm + i * 16 + (lane & 15)];
+          b3[pl][i] = Bs[buf][pl][kr][wn + i * 16 + (lane & 15)];
+        }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          acc_re[i][j] = MF::op(ar[i], br[j], acc_re[i][j]);
-          acc_re[i][j] = MF::op(-ai[i], bi[j], acc_re[i][j]);
-          acc_im[i][j] = MF::op(ar[i], bi[j], acc_im[i][j]);
-          acc_im[i][j] = MF::op(ai[i], br[j], acc_im[i][j]);
+          if constexpr (k3) {
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) acc[pl][i][j] = MF::op(a3[pl][i], b3[pl][j], acc[pl][i][j]);
+          } else {
+            acc[0][i][j] = MF::op(a3[0][i], b3[0][j], acc[0][i][j]);
+            acc[0][i][j] = MF::op(-a3[1][i], b3[1][j], acc[0][i][j]);
+            acc[1][i][j] = MF::op(a3[0][i], b3[1][j], acc[1][i][j]);
+            acc[1][i][j] = MF::op(a3[1][i], b3[0][j], acc[1][i][j]);
+          }
         }
     }
     if (more) store(buf ^ 1);    // the other buffer was released by the previous barrier
@@ -399,7 +411,20 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
     buf ^= 1;
   }
 
-  // epilogue
+  // epilogue: the real and imaginary parts
+  v4 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if constexpr (k3) {
+        acc_re[i][j] = acc[0][i][j] - acc[1][i][j];
+        acc_im[i][j] = acc[NPL - 1][i][j] - acc[0][i][j] - acc[1][i][j];
+      } else {
+        acc_re[i][j] = acc[0][i][j];
+        acc_im[i][j] = acc[1][i][j];
+      }
+    }
   if (ks > 1) {
     cpx<Tc>* W = (cpx<Tc>*)P.work + (long long)split * P.M * P.N;
 #pragma unroll
