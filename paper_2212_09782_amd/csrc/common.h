@@ -148,7 +148,16 @@ __device__ inline c128 coh_load(__amdgpu_buffer_rsrc_t r, int elem) {
   return mk<double>(x.x, x.y);
 }
 
-__device__ inline bool grid_barrier(GridSync gs, unsigned gen, int blk, int nblk, int* smem_flag) {
+struct NoWork {
+  __device__ void operator()() const {}
+};
+// idle: block-local work that every thread runs after its share of the flag
+// polling and before the closing block barrier; threads past the polling
+// range (threadIdx.x >= nblk) start it at once, so it overlaps the wait.  It
+// may read what the block wrote before the call and write what nobody reads
+// before the call returns.
+template <typename F = NoWork>
+__device__ inline bool grid_barrier(GridSync gs, unsigned gen, int blk, int nblk, int* smem_flag, F idle = F{}) {
   constexpr long kSpinLimit = 1L << 22;
   unsigned* flags = gs.base + 16;
   __builtin_amdgcn_s_waitcnt(0);   // this wave's published stores are complete
@@ -160,6 +169,7 @@ __device__ inline bool grid_barrier(GridSync gs, unsigned gen, int blk, int nblk
       if (++spins > kSpinLimit) { *smem_flag = (int)gen; break; }
     }
   }
+  idle();
   __syncthreads();
   const bool ok = *smem_flag != (int)gen;
   if (!ok && threadIdx.x == 0) latch_error(gs.status, ERRBIT_BARRIER);

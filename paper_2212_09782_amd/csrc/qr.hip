@@ -256,6 +256,30 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
   for (int i = rg; i < nr; i += kRowGroups)
     if (r0 + i > 0) acc = cadd(acc, cmulc(P[i * LDP], P[i * LDP + c]));
 
+  // T of the compact-WY form, one column per grid barrier in the waves that
+  // do not poll: T[k][k] = tau_k, T[r][k] = -tau_k sum_q T[r][q] S_k[q]
+  // (q = r..k-1).  The 8 lanes r*8 .. r*8+7 of waves 1-4 build entry r, each
+  // summing every 8th term.
+  for (int idx = tid; idx < NB * NB; idx += kPanelThreads) Tm[idx / NB][idx % NB] = cz();
+  auto t_column = [&](int kc) {
+    const int u = tid - 64;
+    if (u >= 0 && u < 8 * NB) {
+      const int r = u >> 3, part = u & 7;
+      c128 sacc = cz();
+      if (r < kc)
+        for (int q = r + ((part - r) & 7); q < kc; q += 8) sacc = cadd(sacc, cmul(Tm[r][q], Sk[kc][q]));
+      // sum over the 8 lanes of the row (DPP): quad sums, then lanes 4..7 of
+      // each 8-lane group add the quad below, so lane 7 holds the total
+      sacc.re += dpp_mov<0xb1>(sacc.re);
+      sacc.im += dpp_mov<0xb1>(sacc.im);
+      sacc.re += dpp_mov<0x4e>(sacc.re);
+      sacc.im += dpp_mov<0x4e>(sacc.im);
+      sacc.re += dpp_mov<0x114, 0xf, true>(sacc.re);
+      sacc.im += dpp_mov<0x114, 0xf, true>(sacc.im);
+      if (part == 7 && r < kc) Tm[r][kc] = cmul(mk<double>(-taus[kc].re, -taus[kc].im), sacc);
+    }
+  };
+
   for (int k = 0; k < jb; ++k) {
     const int slot = k & 1;
     // block partial over the row groups
@@ -268,7 +292,10 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
       pub_store(a.red + ((long long)slot * nblk + blk) * NB + tid, sblk);
       if (k >= r0 && k < r0 + nr) pub_store(a.rowbuf + slot * NB + tid, P[(k - r0) * LDP + tid]);
     }
-    if (!grid_barrier(gs, (unsigned)(a.gen0 + k + 3), blk, nblk, &flag)) return;
+    if (!grid_barrier(gs, (unsigned)(a.gen0 + k + 3), blk, nblk, &flag, [&]() {
+          if (k >= 2) t_column(k - 1);
+        }))
+      return;
     {  // one round of loads: 8 lanes per column share the block partials
       const int cl = tid / kColLanes, bg = tid % kColLanes;
       constexpr int kMaxPer = kMaxPanelBlocks / kColLanes;
@@ -309,6 +336,7 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
     }
     if (tid == 0) {
       taus[k] = tau;
+      Tm[k][k] = tau;
       if (!isfinite(beta)) latch_error(batch.status, ERRBIT_NONFINITE);
     }
     if (tid < k)  // V[:, j]^dag v_k = conj(V[k, j]) + scale * conj(t_j)
@@ -345,28 +373,9 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
     }
   }
 
-  // T of the compact-WY form: T[k][k] = tau_k, T[r][k] = -tau_k sum_q T[r][q] S_k[q]
-  // (q = r..k-1).  Row r depends only on its own earlier entries: the 8 lanes
-  // r*8 .. r*8+7 (one wave) build it, each summing every 8th term.
+  // the last column of T (the earlier ones were built during the barriers)
   __syncthreads();
-  if (tid < 8 * NB) {
-    const int r = tid >> 3, part = tid & 7;
-    for (int q = part; q < NB; q += 8) Tm[r][q] = (q == r && r < jb) ? taus[r] : cz();
-    for (int k = 1; k < jb; ++k) {
-      c128 sacc = cz();
-      if (r < k)
-        for (int q = r + ((part - r) & 7); q < k; q += 8) sacc = cadd(sacc, cmul(Tm[r][q], Sk[k][q]));
-      // sum over the 8 lanes of the row (DPP): quad sums, then lanes 4..7 of
-      // each 8-lane group add the quad below, so lane 7 holds the total
-      sacc.re += dpp_mov<0xb1>(sacc.re);
-      sacc.im += dpp_mov<0xb1>(sacc.im);
-      sacc.re += dpp_mov<0x4e>(sacc.re);
-      sacc.im += dpp_mov<0x4e>(sacc.im);
-      sacc.re += dpp_mov<0x114, 0xf, true>(sacc.re);
-      sacc.im += dpp_mov<0x114, 0xf, true>(sacc.im);
-      if (part == 7 && r < k) Tm[r][k] = cmul(mk<double>(-taus[k].re, -taus[k].im), sacc);
-    }
-  }
+  if (jb >= 2) t_column(jb - 1);
   __syncthreads();
 
   // write back R / reflectors in place, the explicit V and (block 0) T
