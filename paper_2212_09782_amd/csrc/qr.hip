@@ -63,9 +63,7 @@ constexpr int kMaxPanelRows = 160;
 constexpr int kPanelThreads = 512;   // 16 row groups x 32 columns: two waves per SIMD (1024: slower)
 constexpr int kRowGroups = kPanelThreads / 32;
 constexpr int kStage = NB * NB / kPanelThreads;          // elements of a 32 x 32 tile per thread
-constexpr int kQOut = NB * NB / kPanelThreads;           // V^H A outputs per thread in the pre-phase
 constexpr int kColLanes = kPanelThreads / NB;            // lanes that share one column's partials
-__device__ inline int rg_of(int tid) { return tid >> 5; }
 
 template <typename S>
 __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batch) {
@@ -102,63 +100,56 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
     // block 0, on the 32 rows above (written back: they belong to R).
     const cpx<S>* Vp = (const cpx<S>*)a.Vprev;
     cpx<S>* At = (cpx<S>*)a.Atop;
-    const int cc = tid & 31, q0 = tid >> 5;   // outputs (q0 + (NB / kQOut) o, cc), o < kQOut
-    // V rows in 32-row chunks through Sk (free until the column loop).  Chunk
-    // 0 of block 0 is the 32 rows above the panel (their A rows go through Tm);
-    // the slab's chunks follow.  Each thread loads kStage elements of a
-    // chunk, one chunk ahead of its use.
-    const int top = blk == 0 ? 1 : 0;
-    const int nch = (nr + NB - 1) / NB + top;
-    auto chunk_rows = [&](int ch) { return ch < top ? NB : min(NB, nr - (ch - top) * NB); };
-    auto load_v = [&](int ch, int e) -> c128 {
-      const int idx = tid + kPanelThreads * e, t = idx / NB, q = idx % NB;
-      if (t >= chunk_rows(ch)) return cz();
-      const long long row = ch < top ? t : NB + r0 + (ch - top) * NB + t;
-      return ccast<double>(Vp[row * LDV + q]);
-    };
-    c128 vn[kStage], at[kStage];
+    // This block's share of the rows: the 32 rows above the panel (block 0
+    // only: A rows from Atop) and the slab (A rows in LDS).  Share row t is
+    // row vrow(t) of Vp.  Both products run on FP64 MFMA (16x16x4 blocks,
+    // four real products per complex one); a lane holds A element
+    // (lane & 15, lane >> 4), B element (lane >> 4, lane & 15) and output
+    // rows (lane >> 4) + 4 r of column lane & 15.
+    typedef double v4d __attribute__((ext_vector_type(4)));
+    auto mfma = [](double x, double y, v4d acc) { return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0); };
+    const int top = blk == 0 ? NB : 0, K1 = top + nr;
+    auto vrow = [&](int t) -> long long { return t < top ? t : NB + r0 + (t - top); };
+    const int wv = tid >> 6, lane = tid & 63, lm = lane & 15, lk = lane >> 4;
+    {
+      // W_blk = V^H A over the share: wave wv owns output block (qi, ci) =
+      // (wv & 1, (wv >> 1) & 1) and every other k step (kh = wv >> 2)
+      const int qi = wv & 1, ci = (wv >> 1) & 1, kh = wv >> 2;
+      const int nsteps = (K1 + 3) / 4;
+      constexpr int kB = 8;   // k steps whose operands are loaded together
+      v4d cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+      for (int s0 = kh; s0 < nsteps; s0 += 2 * kB) {
+        c128 va[kB], xa[kB];
 #pragma unroll
-    for (int e = 0; e < kStage; ++e) {
-      vn[e] = load_v(0, e);
-      const int idx = tid + kPanelThreads * e, t = idx / NB, q = idx % NB;
-      at[e] = (top && q < jb) ? ccast<double>(At[(long long)t * a.lda + q]) : cz();
-    }
-    c128 wacc[kQOut][4];
-#pragma unroll
-    for (int o = 0; o < kQOut; ++o)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) wacc[o][u] = cz();
-    for (int ch = 0; ch < nch; ++ch) {
-      {
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < kStage; ++e) {
-          const int idx = tid + kPanelThreads * e;
-          Sk[idx / NB][idx % NB] = vn[e];
-          if (ch < top) Tm[idx / NB][idx % NB] = at[e];
-        }
-        if (ch + 1 < nch)
-#pragma unroll
-          for (int e = 0; e < kStage; ++e) vn[e] = load_v(ch + 1, e);
-        __syncthreads();
-        const int rows = chunk_rows(ch);
-        for (int t0 = 0; t0 < rows; t0 += 4)   // four independent accumulation chains
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int t = t0 + u;
-            if (t < rows) {
-              const c128 x = ch < top ? Tm[t][cc] : P[((ch - top) * NB + t) * LDP + cc];
-#pragma unroll
-              for (int o = 0; o < kQOut; ++o)
-                wacc[o][u] = cadd(wacc[o][u], cmulc(Sk[t][q0 + (NB / kQOut) * o], x));
-            }
+        for (int u = 0; u < kB; ++u) {
+          const int t = 4 * (s0 + 2 * u) + lk, cx = 16 * ci + lm;
+          va[u] = cz();
+          xa[u] = cz();
+          if (t < K1) {
+            va[u] = ccast<double>(Vp[vrow(t) * LDV + 16 * qi + lm]);
+            xa[u] = t >= top ? P[(t - top) * LDP + cx] : (cx < jb ? ccast<double>(At[(long long)t * a.lda + cx]) : cz());
           }
-      }
-    }
+        }
 #pragma unroll
-    for (int o = 0; o < kQOut; ++o)
-      pub_store(a.wx + ((long long)blk * NB + cc) * NB + q0 + (NB / kQOut) * o,
-                cadd(cadd(wacc[o][0], wacc[o][1]), cadd(wacc[o][2], wacc[o][3])));
+        for (int u = 0; u < kB; ++u) {   // A = V^H: (Re V, -Im V)
+          cre = mfma(va[u].re, xa[u].re, cre);
+          cre = mfma(va[u].im, xa[u].im, cre);
+          cim = mfma(va[u].re, xa[u].im, cim);
+          cim = mfma(-va[u].im, xa[u].re, cim);
+        }
+      }
+      // the two k halves meet in Sk (free until the column loop)
+      if (kh == 1)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Sk[16 * qi + lk + 4 * r][16 * ci + lm] = mk<double>(cre[r], cim[r]);
+      __syncthreads();
+      if (kh == 0)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = 16 * qi + lk + 4 * r, cx = 16 * ci + lm;
+          pub_store(a.wx + ((long long)blk * NB + cx) * NB + q, cadd(mk<double>(cre[r], cim[r]), Sk[q][cx]));
+        }
+    }
     if (!grid_barrier(gs, (unsigned)(a.gen0 + 1), blk, nblk, &flag)) return;
     // Block b reduces columns b, b + nblk, ...: W[:, c] = sum of the block
     // partials, then (T^H W)[:, c], published for everyone.
@@ -208,40 +199,42 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
       const int idx = tid + kPanelThreads * e;
       Tm[idx / NB][idx % NB] = coh_load(rwx, nblk * NB * NB + idx);
     }
-    // A -= V W: thread (row t of the chunk, column cc), kRowGroups rows at a time
+    __syncthreads();
+    // A -= V W over the share: wave wv owns row blocks wv, wv + 8, ..., both
+    // column blocks
+    for (int ti = wv; ti < (K1 + 15) / 16; ti += 8) {
+      c128 va[NB / 4];
 #pragma unroll
-    for (int e = 0; e < kStage; ++e) vn[e] = load_v(0, e);
-    for (int ch = 0; ch < nch; ++ch) {
-      {
-        __syncthreads();
+      for (int s4 = 0; s4 < NB / 4; ++s4) {
+        const int t = 16 * ti + lm;
+        va[s4] = t < K1 ? ccast<double>(Vp[vrow(t) * LDV + 4 * s4 + lk]) : cz();
+      }
+      v4d dre[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, dim[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
-        for (int e = 0; e < kStage; ++e) {
-          const int idx = tid + kPanelThreads * e;
-          Sk[idx / NB][idx % NB] = vn[e];
+      for (int s4 = 0; s4 < NB / 4; ++s4)
+#pragma unroll
+        for (int cj = 0; cj < 2; ++cj) {
+          const c128 w = Tm[4 * s4 + lk][16 * cj + lm];
+          dre[cj] = mfma(va[s4].re, w.re, dre[cj]);
+          dre[cj] = mfma(-va[s4].im, w.im, dre[cj]);
+          dim[cj] = mfma(va[s4].re, w.im, dim[cj]);
+          dim[cj] = mfma(va[s4].im, w.re, dim[cj]);
         }
-        if (ch + 1 < nch)
 #pragma unroll
-          for (int e = 0; e < kStage; ++e) vn[e] = load_v(ch + 1, e);
-        __syncthreads();
-        const int rows = chunk_rows(ch);
-        for (int t = rg_of(tid); t < rows; t += kRowGroups) {
-          c128 d4[4] = {cz(), cz(), cz(), cz()};
+      for (int cj = 0; cj < 2; ++cj)
 #pragma unroll
-          for (int q0b = 0; q0b < NB; q0b += 4)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) d4[u] = cadd(d4[u], cmul(Sk[t][q0b + u], Tm[q0b + u][cc]));
-          const c128 d = cadd(cadd(d4[0], d4[1]), cadd(d4[2], d4[3]));
-          if (ch < top) {
-            if (cc < jb) {
-              const long long o = (long long)t * a.lda + cc;
-              At[o] = ccast<S>(csub(ccast<double>(At[o]), d));
-            }
-          } else {
-            c128* x = P + ((ch - top) * NB + t) * LDP + cc;
+        for (int r = 0; r < 4; ++r) {
+          const int t = 16 * ti + lk + 4 * r, cx = 16 * cj + lm;
+          if (t >= K1) continue;
+          const c128 d = mk<double>(dre[cj][r], dim[cj][r]);
+          if (t >= top) {
+            c128* x = P + (t - top) * LDP + cx;
             *x = csub(*x, d);
+          } else if (cx < jb) {
+            const long long o = (long long)t * a.lda + cx;
+            At[o] = ccast<S>(csub(ccast<double>(At[o]), d));
           }
         }
-      }
     }
     __syncthreads();
   }
