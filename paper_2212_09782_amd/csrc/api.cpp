@@ -163,14 +163,15 @@ int mps_ctx_create(int device, mps_ctx* out) {
     return set_error(MPS_ERR_HIP, "context allocation failed");
   }
   // The auxiliary stream (trailing updates of the QR look-ahead) leaves one
-  // CU in eight to the cooperative panel kernels that run beside it, so the
-  // two really overlap; a plain stream if the masked one is unavailable.
+  // CU in four to the panel kernels that run beside it (64 of 256: a whole
+  // panel of one QR), so the two really overlap; a plain stream if the
+  // masked one is unavailable.
   {
     int ncu = 0;
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
     std::vector<uint32_t> mask((std::max(ncu, 1) + 31) / 32, 0u);
     for (int cu = 0; cu < ncu; ++cu)
-      if (cu % 8 != 0) mask[cu / 32] |= 1u << (cu % 32);
+      if (cu % 4 != 0) mask[cu / 32] |= 1u << (cu % 32);
     if (ncu < 64 || hipExtStreamCreateWithCUMask(&c->qa.aux, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
       (void)hipGetLastError();
       c->qa.aux = nullptr;

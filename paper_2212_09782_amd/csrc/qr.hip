@@ -49,6 +49,9 @@ struct PanelProb {
   int m, jb, rows_per_blk, nblk, blk0, gen0, odd;
 };
 constexpr int kMaxPanelProbs = 24;
+// Panel launches of at most this many blocks are plain launches (the CUs
+// that the auxiliary stream's mask leaves free hold them all).
+constexpr int kPlainPanelBlocks = 64;
 struct PanelBatch {
   int nprob;
   int* status;
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
       // (wv & 1, (wv >> 1) & 1) and every other k step (kh = wv >> 2)
       const int qi = wv & 1, ci = (wv >> 1) & 1, kh = wv >> 2;
       const int nsteps = (K1 + 3) / 4;
-      constexpr int kB = 8;   // k steps whose operands are loaded together
+      constexpr int kB = 16;   // k steps whose operands are loaded together
       v4d cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
       for (int s0 = kh; s0 < nsteps; s0 += 2 * kB) {
         c128 va[kB], xa[kB];
@@ -150,7 +153,18 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
           pub_store(a.wx + ((long long)blk * NB + cx) * NB + q, cadd(mk<double>(cre[r], cim[r]), Sk[q][cx]));
         }
     }
-    if (!grid_barrier(gs, (unsigned)(a.gen0 + 1), blk, nblk, &flag)) return;
+    // V rows of this wave's first row block of the update below, requested
+    // while the barrier waits (after its store wait, which would otherwise
+    // wait for them too) so that their latency passes during the reduction
+    c128 va5[NB / 4];
+    auto load_v5 = [&](int ti) {
+#pragma unroll
+      for (int s4 = 0; s4 < NB / 4; ++s4) {
+        const int t = 16 * ti + lm;
+        va5[s4] = t < K1 ? ccast<double>(Vp[vrow(t) * LDV + 4 * s4 + lk]) : cz();
+      }
+    };
+    if (!grid_barrier(gs, (unsigned)(a.gen0 + 1), blk, nblk, &flag, [&]() { load_v5(wv); })) return;
     // Block b reduces columns b, b + nblk, ...: W[:, c] = sum of the block
     // partials, then (T^H W)[:, c], published for everyone.
     c128* w2 = a.wx + (long long)nblk * NB * NB;
@@ -203,12 +217,8 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
     // A -= V W over the share: wave wv owns row blocks wv, wv + 8, ..., both
     // column blocks
     for (int ti = wv; ti < (K1 + 15) / 16; ti += 8) {
-      c128 va[NB / 4];
-#pragma unroll
-      for (int s4 = 0; s4 < NB / 4; ++s4) {
-        const int t = 16 * ti + lm;
-        va[s4] = t < K1 ? ccast<double>(Vp[vrow(t) * LDV + 4 * s4 + lk]) : cz();
-      }
+      if (ti != wv) load_v5(ti);
+      const c128* va = va5;
       v4d dre[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, dim[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
       for (int s4 = 0; s4 < NB / 4; ++s4)
@@ -430,6 +440,16 @@ int launch_panel(const PanelBatch& pb, int nblk_total, int max_rows, hipStream_t
     QT_HIP_CHECK(hipFuncSetAttribute((const void*)qr_panel_kernel<S>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, kMaxPanelRows * LDP * sizeof(c128)));
     attr_set = true;
+  }
+  if (nblk_total <= kPlainPanelBlocks) {
+    // A plain launch stays on the stream's own queue (a cooperative launch
+    // goes through a separate device queue, two cross-queue hops per panel).
+    // Its blocks are co-resident: one block per CU, and the CUs that the
+    // context's auxiliary stream leaves free hold them all; other work only
+    // delays the last blocks (the spins are bounded).
+    hipLaunchKernelGGL(qr_panel_kernel<S>, dim3(nblk_total), dim3(kPanelThreads), shmem, s, pb);
+    QT_HIP_CHECK(hipGetLastError());
+    return 0;
   }
   void* args[] = {(void*)&pb};
   QT_HIP_CHECK(hipLaunchCooperativeKernel((const void*)qr_panel_kernel<S>, dim3(nblk_total), dim3(kPanelThreads), args,
