@@ -41,6 +41,14 @@ __device__ inline void latch_error(int* status, int bit) {
   if (status) atomicOr(status, bit);
 }
 
+// 1/x from the hardware reciprocal refined by two Newton steps (within an ulp
+// or two of the rounded quotient) for finite, nonzero, normal x.
+__device__ inline double rcp_refined(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // ---------------------------------------------------------------- reductions
 // Lane moves inside the VALU (DPP), no LDS traffic.  Lanes whose source is
 // outside the row, or whose row is masked off, receive 0.

@@ -332,10 +332,11 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
     double beta = alpha.re;
     if (!(xnorm2 == 0.0 && alpha.im == 0.0)) {
       beta = -copysign(sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xnorm2), alpha.re);
-      tau = mk<double>((beta - alpha.re) / beta, -alpha.im / beta);
+      const double ib = rcp_refined(beta);
+      tau = mk<double>((beta - alpha.re) * ib, -alpha.im * ib);
       const c128 den = mk<double>(alpha.re - beta, alpha.im);
-      const double dd = cabs2(den);
-      scale = mk<double>(den.re / dd, -den.im / dd);
+      const double idd = rcp_refined(cabs2(den));
+      scale = mk<double>(den.re * idd, -den.im * idd);
     }
     if (tid == 0) {
       taus[k] = tau;
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
     // Every lane reads the old P[i,k] and P[i,k+1] of its row (broadcast) and
     // its own P[i,c] before it writes P[i,c]; rows go in unrolled chunks so
     // their loads are in flight together.
-    constexpr int RU = 4;
+    constexpr int RU = 5;
     for (int i0 = rg; i0 < nr; i0 += kRowGroups * RU) {
       c128 pk[RU], pn[RU], b[RU];
 #pragma unroll
