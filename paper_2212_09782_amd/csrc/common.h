@@ -88,6 +88,43 @@ __device__ inline T wave_sum_to63(T v) {
   v += dpp_mov<0x143, 0xc>(v);        // row_bcast:31 into rows 2 and 3
   return v;
 }
+// Wave sums of 16 values at once by halving: each step pairs two values,
+// every lane keeps one of them and adds the partner lane's copy of it
+// (v_permlane32_swap: lanes l and l + 32; v_permlane16_swap: rows 2i and
+// 2i + 1; DPP row_ror:8; DPP row_half_mirror), then quad sums.  Afterwards
+// lane l holds the wave total of x[l >> 2] (fixed order).
+__device__ inline double swap_sum32(double x, double y) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
+  // first result: x in lanes 0-31, y's lanes 0-31 in lanes 32-63; second: the upper halves
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ inline double swap_sum16(double x, double y) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
+  // first result: rows (x0, y0, x2, y2), second: (x1, y1, x3, y3)
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ inline double wave_sum16(const double (&x)[16]) {
+  const int lane = threadIdx.x & 63;
+  double b[8], c[4], d[2];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) b[e] = swap_sum32(x[e], x[e + 8]);   // half h keeps x[e + 8 h]
+#pragma unroll
+  for (int e = 0; e < 4; ++e) c[e] = swap_sum16(b[e], b[e + 4]);   // row parity j keeps b[e + 4 j]
+  const bool b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {                                   // lane bit 3 keeps c[e + 2 bit3]
+    const double keep = b3 ? c[e + 2] : c[e], send = b3 ? c[e] : c[e + 2];
+    d[e] = keep + dpp_mov<0x128>(send);                           // row_ror:8 (lane i ^ 8)
+  }
+  const double keep = b2 ? d[1] : d[0], send = b2 ? d[0] : d[1];  // lane bit 2 keeps d[bit2]
+  double f = keep + dpp_mov<0x141>(send);                         // row_half_mirror (i <-> 7 - i)
+  f += dpp_mov<0xb1>(f);                                          // quad sums
+  f += dpp_mov<0x4e>(f);
+  return f;
+}
+
 // Wave64 sum, every lane gets it (fixed order).
 __device__ inline double wave_sum(double v) { return lane_read(wave_sum_to63(v), 63); }
 __device__ inline float wave_sum(float v) { return lane_read(wave_sum_to63(v), 63); }

@@ -152,10 +152,11 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriBatch batch) {
     double beta = alpha.re;
     if (!(xn2 == 0.0 && alpha.im == 0.0)) {
       beta = -copysign(sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn2), alpha.re);
-      tau = mk<double>((beta - alpha.re) / beta, -alpha.im / beta);
+      const double ib = rcp_refined(beta);
+      tau = mk<double>((beta - alpha.re) * ib, -alpha.im * ib);
       const c128 den = mk<double>(alpha.re - beta, alpha.im);
-      const double dd = cabs2(den);
-      scale = mk<double>(den.re / dd, -den.im / dd);
+      const double idd = rcp_refined(cabs2(den));
+      scale = mk<double>(den.re * idd, -den.im * idd);
     }
     if (blk == 0 && tid == 0) {
       a.d[kk] = scal[1].re;
@@ -179,11 +180,8 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriBatch batch) {
   // p = tau A v over the own rows i > kk from the partial sums acc[2r], acc[2r+1]
   // of this thread; publishes p, this block's p^H v (slot sl) and returns.
   auto publish_p = [&](double (&acc)[16], int kk, int sl, int vb) {
-#pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] = wave_sum_to63(acc[e]);
-    if (lane == 63)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) wred[wid][e] = acc[e];
+    const double ws = wave_sum16(acc);   // lane l: wave total of acc[l >> 2]
+    if ((lane & 3) == 0) wred[wid][lane >> 2] = ws;
     __syncthreads();
     if (wid == 0) {
       c128 part = z0();
