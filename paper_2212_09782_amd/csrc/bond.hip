@@ -356,7 +356,11 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
       ew[i] = eig_work_carve(W[i].eigw, eta, calls[i].status);
     }
     if ((rc = gemm_run(g.data(), (int)g.size(), GemmTypes{dt, DT_C128}, s))) return rc;
-    for (int i : cb) ej.push_back(EigJob{W[i].G, calls[i].b.eta, kwant_of(calls[i].b), W[i].lam, W[i].E, &ew[i]});
+    // the mixed path re-orthogonalises B~[n] in FP64 after the complex64
+    // rounding of E, so one Newton-Schulz step on E suffices there
+    for (int i : cb)
+      ej.push_back(EigJob{W[i].G, calls[i].b.eta, kwant_of(calls[i].b), W[i].lam, W[i].E, &ew[i],
+                          calls[i].b.prec == 0 ? 2 : 1});
     if ((rc = eig_herm_top_batch(ej.data(), (int)ej.size(), s))) return rc;
     g.clear();
     for (int i : cb) {

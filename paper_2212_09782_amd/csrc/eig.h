@@ -33,6 +33,7 @@ struct EigJob {
   double* lam;
   c128* E;
   const EigWork* w;
+  int ns_steps = 2;   // Newton-Schulz re-orthonormalisation steps of the eigenvectors (0..2)
 };
 int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s);
 

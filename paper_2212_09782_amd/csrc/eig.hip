@@ -833,12 +833,17 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
     hipLaunchKernelGGL(cluster_mgs_kernel, dim3(maxk, sb.njobs), dim3(256), 0, s, sb, 1e-9);
     QT_HIP_CHECK(hipGetLastError());
   }
-  // 6. two Newton-Schulz steps Z <- Z - Z (Z^H Z - 1)/2, grouped over the jobs
+  // 6. Newton-Schulz steps Z <- Z - Z (Z^H Z - 1)/2 (each squares the
+  // orthogonality error of Z), grouped over the jobs
   const GemmTypes ty{DT_C128, DT_C128};
   std::vector<GemmProb> gs;
   for (int it = 0; it < 2; ++it) {
+    std::vector<int> ns;
+    for (int j : big)
+      if (it < jobs[j].ns_steps) ns.push_back(j);
+    if (ns.empty()) break;
     gs.clear();
-    for (int j : big) {
+    for (int j : ns) {
       const EigJob& J = jobs[j];
       // the inverse-iteration factors are dead: their buffer holds split-K partials
       GemmProb g1 = gemm_prob(J.E, J.kwant, OP_C, J.E, J.kwant, OP_N, J.w->gz, J.kwant, J.kwant, J.kwant, J.n);
@@ -848,7 +853,7 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
     }
     if ((rc = gemm_run(gs.data(), (int)gs.size(), ty, s))) return rc;
     gs.clear();
-    for (int j : big) {
+    for (int j : ns) {
       const EigJob& J = jobs[j];
       hipLaunchKernelGGL(sub_identity_kernel, dim3(std::min(4096, (J.kwant * J.kwant + 255) / 256)), dim3(256), 0, s,
                          J.w->gz, J.kwant);
