@@ -28,6 +28,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12
 PEAK = {"c128": 78.6e12, "c64": 157.3e12}   # dense FP64 / FP32 matrix-core peaks (MI355X)
+# HBM bytes per launch of the mixed path's contraction GEMM (mean over its five
+# launches per update), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by the
+# same counters read for a plain 256 MiB copy (--copy-calibration); the
+# commands and raw figures are in profiles/contract_gemm_hbm_d5_chi1024_mixed.md.
+# Only valid for the kernel version those counters were taken on.
+CONTRACT_TRAFFIC_C64 = 1.3548e9
 
 
 def run_precision(lib, torch, prec, chi, d, steps, warmup):
@@ -122,7 +128,18 @@ def main():
     ap.add_argument("--d", type=int, default=5)
     ap.add_argument("--prec", choices=["both", "c128", "mixed"], default="both")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB three times (reference run for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        x = torch.ones(64 * 2**20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print("copied 3 x 256 MiB", flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the bond update is a "
               "single-GPU kernel pipeline; multi-GPU sharding is a design note only)", file=sys.stderr)
@@ -169,7 +186,7 @@ def main():
             "peak": round(PEAK[head] / 1e12, 1),
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK[head], 4),
-            "traffic": None,
+            "traffic": CONTRACT_TRAFFIC_C64 if head == "c64" else None,
         },
     }
     if args.cpu_budget > 0:

@@ -444,156 +444,152 @@ __device__ inline double hash_uniform(unsigned long long x) {
 }
 
 // Inverse iteration for eigenvalue lam[j]: E[:, j] (real, stored complex).
-// lu: [4][n][kwant] (reciprocal pivot, the two further entries of the pivot
-// row, the multiplier), swp: [n][kwant] row-interchange flags; T = (d, e)
-// staged in LDS.  One thread per eigenvalue; every pass over the stored
-// factors loads kPf steps ahead so the recurrences do not wait on memory.
-constexpr int kPf = 16;
+// One thread per eigenvalue, G eigenvalues per block, everything in LDS: T =
+// (d, e) and, per eigenvalue, the factors of T - lam I with partial pivoting
+// and the work vector.  Step k of the factorisation keeps the reciprocal
+// pivot R0 = 1/u0, a flag for a row interchange, and Q = the second entry u1
+// of the pivot row (no interchange) or the displaced pivot candidate c (the
+// multiplier's numerator; an interchanged pivot row is (e[k], d[k+1] - lam,
+// e[k+1])), so the multiplier is e[k] R0 or c R0 either way.  Two solves: a
+// hashed uniform start vector (eliminated while factoring), then the
+// max-normalised first solution; the result has unit 2-norm.
+constexpr int kInvitLds = 159 * 1024;
+constexpr int kIvChunk = 16;   // steps whose operands are loaded before their recurrence
+__host__ __device__ inline size_t invit_lds_bytes(int n, int g) { return ((size_t)2 + 3 * (size_t)g) * n * 8 + (size_t)g * n; }
+inline int invit_group(int n) {
+  int g = 8;
+  while (g > 1 && invit_lds_bytes(n, g) > (size_t)kInvitLds) --g;
+  return g;
+}
 
-__global__ __launch_bounds__(64) void invit_kernel(SmallBatch sb) {
+__global__ __launch_bounds__(64) void invit_kernel(SmallBatch sb, int G) {
+  extern __shared__ double sm[];
   const SmallJob& J = sb.j[blockIdx.y];
-  const double* d = J.d;
-  const double* e = J.e;
   const int n = J.n, kwant = J.kwant;
-  const double* lam = J.lam;
-  double* lu = J.lu;
-  unsigned char* swp = J.swp;
-  c128* E = J.E;
-  if ((int)blockIdx.x * 64 >= kwant) return;
-  __shared__ double sd[kMaxN], se[kMaxN];
+  if ((int)blockIdx.x * G >= kwant) return;
+  double* __restrict__ sd = sm;
+  double* __restrict__ se = sm + n;
+  const int g = threadIdx.x;
+  double tn = 0;
   for (int i = threadIdx.x; i < n; i += 64) {
-    sd[i] = d[i];
-    se[i] = i < n - 1 ? e[i] : 0.0;
+    sd[i] = J.d[i];
+    se[i] = i < n - 1 ? J.e[i] : 0.0;
+    tn = fmax(tn, fabs(J.d[i]) + (i > 0 ? fabs(J.e[i - 1]) : 0.0) + (i < n - 1 ? fabs(J.e[i]) : 0.0));
   }
+  const double tnorm = wave_max(tn);
   __syncthreads();
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= kwant) return;
-  const double l = lam[j];
-  double tnorm = 0;
-  for (int i = 0; i < n; ++i) tnorm = fmax(tnorm, fabs(sd[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0) + fabs(se[i]));
+  const int j = blockIdx.x * G + g;
+  if (g >= G || j >= kwant) return;
+  double* __restrict__ R0 = sm + 2 * (size_t)n + (size_t)g * 3 * n;
+  double* __restrict__ Q = R0 + n;
+  double* __restrict__ W = Q + n;
+  unsigned char* __restrict__ sw = (unsigned char*)(sm + 2 * (size_t)n + (size_t)G * 3 * n) + (size_t)g * n;
+  const double l = J.lam[j];
   const double tiny = fmax(tnorm, 1e-300) * 2.2e-16;
-  double* R0 = lu;
-  double* U1 = lu + (size_t)n * kwant;
-  double* U2 = lu + 2 * (size_t)n * kwant;
-  double* ML = lu + 3 * (size_t)n * kwant;
-  auto at = [&](int i) { return (size_t)i * kwant + j; };
-  // factor T - l I with partial pivoting (row k+1 enters at step k); the
-  // first right-hand side, a hashed uniform start vector, is eliminated on
-  // the fly and stored in E's real parts
-  double c0 = sd[0] - l, c1 = n > 1 ? se[0] : 0.0, c2 = 0.0;
   auto start = [&](int i) { return hash_uniform(((unsigned long long)j << 32) ^ (unsigned)i); };
+  // factor (row k+1 enters at step k) and eliminate the start vector
+  double c0 = sd[0] - l, c1 = n > 1 ? se[0] : 0.0;
   double rc = start(0);
+#pragma unroll 4
   for (int k = 0; k < n - 1; ++k) {
     const double n0 = se[k], n1 = sd[k + 1] - l, n2 = se[k + 1];
     const double bk1 = start(k + 1);
-    double u0, u1, u2, m;
-    unsigned char sw;
-    if (fabs(c0) >= fabs(n0)) {
-      m = c0 != 0.0 ? n0 / c0 : 0.0;
-      u0 = c0; u1 = c1; u2 = c2; sw = 0;
-      c0 = n1 - m * c1; c1 = n2 - m * c2; c2 = 0.0;
-      E[at(k)] = mk<double>(rc, 0.0);
-      rc = bk1 - m * rc;
-    } else {
-      m = c0 / n0;
-      u0 = n0; u1 = n1; u2 = n2; sw = 1;
-      c0 = c1 - m * n1; c1 = c2 - m * n2; c2 = 0.0;
-      E[at(k)] = mk<double>(bk1, 0.0);
-      rc = rc - m * bk1;
-    }
-    if (u0 == 0.0) u0 = tiny;
-    R0[at(k)] = 1.0 / u0; U1[at(k)] = u1; U2[at(k)] = u2; ML[at(k)] = m; swp[at(k)] = sw;
+    // keep: pivot row (c0, c1, 0), else interchange: pivot row (n0, n1, n2);
+    // one path for all lanes (a zero pivot is replaced by tiny; then n0 = 0
+    // and the multiplier is 0)
+    const bool keep = fabs(c0) >= fabs(n0);
+    const double r0 = rcp_refined(keep ? (c0 != 0.0 ? c0 : tiny) : n0);
+    const double m = (keep ? n0 : c0) * r0;
+    R0[k] = r0;
+    Q[k] = keep ? c1 : c0;
+    sw[k] = keep ? 0 : 1;
+    W[k] = keep ? rc : bk1;
+    const double c0n = keep ? n1 - m * c1 : c1 - m * n1;
+    c1 = keep ? n2 : -m * n2;
+    c0 = c0n;
+    rc = keep ? bk1 - m * rc : rc - m * bk1;
   }
-  R0[at(n - 1)] = 1.0 / (c0 == 0.0 ? tiny : c0);
-  U1[at(n - 1)] = 0.0;
-  U2[at(n - 1)] = 0.0;
-  E[at(n - 1)] = mk<double>(rc, 0.0);
+  R0[n - 1] = rcp_refined(c0 == 0.0 ? tiny : c0);
+  Q[n - 1] = 0.0;
+  sw[n - 1] = 0;
+  W[n - 1] = rc;
 
-  double scale = 1.0;
+  double scale = 1.0, f = 1.0;
   for (int it = 0; it < 2; ++it) {
-    if (it == 1) {
-      // forward: the row operations of the factorisation applied to b (scaled)
-      double r = E[at(0)].re * scale;
-      for (int k0 = 0; k0 < n - 1; k0 += kPf) {
-        double bb[kPf], mm[kPf];
-        unsigned char ss[kPf];
+    if (it == 1) {   // the factorisation's row operations on the scaled first solution
+      double r = W[0] * scale;
+      for (int k0 = 0; k0 < n - 1; k0 += kIvChunk) {   // operands of a chunk first, then the recurrence
+        int xs[kIvChunk];
+        double bb[kIvChunk], mm[kIvChunk];
 #pragma unroll
-        for (int t = 0; t < kPf; ++t) {
-          const int k = k0 + t;
-          if (k < n - 1) {
-            bb[t] = E[at(k + 1)].re;
-            mm[t] = ML[at(k)];
-            ss[t] = swp[at(k)];
+        for (int t = 0; t < kIvChunk; ++t)
+          if (k0 + t < n - 1) {
+            xs[t] = sw[k0 + t];
+            bb[t] = W[k0 + t + 1] * scale;
           }
-        }
 #pragma unroll
-        for (int t = 0; t < kPf; ++t) {
-          const int k = k0 + t;
-          if (k < n - 1) {
-            const double bk1 = bb[t] * scale;
-            if (ss[t] == 0) {
-              E[at(k)].re = r;
-              r = bk1 - mm[t] * r;
-            } else {
-              E[at(k)].re = bk1;
-              r = r - mm[t] * bk1;
-            }
+        for (int t = 0; t < kIvChunk; ++t)
+          if (k0 + t < n - 1) mm[t] = *(xs[t] ? Q + k0 + t : se + k0 + t) * R0[k0 + t];   // a selected address
+#pragma unroll
+        for (int t = 0; t < kIvChunk; ++t)
+          if (k0 + t < n - 1) {
+            const bool keep = xs[t] == 0;
+            W[k0 + t] = keep ? r : bb[t];
+            r = keep ? bb[t] - mm[t] * r : r - mm[t] * bb[t];
           }
-        }
       }
-      E[at(n - 1)].re = r;
+      W[n - 1] = r;
     }
     // back substitution; the first pass's max norm rescales the second, the
     // second accumulates the 2-norm
     double z1 = 0.0, z2 = 0.0, nrm = 0.0, s2 = 0.0;
-    for (int i0 = n - 1; i0 >= 0; i0 -= kPf) {
-      double bb[kPf], r0[kPf], u1[kPf], u2[kPf];
+    for (int i0 = n - 1; i0 >= 0; i0 -= kIvChunk) {
+      // operands of a chunk first (loads from selected addresses, no
+      // branches): after an interchange the pivot row is (e[i], d[i+1] - lam,
+      // e[i+1]), else (u0, Q[i], 0); then the recurrence
+      int xs[kIvChunk];
+      double bb[kIvChunk], rr[kIvChunk], a1[kIvChunk], a2[kIvChunk];
 #pragma unroll
-      for (int t = 0; t < kPf; ++t) {
-        const int i = i0 - t;
-        if (i >= 0) {
-          bb[t] = E[at(i)].re;
-          r0[t] = R0[at(i)];
-          u1[t] = U1[at(i)];
-          u2[t] = U2[at(i)];
+      for (int t = 0; t < kIvChunk; ++t)
+        if (i0 - t >= 0) {
+          xs[t] = sw[i0 - t];
+          bb[t] = W[i0 - t];
+          rr[t] = R0[i0 - t];
         }
-      }
 #pragma unroll
-      for (int t = 0; t < kPf; ++t) {
-        const int i = i0 - t;
-        if (i >= 0) {
-          const double z = (bb[t] - u1[t] * z1 - u2[t] * z2) * r0[t];
-          E[at(i)].re = z;
+      for (int t = 0; t < kIvChunk; ++t)
+        if (i0 - t >= 0) {
+          const int i = i0 - t;
+          a1[t] = *(xs[t] ? sd + i + 1 : Q + i) - (xs[t] ? l : 0.0);
+          a2[t] = se[min(i + 1, n - 1)] * (double)xs[t];
+        }
+#pragma unroll
+      for (int t = 0; t < kIvChunk; ++t)
+        if (i0 - t >= 0) {
+          const double z = (bb[t] - a1[t] * z1 - a2[t] * z2) * rr[t];
+          W[i0 - t] = z;
           z2 = z1;
           z1 = z;
           nrm = fmax(nrm, fabs(z));
           s2 += z * z;
         }
-      }
     }
     if (it == 0) {
       scale = nrm > 0 ? 1.0 / nrm : 1.0;
     } else {
-      double f = s2 > 0 ? 1.0 / sqrt(s2) : 0.0;
+      f = s2 > 0 ? 1.0 / sqrt(s2) : 0.0;
       if (nrm > 1e150 || (nrm > 0 && nrm < 1e-150)) {   // sum of squares out of range: rescale by the max
         double t2 = 0.0;
         for (int i = 0; i < n; ++i) {
-          const double z = E[at(i)].re / nrm;
+          const double z = W[i] / nrm;
           t2 += z * z;
         }
         f = 1.0 / (nrm * sqrt(t2));
       }
-      for (int i0 = 0; i0 < n; i0 += kPf) {
-        double zz[kPf];
-#pragma unroll
-        for (int t = 0; t < kPf; ++t)
-          if (i0 + t < n) zz[t] = E[at(i0 + t)].re;
-#pragma unroll
-        for (int t = 0; t < kPf; ++t)
-          if (i0 + t < n) E[at(i0 + t)].re = zz[t] * f;
-      }
     }
   }
+  c128* E = J.E;
+  for (int i = 0; i < n; ++i) E[(size_t)i * kwant + j] = mk<double>(W[i] * f, 0.0);
 }
 
 // T_p for every panel of the tridiagonalisation reflectors (from the Gram
@@ -741,6 +737,8 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
   if (!attr) {
     QT_HIP_CHECK(hipFuncSetAttribute((const void*)tridiag_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)kTriLds));
+    QT_HIP_CHECK(hipFuncSetAttribute((const void*)invit_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kInvitLds));
     attr = true;
   }
   // validation, 1 x 1 problems, barrier words and reflector buffers
@@ -828,7 +826,9 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
     QT_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(bisect_kernel, dim3((maxk + 3) / 4, sb.njobs), dim3(256), 0, s, sb);
     QT_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(invit_kernel, dim3((maxk + 63) / 64, sb.njobs), dim3(64), 0, s, sb);
+    const int ig = invit_group(maxn);
+    hipLaunchKernelGGL(invit_kernel, dim3((maxk + ig - 1) / ig, sb.njobs), dim3(64), invit_lds_bytes(maxn, ig), s, sb,
+                       ig);
     QT_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(cluster_mgs_kernel, dim3(maxk, sb.njobs), dim3(256), 0, s, sb, 1e-9);
     QT_HIP_CHECK(hipGetLastError());
