@@ -36,7 +36,7 @@ PEAK = {"c128": 78.6e12, "c64": 157.3e12}   # dense FP64 / FP32 matrix-core peak
 CONTRACT_TRAFFIC_C64 = 1.3548e9
 
 
-def run_precision(lib, torch, prec, chi, d, steps, warmup):
+def run_precision(lib, torch, prec, chi, d, steps, warmup, sweeps=1):
     ctx = lib.Context(0)
     A, B, lA, lB = inputs_cell(chi, d)
     U = lib.clock_gate(d, 2.0, 0.05)
@@ -49,7 +49,8 @@ def run_precision(lib, torch, prec, chi, d, steps, warmup):
     du = dev(U, torch.complex128)
     chi_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
     eps_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
-    desc = lib.bond_desc(d, chi, chi, chi, eta, chi, 1e-14 if prec == lib.MPS_C128 else 1e-6, True, lib.CBE, prec)
+    desc = lib.bond_desc(d, chi, chi, chi, eta, chi, 1e-14 if prec == lib.MPS_C128 else 1e-6, True, lib.CBE, prec,
+                         sweeps)
     state = {"a": 0, "b": 0}
 
     def one(k):
@@ -128,6 +129,7 @@ def main():
     ap.add_argument("--d", type=int, default=5)
     ap.add_argument("--prec", choices=["both", "c128", "mixed"], default="both")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0: skip)")
+    ap.add_argument("--sweeps", type=int, default=1, help="QR/LQ sweeps per update (1: the paper's single sweep)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB three times (reference run for the HBM byte counters)")
     args = ap.parse_args()
@@ -152,9 +154,10 @@ def main():
 
     res = {}
     if args.prec in ("both", "c128"):
-        res["c128"] = run_precision(lib, torch, lib.MPS_C128, args.chi, args.d, args.steps, args.warmup)
+        res["c128"] = run_precision(lib, torch, lib.MPS_C128, args.chi, args.d, args.steps, args.warmup, args.sweeps)
     if args.prec in ("both", "mixed"):
-        res["c64"] = run_precision(lib, torch, lib.MPS_MIXED_C64, args.chi, args.d, args.steps, args.warmup)
+        res["c64"] = run_precision(lib, torch, lib.MPS_MIXED_C64, args.chi, args.d, args.steps, args.warmup,
+                                   args.sweeps)
     head = "c64" if "c64" in res else "c128"
     h = res[head]
     achieved = h["gemm_flops"] / (h["gemm_ms"] * 1e-3) if h["gemm_ms"] > 0 else 0.0
@@ -172,8 +175,9 @@ def main():
         "dtype": "c64" if head == "c64" else "c128",
         "data": "synthetic",
         "config": {"workload": f"single-bond QR+CBE update, uniform two-site cell, d={args.d}, chi={args.chi}, "
-                               f"eta={args.chi + -(-args.chi // 10)}, chi~={args.chi}, clock gate g=2 dt=0.05",
-                   "d": args.d, "chi": args.chi, "eta": args.chi + -(-args.chi // 10)},
+                               f"eta={args.chi + -(-args.chi // 10)}, chi~={args.chi}, clock gate g=2 dt=0.05"
+                               + (f", {args.sweeps} QR/LQ sweeps" if args.sweeps > 1 else ""),
+                   "d": args.d, "chi": args.chi, "eta": args.chi + -(-args.chi // 10), "sweeps": args.sweeps},
         "p50_ms": round(h["p50_ms"], 4),
         "p99_ms": round(h["p99_ms"], 4),
         "per_precision": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}

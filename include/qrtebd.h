@@ -76,7 +76,13 @@ typedef struct mps_ctx_s* mps_ctx;
  *  svd_min         CBE only: drop Schmidt values below svd_min (absolute;
  *                  the paper uses 1e-14); at least one value is kept
  *  xi_is_diag      1: xi_m is a real vector of chi_l doubles; 0: dense
- *  mode, prec      see above */
+ *  mode, prec      see above
+ *  sweeps          QR/LQ sweeps on theta~ (0 or 1: one, as in Sec. II);
+ *                  more repeat steps (i)-(ii) from Y0 = Q^[n] of the
+ *                  previous sweep, the alternating-least-squares reading of
+ *                  the Sec. II comments (for gates far from the identity);
+ *                  at most 16.  Appended field: a zero-initialised
+ *                  descriptor keeps the single sweep. */
 typedef struct {
   int d, chi_l, chi_m, chi_r;
   int eta;
@@ -85,6 +91,7 @@ typedef struct {
   int xi_is_diag;
   int mode;
   int prec;
+  int sweeps;
 } mps_bond_desc;
 
 /* Create / destroy a context on HIP device `device`.  Workspace grows on
@@ -154,6 +161,7 @@ typedef struct {
   double svd_min;
   int dchi_min;     /* eta = min(chi + max(dchi_min, ceil(dchi_frac*chi)), d chi_l, d chi_r) */
   double dchi_frac;
+  int sweeps;       /* QR/LQ sweeps per bond update, as in mps_bond_desc (0 or 1: one) */
 } mps_sweep_policy;
 
 /* nsteps Trotter steps on every state.  gates[s] points to the device gates

@@ -83,8 +83,12 @@ def select_chi(S, chi_max, svd_min):
     return max(k, 1)
 
 
-def qr_bond_update(xi, bm, bn, U, mode=CBE, eta=None, chi_max=None, svd_min=1e-14):
+def qr_bond_update(xi, bm, bn, U, mode=CBE, eta=None, chi_max=None, svd_min=1e-14, nsweeps=1):
     """QR-based bond update, Sec. II (plain / grow) and Sec. III (CBE).
+
+    nsweeps > 1 repeats steps (i)-(ii) from Y0 = Q^[n] of the previous sweep
+    (the alternating-least-squares reading of the Sec. II comments); the
+    truncation then uses the last sweep's factors.
 
     Returns a dict with
       bm, bn   new tensors [chi_L, d, chi~] and [chi~, d, chi_R]
@@ -112,6 +116,10 @@ def qr_bond_update(xi, bm, bn, U, mode=CBE, eta=None, chi_max=None, svd_min=1e-1
     # Y = Q^dag theta~, LQ -> L, Q^[n]  (Sec. II step (ii))
     Y = Q.conj().T @ Th
     L, Qn = lq(Y)
+    for _ in range(nsweeps - 1):                  # further sweeps from Y0 = Q^[n]
+        Q, _ = np.linalg.qr(Th @ Qn.conj().T, mode="reduced")
+        Y = Q.conj().T @ Th
+        L, Qn = lq(Y)
 
     out = dict(Q=Q, L=L, Qn=Qn, norm2=norm2, Ct=Ct, Th=Th)
     if mode in (PLAIN, GROW):

@@ -93,6 +93,7 @@ int check_desc(const mps_bond_desc* D) {
   if (std::max(mL, mR) > kMaxQrRows)
     return set_error(MPS_ERR_CAPACITY, "d chi=%d too large", std::max(mL, mR));
   if (D->mode == MPS_TRUNC_CBE && D->eta > 2048) return set_error(MPS_ERR_CAPACITY, "eta=%d > 2048", D->eta);
+  if (D->sweeps < 0 || D->sweeps > 16) return set_error(MPS_ERR_ARG, "sweeps=%d outside [0, 16]", D->sweeps);
   return 0;
 }
 
@@ -101,6 +102,7 @@ BondShape shape_of(const mps_bond_desc* D) {
   b.d = D->d; b.chi_l = D->chi_l; b.chi_m = D->chi_m; b.chi_r = D->chi_r;
   b.eta = D->eta; b.chi_max = D->chi_max; b.svd_min = D->svd_min;
   b.xi_is_diag = D->xi_is_diag; b.mode = D->mode; b.prec = D->prec;
+  b.sweeps = std::max(1, D->sweeps);
   return b;
 }
 
@@ -422,6 +424,7 @@ int run_layer(mps_ctx c, std::vector<BondRef>& bonds, const mps_sweep_policy* po
     D.xi_is_diag = 1;
     D.mode = MPS_TRUNC_CBE;
     D.prec = st->prec;
+    D.sweeps = pol->sweeps;
     if ((rc = check_desc(&D))) return rc;
     shapes[k] = shape_of(&D);
     off[k] = total;

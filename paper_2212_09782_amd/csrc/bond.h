@@ -21,6 +21,7 @@ struct BondShape {
   int d, chi_l, chi_m, chi_r, eta, chi_max;
   double svd_min;
   int xi_is_diag, mode, prec;
+  int sweeps = 1;      // QR/LQ sweeps (>= 1)
   int cap() const;     // capacity of the new bond
 };
 

@@ -335,6 +335,52 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
     QT_HIP_CHECK(hipGetLastError());
   }
   if ((rc = qr_form_q_batch(qj.data(), nc, dt, s))) return rc;
+  // further sweeps (bonds with sweeps > it): X = theta~ Q^[n]^dag = theta~ Q',
+  // then steps (i)-(ii) again
+  int maxsw = 1;
+  for (int i = 0; i < nc; ++i) maxsw = std::max(maxsw, calls[i].b.sweeps);
+  for (int it = 1; it < maxsw; ++it) {
+    std::vector<int> act;
+    for (int i = 0; i < nc; ++i)
+      if (calls[i].b.sweeps > it) act.push_back(i);
+    const int na = (int)act.size();
+    std::vector<QrJob> qa(na);
+    g.clear();
+    for (int i : act) {
+      const BondShape& b = calls[i].b;
+      const int mL = b.d * b.chi_l, mR = b.d * b.chi_r, eta = b.eta;
+      g.push_back(gemm_prob(W[i].Th, mR, OP_N, W[i].YH, eta, OP_N, W[i].X, eta, mL, eta, mR));
+    }
+    if ((rc = timed_gemm_batch(tm, g.data(), na, ty, s))) return rc;
+    for (int a = 0; a < na; ++a) {
+      const int i = act[a];
+      const BondShape& b = calls[i].b;
+      qa[a] = QrJob{W[i].X, b.eta, b.d * b.chi_l, b.eta, W[i].X, b.eta, b.eta, &QW[i]};
+    }
+    if ((rc = qr_factor_batch(qa.data(), na, dt, s, as))) return rc;
+    if ((rc = qr_form_q_batch(qa.data(), na, dt, s))) return rc;
+    g.clear();
+    for (int i : act) {
+      const BondShape& b = calls[i].b;
+      const int mL = b.d * b.chi_l, mR = b.d * b.chi_r, eta = b.eta;
+      g.push_back(gemm_prob(W[i].Th, mR, OP_C, W[i].X, eta, OP_N, W[i].YH, eta, mR, eta, mL));
+    }
+    if ((rc = timed_gemm_batch(tm, g.data(), na, ty, s))) return rc;
+    for (int a = 0; a < na; ++a) {
+      const int i = act[a];
+      const BondShape& b = calls[i].b;
+      qa[a] = QrJob{W[i].YH, b.eta, b.d * b.chi_r, b.eta, W[i].YH, b.eta, b.eta, &QW[i]};
+    }
+    if ((rc = qr_factor_batch(qa.data(), na, dt, s, as))) return rc;
+    for (int i : act) {
+      const int eta = calls[i].b.eta;
+      const long long n = (long long)eta * eta;
+      hipLaunchKernelGGL(extract_r_kernel<S>, dim3(grid_for(n)), dim3(256), 0, s, (const cpx<S>*)W[i].YH, eta,
+                         (cpx<S>*)W[i].R);
+      QT_HIP_CHECK(hipGetLastError());
+    }
+    if ((rc = qr_form_q_batch(qa.data(), na, dt, s))) return rc;
+  }
 
   // CBE: L^dag L = R' R'^dag in FP64, eigen-decomposition, selection
   std::vector<int> cb;

@@ -30,12 +30,12 @@ class mps_bond_desc(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int), ("chi_l", ctypes.c_int), ("chi_m", ctypes.c_int),
                 ("chi_r", ctypes.c_int), ("eta", ctypes.c_int), ("chi_max", ctypes.c_int),
                 ("svd_min", ctypes.c_double), ("xi_is_diag", ctypes.c_int), ("mode", ctypes.c_int),
-                ("prec", ctypes.c_int)]
+                ("prec", ctypes.c_int), ("sweeps", ctypes.c_int)]
 
 
 class mps_sweep_policy(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("chi_max", ctypes.c_int), ("svd_min", ctypes.c_double),
-                ("dchi_min", ctypes.c_int), ("dchi_frac", ctypes.c_double)]
+                ("dchi_min", ctypes.c_int), ("dchi_frac", ctypes.c_double), ("sweeps", ctypes.c_int)]
 
 
 class QrtebdError(RuntimeError):
@@ -152,8 +152,9 @@ def clock_gate(d, g, tau, wl=0.5, wr=0.5):
     return out
 
 
-def bond_desc(d, chi_l, chi_m, chi_r, eta, chi_max, svd_min=1e-14, xi_is_diag=True, mode=CBE, prec=MPS_C128):
-    return mps_bond_desc(d, chi_l, chi_m, chi_r, eta, chi_max, svd_min, int(bool(xi_is_diag)), mode, prec)
+def bond_desc(d, chi_l, chi_m, chi_r, eta, chi_max, svd_min=1e-14, xi_is_diag=True, mode=CBE, prec=MPS_C128,
+              sweeps=1):
+    return mps_bond_desc(d, chi_l, chi_m, chi_r, eta, chi_max, svd_min, int(bool(xi_is_diag)), mode, prec, sweeps)
 
 
 def bond_capacity(desc):
@@ -276,8 +277,8 @@ class State:
             pass
 
 
-def sweep_policy(chi_max, svd_min=1e-14, dchi_min=100, dchi_frac=0.1, mode=CBE):
-    return mps_sweep_policy(mode, chi_max, svd_min, dchi_min, dchi_frac)
+def sweep_policy(chi_max, svd_min=1e-14, dchi_min=100, dchi_frac=0.1, mode=CBE, sweeps=1):
+    return mps_sweep_policy(mode, chi_max, svd_min, dchi_min, dchi_frac, sweeps)
 
 
 def mps_sweep(ctx, states, gates, nsteps, order, policy, trunc_err=None, stream=None):

@@ -26,11 +26,11 @@ def ctx():
     c.close()
 
 
-def run_gpu(ctx, xi, bm, bn, U, mode, eta, chi_max, svd_min=1e-14, prec=lib.MPS_C128):
+def run_gpu(ctx, xi, bm, bn, U, mode, eta, chi_max, svd_min=1e-14, prec=lib.MPS_C128, sweeps=1):
     chiL, d, chiM = bm.shape
     chiR = bn.shape[2]
     diag = np.ndim(xi) == 1
-    desc = lib.bond_desc(d, chiL, chiM, chiR, eta, chi_max, svd_min, diag, mode, prec)
+    desc = lib.bond_desc(d, chiL, chiM, chiR, eta, chi_max, svd_min, diag, mode, prec, sweeps)
     cdt = torch.complex128 if prec == lib.MPS_C128 else torch.complex64
     dxi = torch.from_numpy(np.ascontiguousarray(xi).reshape(-1)).to("cuda")
     if not diag:
@@ -83,6 +83,29 @@ def test_bond_update_c128(ctx, case):
     U = inputs.near_identity_unitary(d * d, inputs.rng(d), scale=0.1)
     r = obond.qr_bond_update(xi, bm, bn, U, mode=mode, eta=eta, chi_max=chi_max, svd_min=1e-14)
     g = run_gpu(ctx, xi, bm, bn, U, mode, eta, chi_max)
+    compare(r, g)
+
+
+SWEEP_CASES = [
+    # chiL, chiM, chiR, d, mode, eta, chi_max, sweeps
+    (8, 8, 8, 3, obond.PLAIN, 8, 8, 2),
+    (16, 20, 12, 3, obond.GROW, 30, 30, 3),
+    (40, 40, 40, 4, obond.CBE, 48, 36, 2),
+    (70, 64, 66, 5, obond.CBE, 75, 60, 4),
+]
+
+
+@pytest.mark.parametrize("case", SWEEP_CASES, ids=[f"{c[0]}x{c[1]}x{c[2]}d{c[3]}m{c[4]}s{c[7]}" for c in SWEEP_CASES])
+def test_bond_update_sweeps(ctx, case):
+    """Iterated QR/LQ sweeps (gate far from the identity) against the oracle's nsweeps."""
+    chiL, chiM, chiR, d, mode, eta, chi_max, sweeps = case
+    print("bond sweeps", case, flush=True)
+    xi, bm, bn = inputs.random_bond(chiL, chiM, chiR, d, seed=chiL * 7 + sweeps)
+    U = inputs.near_identity_unitary(d * d, inputs.rng(d + 1), scale=0.6)
+    r = obond.qr_bond_update(xi, bm, bn, U, mode=mode, eta=eta, chi_max=chi_max, nsweeps=sweeps)
+    r1 = obond.qr_bond_update(xi, bm, bn, U, mode=mode, eta=eta, chi_max=chi_max)
+    assert r["eps"] <= r1["eps"] * (1 + 1e-9)
+    g = run_gpu(ctx, xi, bm, bn, U, mode, eta, chi_max, sweeps=sweeps)
     compare(r, g)
 
 

@@ -160,6 +160,25 @@ def test_sweeps_converge_to_svd_optimum():
     assert np.isclose(errs[-1], opt, rtol=1e-6, atol=1e-15)
 
 
+def test_multi_sweep_update_reaches_svd_truncation():
+    """Iterated sweeps (nsweeps > 1, the ALS reading of the Sec. II comments)
+    with a gate far from the identity: eps falls monotonically to the rank-chi
+    optimum of numpy's SVD (plain), and CBE's kept Schmidt values converge to
+    the leading singular values of theta~ (Eckart-Young)."""
+    xi, bm, bn = inputs.random_bond(6, 6, 6, 3, seed=41)
+    U = inputs.near_identity_unitary(9, inputs.rng(4), scale=0.8)
+    rs = [bond.qr_bond_update(xi, bm, bn, U, mode=bond.PLAIN, nsweeps=k) for k in (1, 2, 3, 5, 80)]
+    s = np.linalg.svd(rs[0]["Th"], compute_uv=False)
+    opt = np.sum(s[6:] ** 2) / np.sum(s ** 2)
+    eps = [r["eps"] for r in rs]
+    assert all(e2 <= e1 * (1 + 1e-9) + 1e-16 for e1, e2 in zip(eps, eps[1:]))
+    assert eps[0] > opt * (1 + 1e-3)                 # one sweep is not yet optimal here
+    assert np.isclose(eps[-1], opt, rtol=1e-8, atol=1e-15)
+    r = bond.qr_bond_update(xi, bm, bn, U, mode=bond.CBE, eta=8, chi_max=4, nsweeps=80)
+    assert np.allclose(r["S"][:4], s[:4], rtol=1e-9, atol=0)
+    assert np.isclose(r["eps"], np.sum(s[4:] ** 2) / np.sum(s ** 2), rtol=1e-8, atol=1e-15)
+
+
 # ---------------------------------------------------------------- whole runs
 
 def _gates(d, g, L, finite, dt):
