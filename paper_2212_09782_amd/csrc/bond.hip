@@ -180,7 +180,8 @@ __global__ void reorth_prep_kernel(const c128* G, int cap, const int* chi_new, c
   const long long n = (long long)k * k;
   for (long long idx = blockIdx.x * 256ll + threadIdx.x; idx < n; idx += (long long)gridDim.x * 256) {
     const int i = (int)(idx / k), j = (int)(idx % k);
-    const c128 g = G[(long long)i * cap + j];
+    // G is Hermitian and only its upper triangle was formed
+    const c128 g = i <= j ? G[(long long)i * cap + j] : cconj(G[(long long)j * cap + i]);
     Dc[(long long)i * cap + j] = mk<float>((float)(0.5 * (g.re - (i == j ? 1.0 : 0.0))), (float)(0.5 * g.im));
   }
 }
@@ -396,12 +397,15 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
       // theta~ is no longer needed: its buffer holds the split-K partials
       const size_t th_bytes = (size_t)b.d * b.chi_l * b.d * b.chi_r * sizeof(cpx<S>);
       GemmProb gg = gemm_prob(W[i].R, eta, OP_N, W[i].R, eta, OP_C, W[i].G, eta, eta, eta, eta);
-      gg.ksplit = splitk_auto(eta, eta, eta, th_bytes, sizeof(c128));
+      gg.ksplit = splitk_auto(eta, eta, eta, th_bytes, sizeof(c128), true);
       gg.work = W[i].Th;
+      gg.herm = 1;
       g.push_back(gg);
       ew[i] = eig_work_carve(W[i].eigw, eta, calls[i].status);
     }
     if ((rc = gemm_run(g.data(), (int)g.size(), GemmTypes{dt, DT_C128}, s))) return rc;
+    for (int i : cb)
+      if ((rc = herm_fill_lower(W[i].G, calls[i].b.eta, calls[i].b.eta, s))) return rc;
     // the mixed path re-orthogonalises B~[n] in FP64 after the complex64
     // rounding of E, so one Newton-Schulz step on E suffices there
     for (int i : cb)
@@ -458,8 +462,9 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
       GemmProb g2 = gemm_prob(c.b_n_out, mR, OP_N, c.b_n_out, mR, OP_C, W[i].G2, cap, cap, cap, mR);
       g2.dM = c.chi_new;
       g2.dN = c.chi_new;
-      g2.ksplit = splitk_auto(cap, cap, mR, (size_t)c.b.d * c.b.chi_l * mR * sizeof(cpx<S>), sizeof(c128));
+      g2.ksplit = splitk_auto(cap, cap, mR, (size_t)c.b.d * c.b.chi_l * mR * sizeof(cpx<S>), sizeof(c128), true);
       g2.work = W[i].Th;
+      g2.herm = 1;   // reorth_prep_kernel reads the upper triangle only
       g.push_back(g2);
     }
     if ((rc = gemm_run(g.data(), nc, GemmTypes{DT_C64, DT_C128}, s))) return rc;

@@ -847,11 +847,14 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
       const EigJob& J = jobs[j];
       // the inverse-iteration factors are dead: their buffer holds split-K partials
       GemmProb g1 = gemm_prob(J.E, J.kwant, OP_C, J.E, J.kwant, OP_N, J.w->gz, J.kwant, J.kwant, J.kwant, J.n);
-      g1.ksplit = splitk_auto(J.kwant, J.kwant, J.n, 4 * (size_t)J.n * J.n * 8, sizeof(c128));
+      g1.ksplit = splitk_auto(J.kwant, J.kwant, J.n, 4 * (size_t)J.n * J.n * 8, sizeof(c128), true);
       g1.work = J.w->lu;
+      g1.herm = 1;
       gs.push_back(g1);
     }
     if ((rc = gemm_run(gs.data(), (int)gs.size(), ty, s))) return rc;
+    for (int j : ns)
+      if ((rc = herm_fill_lower(jobs[j].w->gz, jobs[j].kwant, jobs[j].kwant, s))) return rc;
     gs.clear();
     for (int j : ns) {
       const EigJob& J = jobs[j];

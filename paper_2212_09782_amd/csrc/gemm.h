@@ -34,6 +34,8 @@ struct GemmProb {
   int ksplit;
   void* work;
   int skip_reduce;   // ksplit > 1: leave the partials in work (the caller reduces them)
+  int herm;          // C = op(A) op(B) is Hermitian (M == N): only the 64 x 64 tiles on or above
+                     // the diagonal are formed; the caller fills the lower triangle (herm_fill_lower)
 };
 
 constexpr int kGemmMaxProb = 16;
@@ -62,11 +64,15 @@ inline int gemm_one(const GemmProb& p, GemmTypes ty, hipStream_t stream, bool co
   return gemm_run(&p, 1, ty, stream, contract);
 }
 
+// C[i][j] = conj(C[j][i]) for i > j (n x n complex128, row-major, ld ldc).
+int herm_fill_lower(c128* C, long long ldc, int n, hipStream_t stream);
+
 // Split of K for a product whose output has few 64x64 tiles: enough
 // workgroups (about 1024) to fill the GPU, chunks of at least 128, and no
 // more partials ([ks][M][N] of elem bytes) than work_bytes holds.
-inline int splitk_auto(int M, int N, int K, size_t work_bytes, size_t elem) {
-  const long long tiles = (long long)((M + 63) / 64) * ((N + 63) / 64);
+inline int splitk_auto(int M, int N, int K, size_t work_bytes, size_t elem, bool herm = false) {
+  const long long tm = (M + 63) / 64, tn = (N + 63) / 64;
+  const long long tiles = herm ? tm * (tm + 1) / 2 : tm * tn;   // herm: the tiles that do work
   long long ks = (1024 + tiles - 1) / tiles;
   ks = std::min<long long>(ks, std::max(1, K / 128));
   ks = std::min<long long>(ks, (long long)(work_bytes / ((size_t)M * N * elem)));

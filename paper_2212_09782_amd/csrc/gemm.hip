@@ -89,6 +89,7 @@ __device__ __forceinline__ void gemm_body_l(const GemmBatch& b) {
   t -= split * tm * tn;
   int tile_m, tile_n;
   grouped_tile(t, tm, tn, tile_m, tile_n);
+  if (P.herm && tile_m > tile_n) return;   // Hermitian output: upper tiles only
 
   int M = P.M, N = P.N, K = P.K;
   if (P.dM) M = min(M, *P.dM);
@@ -290,6 +291,7 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   t -= split * tm * tn;
   int tile_m, tile_n;
   grouped_tile(t, tm, tn, tile_m, tile_n);
+  if (P.herm && tile_m > tile_n) return;   // Hermitian output: upper tiles only
 
   int M = P.M, N = P.N, K = P.K;
   if (P.dM) M = min(M, *P.dM);
@@ -562,7 +564,33 @@ int launch_typed(const GemmProb* probs, int nprob, hipStream_t stream, bool cont
   return 0;
 }
 
+// Lower triangle from the upper one: 32 x 32 blocks below the diagonal,
+// read transposed through LDS.
+__global__ __launch_bounds__(256) void herm_fill_kernel(c128* C, long long ldc, int n) {
+  __shared__ c128 tile[32][33];
+  const int bi = blockIdx.y, bj = blockIdx.x;   // destination block (bi >= bj)
+  if (bj > bi) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {   // source block (bj, bi): rows bj*32 + r
+    const int i = bj * 32 + r, j = bi * 32 + tx;
+    if (i < n && j < n) tile[r][tx] = C[(long long)i * ldc + j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bi * 32 + r, j = bj * 32 + tx;
+    if (i < n && j < n && i > j) C[(long long)i * ldc + j] = cconj(tile[tx][r]);
+  }
+}
+
 }  // namespace
+
+int herm_fill_lower(c128* C, long long ldc, int n, hipStream_t stream) {
+  if (n <= 1) return 0;
+  const int nb = (n + 31) / 32;
+  hipLaunchKernelGGL(herm_fill_kernel, dim3(nb, nb), dim3(256), 0, stream, C, ldc, n);
+  QT_HIP_CHECK(hipGetLastError());
+  return 0;
+}
 
 int gemm_run(const GemmProb* probs, int nprob, GemmTypes ty, hipStream_t stream, bool contract) {
   if (ty.tin == DT_C128 && ty.tout == DT_C128)
