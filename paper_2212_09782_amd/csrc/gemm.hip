@@ -59,207 +59,6 @@ template <> struct Mfma<float> {
 
 constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
 
-// Large tiles for FP32 products (complex64 in and out): a workgroup owns a
-// 128x128 output tile, each wave a 64x64 quadrant of 4x4 MFMA blocks.  Within
-// a 16-deep stage the four MFMA steps take k = 4g + s for the lanes of group
-// g = lane / 16 (A and B agree, so every k is summed once); operands are
-// stored k-contiguous in LDS, so each lane fetches its four k values of one
-// block and plane with a single 16-byte read.
-constexpr int LBM = 128, LBN = 128, LBK = 16, LKS = LBK + 4;
-
-__device__ __forceinline__ void gemm_body_l(const GemmBatch& b) {
-  using MF = Mfma<float>;
-  using v4 = MF::v4;
-  __shared__ __attribute__((aligned(16))) float As[2][2][LBM][LKS];   // [buffer][re/im][m][k]
-  __shared__ __attribute__((aligned(16))) float Bs[2][2][LBN][LKS];   // [buffer][re/im][n][k]
-
-  int bid;
-  {
-    const int total = b.tile_start[b.nprob];
-    const int g = blockIdx.x, x = g & 7, loc = g >> 3;
-    const int q = total >> 3, r = total & 7;
-    bid = x < r ? x * (q + 1) + loc : r * (q + 1) + (x - r) * q + loc;
-  }
-  int p = 0;
-  while (p + 1 < b.nprob && bid >= b.tile_start[p + 1]) ++p;
-  const GemmProb& P = b.p[p];
-  int t = bid - b.tile_start[p];
-  const int tm = b.tiles_m[p], tn = b.tiles_n[p];
-  const int split = t / (tm * tn);
-  t -= split * tm * tn;
-  int tile_m, tile_n;
-  grouped_tile(t, tm, tn, tile_m, tile_n);
-  if (P.herm && tile_m > tile_n) return;   // Hermitian output: upper tiles only
-
-  int M = P.M, N = P.N, K = P.K;
-  if (P.dM) M = min(M, *P.dM);
-  if (P.dN) N = min(N, *P.dN);
-  if (P.dK) K = min(K, *P.dK);
-  const int m0 = tile_m * LBM, n0 = tile_n * LBN;
-  if (m0 >= M || n0 >= N) return;
-  const int ks = P.ksplit > 1 ? P.ksplit : 1;
-  const int kchunk = ((K + ks - 1) / ks + LBK - 1) / LBK * LBK;
-  const int kbeg = split * kchunk;
-  const int kend = min(K, kbeg + kchunk);
-
-  const c64* __restrict__ A = (const c64*)P.A;
-  const c64* __restrict__ B = (const c64*)P.B;
-  const long long lda = P.lda, ldb = P.ldb;
-  const int opA = P.opA, opB = P.opB;
-  const float sa = opA == OP_C ? -1.f : 1.f;
-  const float sb = opB == OP_C ? -1.f : 1.f;
-
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int wm = (wid & 1) * 64, wn = (wid >> 1) * 64;
-
-  v4 acc_re[4][4], acc_im[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      acc_re[i][j] = v4{0, 0, 0, 0};
-      acc_im[i][j] = v4{0, 0, 0, 0};
-    }
-
-  // staging: 8 elements of each operand per thread and stage.  k-contiguous
-  // source (128 rows x 16 k): 8 consecutive k of one row.  Row-contiguous
-  // source (16 k x 128 columns): 4 consecutive k of 2 adjacent columns, so
-  // that LDS receives 16-byte k-contiguous chunks in both cases.
-  c64 ra[8], rb[8];
-  const int r_row = tid >> 1, r_k = (tid & 1) * 8;
-  const int c_kq = (tid & 3) * 4, c_col = (tid >> 2) * 2;
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      c64 z = mk<float>(0, 0);
-      if (opA == OP_N) {
-        const int m = m0 + r_row, k = k0 + r_k + e;
-        if (m < M && k < kend) z = A[(long long)m * lda + k];
-      } else {   // element e: column c_col + (e & 1), k = c_kq + (e >> 1)
-        const int k = k0 + c_kq + (e >> 1), m = m0 + c_col + (e & 1);
-        if (m < M && k < kend) z = A[(long long)k * lda + m];
-      }
-      ra[e] = z;
-      c64 w = mk<float>(0, 0);
-      if (opB == OP_N) {
-        const int k = k0 + c_kq + (e >> 1), n = n0 + c_col + (e & 1);
-        if (n < N && k < kend) w = B[(long long)k * ldb + n];
-      } else {
-        const int n = n0 + r_row, k = k0 + r_k + e;
-        if (n < N && k < kend) w = B[(long long)n * ldb + k];
-      }
-      rb[e] = w;
-    }
-  };
-  auto store = [&](int buf) {
-    if (opA == OP_N) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        *(v4*)&As[buf][0][r_row][r_k + 4 * h] =
-            v4{ra[4 * h].re, ra[4 * h + 1].re, ra[4 * h + 2].re, ra[4 * h + 3].re};
-        *(v4*)&As[buf][1][r_row][r_k + 4 * h] =
-            v4{sa * ra[4 * h].im, sa * ra[4 * h + 1].im, sa * ra[4 * h + 2].im, sa * ra[4 * h + 3].im};
-      }
-    } else {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        *(v4*)&As[buf][0][c_col + h][c_kq] = v4{ra[h].re, ra[2 + h].re, ra[4 + h].re, ra[6 + h].re};
-        *(v4*)&As[buf][1][c_col + h][c_kq] =
-            v4{sa * ra[h].im, sa * ra[2 + h].im, sa * ra[4 + h].im, sa * ra[6 + h].im};
-      }
-    }
-    if (opB != OP_N) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        *(v4*)&Bs[buf][0][r_row][r_k + 4 * h] =
-            v4{rb[4 * h].re, rb[4 * h + 1].re, rb[4 * h + 2].re, rb[4 * h + 3].re};
-        *(v4*)&Bs[buf][1][r_row][r_k + 4 * h] =
-            v4{sb * rb[4 * h].im, sb * rb[4 * h + 1].im, sb * rb[4 * h + 2].im, sb * rb[4 * h + 3].im};
-      }
-    } else {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        *(v4*)&Bs[buf][0][c_col + h][c_kq] = v4{rb[h].re, rb[2 + h].re, rb[4 + h].re, rb[6 + h].re};
-        *(v4*)&Bs[buf][1][c_col + h][c_kq] =
-            v4{sb * rb[h].im, sb * rb[2 + h].im, sb * rb[4 + h].im, sb * rb[6 + h].im};
-      }
-    }
-  };
-
-  if (kbeg < kend) {
-    load(kbeg);
-    store(0);
-  }
-  __syncthreads();
-  int buf = 0;
-  const int fr = lane & 15, fk = 4 * (lane >> 4);
-  for (int k0 = kbeg; k0 < kend; k0 += LBK) {
-    const bool more = k0 + LBK < kend;
-    if (more) load(k0 + LBK);     // global -> registers, overlapping the MFMAs below
-    v4 ar[4], ai[4], br[4], bi[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      ar[i] = *(const v4*)&As[buf][0][wm + 16 * i + fr][fk];
-      ai[i] = *(const v4*)&As[buf][1][wm + 16 * i + fr][fk];
-      br[i] = *(const v4*)&Bs[buf][0][wn + 16 * i + fr][fk];
-      bi[i] = *(const v4*)&Bs[buf][1][wn + 16 * i + fr][fk];
-    }
-#pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float a_r = ar[i][s4], a_i = ai[i][s4], na_i = -a_i;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc_re[i][j] = MF::op(a_r, br[j][s4], acc_re[i][j]);
-          acc_re[i][j] = MF::op(na_i, bi[j][s4], acc_re[i][j]);
-          acc_im[i][j] = MF::op(a_r, bi[j][s4], acc_im[i][j]);
-          acc_im[i][j] = MF::op(a_i, br[j][s4], acc_im[i][j]);
-        }
-      }
-    if (more) store(buf ^ 1);    // the other buffer was released by the previous barrier
-    __syncthreads();
-    buf ^= 1;
-  }
-
-  if (ks > 1) {
-    c64* W = (c64*)P.work + (long long)split * P.M * P.N;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = m0 + wm + i * 16 + MF::row(lane, r);
-          const int col = n0 + wn + j * 16 + fr;
-          if (row < M && col < N) W[(long long)row * P.N + col] = mk<float>(acc_re[i][j][r], acc_im[i][j][r]);
-        }
-    return;
-  }
-  c64* C = (c64*)P.C;
-  const long long ldc = P.ldc_live_N ? (long long)N : P.ldc;
-  const float alpha = P.alpha, beta = P.beta;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + i * 16 + MF::row(lane, r);
-        const int col = n0 + wn + j * 16 + fr;
-        if (row < M && col < N) {
-          float vr = alpha * acc_re[i][j][r], vi = alpha * acc_im[i][j][r];
-          c64* c = C + (long long)row * ldc + col;
-          if (beta != 0.f) {
-            const c64 o = *c;
-            vr += beta * o.re;
-            vi += beta * o.im;
-          }
-          *c = mk<float>(vr, vi);
-        }
-      }
-}
-
 template <typename Tin, typename Tout, typename Tc>
 __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   using MF = Mfma<Tc>;
@@ -267,7 +66,7 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   // FP32 products take the 3-product form (P1 = Re A Re B, P2 = Im A Im B,
   // P3 = (Re A + Im A)(Re B + Im B); Re C = P1 - P2, Im C = P3 - P1 - P2),
   // a quarter fewer MFMAs; FP64 keeps the 4-product form, whose smaller
-  // accumulator set leaves room for two waves per SIMD.
+  // accumulator set fits two waves per SIMD (the 3-product form does not).
   constexpr bool k3 = sizeof(Tc) == 4;
   constexpr int NPL = k3 ? 3 : 2;            // LDS planes per operand
   __shared__ Tc As[2][NPL][BK][BM + PAD];   // [buffer][re / im (/ re + im)][k][m]
@@ -468,12 +267,14 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
 // Two entry points with the same body: the contractions of the bond update
 // (the dominant kernel, reported on its own by profilers) and all other
 // products (QR trailing updates, explicit Q, Gram matrices).
+// FP64 arithmetic: at least two waves per SIMD (the register allocation fits
+// without spills; one wave left the matrix cores idle during staging).
 template <typename Tin, typename Tout, typename Tc>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmBatch b) { gemm_body<Tin, Tout, Tc>(b); }
+__global__ __launch_bounds__(256, sizeof(Tc) == 8 ? 2 : 1) void gemm_kernel(GemmBatch b) { gemm_body<Tin, Tout, Tc>(b); }
 template <typename Tin, typename Tout, typename Tc>
-__global__ __launch_bounds__(256) void contract_gemm_kernel(GemmBatch b) { gemm_body<Tin, Tout, Tc>(b); }
-__global__ __launch_bounds__(256, 2) void gemm_kernel_l(GemmBatch b) { gemm_body_l(b); }
-__global__ __launch_bounds__(256, 2) void contract_gemm_kernel_l(GemmBatch b) { gemm_body_l(b); }
+__global__ __launch_bounds__(256, sizeof(Tc) == 8 ? 2 : 1) void contract_gemm_kernel(GemmBatch b) {
+  gemm_body<Tin, Tout, Tc>(b);
+}
 
 // C = alpha * sum_s work[s] + beta * C over the live M x N.
 template <typename Tout, typename Tc>
@@ -507,57 +308,39 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmProb P) {
   }
 }
 
-// Large tiles: only where both output dimensions span a 128-wide tile and
-// the product is deep.  Switched off until their LDS staging is conflict-free
-// for row-contiguous operands (measured slower than the 64x64 tiles).
-constexpr bool kLargeTiles = false;
-inline bool use_large(const GemmProb& q) { return kLargeTiles && q.M >= LBM && q.N >= LBN && q.K >= 256; }
-
 template <typename Tin, typename Tout, typename Tc>
 int launch_typed(const GemmProb* probs, int nprob, hipStream_t stream, bool contract) {
-  constexpr bool kHasLarge = sizeof(Tin) == 4 && sizeof(Tout) == 4 && sizeof(Tc) == 4;
-  for (int pass = 0; pass < (kHasLarge ? 2 : 1); ++pass) {
-    const bool large = pass == 1;
-    const int bm = large ? LBM : BM, bn = large ? LBN : BN;
-    int i = 0;
-    while (i < nprob) {
-      GemmBatch b{};
-      int total = 0;
-      b.nprob = 0;
-      while (i < nprob && b.nprob < kGemmMaxProb) {
-        const GemmProb& q = probs[i++];
-        if (q.M <= 0 || q.N <= 0) continue;
-        if (kHasLarge && use_large(q) != large) continue;
-        const int tm = (q.M + bm - 1) / bm, tn = (q.N + bn - 1) / bn;
-        const int ks = q.ksplit > 1 ? q.ksplit : 1;
-        b.p[b.nprob] = q;
-        b.tiles_m[b.nprob] = tm;
-        b.tiles_n[b.nprob] = tn;
-        b.tile_start[b.nprob] = total;
-        total += tm * tn * ks;
-        b.nprob++;
-      }
-      if (b.nprob == 0) continue;
+  int i = 0;
+  while (i < nprob) {
+    GemmBatch b{};
+    int total = 0;
+    b.nprob = 0;
+    while (i < nprob && b.nprob < kGemmMaxProb) {
+      const GemmProb& q = probs[i++];
+      if (q.M <= 0 || q.N <= 0) continue;
+      const int tm = (q.M + BM - 1) / BM, tn = (q.N + BN - 1) / BN;
+      const int ks = q.ksplit > 1 ? q.ksplit : 1;
+      b.p[b.nprob] = q;
+      b.tiles_m[b.nprob] = tm;
+      b.tiles_n[b.nprob] = tn;
       b.tile_start[b.nprob] = total;
-      if (large) {
-        if (contract)
-          hipLaunchKernelGGL(contract_gemm_kernel_l, dim3(total), dim3(256), 0, stream, b);
-        else
-          hipLaunchKernelGGL(gemm_kernel_l, dim3(total), dim3(256), 0, stream, b);
-      } else if (contract) {
-        hipLaunchKernelGGL((contract_gemm_kernel<Tin, Tout, Tc>), dim3(total), dim3(256), 0, stream, b);
-      } else {
-        hipLaunchKernelGGL((gemm_kernel<Tin, Tout, Tc>), dim3(total), dim3(256), 0, stream, b);
-      }
-      QT_HIP_CHECK(hipGetLastError());
-      for (int q = 0; q < b.nprob; ++q) {
-        const GemmProb& pr = b.p[q];
-        if (pr.ksplit > 1 && !pr.skip_reduce) {
-          const long long tot = (long long)pr.M * pr.N;
-          const int grid = (int)std::min<long long>((tot + 255) / 256, 4096);
-          hipLaunchKernelGGL((splitk_reduce_kernel<Tout, Tc>), dim3(grid), dim3(256), 0, stream, pr);
-          QT_HIP_CHECK(hipGetLastError());
-        }
+      total += tm * tn * ks;
+      b.nprob++;
+    }
+    if (b.nprob == 0) continue;
+    b.tile_start[b.nprob] = total;
+    if (contract)
+      hipLaunchKernelGGL((contract_gemm_kernel<Tin, Tout, Tc>), dim3(total), dim3(256), 0, stream, b);
+    else
+      hipLaunchKernelGGL((gemm_kernel<Tin, Tout, Tc>), dim3(total), dim3(256), 0, stream, b);
+    QT_HIP_CHECK(hipGetLastError());
+    for (int q = 0; q < b.nprob; ++q) {
+      const GemmProb& pr = b.p[q];
+      if (pr.ksplit > 1 && !pr.skip_reduce) {
+        const long long tot = (long long)pr.M * pr.N;
+        const int grid = (int)std::min<long long>((tot + 255) / 256, 4096);
+        hipLaunchKernelGGL((splitk_reduce_kernel<Tout, Tc>), dim3(grid), dim3(256), 0, stream, pr);
+        QT_HIP_CHECK(hipGetLastError());
       }
     }
   }
