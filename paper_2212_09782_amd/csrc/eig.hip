@@ -606,22 +606,36 @@ __global__ __launch_bounds__(256) void larft_kernel(SmallBatch sb) {
   if (p * NB >= nrefl) return;
   const int j0 = p * NB, jb = min(NB, nrefl - j0), mp = m - j0;
   const c128* Vp = V + qr_v_offset(p, m);
-  c128 g[4];
+  // G = V_p^H V_p over 64-row slabs; the next slab is loaded (all of its
+  // loads in flight) while the current one is summed, two chains per entry
+  constexpr int kE = 64 * NB / 256;
+  c128 g[4][2], nx[kE];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) g[q] = z0();
+  for (int q = 0; q < 4; ++q) g[q][0] = g[q][1] = z0();
+  auto load_slab = [&](int r0) {
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+      const int idx = tid + 256 * e, i = idx / NB, c = idx % NB;
+      nx[e] = (r0 + i < mp) ? Vp[(long long)(r0 + i) * kQrLdv + c] : z0();
+    }
+  };
+  load_slab(0);
   for (int r0 = 0; r0 < mp; r0 += 64) {
     __syncthreads();
-    for (int idx = tid; idx < 64 * NB; idx += 256) {
-      const int i = idx / NB, c = idx % NB;
-      slab[i][c] = (r0 + i < mp) ? Vp[(long long)(r0 + i) * kQrLdv + c] : z0();
+#pragma unroll
+    for (int e = 0; e < kE; ++e) {
+      const int idx = tid + 256 * e;
+      slab[idx / NB][idx % NB] = nx[e];
     }
+    if (r0 + 64 < mp) load_slab(r0 + 64);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q, aa = e / NB, bb = e % NB;
-      c128 s = g[q];
-      for (int i = 0; i < 64; ++i) s = cadd(s, cmulc(slab[i][aa], slab[i][bb]));
-      g[q] = s;
+      for (int i = 0; i < 64; i += 2) {
+        g[q][0] = cadd(g[q][0], cmulc(slab[i][aa], slab[i][bb]));
+        g[q][1] = cadd(g[q][1], cmulc(slab[i + 1][aa], slab[i + 1][bb]));
+      }
     }
   }
   __syncthreads();
@@ -629,7 +643,7 @@ __global__ __launch_bounds__(256) void larft_kernel(SmallBatch sb) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int e = tid + 256 * q;
-    slab[e / NB][e % NB] = g[q];
+    slab[e / NB][e % NB] = cadd(g[q][0], g[q][1]);
     Tm[e / NB][e % NB] = z0();
   }
   __syncthreads();

@@ -552,11 +552,14 @@ __global__ __launch_bounds__(256) void reduce_tw_kernel(TwBatch b) {
   const TwJob& J = b.j[blockIdx.y];
   const int n0 = blockIdx.x * kTwCols;
   if (n0 >= J.nt) return;
-  for (int idx = threadIdx.x; idx < kTwRows * kTwRows; idx += 256) {
-    const int r = idx / kTwRows, q = idx % kTwRows;
-    c128 t = cz();
-    if (r < J.jb && q < J.jb) t = b.herm ? cconj(J.T[q * J.ldt + r]) : J.T[r * J.ldt + q];
-    Ts[r][q] = t;
+  // op(T): all loads in flight together, stored to LDS after the partial sums
+  constexpr int kTe = kTwRows * kTwRows / 256;
+  c128 tv[kTe];
+#pragma unroll
+  for (int e = 0; e < kTe; ++e) {
+    const int idx = threadIdx.x + 256 * e, r = idx / kTwRows, q = idx % kTwRows;
+    tv[e] = cz();
+    if (r < J.jb && q < J.jb) tv[e] = b.herm ? cconj(J.T[q * J.ldt + r]) : J.T[r * J.ldt + q];
   }
   const int r = threadIdx.x / kTwCols, nn = threadIdx.x % kTwCols, n = n0 + nn;
   const cpx<S>* src = (const cpx<S>*)J.src + (long long)r * J.nt + n;
@@ -574,6 +577,11 @@ __global__ __launch_bounds__(256) void reduce_tw_kernel(TwBatch b) {
     for (; k < J.ks; ++k) acc = cadd(acc, ccast<double>(src[k * stride]));
   }
   Sm[r][nn] = acc;
+#pragma unroll
+  for (int e = 0; e < kTe; ++e) {
+    const int idx = threadIdx.x + 256 * e;
+    Ts[idx / kTwRows][idx % kTwRows] = tv[e];
+  }
   __syncthreads();
   if (n >= J.nt || r >= J.jb) return;
   c128 o = cz();
@@ -583,15 +591,16 @@ __global__ __launch_bounds__(256) void reduce_tw_kernel(TwBatch b) {
 
 // Merged compact-WY factor of a pair of panels: for H = H_e H_o with
 // H_x = I - V_x T_x V_x^H, T = [[T_e, -T_e (V_e^H V_o) T_o], [0, T_o]].
-// gpart_kernel: partial sums of G = V_e^H V_o over 64-row chunks of the pair
-// block (one block per chunk and pair); tpair_kernel: sums them and forms T.
+// G = V_e^H V_o is a split-K GEMM on FP64 matrix cores whose partials stay
+// in gpart; tpair_kernel sums them and forms T.
 struct PairTask {
   const void* V;     // pair block, ld LDV
   int rows;          // rows of the pair block
   int has_odd;
   const c128* Te;    // 32 x 32
   const c128* To;    // 32 x 32 (has_odd)
-  c128* gpart;       // nchunk x 32 x 32
+  c128* gpart;       // nparts x 32 x 32 partial sums of V_e^H V_o
+  int nparts;
   c128* Tp;          // 64 x 64
 };
 constexpr int kMaxPairTasks = 64;
@@ -599,29 +608,6 @@ struct PairBatch {
   int n;
   PairTask t[kMaxPairTasks];
 };
-
-template <typename S>
-__global__ __launch_bounds__(256) void gpart_kernel(PairBatch b) {
-  __shared__ c128 Vs[64][LDV + 1];
-  const PairTask& T = b.t[blockIdx.y];
-  const int r0 = blockIdx.x * 64;
-  if (!T.has_odd || r0 >= T.rows) return;
-  const cpx<S>* V = (const cpx<S>*)T.V;
-  const int nr = min(64, T.rows - r0);
-  for (int idx = threadIdx.x; idx < 64 * LDV; idx += 256) {
-    const int i = idx / LDV, c = idx % LDV;
-    Vs[i][c] = i < nr ? ccast<double>(V[(long long)(r0 + i) * LDV + c]) : cz();
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    const int q = e / NB, c = e % NB;
-    c128 acc[4] = {cz(), cz(), cz(), cz()};
-    for (int i = 0; i < 64; i += 4)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] = cadd(acc[u], cmulc(Vs[i + u][q], Vs[i + u][NB + c]));
-    T.gpart[(long long)blockIdx.x * NB * NB + e] = cadd(cadd(acc[0], acc[1]), cadd(acc[2], acc[3]));
-  }
-}
 
 __global__ __launch_bounds__(256) void tpair_kernel(PairBatch b) {
   __shared__ c128 G[NB][NB + 1], X[NB][NB + 1], Te[NB][NB + 1], To[NB][NB + 1];
@@ -632,7 +618,7 @@ __global__ __launch_bounds__(256) void tpair_kernel(PairBatch b) {
     To[q][c] = T.has_odd ? T.To[e] : cz();
     c128 g = cz();
     if (T.has_odd) {
-      const int nch = (T.rows + 63) / 64;
+      const int nch = T.nparts;
       for (int k0 = 0; k0 < nch; k0 += 8) {   // eight loads in flight
         c128 l[8];
 #pragma unroll
@@ -819,7 +805,7 @@ int qr_factor_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s, const Q
 static int build_pair_factors(const QrJob* jobs, int njobs, int dt, hipStream_t s) {
   const int es = dt == DT_C128 ? 16 : 8;
   std::vector<PairTask> tasks;
-  int maxch = 1;
+  std::vector<GemmProb> gp;
   for (int j = 0; j < njobs; ++j) {
     const QrJob& J = jobs[j];
     const QrWork& w = *J.w;
@@ -833,18 +819,23 @@ static int build_pair_factors(const QrJob* jobs, int njobs, int dt, hipStream_t 
       t.To = w.T + (size_t)(2 * g + 1) * NB * NB;
       t.gpart = w.gpart + (size_t)g * nch * NB * NB;
       t.Tp = w.Tp + (size_t)g * 4 * NB * NB;
+      t.nparts = 0;
+      if (t.has_odd) {   // G = V_e^H V_o; one split writes gpart[0] directly
+        GemmProb q = gemm_prob(t.V, LDV, OP_C, (const char*)t.V + NB * es, LDV, OP_N, t.gpart, NB, NB, NB, t.rows);
+        q.ksplit = splitk_auto(NB, NB, t.rows, (size_t)nch * NB * NB * sizeof(c128), sizeof(c128));
+        q.work = t.gpart;
+        q.skip_reduce = 1;
+        t.nparts = q.ksplit;
+        gp.push_back(q);
+      }
       tasks.push_back(t);
-      maxch = std::max(maxch, (t.rows + 63) / 64);
     }
   }
+  int rc;
+  if (!gp.empty() && (rc = gemm_run(gp.data(), (int)gp.size(), GemmTypes{dt, DT_C128}, s))) return rc;
   for (size_t i0 = 0; i0 < tasks.size(); i0 += kMaxPairTasks) {
     PairBatch b{};
     for (size_t i = i0; i < tasks.size() && b.n < kMaxPairTasks; ++i) b.t[b.n++] = tasks[i];
-    if (dt == DT_C128)
-      hipLaunchKernelGGL(gpart_kernel<double>, dim3(maxch, b.n), dim3(256), 0, s, b);
-    else
-      hipLaunchKernelGGL(gpart_kernel<float>, dim3(maxch, b.n), dim3(256), 0, s, b);
-    QT_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(tpair_kernel, dim3(b.n), dim3(256), 0, s, b);
     QT_HIP_CHECK(hipGetLastError());
   }
