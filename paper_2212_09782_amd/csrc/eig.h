@@ -14,6 +14,7 @@ struct EigWork {
   QrWork qtri;      // reflectors of the tridiagonalisation, (n-1) x (n-1) problem with n work columns
   c128* gz;         // n x n Gram matrix of the eigenvector block (Newton-Schulz polish)
   c128* ztmp;       // n x n copy of the eigenvector block
+  c128* tpart;      // split-K partials of V_p^H V_p for every reflector panel (8 x 32 x 32 each)
   int* status;
 };
 

@@ -358,6 +358,7 @@ struct SmallJob {
   c128* V;
   c128* T;
   const c128* tau;
+  const c128* tpart;
   int n, kwant;
 };
 constexpr int kMaxSmallJobs = 24;
@@ -592,58 +593,39 @@ __global__ __launch_bounds__(64) void invit_kernel(SmallBatch sb, int G) {
   for (int i = 0; i < n; ++i) E[(size_t)i * kwant + j] = mk<double>(W[i] * f, 0.0);
 }
 
-// T_p for every panel of the tridiagonalisation reflectors (from the Gram
-// matrix V_p^H V_p; V_p is staged through LDS in 64-row slabs).
+// Split-K parts of the panel Gram products V_p^H V_p (K = rows of the panel).
+constexpr int kLarftParts = 8;
+__host__ __device__ inline int larft_parts(int K) { return K / 128 < 1 ? 1 : (K / 128 > kLarftParts ? kLarftParts : K / 128); }
+
+// T_p for every panel of the tridiagonalisation reflectors from the Gram
+// matrix V_p^H V_p (summed from the split-K partials of the GEMM launched
+// before this kernel).
 __global__ __launch_bounds__(256) void larft_kernel(SmallBatch sb) {
-  __shared__ c128 slab[64][NB + 1];
+  __shared__ c128 slab[NB][NB + 1];
   __shared__ c128 Tm[NB][NB + 1];
   const SmallJob& J = sb.j[blockIdx.y];
-  c128* V = J.V;
   c128* T = J.T;
   const c128* tau = J.tau;
   const int m = J.n - 1, nrefl = J.n - 1;
   const int p = blockIdx.x, tid = threadIdx.x;
   if (p * NB >= nrefl) return;
   const int j0 = p * NB, jb = min(NB, nrefl - j0), mp = m - j0;
-  const c128* Vp = V + qr_v_offset(p, m);
-  // G = V_p^H V_p over 64-row slabs; the next slab is loaded (all of its
-  // loads in flight) while the current one is summed, two chains per entry
-  constexpr int kE = 64 * NB / 256;
-  c128 g[4][2], nx[kE];
+  const int parts = larft_parts(mp);
+  const c128* gp = J.tpart + (size_t)p * kLarftParts * NB * NB;
+  c128 g[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) g[q][0] = g[q][1] = z0();
-  auto load_slab = [&](int r0) {
+  for (int q = 0; q < 4; ++q) {
+    c128 l[kLarftParts];
 #pragma unroll
-    for (int e = 0; e < kE; ++e) {
-      const int idx = tid + 256 * e, i = idx / NB, c = idx % NB;
-      nx[e] = (r0 + i < mp) ? Vp[(long long)(r0 + i) * kQrLdv + c] : z0();
-    }
-  };
-  load_slab(0);
-  for (int r0 = 0; r0 < mp; r0 += 64) {
-    __syncthreads();
+    for (int u = 0; u < kLarftParts; ++u) l[u] = u < parts ? gp[(size_t)u * NB * NB + tid + 256 * q] : z0();
+    g[q] = l[0];
 #pragma unroll
-    for (int e = 0; e < kE; ++e) {
-      const int idx = tid + 256 * e;
-      slab[idx / NB][idx % NB] = nx[e];
-    }
-    if (r0 + 64 < mp) load_slab(r0 + 64);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q, aa = e / NB, bb = e % NB;
-      for (int i = 0; i < 64; i += 2) {
-        g[q][0] = cadd(g[q][0], cmulc(slab[i][aa], slab[i][bb]));
-        g[q][1] = cadd(g[q][1], cmulc(slab[i + 1][aa], slab[i + 1][bb]));
-      }
-    }
+    for (int u = 1; u < kLarftParts; ++u) g[q] = cadd(g[q], l[u]);
   }
-  __syncthreads();
-  // G overwrites the slab storage (NB x NB <= 64 x (NB+1))
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int e = tid + 256 * q;
-    slab[e / NB][e % NB] = cadd(g[q][0], g[q][1]);
+    slab[e / NB][e % NB] = g[q];
     Tm[e / NB][e % NB] = z0();
   }
   __syncthreads();
@@ -724,6 +706,7 @@ size_t eig_work_bytes(int n) {
   b += align256((2 * 257 + 4 * (size_t)n) * 16);     // red + pbuf + rowbuf
   b += align256(qr_work_bytes(std::max(n - 1, 1), std::max(n - 1, 1), 16, n));
   b += 2 * align256((size_t)n * n * 16);
+  b += align256((size_t)((n - 1 + NB - 1) / NB + 1) * kLarftParts * NB * NB * 16);
   return b;
 }
 
@@ -741,6 +724,7 @@ EigWork eig_work_carve(void* base, int n, int* status) {
   p += align256(qr_work_bytes(std::max(n - 1, 1), std::max(n - 1, 1), 16, n));
   w.gz = (c128*)p; p += align256((size_t)n * n * 16);
   w.ztmp = (c128*)p; p += align256((size_t)n * n * 16);
+  w.tpart = (c128*)p; p += align256((size_t)((n - 1 + NB - 1) / NB + 1) * kLarftParts * NB * NB * 16);
   w.status = status;
   return w;
 }
@@ -815,6 +799,7 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
     if ((rc = flush())) return rc;
   }
   // 2-5. larft, bisection, inverse iteration, clustered MGS (batched small kernels)
+  std::vector<GemmProb> gram;
   for (size_t j0 = 0; j0 < big.size(); j0 += kMaxSmallJobs) {
     SmallBatch sb{};
     int maxn = 0, maxk = 0;
@@ -830,11 +815,27 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
       S.V = (c128*)J.w->qtri.V;
       S.T = J.w->qtri.T;
       S.tau = J.w->tau;
+      S.tpart = J.w->tpart;
       S.n = J.n;
       S.kwant = J.kwant;
       maxn = std::max(maxn, J.n);
       maxk = std::max(maxk, J.kwant);
+      // V_p^H V_p for every panel p of the reflectors (FP64 matrix cores,
+      // split-K partials left for larft_kernel; one part writes them directly)
+      const int m = J.n - 1;
+      for (int p0 = 0; p0 < m; p0 += NB) {
+        const int p = p0 / NB, mp = m - p0;
+        const c128* Vp = (const c128*)J.w->qtri.V + qr_v_offset(p, m);
+        c128* out = J.w->tpart + (size_t)p * kLarftParts * NB * NB;
+        GemmProb q = gemm_prob(Vp, kQrLdv, OP_C, Vp, kQrLdv, OP_N, out, NB, NB, NB, mp);
+        q.ksplit = larft_parts(mp);
+        q.work = out;
+        q.skip_reduce = 1;
+        gram.push_back(q);
+      }
     }
+    if (!gram.empty() && (rc = gemm_run(gram.data(), (int)gram.size(), GemmTypes{DT_C128, DT_C128}, s))) return rc;
+    gram.clear();
     const int npan = (maxn - 1 + NB - 1) / NB;
     hipLaunchKernelGGL(larft_kernel, dim3(npan, sb.njobs), dim3(256), 0, s, sb);
     QT_HIP_CHECK(hipGetLastError());
