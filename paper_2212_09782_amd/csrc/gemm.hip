@@ -68,9 +68,16 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   // a quarter fewer MFMAs; FP64 keeps the 4-product form, whose smaller
   // accumulator set fits two waves per SIMD (the 3-product form does not).
   constexpr bool k3 = sizeof(Tc) == 4;
-  constexpr int NPL = k3 ? 3 : 2;            // LDS planes per operand
-  __shared__ Tc As[2][NPL][BK][BM + PAD];   // [buffer][re / im (/ re + im)][k][m]
-  __shared__ Tc Bs[2][NPL][BK][BN + PAD];
+  constexpr int NPL = k3 ? 3 : 2;            // accumulator sets (real products)
+  // LDS holds the re and im planes of each operand tile, double-buffered.
+  // 3-product form: [m][k] rows with k contiguous (stride BK + 4), so a lane
+  // reads the four k values of its four MFMA steps with one 16-byte read (the
+  // steps take k = 4 (lane / 16) + s, the same for A and B), re + im is
+  // formed in registers.  4-product form: [k][m] rows (stride BM + 1).
+  constexpr int KS = BK + 4;
+  constexpr int D1 = k3 ? BM : BK, D2 = k3 ? KS : BM + PAD;
+  __shared__ __attribute__((aligned(16))) Tc As[2][2][D1][D2];
+  __shared__ __attribute__((aligned(16))) Tc Bs[2][2][D1][D2];
 
   // XCD-aware remap: hardware workgroup g runs on XCD g % 8; give XCD x the
   // contiguous logical range [start_x, start_x + count_x)
@@ -154,20 +161,41 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
     }
   };
   auto store = [&](int buf) {
+    if constexpr (k3) {
+      static_assert(EPT == 4, "16-byte LDS rows need four k values per thread");
+      typedef float f4 __attribute__((ext_vector_type(4)));
+      if (opA == OP_N) {   // four consecutive k of row rowq: one 16-byte write per plane
+        *(f4*)&As[buf][0][rowq][colq] = f4{(Tc)ra[0].re, (Tc)ra[1].re, (Tc)ra[2].re, (Tc)ra[3].re};
+        *(f4*)&As[buf][1][rowq][colq] =
+            f4{sa * (Tc)ra[0].im, sa * (Tc)ra[1].im, sa * (Tc)ra[2].im, sa * (Tc)ra[3].im};
+      } else {
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int g = e >> 2, e4 = e & 3;
-      const Tc a_r = (Tc)ra[e].re, a_i = sa * (Tc)ra[e].im;
-      const Tc b_r = (Tc)rb[e].re, b_i = sb * (Tc)rb[e].im;
-      const int ak = opA == OP_N ? colq + e : rowk + 16 * g, am = opA == OP_N ? rowq : colk + e4;
-      const int bk = opB == OP_N ? rowk + 16 * g : colq + e, bn = opB == OP_N ? colk + e4 : rowq;
-      As[buf][0][ak][am] = a_r;
-      As[buf][1][ak][am] = a_i;
-      Bs[buf][0][bk][bn] = b_r;
-      Bs[buf][1][bk][bn] = b_i;
-      if constexpr (k3) {
-        As[buf][NPL - 1][ak][am] = a_r + a_i;
-        Bs[buf][NPL - 1][bk][bn] = b_r + b_i;
+        for (int e = 0; e < EPT; ++e) {
+          As[buf][0][colk + e][rowk] = (Tc)ra[e].re;
+          As[buf][1][colk + e][rowk] = sa * (Tc)ra[e].im;
+        }
+      }
+      if (opB != OP_N) {
+        *(f4*)&Bs[buf][0][rowq][colq] = f4{(Tc)rb[0].re, (Tc)rb[1].re, (Tc)rb[2].re, (Tc)rb[3].re};
+        *(f4*)&Bs[buf][1][rowq][colq] =
+            f4{sb * (Tc)rb[0].im, sb * (Tc)rb[1].im, sb * (Tc)rb[2].im, sb * (Tc)rb[3].im};
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          Bs[buf][0][colk + e][rowk] = (Tc)rb[e].re;
+          Bs[buf][1][colk + e][rowk] = sb * (Tc)rb[e].im;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int g = e >> 2, e4 = e & 3;
+        const int ak = opA == OP_N ? colq + e : rowk + 16 * g, am = opA == OP_N ? rowq : colk + e4;
+        const int bk = opB == OP_N ? rowk + 16 * g : colq + e, bn = opB == OP_N ? colk + e4 : rowq;
+        As[buf][0][ak][am] = (Tc)ra[e].re;
+        As[buf][1][ak][am] = sa * (Tc)ra[e].im;
+        Bs[buf][0][bk][bn] = (Tc)rb[e].re;
+        Bs[buf][1][bk][bn] = sb * (Tc)rb[e].im;
       }
     }
   };
@@ -181,31 +209,50 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
     const bool more = k0 + BK < kend;
     if (more) load(k0 + BK);     // global -> registers, overlapping the MFMAs below
+    if constexpr (k3) {
+      typedef float f4 __attribute__((ext_vector_type(4)));
+      const int kq = 4 * (lane >> 4);
+      f4 a2[2][2], b2[2][2];   // [re / im][block]: k = kq .. kq + 3
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      Tc a3[NPL][2], b3[NPL][2];
-#pragma unroll
-      for (int pl = 0; pl < NPL; ++pl)
+      for (int pl = 0; pl < 2; ++pl)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          a3[pl][i] = As[buf][pl][kr][wm + i * 16 + (lane & 15)];
-          b3[pl][i] = Bs[buf][pl][kr][wn + i * 16 + (lane & 15)];
+          a2[pl][i] = *(const f4*)&As[buf][pl][wm + i * 16 + (lane & 15)][kq];
+          b2[pl][i] = *(const f4*)&Bs[buf][pl][wn + i * 16 + (lane & 15)][kq];
         }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          if constexpr (k3) {
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int pl = 0; pl < NPL; ++pl) acc[pl][i][j] = MF::op(a3[pl][i], b3[pl][j], acc[pl][i][j]);
-          } else {
+          for (int j = 0; j < 2; ++j) {
+            const Tc ar = a2[0][i][s4], ai = a2[1][i][s4], br = b2[0][j][s4], bi = b2[1][j][s4];
+            acc[0][i][j] = MF::op(ar, br, acc[0][i][j]);
+            acc[1][i][j] = MF::op(ai, bi, acc[1][i][j]);
+            acc[2][i][j] = MF::op(ar + ai, br + bi, acc[2][i][j]);
+          }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        Tc a3[2][2], b3[2][2];
+#pragma unroll
+        for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            a3[pl][i] = As[buf][pl][kr][wm + i * 16 + (lane & 15)];
+            b3[pl][i] = Bs[buf][pl][kr][wn + i * 16 + (lane & 15)];
+          }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
             acc[0][i][j] = MF::op(a3[0][i], b3[0][j], acc[0][i][j]);
             acc[0][i][j] = MF::op(-a3[1][i], b3[1][j], acc[0][i][j]);
             acc[1][i][j] = MF::op(a3[0][i], b3[1][j], acc[1][i][j]);
             acc[1][i][j] = MF::op(a3[1][i], b3[0][j], acc[1][i][j]);
           }
-        }
+      }
     }
     if (more) store(buf ^ 1);    // the other buffer was released by the previous barrier
     __syncthreads();
@@ -267,12 +314,12 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
 // Two entry points with the same body: the contractions of the bond update
 // (the dominant kernel, reported on its own by profilers) and all other
 // products (QR trailing updates, explicit Q, Gram matrices).
-// FP64 arithmetic: at least two waves per SIMD (the register allocation fits
-// without spills; one wave left the matrix cores idle during staging).
+// Occupancy floors: FP64 two waves per SIMD, FP32 three (both fit without
+// spills; fewer waves left the matrix cores idle during staging).
 template <typename Tin, typename Tout, typename Tc>
-__global__ __launch_bounds__(256, sizeof(Tc) == 8 ? 2 : 1) void gemm_kernel(GemmBatch b) { gemm_body<Tin, Tout, Tc>(b); }
+__global__ __launch_bounds__(256, sizeof(Tc) == 8 ? 2 : 3) void gemm_kernel(GemmBatch b) { gemm_body<Tin, Tout, Tc>(b); }
 template <typename Tin, typename Tout, typename Tc>
-__global__ __launch_bounds__(256, sizeof(Tc) == 8 ? 2 : 1) void contract_gemm_kernel(GemmBatch b) {
+__global__ __launch_bounds__(256, sizeof(Tc) == 8 ? 2 : 3) void contract_gemm_kernel(GemmBatch b) {
   gemm_body<Tin, Tout, Tc>(b);
 }
 
