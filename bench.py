@@ -33,7 +33,7 @@ PEAK = {"c128": 78.6e12, "c64": 157.3e12}   # dense FP64 / FP32 matrix-core peak
 # same counters read for a plain 256 MiB copy (--copy-calibration); the
 # commands and raw figures are in profiles/contract_gemm_hbm_d5_chi1024_mixed.md.
 # Only valid for the kernel version those counters were taken on.
-CONTRACT_TRAFFIC_C64 = 1.3537e9
+CONTRACT_TRAFFIC_C64 = 1.3111e9
 
 
 def run_precision(lib, torch, prec, chi, d, steps, warmup, sweeps=1):
