@@ -30,12 +30,12 @@ def product_state_lists(L, d):
     return [e.copy() for _ in range(L)], [np.ones(1) for _ in range(L)]
 
 
-def run_pair(ctx, d, g, L, finite, dt, nsteps, chi_max, dchi_min=100, dchi_frac=0.1, prec=lib.MPS_C128):
+def run_pair(ctx, d, g, L, finite, dt, nsteps, chi_max, dchi_min=100, dchi_frac=0.1, prec=lib.MPS_C128, sweeps=1):
     """Run the GPU sweep and the oracle side by side; yield per-step observables."""
     B, Xi = product_state_lists(L, d)
     st = lib.State(ctx, B, Xi, finite=finite, chi_cap=chi_max, prec=prec)
     gates = lib.chain_gates(d, g, L, finite, dt)
-    pol = lib.sweep_policy(chi_max, 1e-14 if prec == lib.MPS_C128 else 1e-6, dchi_min, dchi_frac)
+    pol = lib.sweep_policy(chi_max, 1e-14 if prec == lib.MPS_C128 else 1e-6, dchi_min, dchi_frac, sweeps=sweeps)
     Z, _ = clock.clock_ops(d)
     zz = torch.from_numpy((Z + Z.conj().T).reshape(-1)).to("cuda")
     hs = clock.chain_hamiltonians(d, g, L, finite)
@@ -52,7 +52,7 @@ def run_pair(ctx, d, g, L, finite, dt, nsteps, chi_max, dchi_min=100, dchi_frac=
         lib.mps_measure(ctx, st, op1=zz, site_vals=site, norms=norms, entropies=ent)
         ctx.sync()
         eps_cum += omps.trotter_step(ost, gh, gf, chi_max=chi_max,
-                                     dchi_rule=lambda c: max(dchi_min, int(np.ceil(dchi_frac * c))))
+                                     dchi_rule=lambda c: max(dchi_min, int(np.ceil(dchi_frac * c))), nsweeps=sweeps)
         zo, no = omps.site_expectation(ost, Z + Z.conj().T)
         eo = omps.bond_entropies(ost)
         out.append(dict(eps_cum=eps_cum, z_gpu=site.cpu().numpy().reshape(L, 2), n_gpu=norms.cpu().numpy(),
@@ -104,6 +104,18 @@ def test_uniform_cell_quench(ctx):
     st, ost, out = run_pair(ctx, 3, 2.0, 2, False, 0.05, 10, 24, dchi_min=8)
     for k, o in enumerate(out):
         assert np.max(np.abs(o["z_gpu"][:, 0] - o["z_or"].real)) < tol(o), k
+        assert np.max(np.abs(o["e_gpu"] - o["e_or"])) < 1e-9 + 10 * tol(o), k
+
+
+def test_quench_two_sweeps(ctx):
+    """mps_sweep with two QR/LQ sweeps per bond (policy sweeps = 2) against the
+    oracle's trotter_step with nsweeps = 2: finite L = 10, d = 3, g = 2, a large
+    step dt = 0.2 (gates further from the identity), chi_max = 16, 6 steps."""
+    st, ost, out = run_pair(ctx, 3, 2.0, 10, True, 0.2, 6, 16, dchi_min=4, sweeps=2)
+    for k, o in enumerate(out):
+        err = np.max(np.abs(o["z_gpu"][:, 0] - o["z_or"].real))
+        print(f"step {k}: max|dZ| {err:.2e}  cumulative eps {o['eps_cum']:.2e}", flush=True)
+        assert err < tol(o), k
         assert np.max(np.abs(o["e_gpu"] - o["e_or"])) < 1e-9 + 10 * tol(o), k
 
 
