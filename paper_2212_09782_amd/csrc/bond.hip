@@ -36,25 +36,40 @@ inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 template <typename S>
 __global__ __launch_bounds__(64) void gate_kernel(cpx<S>* C, cpx<S>* Th, const c128* __restrict__ U,
                                                   const double* xi, int d, int chiR, double* partial) {
-  extern __shared__ c128 Cs[];  // d^2 x 64, one column per thread
+  extern __shared__ unsigned char gate_lds[];
+  cpx<S>* Cs = reinterpret_cast<cpx<S>*>(gate_lds);  // d^2 x 64 in storage precision, one column per thread
+  constexpr int G = 5;                                // outputs per pass: G independent FP64 chains per LDS read
   const int d2 = d * d, t = threadIdx.x;
   const int alpha = blockIdx.y, delta = blockIdx.x * 64 + t;
   const long long base = (long long)alpha * d2 * chiR;
   const bool live = delta < chiR;
-  for (int q = 0; q < d2; ++q)
-    Cs[q * 64 + t] = live ? ccast<double>(C[base + (long long)q * chiR + delta]) : mk<double>(0, 0);
+  for (int q = 0; q < d2; ++q) Cs[q * 64 + t] = live ? C[base + (long long)q * chiR + delta] : mk<S>(0, 0);
   const double x = xi ? xi[alpha] : 1.0;
   double nrm = 0;
   if (live) {
-    for (int o = 0; o < d2; ++o) {
-      c128 acc = mk<double>(0, 0);
-      for (int q = 0; q < d2; ++q) acc = cadd(acc, cmul(U[o * d2 + q], Cs[q * 64 + t]));
-      const long long off = base + (long long)o * chiR + delta;
-      C[off] = ccast<S>(acc);
-      if (Th) {
-        const cpx<S> th = ccast<S>(cscale(acc, x));
-        Th[off] = th;
-        nrm += (double)th.re * th.re + (double)th.im * th.im;
+    for (int o0 = 0; o0 < d2; o0 += G) {
+      c128 acc[G];
+      int row[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        acc[u] = mk<double>(0, 0);
+        row[u] = min(o0 + u, d2 - 1) * d2;  // rows past d^2 recompute the last one and are not stored
+      }
+      for (int q = 0; q < d2; ++q) {
+        const c128 c = ccast<double>(Cs[q * 64 + t]);
+#pragma unroll
+        for (int u = 0; u < G; ++u) acc[u] = cadd(acc[u], cmul(U[row[u] + q], c));
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        if (o0 + u >= d2) break;
+        const long long off = base + (long long)(o0 + u) * chiR + delta;
+        C[off] = ccast<S>(acc[u]);
+        if (Th) {
+          const cpx<S> th = ccast<S>(cscale(acc[u], x));
+          Th[off] = th;
+          nrm += (double)th.re * th.re + (double)th.im * th.im;
+        }
       }
     }
   }
@@ -268,7 +283,7 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
     BondBufs& w = W[i];
     const int d = b.d, chiL = b.chi_l, chiR = b.chi_r, mL = d * chiL, mR = d * chiR;
     const dim3 grid((chiR + 63) / 64, chiL);
-    const size_t shm = (size_t)d * d * 64 * sizeof(c128);
+    const size_t shm = (size_t)d * d * 64 * sizeof(cpx<S>);
     static bool attr = false;
     if (!attr) {
       QT_HIP_CHECK(hipFuncSetAttribute((const void*)gate_kernel<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
