@@ -49,6 +49,14 @@ __device__ inline double rcp_refined(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
+// 1/sqrt(x) for x > 0: the hardware estimate plus two Newton steps
+// y <- y (3 - x y^2) / 2.
+__device__ inline double rsq_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  return y * fma(-0.5 * x * y, y, 1.5);
+}
+
 // ---------------------------------------------------------------- reductions
 // Lane moves inside the VALU (DPP), no LDS traffic.  Lanes whose source is
 // outside the row, or whose row is masked off, receive 0.

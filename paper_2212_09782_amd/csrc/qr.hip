@@ -47,6 +47,7 @@ struct PanelProb {
   c128* rowbuf;
   unsigned* sync;
   int m, jb, rows_per_blk, nblk, blk0, gen0, odd;
+  int chol;   // Cholesky path (two slabs of LDS)
 };
 constexpr int kMaxPanelProbs = 24;
 // Panel launches of at most this many blocks are plain launches (the CUs
@@ -78,6 +79,10 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
   __shared__ c128 taus[NB];
   __shared__ c128 rowk[NB];
   __shared__ int flag;
+  __shared__ c128 Xm[NB][NB + 1];   // small factors of the Cholesky path
+  __shared__ c128 bc[2][3][NB];      // row / column broadcasts of its sweeps (two steps in flight)
+  __shared__ double fscr[kPanelThreads / 64];
+  __shared__ double pivs[NB];        // per-step reciprocal pivots of those sweeps
 
   int pi = 0;
   while (pi + 1 < batch.nprob && (int)blockIdx.x >= batch.p[pi + 1].blk0) ++pi;
@@ -249,6 +254,315 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
     __syncthreads();
   }
 
+
+  // ---- Cholesky path (panels whose blocks hold two slabs in LDS).  QR of
+  // the slab stack by CholeskyQR2 (A = Q1 R1, Q1 = Q R2 from the Gram
+  // matrices, four barriers), then the compact-WY form of Householder
+  // reflectors for the same Q: the LU factorisation of [I; 0] - Q D, with the
+  // unit-modulus diagonal D chosen at every step so the pivot is 1 + |q|
+  // (Ballard et al., Reconstructing Householder vectors from tall-skinny QR),
+  // gives V (unit lower trapezoidal) and U; T = U V1^-H, R = D^H R2 R1.  The
+  // Gram matrices reach every block in the same order, so every block takes
+  // the same decision: when Cholesky breaks down or Q1 is far from
+  // orthonormal (||Q1^H Q1 - I||_F > 1/4), the panel falls back to the
+  // Householder column loop below with the slab untouched.
+  int gen_loop = 3;   // generation of the column loop's first barrier
+  if (a.chol) {
+    c128* P2 = P + (size_t)a.rows_per_blk * LDP;   // second slab
+    c128* gsum = a.wx + (long long)nblk * NB * NB;  // reduced Gram matrix
+    const int i0 = tid >> 5, jc = tid & 31;         // owner of entries (i0, jc), (i0 + 16, jc)
+
+    // FP64 MFMA (16x16x4 blocks, four real products per complex one); lane
+    // layout as in the product above: A element (lm, lk), B element (lk, lm),
+    // output rows lk + 4 r of column lm
+    typedef double f64x4 __attribute__((ext_vector_type(4)));
+    auto mf = [](double x, double y, f64x4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0); };
+    const int wv = tid >> 6, lm = tid & 15, lk = (tid >> 4) & 3;
+    // Gram matrix X^H X of slab X over this block's rows, as a block partial
+    // (nblk > 1) or directly into Sk: wave wv forms output block (wv & 1,
+    // (wv >> 1) & 1) over every other k step; the halves meet in Tm
+    auto gram = [&](const c128* X) {
+      const int qi = wv & 1, ci = (wv >> 1) & 1, kh = wv >> 2, nst = (nr + 3) / 4;
+      f64x4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+#pragma unroll 2
+      for (int st = kh; st < nst; st += 2) {
+        const int t = 4 * st + lk;
+        const c128 xa = t < nr ? X[t * LDP + 16 * qi + lm] : cz(), xb = t < nr ? X[t * LDP + 16 * ci + lm] : cz();
+        cre = mf(xa.re, xb.re, cre);
+        cre = mf(xa.im, xb.im, cre);
+        cim = mf(xa.re, xb.im, cim);
+        cim = mf(-xa.im, xb.re, cim);
+      }
+      if (kh == 1)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Tm[16 * qi + lk + 4 * r][16 * ci + lm] = mk<double>(cre[r], cim[r]);
+      __syncthreads();
+      if (kh == 0)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ca = 16 * qi + lk + 4 * r, cb = 16 * ci + lm;
+          const c128 g = cadd(mk<double>(cre[r], cim[r]), Tm[ca][cb]);
+          if (nblk > 1) pub_store(a.wx + (long long)blk * NB * NB + ca * NB + cb, g);
+          else Sk[ca][cb] = (ca == cb && ca >= jb) ? mk<double>(1, 0) : g;
+        }
+    };
+    // sum of the block partials: block b reduces one share of the entries
+    // (barrier gen), then every block gathers the sums (barrier gen + 1);
+    // columns past jb are given a unit diagonal
+    auto reduce_gram = [&](unsigned gen) -> bool {
+      if (nblk == 1) {
+        __syncthreads();
+        return true;
+      }
+      if (!grid_barrier(gs, gen, blk, nblk, &flag)) return false;
+      const int per = (NB * NB + nblk - 1) / nblk, e0 = blk * per;
+      const int cnt = min(per, NB * NB - e0), groups = kPanelThreads / per;
+      c128* stage = &part[0][0];
+      const auto rwx = coh_rsrc(a.wx);
+      {
+        const int g = tid / per, el = tid - g * per;
+        if (g < groups && el < cnt) {
+          c128 acc2 = cz();
+          for (int b = g; b < nblk; b += groups) acc2 = cadd(acc2, coh_load(rwx, b * NB * NB + e0 + el));
+          stage[g * per + el] = acc2;
+        }
+      }
+      __syncthreads();
+      if (tid < cnt) {
+        c128 t = cz();
+        for (int g = 0; g < groups; ++g) t = cadd(t, stage[g * per + tid]);
+        pub_store(gsum + e0 + tid, t);
+      }
+      if (!grid_barrier(gs, gen + 1, blk, nblk, &flag)) return false;
+      const auto rgs = coh_rsrc(gsum);
+      for (int e = tid; e < NB * NB; e += kPanelThreads) {
+        const int ca = e >> 5, cb = e & 31;
+        Sk[ca][cb] = (ca == cb && ca >= jb) ? mk<double>(1, 0) : coh_load(rgs, e);
+      }
+      __syncthreads();
+      return true;
+    };
+    // Cholesky G = R^H R of the Hermitian matrix in Gm (upper triangle) by
+    // row elimination on [G | I] without square roots (rows of D R and of
+    // D R^-H, D the pivots), each row scaled by 1/sqrt(pivot) at the end:
+    // R into Ro, R^-1 into Rio (both may alias Gm).  True when every pivot
+    // is positive.
+    auto chol_inv = [&](c128 (*Gm)[NB + 1], c128 (*Ro)[NB + 1], c128 (*Rio)[NB + 1]) -> bool {
+      // entries (i0, jc) and (i0 + 16, jc) of the left and right halves
+      c128 la = jc >= i0 ? Gm[i0][jc] : cz(), lb = jc >= i0 + 16 ? Gm[i0 + 16][jc] : cz();
+      c128 ra = mk<double>(i0 == jc ? 1.0 : 0.0, 0.0), rb = mk<double>(i0 + 16 == jc ? 1.0 : 0.0, 0.0);
+      bool ok = true;
+      // step k publishes row k (held as pl, pr by its owners); the two halves
+      // of k run as separate loops so the owned entries stay in registers
+      auto step = [&](int k, c128 pl, c128 pr) {
+        const int b = k & 1;
+        if (i0 == (k & 15)) {
+          bc[b][0][jc] = pl;
+          bc[b][1][jc] = pr;
+        }
+        __syncthreads();
+        const double piv = bc[b][0][k].re;
+        ok = ok && piv > 0.0 && isfinite(piv);
+        const double ip = piv > 0.0 ? rcp_refined(piv) : 0.0;
+        if (tid == 0) pivs[k] = ip;
+        auto upd = [&](c128& lv, c128& rv, int r) {
+          if (r > k) {
+            const c128 gkr = bc[b][0][r];
+            if (jc >= r) lv = csub(lv, cscale(cmulc(gkr, bc[b][0][jc]), ip));
+            rv = csub(rv, cscale(cmulc(gkr, bc[b][1][jc]), ip));
+          }
+        };
+        upd(la, ra, i0);
+        upd(lb, rb, i0 + 16);
+      };
+      for (int k = 0; k < 16; ++k) step(k, la, ra);
+      for (int k = 16; k < NB; ++k) step(k, lb, rb);
+      __syncthreads();
+      // rows of the LDL^H form scaled by 1/sqrt(pivot)
+      {
+        const double sa = sqrt(pivs[i0]), sb = sqrt(pivs[i0 + 16]);
+        la = cscale(la, sa);
+        ra = cscale(ra, sa);
+        lb = cscale(lb, sb);
+        rb = cscale(rb, sb);
+      }
+      Ro[i0][jc] = la;
+      Ro[i0 + 16][jc] = lb;
+      Rio[jc][i0] = cconj(ra);
+      Rio[jc][i0 + 16] = cconj(rb);
+      __syncthreads();
+      return ok;
+    };
+    // X M over this block's rows (M: 32 x 32, row stride LDP), each
+    // product element handed to out(row, col, value); waves take 16 x 16
+    // output blocks in turn
+    auto slab_mul = [&](const c128* X, const c128* M, auto&& out) {
+      const int nrb = (nr + 15) / 16;
+      for (int ob = wv; ob < 2 * nrb; ob += kPanelThreads / 64) {
+        const int rb = ob >> 1, cb = ob & 1, row = 16 * rb + lm;
+        f64x4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+#pragma unroll 4
+        for (int st = 0; st < NB / 4; ++st) {
+          const int k = 4 * st + lk;
+          const c128 xa = row < nr ? X[row * LDP + k] : cz(), mb = M[k * LDP + 16 * cb + lm];
+          cre = mf(xa.re, mb.re, cre);
+          cre = mf(-xa.im, mb.im, cre);
+          cim = mf(xa.re, mb.im, cim);
+          cim = mf(xa.im, mb.re, cim);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int orow = 16 * rb + lk + 4 * r;
+          if (orow < nr) out(orow, 16 * cb + lm, mk<double>(cre[r], cim[r]));
+        }
+      }
+      __syncthreads();
+    };
+
+    // pass 1: G1 = A^H A, R1 (Xm), R1^-1 (Tm), Q1 = A R1^-1 (P2)
+    gram(P);
+    if (!reduce_gram((unsigned)(a.gen0 + 3))) return;
+    bool ok = chol_inv(Sk, Xm, Tm);
+    slab_mul(P, &Tm[0][0], [&](int r, int c, c128 v) { P2[r * LDP + c] = v; });
+    // pass 2: G2 = Q1^H Q1, R2 (Sk), R2^-1 (Tm)
+    gram(P2);
+    if (!reduce_gram((unsigned)(a.gen0 + 5))) return;
+    double dev = 0;
+    for (int e = tid; e < NB * NB; e += kPanelThreads) {
+      const int ca = e >> 5, cb = e & 31;
+      if (ca <= cb && cb < jb) {
+        const c128 g = Sk[ca][cb];
+        dev += ca == cb ? (g.re - 1) * (g.re - 1) + g.im * g.im : 2 * cabs2(g);
+      }
+    }
+    dev = block_sum(dev, fscr);
+    ok = ok && dev <= 0.0625 && isfinite(dev);
+    ok = chol_inv(Sk, Sk, Tm) && ok;
+    if (ok) {
+      slab_mul(P2, &Tm[0][0], [&](int r, int c, c128 v) { P[r * LDP + c] = v; });   // Q; P2 is free from here on
+      c128 rra = cz(), rrb = cz();   // R = R2 R1, entries (i0, jc), (i0 + 16, jc) (block 0)
+      if (blk == 0) {
+#pragma unroll 4
+        for (int l = 0; l < NB; ++l) {
+          rra = cadd(rra, cmul(Sk[i0][l], Xm[l][jc]));
+          rrb = cadd(rrb, cmul(Sk[i0 + 16][l], Xm[l][jc]));
+        }
+        __syncthreads();
+        // LU of [I; 0] - Q D on the top 32 rows, with [.. | I] alongside:
+        // V1 (Sk, strictly lower), d (taus), U (Xm), V1^-1 (Tm)
+        c128 qa = i0 < nr ? P[i0 * LDP + jc] : cz(), qb = i0 + 16 < nr ? P[(i0 + 16) * LDP + jc] : cz();
+        c128 ea = mk<double>(i0 == jc ? 1.0 : 0.0, 0.0), eb = mk<double>(i0 + 16 == jc ? 1.0 : 0.0, 0.0);
+        auto lu_step = [&](int i, c128 pq, c128 pe) {
+          const int b = i & 1;
+          if (i0 == (i & 15)) {
+            bc[b][0][jc] = pq;
+            bc[b][1][jc] = pe;
+          }
+          if (jc == i) {
+            bc[b][2][i0] = qa;
+            bc[b][2][i0 + 16] = qb;
+          }
+          __syncthreads();
+          const c128 av = bc[b][0][i];
+          const double m2 = cabs2(av), rs = m2 > 0.0 ? rsq_refined(m2) : 0.0, mag = m2 * rs;
+          const c128 di = m2 > 0.0 ? mk<double>(-av.re * rs, av.im * rs) : mk<double>(1, 0);   // -conj(a)/|a|
+          const double iu = rcp_refined(1.0 + mag);
+          auto upd = [&](c128& qv, c128& ev, int r) {
+            if (r > i) {
+              const c128 l = cscale(cmul(bc[b][2][r], di), -iu);
+              if (jc == i) Sk[r][i] = l;
+              if (jc > i) qv = csub(qv, cmul(l, bc[b][0][jc]));
+              ev = csub(ev, cmul(l, bc[b][1][jc]));
+            }
+          };
+          upd(qa, ea, i0);
+          upd(qb, eb, i0 + 16);
+          if (tid == 0) {
+            taus[i] = di;
+            rowk[i] = mk<double>(1.0 + mag, 0.0);
+            pivs[i] = iu;
+          }
+        };
+        for (int i = 0; i < 16; ++i) lu_step(i, qa, ea);
+        for (int i = 16; i < NB; ++i) lu_step(i, qb, eb);
+        __syncthreads();
+        Xm[i0][jc] = jc > i0 ? cscale(cmul(qa, taus[jc]), -1.0) : (jc == i0 ? rowk[i0] : cz());
+        Xm[i0 + 16][jc] = jc > i0 + 16 ? cscale(cmul(qb, taus[jc]), -1.0) : (jc == i0 + 16 ? rowk[i0 + 16] : cz());
+        Tm[i0][jc] = ea;
+        Tm[i0 + 16][jc] = eb;
+        __syncthreads();
+        // U^-1 by back substitution on [U | I]
+        c128 xa = mk<double>(i0 == jc ? 1.0 : 0.0, 0.0), xb = mk<double>(i0 + 16 == jc ? 1.0 : 0.0, 0.0);
+        auto bs_step = [&](int i, c128 px) {
+          const int b = i & 1;
+          if (i0 == (i & 15)) bc[b][1][jc] = px;
+          __syncthreads();
+          const double ip = pivs[i];   // 1 / U[i][i]
+          auto upd = [&](c128& xv, int r) {
+            if (r < i) xv = csub(xv, cmul(cscale(Xm[r][i], ip), bc[b][1][jc]));
+            else if (r == i) xv = cscale(xv, ip);
+          };
+          upd(xa, i0);
+          upd(xb, i0 + 16);
+        };
+        for (int i = NB - 1; i >= 16; --i) bs_step(i, xb);
+        for (int i = 15; i >= 0; --i) bs_step(i, xa);
+        P2[i0 * LDP + jc] = xa;
+        P2[(i0 + 16) * LDP + jc] = xb;
+        if (nblk > 1) {
+          pub_store(a.wx + i0 * NB + jc, xa);
+          pub_store(a.wx + (i0 + 16) * NB + jc, xb);
+          if (tid < NB) pub_store(a.wx + NB * NB + tid, taus[tid]);
+        }
+      }
+      if (nblk > 1) {
+        if (!grid_barrier(gs, (unsigned)(a.gen0 + 7), blk, nblk, &flag)) return;
+        if (blk != 0) {
+          const auto rwx = coh_rsrc(a.wx);
+          for (int e = tid; e < NB * NB; e += kPanelThreads) P2[(e >> 5) * LDP + (e & 31)] = coh_load(rwx, e);
+          if (tid < NB) taus[tid] = coh_load(rwx, NB * NB + tid);
+        }
+      }
+      __syncthreads();
+      // write back: rows past jb hold V2 = Q M with M = -D U^-1 (in A below
+      // the diagonal and in V); the top rows (block 0) R_h = D^H R above the
+      // diagonal and V1 below it
+      for (int e = tid; e < NB * NB; e += kPanelThreads) {
+        c128* x = P2 + (e >> 5) * LDP + (e & 31);
+        *x = cscale(cmul(taus[e >> 5], *x), -1.0);
+      }
+      __syncthreads();
+      cpx<S>* V = (cpx<S>*)a.V;
+      slab_mul(P, P2, [&](int r, int c, c128 v) {
+        if (r0 + r < jb) return;
+        const long long row = r0 + r;
+        if (c < jb) A[row * a.lda + c] = ccast<S>(v);
+        V[row * LDV + c] = ccast<S>(c < jb ? v : cz());
+      });
+      if (blk == 0) {
+        auto top_row = [&](int r, c128 rv) {
+          if (r >= jb) return;
+          if (jc < jb) A[(long long)r * a.lda + jc] = ccast<S>(jc >= r ? cmul(cconj(taus[r]), rv) : Sk[r][jc]);
+          const c128 vc = jc < jb ? (jc < r ? Sk[r][jc] : (jc == r ? mk<double>(1, 0) : cz())) : cz();
+          V[(long long)r * LDV + jc] = ccast<S>(vc);
+        };
+        top_row(i0, rra);
+        top_row(i0 + 16, rrb);
+        if (a.odd)
+          for (int idx = tid; idx < NB * NB; idx += kPanelThreads)
+            V[(long long)(idx / NB - NB) * LDV + idx % NB] = ccast<S>(cz());
+        // T = U V1^-H
+        for (int r = i0; r < NB; r += 16) {
+          c128 t = cz();
+          for (int l = r; l <= jc; ++l) t = cadd(t, cmul(Xm[r][l], cconj(Tm[jc][l])));
+          a.T[r * NB + jc] = (r < jb && jc < jb) ? t : cz();
+        }
+      }
+      return;
+    }
+    gen_loop = 7;
+  }
+
   // Thread (rg, c) owns column c of the slab rows rg, rg + 16, ...  Its running
   // partial t_c = sum_i conj(P[i,k]) P[i,c] over its rows strictly below the
   // diagonal is formed for column 0 here and for column k + 1 during the
@@ -295,7 +609,7 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
       pub_store(a.red + ((long long)slot * nblk + blk) * NB + tid, sblk);
       if (k >= r0 && k < r0 + nr) pub_store(a.rowbuf + slot * NB + tid, P[(k - r0) * LDP + tid]);
     }
-    if (!grid_barrier(gs, (unsigned)(a.gen0 + k + 3), blk, nblk, &flag, [&]() {
+    if (!grid_barrier(gs, (unsigned)(a.gen0 + gen_loop + k), blk, nblk, &flag, [&]() {
           if (k >= 2) t_column(k - 1);
         }))
       return;
@@ -435,7 +749,7 @@ int panel_blocks_max(int m) {
 
 template <typename S>
 int launch_panel(const PanelBatch& pb, int nblk_total, int max_rows, hipStream_t s) {
-  const size_t shmem = (size_t)max_rows * LDP * sizeof(c128);
+  const size_t shmem = (size_t)(pb.p[0].chol ? 2 : 1) * max_rows * LDP * sizeof(c128);
   static bool attr_set = false;
   if (!attr_set) {
     QT_HIP_CHECK(hipFuncSetAttribute((const void*)qr_panel_kernel<S>,
@@ -679,6 +993,8 @@ static int launch_panels(const QrJob* jobs, int njobs, int p, int dt, hipStream_
   int rc;
   auto flush = [&]() -> int {
     if (pb.nprob == 0) return 0;
+    // the Cholesky path keeps a second slab in LDS
+    for (int q = 0; q < pb.nprob; ++q) pb.p[q].chol = 2 * max_rows <= kMaxPanelRows;
     int r = dt == DT_C128 ? launch_panel<double>(pb, used, max_rows, s) : launch_panel<float>(pb, used, max_rows, s);
     pb = PanelBatch{};
     used = 0;
@@ -707,8 +1023,8 @@ static int launch_panels(const QrJob* jobs, int njobs, int p, int dt, hipStream_
       pp.Vprev = (const char*)w.V + qr_v_offset(p - 1, J.m) * es;
       pp.Tprev = w.T + (size_t)(p - 1) * NB * NB;
       pp.Atop = (char*)J.A + ((long long)(j0 - NB) * J.lda + j0) * es;
-      pp.wx = w.wx;
     }
+    pp.wx = w.wx;
     pp.red = w.red;
     pp.rowbuf = w.red + 2 * (size_t)kMaxPanelBlocks * NB;
     pp.sync = w.sync;
@@ -717,7 +1033,8 @@ static int launch_panels(const QrJob* jobs, int njobs, int p, int dt, hipStream_
     pp.rows_per_blk = rows;
     pp.nblk = nblk;
     pp.blk0 = used;
-    pp.gen0 = p * (NB + 2);   // two barriers before the columns, one per column; increasing over the panels
+    pp.gen0 = p * (NB + 8);   // two barriers before the columns, up to five of the Cholesky path, one per
+                              // column; increasing over the panels
     used += nblk;
     max_rows = std::max(max_rows, rows);
   }
