@@ -102,6 +102,25 @@ def test_qr_rank_deficient(ctx, mnr):
     assert np.linalg.norm(P @ A - A) <= 1e-13 * np.linalg.norm(A)
 
 
+@pytest.mark.parametrize("dt", [lib.DT_C128, lib.DT_C64])
+@pytest.mark.parametrize("mnc", [(1000, 64, 1e10), (2600, 96, 1e6), (5000, 40, 1e13)])
+def test_qr_ill_conditioned(ctx, dt, mnc):
+    """Full rank with condition number cond (singular vectors mixed on both
+    sides): panels whose Gram-matrix Cholesky loses orthogonality fall back to
+    the column-by-column Householder loop; Q stays an isometry spanning A."""
+    m, n, cond = mnc
+    print(f"qr ill-conditioned dt={dt} shape={(m, n)} cond={cond:g}", flush=True)
+    r = inputs.rng(91 + m)
+    W = np.linalg.qr(inputs.gaussian_complex((m, n), r))[0]
+    A = (W * np.logspace(0, -np.log10(cond), n)[None, :]) @ inputs.random_unitary(n, r)
+    if dt == lib.DT_C64:
+        A = A.astype(np.complex64).astype(np.complex128)
+    tol = (1e-13, 1e-13) if dt == lib.DT_C128 else (2e-5, 2e-5)
+    Q, R = _qr_check(ctx, A, dt, *tol)
+    P = Q @ Q.conj().T
+    assert np.linalg.norm(P @ A - A) <= tol[0] * np.linalg.norm(A)
+
+
 def _herm(n, kind, r):
     if kind == "random":
         G = inputs.gaussian_complex((n, n), r)
