@@ -350,11 +350,25 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
                        (cpx<S>*)W[i].R);
     QT_HIP_CHECK(hipGetLastError());
   }
-  if ((rc = qr_form_q_batch(qj.data(), nc, dt, s))) return rc;
   // further sweeps (bonds with sweeps > it): X = theta~ Q^[n]^dag = theta~ Q',
   // then steps (i)-(ii) again
   int maxsw = 1;
-  for (int i = 0; i < nc; ++i) maxsw = std::max(maxsw, calls[i].b.sweeps);
+  bool all_cbe = true;
+  for (int i = 0; i < nc; ++i) {
+    maxsw = std::max(maxsw, calls[i].b.sweeps);
+    all_cbe = all_cbe && calls[i].b.mode == 2;
+  }
+  // With one sweep and CBE, Q' is next read by the B~^[n] product after the
+  // eigen-decomposition (which reads only R'): it is formed on the auxiliary
+  // stream, beside the latency-bound eigensolver, and joined before that
+  // product.  Its launches are issued after the eigensolver's, so that the
+  // host's launch time does not delay the eigensolver.
+  const bool q_aside = as && as->aux && maxsw == 1 && all_cbe;
+  if (q_aside) {
+    QT_HIP_CHECK(hipEventRecord(as->ev_panel, s));
+  } else if ((rc = qr_form_q_batch(qj.data(), nc, dt, s))) {
+    return rc;
+  }
   for (int it = 1; it < maxsw; ++it) {
     std::vector<int> act;
     for (int i = 0; i < nc; ++i)
@@ -427,6 +441,11 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
       ej.push_back(EigJob{W[i].G, calls[i].b.eta, kwant_of(calls[i].b), W[i].lam, W[i].E, &ew[i],
                           calls[i].b.prec == 0 ? 2 : 1});
     if ((rc = eig_herm_top_batch(ej.data(), (int)ej.size(), s))) return rc;
+    if (q_aside) {
+      QT_HIP_CHECK(hipStreamWaitEvent(as->aux, as->ev_panel, 0));
+      if ((rc = qr_form_q_batch(qj.data(), nc, dt, as->aux))) return rc;
+      QT_HIP_CHECK(hipEventRecord(as->ev_trail, as->aux));
+    }
     g.clear();
     for (int i : cb) {
       const BondCall& c = calls[i];
@@ -446,6 +465,7 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
       gp.dM = c.chi_new;
       g.push_back(gp);
     }
+    if (q_aside) QT_HIP_CHECK(hipStreamWaitEvent(s, as->ev_trail, 0));
     if ((rc = timed_gemm_batch(tm, g.data(), (int)g.size(), ty, s))) return rc;
   }
   // plain / grow: Xi~ = L/|L|, B~^[n] = Q'^dag
