@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
   __shared__ c128 rowk[NB];
   __shared__ int flag;
   __shared__ c128 Xm[NB][NB + 1];   // small factors of the Cholesky path
-  __shared__ c128 bc[2][3][NB];      // row / column broadcasts of its sweeps (two steps in flight)
+  __shared__ c128 bc[2][4][NB];      // row / column broadcasts of its sweeps (two steps in flight)
   __shared__ double fscr[kPanelThreads / 64];
   __shared__ double pivs[NB];        // per-step reciprocal pivots of those sweeps
 
@@ -352,31 +352,54 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
       c128 la = jc >= i0 ? Gm[i0][jc] : cz(), lb = jc >= i0 + 16 ? Gm[i0 + 16][jc] : cz();
       c128 ra = mk<double>(i0 == jc ? 1.0 : 0.0, 0.0), rb = mk<double>(i0 + 16 == jc ? 1.0 : 0.0, 0.0);
       bool ok = true;
-      // step k publishes row k (held as pl, pr by its owners); the two halves
-      // of k run as separate loops so the owned entries stay in registers
-      auto step = [&](int k, c128 pl, c128 pr) {
-        const int b = k & 1;
+      // Two pivots per block barrier: the owners publish rows k and k + 1 (as
+      // left after step k - 1; pl, pr are the owner's entries), and every
+      // thread forms the entries of row k + 1 after step k that it needs with
+      // the owner's own expression.  The two halves of k run as separate
+      // loops so the owned entries stay in registers.
+      auto step2 = [&](int k, c128 pl, c128 pr) {
+        const int b = (k >> 1) & 1;
         if (i0 == (k & 15)) {
           bc[b][0][jc] = pl;
           bc[b][1][jc] = pr;
         }
+        if (i0 == ((k + 1) & 15)) {
+          bc[b][2][jc] = pl;
+          bc[b][3][jc] = pr;
+        }
         __syncthreads();
-        const double piv = bc[b][0][k].re;
-        ok = ok && piv > 0.0 && isfinite(piv);
-        const double ip = piv > 0.0 ? rcp_refined(piv) : 0.0;
-        if (tid == 0) pivs[k] = ip;
+        const double piv0 = bc[b][0][k].re;
+        const double ip0 = piv0 > 0.0 ? rcp_refined(piv0) : 0.0;
+        const c128 g01 = bc[b][0][k + 1];
+        auto row1L = [&](int x) { return csub(bc[b][2][x], cscale(cmulc(g01, bc[b][0][x]), ip0)); };
+        auto row1R = [&](int x) { return csub(bc[b][3][x], cscale(cmulc(g01, bc[b][1][x]), ip0)); };
+        const double piv1 = row1L(k + 1).re;
+        const double ip1 = piv1 > 0.0 ? rcp_refined(piv1) : 0.0;
+        ok = ok && piv0 > 0.0 && isfinite(piv0) && piv1 > 0.0 && isfinite(piv1);
+        if (tid == 0) {
+          pivs[k] = ip0;
+          pivs[k + 1] = ip1;
+        }
+        const c128 l1j = row1L(jc), r1j = row1R(jc);
         auto upd = [&](c128& lv, c128& rv, int r) {
           if (r > k) {
             const c128 gkr = bc[b][0][r];
-            if (jc >= r) lv = csub(lv, cscale(cmulc(gkr, bc[b][0][jc]), ip));
-            rv = csub(rv, cscale(cmulc(gkr, bc[b][1][jc]), ip));
+            if (jc >= r) lv = csub(lv, cscale(cmulc(gkr, bc[b][0][jc]), ip0));
+            rv = csub(rv, cscale(cmulc(gkr, bc[b][1][jc]), ip0));
+          }
+          if (r > k + 1) {
+            const c128 g1r = row1L(r);
+            if (jc >= r) lv = csub(lv, cscale(cmulc(g1r, l1j), ip1));
+            rv = csub(rv, cscale(cmulc(g1r, r1j), ip1));
           }
         };
         upd(la, ra, i0);
         upd(lb, rb, i0 + 16);
       };
-      for (int k = 0; k < 16; ++k) step(k, la, ra);
-      for (int k = 16; k < NB; ++k) step(k, lb, rb);
+#pragma unroll 1
+      for (int k = 0; k < 16; k += 2) step2(k, la, ra);
+#pragma unroll 1
+      for (int k = 16; k < NB; k += 2) step2(k, lb, rb);
       __syncthreads();
       // rows of the LDL^H form scaled by 1/sqrt(pivot)
       {
