@@ -135,6 +135,11 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   cpx<Tin> ra[EPT], rb[EPT];
   const int rowq = tid >> 2, colq = (tid & 3) * (BK / 4);   // 64 rows x BK cols (k contiguous)
   const int rowk = tid >> 4, colk = (tid & 15) * 4;         // BK k-rows (16 per group) x 64 cols
+  // 3-product form, operands stored k-major (A^T / A^H, B as stored): lane ->
+  // m (or n), wave -> four consecutive k, so the global loads stay coalesced
+  // (64 consecutive elements per load) and each lane writes one 16-byte LDS
+  // row segment per plane, the conflict-free pattern of the reads
+  const int kml = tid & 63, kmk = 4 * (tid >> 6);
 
   auto load = [&](int k0) {
 #pragma unroll
@@ -144,13 +149,19 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
       if (opA == OP_N) {
         const int m = m0 + rowq, k = k0 + colq + e;
         if (m < M && k < kend) z = A[(long long)m * lda + k];
+      } else if (k3) {
+        const int k = k0 + kmk + e, m = m0 + kml;
+        if (m < M && k < kend) z = A[(long long)k * lda + m];
       } else {
         const int k = k0 + rowk + 16 * g, m = m0 + colk + e4;
         if (m < M && k < kend) z = A[(long long)k * lda + m];
       }
       ra[e] = z;
       cpx<Tin> w = mk<Tin>(0, 0);
-      if (opB == OP_N) {
+      if (opB == OP_N && k3) {
+        const int k = k0 + kmk + e, n = n0 + kml;
+        if (n < N && k < kend) w = B[(long long)k * ldb + n];
+      } else if (opB == OP_N) {
         const int k = k0 + rowk + 16 * g, n = n0 + colk + e4;
         if (n < N && k < kend) w = B[(long long)k * ldb + n];
       } else {
@@ -168,23 +179,19 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
         *(f4*)&As[buf][0][rowq][colq] = f4{(Tc)ra[0].re, (Tc)ra[1].re, (Tc)ra[2].re, (Tc)ra[3].re};
         *(f4*)&As[buf][1][rowq][colq] =
             f4{sa * (Tc)ra[0].im, sa * (Tc)ra[1].im, sa * (Tc)ra[2].im, sa * (Tc)ra[3].im};
-      } else {
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-          As[buf][0][colk + e][rowk] = (Tc)ra[e].re;
-          As[buf][1][colk + e][rowk] = sa * (Tc)ra[e].im;
-        }
+      } else {   // four consecutive k of row kml
+        *(f4*)&As[buf][0][kml][kmk] = f4{(Tc)ra[0].re, (Tc)ra[1].re, (Tc)ra[2].re, (Tc)ra[3].re};
+        *(f4*)&As[buf][1][kml][kmk] =
+            f4{sa * (Tc)ra[0].im, sa * (Tc)ra[1].im, sa * (Tc)ra[2].im, sa * (Tc)ra[3].im};
       }
       if (opB != OP_N) {
         *(f4*)&Bs[buf][0][rowq][colq] = f4{(Tc)rb[0].re, (Tc)rb[1].re, (Tc)rb[2].re, (Tc)rb[3].re};
         *(f4*)&Bs[buf][1][rowq][colq] =
             f4{sb * (Tc)rb[0].im, sb * (Tc)rb[1].im, sb * (Tc)rb[2].im, sb * (Tc)rb[3].im};
       } else {
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-          Bs[buf][0][colk + e][rowk] = (Tc)rb[e].re;
-          Bs[buf][1][colk + e][rowk] = sb * (Tc)rb[e].im;
-        }
+        *(f4*)&Bs[buf][0][kml][kmk] = f4{(Tc)rb[0].re, (Tc)rb[1].re, (Tc)rb[2].re, (Tc)rb[3].re};
+        *(f4*)&Bs[buf][1][kml][kmk] =
+            f4{sb * (Tc)rb[0].im, sb * (Tc)rb[1].im, sb * (Tc)rb[2].im, sb * (Tc)rb[3].im};
       }
     } else {
 #pragma unroll
