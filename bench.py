@@ -32,9 +32,8 @@ PEAK = {"c128": 78.6e12, "c64": 157.3e12}   # dense FP64 / FP32 matrix-core peak
 # launches per update), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by the
 # same counters read for a plain 256 MiB copy (--copy-calibration); the
 # commands and raw figures are in profiles/contract_gemm_hbm_d5_chi1024_mixed.md.
-# Only valid for the kernel version those counters were taken on (None: not
-# yet counted for the current version).
-CONTRACT_TRAFFIC_C64 = None
+# Only valid for the kernel version those counters were taken on.
+CONTRACT_TRAFFIC_C64 = 1.3325e9
 
 
 def run_precision(lib, torch, prec, chi, d, steps, warmup, sweeps=1):
