@@ -460,7 +460,43 @@ __global__ __launch_bounds__(kPanelThreads) void qr_panel_kernel(PanelBatch batc
     }
     dev = block_sum(dev, fscr);
     ok = ok && dev <= 0.0625 && isfinite(dev);
-    ok = chol_inv(Sk, Sk, Tm) && ok;
+    if (ok && dev <= 1e-12) {
+      // G2 = I + E with ||E||_F <= 1e-6: the Cholesky factor to second order,
+      // U1 = upper(E) with half its diagonal, U2 = -upper(U1^H U1) with half
+      // its diagonal, R2 = I + U1 + U2, R2^-1 = I - U1 - U2 + U1^2, both
+      // exact to O(||E||^3), below the rounding of FP64
+      for (int e = tid; e < NB * NB; e += kPanelThreads) {
+        const int ca = e >> 5, cb = e & 31;
+        const c128 g = Sk[ca][cb];
+        Sk[ca][cb] = ca < cb ? g : (ca == cb ? mk<double>(0.5 * (g.re - 1.0), 0.0) : cz());
+      }
+      __syncthreads();
+      c128 r2[2], m2[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = i0 + 16 * h;
+        c128 s1 = cz(), s2 = cz();
+#pragma unroll 4
+        for (int l = 0; l < NB; ++l) {
+          s1 = cadd(s1, cmulc(Sk[l][r], Sk[l][jc]));   // (U1^H U1)[r][jc]
+          s2 = cadd(s2, cmul(Sk[r][l], Sk[l][jc]));    // (U1 U1)[r][jc]
+        }
+        const c128 u1 = Sk[r][jc];
+        const c128 u2 = r < jc ? cscale(s1, -1.0) : (r == jc ? mk<double>(-0.5 * s1.re, 0.0) : cz());
+        const double id = r == jc ? 1.0 : 0.0;
+        r2[h] = mk<double>(id + u1.re + u2.re, u1.im + u2.im);
+        m2[h] = mk<double>(id - u1.re - u2.re + s2.re, -u1.im - u2.im + s2.im);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        Sk[i0 + 16 * h][jc] = r2[h];
+        Tm[i0 + 16 * h][jc] = m2[h];
+      }
+      __syncthreads();
+    } else {
+      ok = chol_inv(Sk, Sk, Tm) && ok;
+    }
     if (ok) {
       slab_mul(P2, &Tm[0][0], [&](int r, int c, c128 v) { P[r * LDP + c] = v; });   // Q; P2 is free from here on
       c128 rra = cz(), rrb = cz();   // R = R2 R1, entries (i0, jc), (i0 + 16, jc) (block 0)
