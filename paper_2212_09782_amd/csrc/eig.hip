@@ -70,16 +70,27 @@ struct TriBatch {
   TriProb p[kMaxTriProbs];
 };
 
-// Fixed-order block sum of a complex value (every thread gets the result).
-__device__ inline c128 block_sum_c(c128 v, c128* scr) {
+// Fixed-order block sums (every thread gets the result) with one barrier:
+// scr (one entry per wave) must not be read by any thread after the block's
+// previous barrier, so callers alternate between two buffers from one call
+// to the next.
+__device__ inline c128 block_sum_c1(c128 v, c128* scr) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   v.re = wave_sum(v.re);
   v.im = wave_sum(v.im);
-  __syncthreads();
   if (lane == 0) scr[wid] = v;
   __syncthreads();
   c128 s = z0();
   for (int w = 0; w < nw; ++w) s = cadd(s, scr[w]);
+  return s;
+}
+__device__ inline double block_sum1(double v, double* scr) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) scr[wid] = v;
+  __syncthreads();
+  double s = 0;
+  for (int w = 0; w < nw; ++w) s += scr[w];
   return s;
 }
 
@@ -94,8 +105,8 @@ __device__ inline c128 block_sum_c(c128 v, c128* scr) {
 // first from the updated row k+1 (published by its owner before the barrier).
 __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriBatch batch) {
   extern __shared__ c128 rows[];  // rows_loc x n, local row r = global row blk + r * P
-  __shared__ double scratch[8];
-  __shared__ c128 cscr[8];
+  __shared__ double scratch[2][kTriThreads / 64];   // alternating buffers of the block sums
+  __shared__ c128 cscr[2][kTriThreads / 64];
   __shared__ double wred[kTriThreads / 64][16];
   __shared__ c128 vloc[2][kTriRows], wloc[kTriRows];
   __shared__ c128 scal[4];
@@ -145,7 +156,7 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriBatch batch) {
       if (j == kk + 1) scal[0] = cconj(rk[q]);
       if (j == kk) scal[1] = rk[q];
     }
-    xn2 = block_sum(xn2, scratch);  // its barriers also publish scal[0], scal[1]
+    xn2 = block_sum1(xn2, scratch[kk & 1]);  // its barrier also publishes scal[0], scal[1]
     const c128 alpha = scal[0];
     c128 scale = z0();
     tau = z0();
@@ -240,7 +251,7 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriBatch batch) {
       pv[q] = (j > k && j < n) ? pub_load(a.pbuf + (long long)slot * n + j) : z0();
       xb[q] = j < n ? pub_load(a.rowbuf + (long long)slot * n + j) : z0();
     }
-    const c128 ptv = block_sum_c(rv, cscr);   // p^H v
+    const c128 ptv = block_sum_c1(rv, cscr[k & 1]);   // p^H v
     const c128 alpha2 = cscale(cmul(tau, ptv), -0.5);
     // ---- w = p + alpha2 v
 #pragma unroll
