@@ -156,7 +156,9 @@ int mps_state_chis(mps_state st, int* chi_out);
 
 /* Sweep policy shared by all states of one call. */
 typedef struct {
-  int mode;         /* mps_trunc; PLAIN keeps chi fixed */
+  int mode;         /* must be MPS_TRUNC_CBE: the states keep diagonal bond
+                       matrices (plain / grow updates, whose Xi~ is a dense L,
+                       run through mps_bond_update) */
   int chi_max;
   double svd_min;
   int dchi_min;     /* eta = min(chi + max(dchi_min, ceil(dchi_frac*chi)), d chi_l, d chi_r) */

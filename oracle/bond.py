@@ -83,12 +83,18 @@ def select_chi(S, chi_max, svd_min):
     return max(k, 1)
 
 
-def qr_bond_update(xi, bm, bn, U, mode=CBE, eta=None, chi_max=None, svd_min=1e-14, nsweeps=1):
+def qr_bond_update(xi, bm, bn, U, mode=CBE, eta=None, chi_max=None, svd_min=1e-14, nsweeps=1, eig_backward=None):
     """QR-based bond update, Sec. II (plain / grow) and Sec. III (CBE).
 
     nsweeps > 1 repeats steps (i)-(ii) from Y0 = Q^[n] of the previous sweep
     (the alternating-least-squares reading of the Sec. II comments); the
     truncation then uses the last sweep's factors.
+
+    eig_backward (tests only): None, or (rng, c) to hand the eigensolver of
+    step (iv) L^dag L + E instead of L^dag L, with E a random Hermitian matrix
+    of spectral norm c u |L^dag L|_2 (u = 2^-52): the backward error a stable
+    eigensolver is allowed.  Running the update with and without it measures
+    how far two correct FP64 implementations may drift apart.
 
     Returns a dict with
       bm, bn   new tensors [chi_L, d, chi~] and [chi~, d, chi_R]
@@ -131,7 +137,14 @@ def qr_bond_update(xi, bm, bn, U, mode=CBE, eta=None, chi_max=None, svd_min=1e-1
         kept2 = float(np.sum(np.abs(L) ** 2))
     else:
         # Sec. III (iv): L^dag L = V^dag S^2 V;  (v): B~[n] = P V Q^[n], Xi~ = P S P.
-        w, E = np.linalg.eigh(L.conj().T @ L)
+        G = L.conj().T @ L
+        if eig_backward is not None:
+            rng, c = eig_backward
+            n = G.shape[0]
+            P = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+            P = (P + P.conj().T) / 2
+            G = G + P * (c * 2.0 ** -52 * np.linalg.norm(G, 2) / np.linalg.norm(P, 2))
+        w, E = np.linalg.eigh(G)
         order = np.argsort(-w, kind="stable")
         w, E = w[order], E[:, order]
         S = np.sqrt(np.maximum(w, 0.0))

@@ -83,3 +83,18 @@ def exact_evolve(psi, H, t):
 
 def site_expectations(psi, O, L, d):
     return np.array([np.vdot(psi, apply_one_site(psi, O, m, L, d)) for m in range(L)])
+
+
+def cut_entropy(psi, m, L, d):
+    """Von Neumann entropy -Tr rho ln rho of sites 0..m-1 (Sec. IV, Fig. 4 quantity).
+
+    rho is the reduced density matrix Psi Psi^dag of the state vector viewed
+    as the d^m x d^(L-m) matrix Psi, normalised to unit trace; its spectrum
+    comes from numpy's Hermitian eigensolver.  This is the definition of the
+    bipartite entanglement entropy, independent of any MPS form.
+    """
+    P = psi.reshape(d ** m, d ** (L - m))
+    rho = P @ P.conj().T
+    w = np.linalg.eigvalsh(rho / np.trace(rho).real)
+    w = w[w > 1e-300]
+    return float(-np.sum(w * np.log(w)))

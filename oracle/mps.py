@@ -34,12 +34,16 @@ def bonds_of_layer(L, finite, parity):
     return [(m, (m + 1) % L) for m in range(parity, L, 2)]
 
 
-def apply_layer(state, gates, parity, mode, dchi_rule, chi_max, svd_min, scheme="qr", nsweeps=1):
+def apply_layer(state, gates, parity, mode, dchi_rule, chi_max, svd_min, scheme="qr", nsweeps=1, log=None,
+                eig_backward=None):
     """Update every bond of one layer; gates[b] is the gate of the bond starting at site b.
 
     dchi_rule(chi_m) gives the expansion dchi used for eta (Sec. III); nsweeps
     QR/LQ sweeps per bond (Sec. II comments).  Returns the list of truncation
-    errors.
+    errors.  log (a list, optional) receives per bond the site m, the Schmidt
+    values S of the update and the kept number chi~ (bookkeeping for tests
+    that need the spectrum at the cut); eig_backward is passed to every
+    update (see bond.qr_bond_update).
     """
     B, Xi, finite = state["B"], state["Xi"], state["finite"]
     L = len(B)
@@ -53,22 +57,27 @@ def apply_layer(state, gates, parity, mode, dchi_rule, chi_max, svd_min, scheme=
         else:
             eta = chiM if mode == _bond.PLAIN else _bond.eta_cbe(chiL, chiM, chiR, d, dchi_rule(chiM))
             r = _bond.qr_bond_update(Xi[m], bm, bn, gates[m], mode=mode, eta=eta,
-                                     chi_max=chi_max, svd_min=svd_min, nsweeps=nsweeps)
+                                     chi_max=chi_max, svd_min=svd_min, nsweeps=nsweeps,
+                                     eig_backward=eig_backward)
         B[m], B[n], Xi[n] = r["bm"], r["bn"], r["xi"]
         eps.append(r["eps"])
+        if log is not None:
+            log.append(dict(m=m, S=np.asarray(r["S"]), chi=r["chi"], eps=r["eps"]))
     return eps
 
 
 def trotter_step(state, gates_half, gates_full, order=2, mode=_bond.CBE,
                  dchi_rule=lambda c: max(100, -(-c // 10)), chi_max=None,
-                 svd_min=1e-14, scheme="qr", nsweeps=1):
+                 svd_min=1e-14, scheme="qr", nsweeps=1, log=None, eig_backward=None):
     """One Trotter step of length dt (Fig. 2a).
 
     order 2: even(dt/2) odd(dt) even(dt/2);  order 1: even(dt) odd(dt), where
     gates_half / gates_full are the per-bond gates for dt/2 / dt.
-    Returns the summed truncation error of the step.
+    Returns the summed truncation error of the step (log, eig_backward: see
+    apply_layer).
     """
-    kw = dict(mode=mode, dchi_rule=dchi_rule, chi_max=chi_max, svd_min=svd_min, scheme=scheme, nsweeps=nsweeps)
+    kw = dict(mode=mode, dchi_rule=dchi_rule, chi_max=chi_max, svd_min=svd_min, scheme=scheme, nsweeps=nsweeps,
+              log=log, eig_backward=eig_backward)
     eps = []
     if order == 2:
         eps += apply_layer(state, gates_half, 0, **kw)

@@ -35,7 +35,6 @@ def right_isometric(chi_l, d, chi_r, r):
 def random_lambda(chi, r):
     """Positive bond weights: sorted U(0,1) draws, descending, unit 2-norm."""
     u = np.sort(r.uniform(0.0, 1.0, chi))[::-1].copy()
-    u = np.maximum(u, 1e-3)
     return u / np.linalg.norm(u)
 
 

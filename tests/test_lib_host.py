@@ -54,3 +54,75 @@ def test_bond_capacity():
     assert lib.bond_capacity(lib.bond_desc(5, 64, 64, 64, eta=71, chi_max=64)) == 64
     assert lib.bond_capacity(lib.bond_desc(5, 64, 64, 64, eta=71, chi_max=100)) == 71
     assert lib.bond_capacity(lib.bond_desc(5, 64, 64, 64, eta=64, chi_max=8, mode=lib.PLAIN)) == 64
+
+
+def _ws_query(desc):
+    L = lib.load()
+    n = ctypes.c_size_t(0)
+    rc = L.mps_workspace_query(None, ctypes.byref(desc), ctypes.byref(n))
+    return rc, n.value, L.mps_last_error().decode()
+
+
+BAD_DESCRIPTORS = [
+    # (description, descriptor fields, expected status, text in the message)
+    ("d < 1", dict(d=0), lib.MPS_ERR_ARG, "dimensions"),
+    ("chi_l < 1", dict(chi_l=0), lib.MPS_ERR_ARG, "dimensions"),
+    ("chi_r < 1", dict(chi_r=-3), lib.MPS_ERR_ARG, "dimensions"),
+    ("unknown mode", dict(mode=3), lib.MPS_ERR_ARG, "mode"),
+    ("unknown precision", dict(prec=2), lib.MPS_ERR_ARG, "precision"),
+    ("plain with eta != chi_m", dict(mode=lib.PLAIN, eta=9), lib.MPS_ERR_ARG, "eta == chi_m"),
+    ("eta = 0", dict(eta=0), lib.MPS_ERR_ARG, "eta"),
+    ("eta > d chi", dict(eta=17), lib.MPS_ERR_ARG, "eta"),
+    ("CBE chi_max = 0", dict(chi_max=0), lib.MPS_ERR_ARG, "chi_max"),
+    ("negative svd_min", dict(svd_min=-1.0), lib.MPS_ERR_ARG, "svd_min"),
+    ("NaN svd_min", dict(svd_min=float("nan")), lib.MPS_ERR_ARG, "svd_min"),
+    ("sweeps > 16", dict(sweeps=17), lib.MPS_ERR_ARG, "sweeps"),
+    ("negative sweeps", dict(sweeps=-1), lib.MPS_ERR_ARG, "sweeps"),
+    ("d^2 > 160", dict(d=13, chi_l=1, chi_m=1, chi_r=1, eta=1), lib.MPS_ERR_CAPACITY, "d=13"),
+    ("d chi beyond the QR row limit", dict(d=5, chi_l=8200, chi_m=8200, chi_r=8200, eta=100, chi_max=100),
+     lib.MPS_ERR_CAPACITY, "too large"),
+    ("CBE eta > 2048", dict(d=4, chi_l=1024, chi_m=1024, chi_r=1024, eta=2049, chi_max=100),
+     lib.MPS_ERR_CAPACITY, "2048"),
+]
+
+
+@pytest.mark.parametrize("what,fields,code,text", BAD_DESCRIPTORS, ids=[b[0] for b in BAD_DESCRIPTORS])
+def test_descriptor_errors(what, fields, code, text):
+    """Every host-side argument / capacity check of the bond descriptor returns
+    its status and message before any device work (no context needed)."""
+    base = dict(d=4, chi_l=4, chi_m=4, chi_r=4, eta=6, chi_max=4, svd_min=1e-14, xi_is_diag=True,
+                mode=lib.CBE, prec=lib.MPS_C128, sweeps=1)
+    base.update(fields)
+    rc, _, msg = _ws_query(lib.bond_desc(**base))
+    assert rc == code, (what, rc, msg)
+    assert text in msg, (what, msg)
+
+
+def test_workspace_query_valid_and_monotone():
+    """Valid descriptors report a positive workspace that grows with chi."""
+    sizes = []
+    for chi in (16, 64, 256, 1024):
+        rc, n, _ = _ws_query(lib.bond_desc(5, chi, chi, chi, chi + -(-chi // 10), chi))
+        assert rc == lib.MPS_OK
+        sizes.append(n)
+    assert all(a < b for a, b in zip(sizes, sizes[1:])) and sizes[0] > 0
+    rc, n, _ = _ws_query(lib.bond_desc(5, 64, 64, 64, 64, 64, mode=lib.PLAIN))
+    assert rc == lib.MPS_OK and n > 0
+
+
+def test_null_pointer_errors():
+    """Null context / descriptor / outputs are argument errors, not crashes."""
+    L = lib.load()
+    assert L.mps_workspace_query(None, None, None) == lib.MPS_ERR_ARG
+    assert L.mps_bond_capacity(None) == lib.MPS_ERR_ARG
+    assert L.mps_sync(None, None) == lib.MPS_ERR_ARG
+    assert L.mps_zgemm(None, 1, 0, 0, 4, 4, 4, None, 4, None, 4, None, 4, 1.0, 0.0, None) == lib.MPS_ERR_ARG
+    assert L.mps_qr(None, 1, 4, 4, None, None, None) == lib.MPS_ERR_ARG
+    assert L.mps_heig(None, 4, 4, None, None, None, None) == lib.MPS_ERR_ARG
+    assert L.mps_measure(None, None, None, None, None, None, None, None, None) == lib.MPS_ERR_ARG
+    assert L.mps_sweep(None, None, 1, None, 1, 2, None, None, None) == lib.MPS_ERR_ARG
+    assert L.mps_state_chis(None, None) == lib.MPS_ERR_ARG
+    assert L.mps_profile_enable(None, 1, 10) == lib.MPS_ERR_ARG
+    out = np.zeros(8)
+    assert L.mps_clock_gate(0, 1.0, 0.1, 0.5, 0.5, out.ctypes.data_as(ctypes.c_void_p)) == lib.MPS_ERR_ARG
+    assert L.mps_clock_gate(2, 1.0, 0.1, 0.5, 0.5, None) == lib.MPS_ERR_ARG

@@ -313,3 +313,119 @@ def test_uniform_cell_bookkeeping():
     assert st["B"][1].shape[2] == st["B"][0].shape[0]
     # the two sites of a translation-invariant evolution carry the same <Z>
     assert abs(vals[0] - vals[1]) < 1e-8
+
+
+# ---------------------------------------------------------------- plain / grow bond matrices, entropies
+
+def _grow_then_plain(d, g, L, dt, n_grow, n_plain):
+    """TEBD from |0..0>: n_grow steps of full-eta GROW (exact, chi grows to the
+    saturated profile), then n_plain steps of PLAIN (eta = chi_M, exact once
+    chi_M = min(d chi_L, d chi_R) on every bond).  Both keep the dense bond
+    matrices Xi~ = L / |L| of Sec. II step (iii)."""
+    hs, gh, gf = _gates(d, g, L, True, dt)
+    st = mps.product_state(L, d)
+    for mode, n in ((bond.GROW, n_grow), (bond.PLAIN, n_plain)):
+        for _ in range(n):
+            mps.trotter_step(st, gh, gf, mode=mode, dchi_rule=lambda c: 10 ** 6, chi_max=None)
+    psi = ed.trotter_circuit(ed.product_vector(L, d), gh, gf, L, d, n_grow + n_plain)
+    return st, psi
+
+
+def test_plain_and_grow_bond_matrices_against_statevector():
+    """Plain and grow Xi~ = L/|L| (Sec. II (iii)): local <Z_m> from Xi^[m] B^[m]
+    (Fig. 1c) on every site equals the state-vector Trotter circuit, which
+    fixes the orientation of L (L, not L^T: the two share singular values but
+    give different Xi^dag Xi), and the carried state equals the circuit."""
+    d, g, L = 3, 2.0, 6
+    st, psi = _grow_then_plain(d, g, L, 0.05, 4, 3)
+    full = [min(d ** b, d ** (L - b)) for b in range(L + 1)]
+    assert [b.shape[0] for b in st["B"]] + [1] == full          # saturated profile
+    assert all(np.ndim(x) == 2 for x in st["Xi"][1:])           # dense L factors
+    v = mps.to_statevector(st)
+    assert abs(abs(np.vdot(v, psi)) - 1.0) < 1e-12
+    Z, _ = clock.clock_ops(d)
+    loc, norms = mps.site_expectation(st, Z)
+    assert np.allclose(norms, 1.0, atol=1e-12)
+    assert np.max(np.abs(loc - ed.site_expectations(psi, Z, L, d))) < 1e-11
+
+
+def test_bond_entropies_against_reduced_density_matrix():
+    """Entropies from the singular values of Xi (Sec. II, Fig. 4) equal
+    -Tr rho ln rho of the state vector's reduced density matrix at every cut,
+    with dense (grow / plain) and diagonal (CBE) bond matrices."""
+    d, g, L = 3, 2.0, 6
+    st, psi = _grow_then_plain(d, g, L, 0.1, 3, 2)
+    ent = mps.bond_entropies(st)
+    ref = [ed.cut_entropy(psi, m, L, d) for m in range(1, L)]
+    assert ent[0] == 0.0
+    assert np.max(np.abs(ent[1:] - ref)) < 1e-10
+    assert min(ref) > 0.05                                      # a non-trivial spectrum
+    hs, gh, gf = _gates(d, g, L, True, 0.1)
+    st = mps.product_state(L, d)
+    for _ in range(5):
+        mps.trotter_step(st, gh, gf, dchi_rule=lambda c: 10 ** 6, chi_max=10 ** 6)
+    psi = ed.trotter_circuit(ed.product_vector(L, d), gh, gf, L, d, 5)
+    ref = [ed.cut_entropy(psi, m, L, d) for m in range(1, L)]
+    assert np.max(np.abs(mps.bond_entropies(st)[1:] - ref)) < 1e-10
+
+
+def test_bond_entropy_closed_forms():
+    """Product state: 0.  Two Schmidt values (cos a, sin a): the binary entropy
+    -c^2 ln c^2 - s^2 ln s^2.  k equal values: ln k."""
+    st = mps.product_state(4, 3)
+    assert np.all(mps.bond_entropies(st) == 0.0)
+    a = 0.3
+    c2, s2 = np.cos(a) ** 2, np.sin(a) ** 2
+    st = dict(B=[None] * 3, Xi=[np.ones(1), np.array([np.cos(a), np.sin(a)]), np.full(5, 0.2 ** 0.5)], finite=True)
+    ent = mps.bond_entropies(st)
+    assert abs(ent[1] - (-c2 * np.log(c2) - s2 * np.log(s2))) < 1e-15
+    assert abs(ent[2] - np.log(5)) < 1e-15
+    dense = np.array([[np.cos(a), 0], [0.0, np.sin(a)]]) @ inputs.random_unitary(2, inputs.rng(1))
+    st["Xi"][1] = dense
+    assert abs(mps.bond_entropies(st)[1] - ent[1]) < 1e-14
+
+
+# ---------------------------------------------------------------- uniform two-site cell
+
+def _cell_run(d, g, dt, n, chi_max):
+    hs = clock.chain_hamiltonians(d, g, 2, finite=False)
+    gh = [clock.gate(h, dt / 2) for h in hs]
+    gf = [clock.gate(h, dt) for h in hs]
+    st = mps.product_state(2, d, finite=False)
+    Z, _ = clock.clock_ops(d)
+    zs, es = [], []
+    for _ in range(n):
+        mps.trotter_step(st, gh, gf, chi_max=chi_max, dchi_rule=lambda c: 10 ** 6)
+        zs.append(mps.site_expectation(st, Z)[0])
+        es.append(mps.bond_expectation(st, hs))
+    return np.array(zs), np.array(es)
+
+
+@pytest.mark.parametrize("d", [2, 3, 5])
+def test_uniform_cell_short_time_closed_form(d):
+    """P10 on the uniform cell: <Z(t)> = 1 - 2 g^2 (1 - cos 2pi/d) t^2 (d >= 3),
+    1 - 8 g^2 t^2 (d = 2), on both sites, up to O(t^4)."""
+    g, dt, n = 2.0, 0.0025, 4
+    zs, _ = _cell_run(d, g, dt, n, chi_max=64)
+    t = dt * n
+    c = 8 * g ** 2 if d == 2 else 2 * g ** 2 * (1 - np.cos(2 * np.pi / d))
+    assert np.max(np.abs(zs[-1].real - (1 - c * t * t))) < 50 * (g * t) ** 4
+
+
+def test_uniform_cell_matches_finite_chain_bulk():
+    """P17: the uniform two-site cell (bonds (A,B) even, (B,A) odd) follows the
+    centre of a long finite chain with the same even/odd Trotter sequence
+    (sites 20, 21 of L = 42) while the light cone has not reached the ends:
+    <Z> and the bond energies of both bond kinds agree."""
+    d, g, dt, n, L, chi_max = 3, 2.0, 0.05, 8, 42, 40
+    zc, ec = _cell_run(d, g, dt, n, chi_max)
+    hs, gh, gf = _gates(d, g, L, True, dt)
+    st = mps.product_state(L, d)
+    Z, _ = clock.clock_ops(d)
+    for k in range(n):
+        mps.trotter_step(st, gh, gf, chi_max=chi_max, dchi_rule=lambda c: 10 ** 6)
+        z = mps.site_expectation(st, Z)[0]
+        e = mps.bond_expectation(st, hs)
+        assert np.max(np.abs(z[20:22] - zc[k])) < 1e-8, k
+        assert np.max(np.abs(e[20:22] - ec[k])) < 1e-8, k
+    assert abs(zc[-1][0] - 1.0) > 0.3                            # the quench has moved <Z>
