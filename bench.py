@@ -2,22 +2,28 @@
 """Single-bond QR+CBE TEBD benchmark on one MI355X.
 
 Workload (the single-bond microbenchmark): a uniform two-site cell with d = 5,
-chi = 1024, A and B Gaussian right-isometric [chi, d, chi], random positive
-bond weights, the clock-model gate U = expm(-i 0.05 h_bond) (g = 2), and
-controlled bond expansion with eta = chi + ceil(chi/10) truncated back to
-chi~ = chi.  One step = one bond update (Sec. II/III of the paper), bonds
-alternating (A,B), (B,A); consecutive updates are dependent, so throughput is
-1 / latency.  Both precisions are timed: complex128 (FP64 throughout) and the
-mixed path (complex64 storage, FP32 matrix cores, FP64 panels / eig /
-re-orthogonalisation / normalisation).  `value` is the mixed path's rate.
+A and B Gaussian right-isometric [chi, d, chi], random positive bond weights,
+the clock-model gate U = expm(-i 0.05 h_bond) (g = 2), and controlled bond
+expansion with eta = chi + ceil(chi/10) truncated back to chi~ = chi.  One
+step = one bond update (Sec. II/III of the paper), bonds alternating (A,B),
+(B,A); consecutive updates are dependent, so throughput is 1 / latency.
 
-Prints one JSON line (see the keys below).  --gpus above 1 is refused: the
-benchmark runs on one GPU.
+Both precisions are timed at every chi of --chis: complex128 (FP64
+throughout, the paper's precision) and the mixed path (complex64 storage,
+FP32 matrix cores, FP64 panels / eig / re-orthogonalisation /
+normalisation).  `value` is the complex128 rate at the first chi (1024 by
+default); the mixed rate, its ratio to complex128 and both precisions'
+roofline objects are in `per_precision`, the other chis in `per_chi`.
+
+Prints one JSON line.  --gpus above 1 is refused: the benchmark runs on one
+GPU.
 """
 import argparse
+import hashlib
 import json
-import math
 import os
+import re
+import subprocess
 import sys
 import time
 
@@ -26,19 +32,34 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK = 8.0e12
 PEAK = {"c128": 78.6e12, "c64": 157.3e12}   # dense FP64 / FP32 matrix-core peaks (MI355X)
-# HBM bytes per launch of the mixed path's contraction GEMM (mean over its five
-# launches per update), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by the
-# same counters read for a plain 256 MiB copy (--copy-calibration); the
-# commands and raw figures are in profiles/contract_gemm_hbm_d5_chi1024_mixed.md.
-# Only valid for the kernel version those counters were taken on.
-CONTRACT_TRAFFIC_C64 = 1.3325e9
+KERNEL = {"c128": "contract_gemm_kernel<double, double, double>", "c64": "contract_gemm_kernel<float, float, float>"}
+GEMM_SOURCES = ["paper_2212_09782_amd/csrc/gemm.hip", "paper_2212_09782_amd/csrc/gemm.h",
+                "paper_2212_09782_amd/csrc/common.h"]
+# HBM bytes per launch of the contraction GEMM at d=5, chi=1024 (mean over the
+# five launches of an update), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled
+# by the same counters read for a plain 256 MiB copy (--copy-calibration); the
+# commands and raw figures are in profiles/contract_gemm_hbm_d5_chi1024.md.
+# Each figure holds only for the kernel sources it was counted on (sha256 of
+# GEMM_SOURCES): after a change to them the bench reports traffic null.
+TRAFFIC = {
+    "c64": (None, None),
+    "c128": (None, None),
+}
+
+
+def gemm_source_hash():
+    h = hashlib.sha256()
+    for p in GEMM_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def run_precision(lib, torch, prec, chi, d, steps, warmup, sweeps=1):
+    from paper_2212_09782_amd import inputs
     ctx = lib.Context(0)
-    A, B, lA, lB = inputs_cell(chi, d)
+    A, B, lA, lB = inputs.microbench_cell(chi, d, seed=0)
     U = lib.clock_gate(d, 2.0, 0.05)
     eta = chi + -(-chi // 10)
     cdt = torch.complex128 if prec == lib.MPS_C128 else torch.complex64
@@ -52,6 +73,7 @@ def run_precision(lib, torch, prec, chi, d, steps, warmup, sweeps=1):
     desc = lib.bond_desc(d, chi, chi, chi, eta, chi, 1e-14 if prec == lib.MPS_C128 else 1e-6, True, lib.CBE, prec,
                          sweeps)
     state = {"a": 0, "b": 0}
+    stream = torch.cuda.current_stream()
 
     def one(k):
         # even k: bond (A, B) with Xi = Lambda_A; odd k: bond (B, A) with Xi = Lambda_B
@@ -61,7 +83,7 @@ def run_precision(lib, torch, prec, chi, d, steps, warmup, sweeps=1):
         else:
             src_m, src_n, xi, new_xi = bufB[state["b"]], bufA[state["a"]], lam["B"], lam["A"]
             dst_m, dst_n = bufB[1 - state["b"]], bufA[1 - state["a"]]
-        lib.mps_bond_update(ctx, desc, xi, src_m, src_n, du, dst_m, new_xi, dst_n, chi_dev, eps_dev)
+        lib.mps_bond_update(ctx, desc, xi, src_m, src_n, du, dst_m, new_xi, dst_n, chi_dev, eps_dev, stream)
         state["a"], state["b"] = 1 - state["a"], 1 - state["b"]
 
     for k in range(warmup):
@@ -72,11 +94,12 @@ def run_precision(lib, torch, prec, chi, d, steps, warmup, sweeps=1):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        ev[k][0].record()
+        ev[k][0].record(stream)
         one(warmup + k)
-        ev[k][1].record()
+        ev[k][1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # HIP events the library recorded on `stream` around each contraction launch
     gemm_ms, gemm_flops, launches = ctx.profile_read()
     ctx.profile_enable(False)
     ctx.sync()
@@ -94,30 +117,77 @@ def run_precision(lib, torch, prec, chi, d, steps, warmup, sweeps=1):
     )
 
 
-def inputs_cell(chi, d):
-    from paper_2212_09782_amd import inputs
-    return inputs.microbench_cell(chi, d, seed=0)
+def roofline(r, key, traffic_ok):
+    achieved = r["gemm_flops"] / (r["gemm_ms"] * 1e-3) if r["gemm_ms"] > 0 else 0.0
+    tb = TRAFFIC[key][0] if traffic_ok.get(key) else None
+    return {
+        "kernel": KERNEL[key] + " (the 5 contraction GEMMs of each update)",
+        "bound": "mfma",
+        "achieved": round(achieved / 1e12, 3),
+        "peak": round(PEAK[key] / 1e12, 1),
+        "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK[key], 4),
+        "traffic": tb,
+        "avg_launch_us": round(1e3 * r["gemm_ms"] / max(1, r["gemm_launches"]), 2),
+        "flops_per_launch": round(r["gemm_flops"] / max(1, r["gemm_launches"])),
+    }
+
+
+def _cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        f = dict(re.findall(r"^([^:]+):\s*(.*)$", out, re.M))
+        model = f.get("Model name", "?")
+        phys = int(f.get("Core(s) per socket", "0")) * int(f.get("Socket(s)", "0"))
+        return model, phys or None, int(f.get("CPU(s)", "0")) or None
+    except Exception:
+        return "?", None, os.cpu_count()
 
 
 def cpu_baseline(chi, d, budget_s):
-    """The oracle (numpy, complex128) on this host's cores: a bounded sample of the same workload."""
+    """The oracle (numpy/LAPACK) on this host's cores: bounded samples of the same workload.
+
+    Main leg: complex128 at the benchmark's chi with every BLAS thread (the
+    figure in `value`).  Extra legs: the same update with complex64 inputs
+    (the oracle computes in the inputs' precision), and complex128 on one
+    thread at a quarter of the chi (a full-size update on one core takes tens
+    of seconds; the rate is also given scaled by chi^3 to the benchmark's chi).
+    """
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import bond as obond
-    from paper_2212_09782_amd import inputs
     from oracle import clock
-    A, B, lA, lB = inputs.microbench_cell(chi, d, seed=0)
-    U = clock.gate(clock.bond_hamiltonian(d, 2.0), 0.05)
-    eta = chi + -(-chi // 10)
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        obond.qr_bond_update(lA, A, B, U, mode=obond.CBE, eta=eta, chi_max=chi)
-        n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n / dt, "unit": "bond updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} QR+CBE update(s) at d={d} chi={chi} eta={eta}, complex128 numpy/LAPACK, {dt:.1f} s"}
+    from paper_2212_09782_amd import inputs
+
+    def leg(c, dtype, budget, min_n=1):
+        A, B, lA, lB = inputs.microbench_cell(c, d, seed=0)
+        U = clock.gate(clock.bond_hamiltonian(d, 2.0), 0.05)
+        if dtype == "c64":
+            A, B, U, lA = A.astype(np.complex64), B.astype(np.complex64), U.astype(np.complex64), lA.astype(np.float32)
+        eta = c + -(-c // 10)
+        n, t0 = 0, time.perf_counter()
+        while True:
+            obond.qr_bond_update(lA, A, B, U, mode=obond.CBE, eta=eta, chi_max=c)
+            n += 1
+            if n >= min_n and time.perf_counter() - t0 > budget:
+                break
+        return n, time.perf_counter() - t0, eta
+
+    threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    model, phys, logical = _cpu_model()
+    n, dt, eta = leg(chi, "c128", budget_s * 0.5)
+    out = {"value": n / dt, "unit": "bond updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n} QR+CBE update(s) at d={d} chi={chi} eta={eta}, complex128 numpy/LAPACK, "
+                     f"{threads} BLAS threads, {dt:.1f} s",
+           "cpu_model": model, "physical_cores": phys, "logical_cpus": logical}
+    n, dt, _ = leg(chi, "c64", budget_s * 0.3)
+    out["c64"] = {"value": n / dt, "threads": threads,
+                  "sample": f"{n} update(s) at chi={chi} with complex64 inputs, {dt:.1f} s"}
+    c1 = max(16, chi // 4)
+    with threadpool_limits(limits=1, user_api="blas"):
+        n, dt, _ = leg(c1, "c128", budget_s * 0.2)
+    out["one_thread"] = {"value": n / dt, "chi": c1, "value_scaled_to_chi": (n / dt) * (c1 / chi) ** 3,
+                         "sample": f"{n} complex128 update(s) at chi={c1} on 1 BLAS thread, {dt:.1f} s"}
+    return out
 
 
 def main():
@@ -125,10 +195,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--chi", type=int, default=1024)
+    ap.add_argument("--chis", default="1024,512,256", help="bond dimensions; the first is the headline")
+    ap.add_argument("--chi", type=int, default=None, help="one bond dimension only (overrides --chis)")
     ap.add_argument("--d", type=int, default=5)
     ap.add_argument("--prec", choices=["both", "c128", "mixed"], default="both")
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0: skip)")
+    ap.add_argument("--cpu-budget", type=float, default=24.0, help="seconds of oracle time (0: skip)")
     ap.add_argument("--sweeps", type=int, default=1, help="QR/LQ sweeps per update (1: the paper's single sweep)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB three times (reference run for the HBM byte counters)")
@@ -152,17 +223,31 @@ def main():
     lib.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
-    res = {}
-    if args.prec in ("both", "c128"):
-        res["c128"] = run_precision(lib, torch, lib.MPS_C128, args.chi, args.d, args.steps, args.warmup, args.sweeps)
-    if args.prec in ("both", "mixed"):
-        res["c64"] = run_precision(lib, torch, lib.MPS_MIXED_C64, args.chi, args.d, args.steps, args.warmup,
-                                   args.sweeps)
-    head = "c64" if "c64" in res else "c128"
+    chis = [args.chi] if args.chi else [int(c) for c in args.chis.split(",") if c.strip()]
+    src = gemm_source_hash()
+    traffic_ok = {k: (v[0] is not None and v[1] == src and args.d == 5 and chis[0] == 1024) for k, v in TRAFFIC.items()}
+    precs = [("c128", lib.MPS_C128)] * (args.prec in ("both", "c128")) + \
+            [("c64", lib.MPS_MIXED_C64)] * (args.prec in ("both", "mixed"))
+    per_chi = {}
+    for chi in chis:
+        res = {}
+        for key, p in precs:
+            print(f"# timing {key} d={args.d} chi={chi}: {args.warmup} warm-up + {args.steps} updates",
+                  file=sys.stderr, flush=True)
+            res[key] = run_precision(lib, torch, p, chi, args.d, args.steps, args.warmup, args.sweeps)
+            res[key]["roofline"] = roofline(res[key], key, traffic_ok if chi == chis[0] else {})
+        if "c128" in res and "c64" in res:
+            res["mixed_over_c128"] = res["c64"]["updates_per_s"] / res["c128"]["updates_per_s"]
+        per_chi[chi] = res
+    chi = chis[0]
+    res = per_chi[chi]
+    head = "c128" if "c128" in res else "c64"
     h = res[head]
-    achieved = h["gemm_flops"] / (h["gemm_ms"] * 1e-3) if h["gemm_ms"] > 0 else 0.0
+    eta = chi + -(-chi // 10)
+    rnd = lambda v: {k: (round(x, 6) if isinstance(x, float) else rnd(x) if isinstance(x, dict) else x)
+                     for k, x in v.items()}
     line = {
-        "metric": f"bond updates/s at d={args.d} chi={args.chi} (mixed vs FP64) + p50/p99 step latency",
+        "metric": f"bond updates/s at d={args.d} chi={chi} (mixed vs FP64) + p50/p99 step latency",
         "value": round(h["updates_per_s"], 4),
         "unit": "bond updates/s",
         "n_gpus": 1,
@@ -172,29 +257,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64" if head == "c64" else "c128",
+        "dtype": head,
         "data": "synthetic",
-        "config": {"workload": f"single-bond QR+CBE update, uniform two-site cell, d={args.d}, chi={args.chi}, "
-                               f"eta={args.chi + -(-args.chi // 10)}, chi~={args.chi}, clock gate g=2 dt=0.05"
+        "config": {"workload": f"single-bond QR+CBE update, uniform two-site cell, d={args.d}, chi={chi}, "
+                               f"eta={eta}, chi~={chi}, clock gate g=2 dt=0.05"
                                + (f", {args.sweeps} QR/LQ sweeps" if args.sweeps > 1 else ""),
-                   "d": args.d, "chi": args.chi, "eta": args.chi + -(-args.chi // 10), "sweeps": args.sweeps},
+                   "d": args.d, "chi": chi, "eta": eta, "sweeps": args.sweeps},
         "p50_ms": round(h["p50_ms"], 4),
         "p99_ms": round(h["p99_ms"], 4),
-        "per_precision": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                          for k, v in res.items()},
-        "roofline": {
-            "kernel": ("contract_gemm_kernel<float, float, float>" if head == "c64" else "contract_gemm_kernel<double, double, double>")
-                      + " (the 5 contraction GEMMs of each update)",
-            "bound": "mfma",
-            "achieved": round(achieved / 1e12, 3),
-            "peak": round(PEAK[head] / 1e12, 1),
-            "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK[head], 4),
-            "traffic": CONTRACT_TRAFFIC_C64 if head == "c64" else None,
-        },
+        "per_precision": {k: (rnd(v) if isinstance(v, dict) else round(v, 4)) for k, v in res.items()},
+        "roofline": h["roofline"],
+        "per_chi": {str(c): {k: {"updates_per_s": round(v["updates_per_s"], 3), "p50_ms": round(v["p50_ms"], 3),
+                                 "p99_ms": round(v["p99_ms"], 3), "contract_frac": v["roofline"]["frac"]}
+                             for k, v in r.items() if isinstance(v, dict)}
+                    for c, r in per_chi.items() if c != chi},
+        "gemm_source": src,
     }
     if args.cpu_budget > 0:
-        line["cpu_baseline"] = cpu_baseline(args.chi, args.d, args.cpu_budget)
+        print("# timing the CPU oracle", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(chi, args.d, args.cpu_budget)
     print(json.dumps(line), flush=True)
 
 

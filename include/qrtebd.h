@@ -71,7 +71,9 @@ typedef struct mps_ctx_s* mps_ctx;
  *                  right of n
  *  eta             dimension of the QR / LQ step: PLAIN requires
  *                  eta == chi_m; GROW and CBE require
- *                  1 <= eta <= min(d chi_l, d chi_r) (Sec. III: eta = chi + dchi)
+ *                  1 <= eta <= min(d chi_l, d chi_r) (Sec. III: eta = chi + dchi);
+ *                  CBE also needs eta <= 1536 (the eigensolver's limit,
+ *                  MPS_ERR_CAPACITY beyond)
  *  chi_max         CBE only: keep at most chi_max Schmidt values
  *  svd_min         CBE only: drop Schmidt values below svd_min (absolute;
  *                  the paper uses 1e-14); at least one value is kept
@@ -214,7 +216,7 @@ int mps_zgemm(mps_ctx ctx, int dt, int opA, int opB, int M, int N, int K, const 
 int mps_qr(mps_ctx ctx, int dt, int m, int n, void* A, void* Q, mps_stream stream);
 
 /* The k largest eigenpairs of the Hermitian n x n complex128 matrix G
- * (destroyed): lam (k doubles, descending) and E (n x k complex128, ld k,
+ * (destroyed; 1 <= k <= n <= 1536, MPS_ERR_CAPACITY for larger n): lam (k doubles, descending) and E (n x k complex128, ld k,
  * orthonormal columns).  The FP64 eigensolver of Sec. III step (iv). */
 int mps_heig(mps_ctx ctx, int n, int k, void* G, double* lam, void* E, mps_stream stream);
 

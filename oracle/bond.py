@@ -92,9 +92,12 @@ def qr_bond_update(xi, bm, bn, U, mode=CBE, eta=None, chi_max=None, svd_min=1e-1
 
     eig_backward (tests only): None, or (rng, c) to hand the eigensolver of
     step (iv) L^dag L + E instead of L^dag L, with E a random Hermitian matrix
-    of spectral norm c u |L^dag L|_2 (u = 2^-52): the backward error a stable
-    eigensolver is allowed.  Running the update with and without it measures
-    how far two correct FP64 implementations may drift apart.
+    of spectral norm c sqrt(n) u |L^dag L|_2 (u = 2^-52, n the order of
+    L^dag L): the backward error a stable eigensolver is allowed, with the
+    sqrt(n) growth that independent rounding errors of the n-term sums of a
+    Householder reduction typically show.  Running the update with and
+    without it measures how far two correct FP64 implementations may drift
+    apart.
 
     Returns a dict with
       bm, bn   new tensors [chi_L, d, chi~] and [chi~, d, chi_R]
@@ -143,7 +146,7 @@ def qr_bond_update(xi, bm, bn, U, mode=CBE, eta=None, chi_max=None, svd_min=1e-1
             n = G.shape[0]
             P = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
             P = (P + P.conj().T) / 2
-            G = G + P * (c * 2.0 ** -52 * np.linalg.norm(G, 2) / np.linalg.norm(P, 2))
+            G = G + P * (c * np.sqrt(n) * 2.0 ** -52 * np.linalg.norm(G, 2) / np.linalg.norm(P, 2))
         w, E = np.linalg.eigh(G)
         order = np.argsort(-w, kind="stable")
         w, E = w[order], E[:, order]

@@ -92,7 +92,8 @@ int check_desc(const mps_bond_desc* D) {
   if (D->d * D->d > 160) return set_error(MPS_ERR_CAPACITY, "d=%d too large (d^2 <= 160)", D->d);
   if (std::max(mL, mR) > kMaxQrRows)
     return set_error(MPS_ERR_CAPACITY, "d chi=%d too large", std::max(mL, mR));
-  if (D->mode == MPS_TRUNC_CBE && D->eta > 2048) return set_error(MPS_ERR_CAPACITY, "eta=%d > 2048", D->eta);
+  if (D->mode == MPS_TRUNC_CBE && D->eta > kEigMaxN)
+    return set_error(MPS_ERR_CAPACITY, "eta=%d > %d (CBE eigensolver limit)", D->eta, kEigMaxN);
   if (D->sweeps < 0 || D->sweeps > 16) return set_error(MPS_ERR_ARG, "sweeps=%d outside [0, 16]", D->sweeps);
   return 0;
 }
@@ -571,7 +572,7 @@ int mps_qr(mps_ctx c, int dt, int m, int n, void* A, void* Q, mps_stream stream)
 int mps_heig(mps_ctx c, int n, int k, void* G, double* lam, void* E, mps_stream stream) {
   if (!c || !G || !lam || !E) return set_error(MPS_ERR_ARG, "null argument");
   if (n < 1 || k < 1 || k > n) return set_error(MPS_ERR_ARG, "need 1 <= k <= n");
-  if (n > 2048) return set_error(MPS_ERR_CAPACITY, "n=%d > 2048", n);
+  if (n > kEigMaxN) return set_error(MPS_ERR_CAPACITY, "n=%d > %d", n, kEigMaxN);
   hipStream_t s = (hipStream_t)stream;
   int rc;
   if ((rc = ensure(&c->ws, &c->ws_bytes, eig_work_bytes(n), s))) return rc;

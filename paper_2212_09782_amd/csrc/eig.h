@@ -4,6 +4,11 @@
 
 namespace qrtebd {
 
+// Largest matrix the eigensolver takes: the cooperative tridiagonalisation
+// keeps every row in LDS (at most 150 KiB per block, one block per CU), so
+// ceil(n / floor(150 KiB / (16 n))) blocks must fit the 256 CUs.
+constexpr int kEigMaxN = 1536;
+
 struct EigWork {
   double* d;        // n   diagonal of the tridiagonal matrix
   double* e;        // n   off-diagonal (real, >= 0 up to sign)

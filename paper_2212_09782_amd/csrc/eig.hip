@@ -38,6 +38,9 @@ constexpr int kTriThreads = 512;    // threads of a tridiagonalisation block (tw
 constexpr int QMAX = kMaxN / kTriThreads;   // register slots per thread
 constexpr size_t kTriLds = 150 * 1024;
 constexpr int kTriRows = 8;           // rows per block at most (register partials of A v)
+static_assert(kEigMaxN <= kMaxN, "eigensolver limit above the register layout");
+static_assert((kEigMaxN + (int)(kTriLds / (16 * (size_t)kEigMaxN)) - 1) / (int)(kTriLds / (16 * (size_t)kEigMaxN)) <= 256,
+              "rows of the largest matrix do not fit one block per CU");
 
 __device__ inline c128 z0() { return mk<double>(0, 0); }
 
@@ -755,7 +758,7 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
   for (int j = 0; j < njobs; ++j) {
     const EigJob& J = jobs[j];
     if (J.n < 1 || J.kwant < 1 || J.kwant > J.n) return set_error(-1, "eig: bad sizes n=%d kwant=%d", J.n, J.kwant);
-    if (J.n > kMaxN) return set_error(-2, "eig: n=%d exceeds the supported %d", J.n, kMaxN);
+    if (J.n > kEigMaxN) return set_error(-2, "eig: n=%d exceeds the supported %d", J.n, kEigMaxN);
     if (J.n == 1) {
       hipLaunchKernelGGL(eig1_kernel, dim3(1), dim3(1), 0, s, J.G, J.lam, J.E);
       QT_HIP_CHECK(hipGetLastError());

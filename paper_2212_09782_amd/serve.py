@@ -54,9 +54,40 @@ class Request:
         return 2 * math.ceil(nb / 2) + nb // 2
 
 
+# Plain-launched QR panels use one block per CU on at most 64 CUs each; with
+# this many slots running panels at once they still fit the 256 CUs, so every
+# panel's blocks are co-resident (more slots could stall its grid barriers).
+MAX_SLOTS = 4
+
+
 def state_bytes(req):
     es = 16 if req.prec == 0 else 8
     return req.L * (req.chi_max * req.d * req.chi_max * es + req.chi_max * 8)
+
+
+def saturated_chis(req):
+    """Bond dimensions (L + 1 entries, bond left of each site) once chi has
+    grown to its cap: min(d^b, d^(L-b), chi_max) on a finite chain, chi_max
+    on the uniform cell."""
+    if not req.finite:
+        return [req.chi_max] * 3
+    out = [1]
+    for b in range(1, req.L):
+        out.append(int(min(req.d ** min(b, 30), req.d ** min(req.L - b, 30), req.chi_max)))
+    return out + [1]
+
+
+def layer_bonds(req, parity):
+    """(chi_l, chi_m, chi_r) of the bonds one layer of this request updates."""
+    ch = saturated_chis(req)
+    if not req.finite:
+        return [(ch[0], ch[1], ch[0])]
+    return [(ch[m], ch[m + 1], ch[m + 2]) for m in range(parity, req.L - 1, 2)]
+
+
+def eta_of(d, chi_l, chi_m, chi_r, dchi_min=100, dchi_frac=0.1):
+    """The sweep's eta rule: min(chi_m + max(dchi_min, ceil(dchi_frac chi_m)), d chi_l, d chi_r)."""
+    return min(chi_m + max(dchi_min, math.ceil(dchi_frac * chi_m)), d * chi_l, d * chi_r)
 
 
 class Executor:
@@ -71,14 +102,21 @@ class Executor:
         self.stream = torch.cuda.Stream(device=device)
         self.states = {}
 
-    def workspace_bytes(self, req):
-        lib = self.lib
-        eta = min(req.chi_max + max(100, math.ceil(0.1 * req.chi_max)), req.d * req.chi_max)
-        desc = lib.bond_desc(req.d, req.chi_max, req.chi_max, req.chi_max, eta, req.chi_max, prec=req.prec)
+    def bond_workspace_bytes(self, req, chi_l, chi_m, chi_r):
+        """mps_workspace_query of one bond of this request."""
         import ctypes
+        lib = self.lib
+        eta = eta_of(req.d, chi_l, chi_m, chi_r)
+        desc = lib.bond_desc(req.d, chi_l, chi_m, chi_r, eta, req.chi_max, prec=req.prec)
         n = ctypes.c_size_t()
         lib._check(lib.load().mps_workspace_query(self.ctx.h, ctypes.byref(desc), ctypes.byref(n)))
         return int(n.value)
+
+    def workspace_bytes(self, req):
+        """Workspace of this request's larger layer: mps_sweep carves one
+        region per bond of a layer, so a layer needs the sum over its bonds
+        (at the saturated chi profile)."""
+        return max(sum(self.bond_workspace_bytes(req, *b) for b in layer_bonds(req, p)) for p in (0, 1))
 
     def admit(self, req):
         lib, torch = self.lib, self.torch
@@ -93,14 +131,24 @@ class Executor:
         self.states[req.rid] = (st, gates, zz)
 
     def step(self, reqs):
-        """One Trotter step of every request in reqs as one mps_sweep call."""
+        """One Trotter step of every request in reqs: one mps_sweep call per
+        precision (the policy's svd_min depends on it; chi_max is each
+        state's own cap)."""
         lib = self.lib
-        sts = [self.states[r.rid][0] for r in reqs]
-        gts = [self.states[r.rid][1] for r in reqs]
-        pol = lib.sweep_policy(max(r.chi_max for r in reqs), 1e-14 if reqs[0].prec == 0 else 1e-6)
-        # one policy per call: requests of one batch share chi_max caps through their states
-        lib.mps_sweep(self.ctx, sts, gts, 1, 2, pol, stream=self.stream)
+        for prec in sorted({r.prec for r in reqs}):
+            group = [r for r in reqs if r.prec == prec]
+            sts = [self.states[r.rid][0] for r in group]
+            gts = [self.states[r.rid][1] for r in group]
+            pol = lib.sweep_policy(max(r.chi_max for r in group), 1e-14 if prec == 0 else 1e-6)
+            lib.mps_sweep(self.ctx, sts, gts, 1, 2, pol, stream=self.stream)
         self.stream.synchronize()
+        lib._check(lib.load().mps_sync(self.ctx.h, lib._stream(self.stream)))
+
+    def drop(self, req):
+        """Release a request's device state without measuring (after a failure)."""
+        ent = self.states.pop(req.rid, None)
+        if ent is not None:
+            ent[0].close()
 
     def finish(self, req):
         torch, lib = self.torch, self.lib
@@ -119,26 +167,34 @@ class Executor:
 
 
 class Engine:
-    """Continuous-batching scheduler over `nslots` executors and an HBM budget."""
+    """Continuous-batching scheduler over at most MAX_SLOTS executors and an HBM budget.
+
+    HBM accounting: every admitted request holds its state buffers; every
+    slot holds its context's workspace, which grows to the largest layer
+    workspace (sum over the layer's bonds of every request in the batch)
+    the slot has run and is kept while the slot lives.  A request is
+    admitted only if its state plus the growth of its slot's workspace
+    fits the budget.
+    """
 
     def __init__(self, executors, hbm_budget, max_batch=8, clock=time.perf_counter):
+        if not 1 <= len(executors) <= MAX_SLOTS:
+            raise ValueError(f"1 to {MAX_SLOTS} executors (slots) are supported, got {len(executors)}")
         self.execs = executors
         self.budget = hbm_budget
         self.max_batch = max_batch
         self.clock = clock
         self.lock = threading.Lock()
-        self.used = 0
+        self.used = 0              # states of admitted requests + every slot's workspace high-water mark
         self.peak_used = 0
         self.waiting = []          # (arrival, rid, req) heap of arrived, not yet admitted
         self.pending = []          # not yet arrived (sorted by arrival)
         self.batches = [[] for _ in executors]
+        self.ws_batch = [0 for _ in executors]   # layer workspace of the slot's current batch
+        self.ws_high = [0 for _ in executors]    # the slot context's workspace (grow-only)
         self.finished = []
+        self.errors = []
         self.t0 = None
-
-    def _cost(self, req, ex):
-        # resident state plus the largest bond's workspace (conservative: the
-        # slot's workspace is shared by its batch)
-        return state_bytes(req) + ex.workspace_bytes(req)
 
     def _try_admit(self, slot):
         """Move arrived requests into this slot's batch while budget and batch size allow."""
@@ -151,23 +207,52 @@ class Engine:
             joined = []
             while self.waiting and len(self.batches[slot]) + len(joined) < self.max_batch:
                 _, _, r = self.waiting[0]
-                c = self._cost(r, ex)
-                if self.used + c > self.budget:
-                    if self.used == 0:       # never admittable: reject rather than stall
+                sb, wb = state_bytes(r), ex.workspace_bytes(r)
+                grow = max(0, self.ws_batch[slot] + wb - self.ws_high[slot])
+                if self.used + sb + grow > self.budget:
+                    alone = sb + max(wb, max(self.ws_high))
+                    if alone > self.budget:   # never admittable: reject rather than stall
                         heapq.heappop(self.waiting)
                         r.result = {"rejected": True}
                         self.finished.append(r)
                         continue
                     break
                 heapq.heappop(self.waiting)
-                self.used += c
+                self.used += sb + grow
+                self.ws_high[slot] += grow
+                self.ws_batch[slot] += wb
                 self.peak_used = max(self.peak_used, self.used)
-                r._cost = c
+                r._state_bytes, r._ws_bytes = sb, wb
                 r.admitted_at = now
                 joined.append(r)
         for r in joined:
-            ex.admit(r)
+            try:
+                ex.admit(r)
+            except Exception as e:   # noqa: BLE001 - a failed request must not stop the engine
+                self._fail(slot, [r], e, admitted=False)
+                continue
             self.batches[slot].append(r)
+
+    def _release(self, slot, r):
+        with self.lock:
+            self.used -= r._state_bytes
+            self.ws_batch[slot] -= r._ws_bytes
+
+    def _fail(self, slot, reqs, err, admitted=True):
+        """Mark requests failed, free their state and budget, record the error."""
+        ex = self.execs[slot]
+        for r in reqs:
+            if admitted:
+                try:
+                    ex.drop(r)
+                except Exception:   # noqa: BLE001
+                    pass
+            r.result = {"failed": True, "error": f"{type(err).__name__}: {err}"}
+            r.done_at = self.clock() - self.t0
+            self._release(slot, r)
+            with self.lock:
+                self.finished.append(r)
+                self.errors.append((r.rid, str(err)))
 
     def _worker(self, slot):
         ex = self.execs[slot]
@@ -181,17 +266,26 @@ class Engine:
                     return
                 time.sleep(0.002)
                 continue
-            ex.step(batch)
+            try:
+                ex.step(batch)
+            except Exception as e:   # noqa: BLE001 - fail this batch, keep serving the others
+                self._fail(slot, batch, e)
+                self.batches[slot] = []
+                continue
             now = self.clock() - self.t0
             keep = []
             for r in batch:
                 r.step_times.append(now)
                 r.bond_updates += r.bonds_per_step()
                 if len(r.step_times) >= r.nsteps:
-                    ex.finish(r)
+                    try:
+                        ex.finish(r)
+                    except Exception as e:   # noqa: BLE001
+                        self._fail(slot, [r], e)
+                        continue
                     r.done_at = now
+                    self._release(slot, r)
                     with self.lock:
-                        self.used -= r._cost
                         self.finished.append(r)
                 else:
                     keep.append(r)
@@ -212,7 +306,7 @@ class Engine:
         lat = []
         total = 0
         for r in self.finished:
-            if r.result and r.result.get("rejected"):
+            if r.result and (r.result.get("rejected") or r.result.get("failed")):
                 continue
             prev = r.admitted_at
             for t in r.step_times:
@@ -223,6 +317,7 @@ class Engine:
         return {
             "requests": len(self.finished),
             "rejected": sum(1 for r in self.finished if r.result and r.result.get("rejected")),
+            "failed": sum(1 for r in self.finished if r.result and r.result.get("failed")),
             "makespan_s": makespan,
             "bond_updates": total,
             "bond_updates_per_s": total / makespan if makespan > 0 else 0.0,

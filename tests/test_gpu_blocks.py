@@ -139,14 +139,14 @@ def _herm(n, kind, r):
 
 HEIG = [(n, kind, n if n < 10 else (n * 3) // 4) for n in (1, 2, 3, 17, 64, 100, 257, 600)
         for kind in ("random", "gram", "degenerate")]
-HEIG += [(1127, "gram", 1024), (1127, "random", 1127), (2048, "gram", 2048), (2048, "degenerate", 1536)]
+HEIG += [(1127, "gram", 1024), (1127, "random", 1127), (1536, "gram", 1536), (1536, "degenerate", 1152)]
 
 
 @pytest.mark.parametrize("n,kind,k", HEIG, ids=[f"n{n}-{kind}-k{k}" for n, kind, k in HEIG])
 def test_heig(ctx, n, kind, k):
     """Eigenvalues against numpy's eigvalsh, eigenvectors by orthonormality and
     residual; n = 1127, k = 1024 is the eigen-decomposition of the headline
-    bond update, n = 2048 the largest eta the library accepts."""
+    bond update, n = 1536 the largest eta the library accepts."""
     print(f"heig n={n} kind={kind} k={k}", flush=True)
     r = inputs.rng(n + 11)
     G = _herm(n, kind, r)

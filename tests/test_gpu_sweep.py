@@ -13,9 +13,11 @@ return the exact decomposition of L^dag L + E with |E| ~ u |L^dag L|; in the
 Hastings form of the update such a perturbation moves later observables by
 far more than u (on config 1 about 2e-9 after 20 steps, with or without
 truncation).  Each run therefore also takes the oracle a second time with a
-random backward error of size u |L^dag L| in every eigen-decomposition
-(oracle option eig_backward), and where that measured sensitivity exceeds
-1e-11 the bound at that step becomes 10 x the sensitivity.  Where a chi_max
+random backward error of size sqrt(n) u |L^dag L| in every n x n
+eigen-decomposition (oracle option eig_backward; sqrt(n) is the usual growth
+of independent rounding errors over n-term sums), and where that measured
+sensitivity exceeds 1e-11 the bound at that step becomes 10 x the
+sensitivity.  Where a chi_max
 cut falls inside a near-degenerate pair (relative gap below 1e-6 in the
 oracle's spectrum) the kept subspace is not unique either: from that step on
 the bound also admits 10 x the cumulative discarded weight.
