@@ -132,6 +132,21 @@ int mps_bond_update(mps_ctx ctx, const mps_bond_desc* desc, const void* xi_m, co
                     const void* b_n, const void* u, void* b_m_out, void* xi_n_out, void* b_n_out,
                     int* chi_new_dev, double* trunc_err_dev, mps_stream stream);
 
+/* mps_bond_update without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, outputs and errors as
+ * mps_bond_update; the workspace is a fixed 128 MiB device array per GPU
+ * (allocated when the library is loaded, kept until the process ends), so
+ * the call makes no hipMalloc / hipFree.  Bonds whose workspace
+ * (mps_workspace_query) exceeds 128 MiB return MPS_ERR_CAPACITY (d = 5:
+ * chi up to about 256 with eta = chi + chi/10, either precision).  Every call
+ * on one GPU, from any context, shares that array: calls that overlap on one
+ * GPU (other streams, other threads) race and must be serialised by the
+ * caller.  Each call zeroes what it needs zeroed. */
+int mps_bond_update_noalloc(mps_ctx ctx, const mps_bond_desc* desc, const void* xi_m, const void* b_m,
+                            const void* b_n, const void* u, void* b_m_out, void* xi_n_out, void* b_n_out,
+                            int* chi_new_dev, double* trunc_err_dev, mps_stream stream);
+
 /* Two-site Trotter gate of the d-state clock model (Sec. IV):
  * U = expm(-i tau h), h = -(Z (x) Z^dag + h.c.) - g (wl (X+X^dag) (x) 1 +
  * wr 1 (x) (X+X^dag)), Z = diag(w^k), w = exp(2 pi i/d), X the cyclic shift.

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/qrtebd.h"
@@ -37,8 +38,42 @@ int set_hip_error(hipError_t e, const char* expr, const char* file, int line) {
 
 using namespace qrtebd;
 
+// Fixed workspace of mps_bond_update_noalloc: one copy per GPU, held until the
+// process ends.  Host code uses only the address hipGetSymbolAddress returns
+// for the current device (kept per device in g_scratch_dev); the array's name
+// itself is not a device address on the host.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Address of this device's scratch array; `device` must be current.
+int scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return set_error(MPS_ERR_ARG, "device %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return set_error(MPS_ERR_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", device,
+                       hipGetErrorString(e));
+    }
+    g_scratch_dev[device] = p;
+  }
+  *out = g_scratch_dev[device];
+  return 0;
+}
+
+}  // namespace
+
 struct mps_ctx_s {
   int device = 0;
+  void* scratch = nullptr;   // this device's scratch array (device address)
   void* ws = nullptr;
   size_t ws_bytes = 0;
   int* status = nullptr;     // device error word
@@ -158,6 +193,10 @@ int mps_ctx_create(int device, mps_ctx* out) {
   QT_HIP_CHECK(hipSetDevice(device));
   mps_ctx c = new mps_ctx_s();
   c->device = device;
+  if (int rc = scratch_address(device, &c->scratch)) {
+    delete c;
+    return rc;
+  }
   if (hipMalloc(&c->status, 256) != hipSuccess || hipMemset(c->status, 0, 256) != hipSuccess ||
       hipHostMalloc(&c->chi_host, 4096 * sizeof(int)) != hipSuccess ||
       hipHostMalloc(&c->eps_host, 64 * sizeof(double)) != hipSuccess) {
@@ -251,6 +290,24 @@ int mps_bond_update(mps_ctx c, const mps_bond_desc* D, const void* xi_m, const v
   if ((rc = ensure(&c->ws, &c->ws_bytes, bond_work_bytes(b), s))) return rc;
   return bond_update_run(b, c->ws, c->status, xi_m, b_m, b_n, (const c128*)u, b_m_out, xi_n_out, b_n_out,
                          chi_new_dev, trunc_err_dev, s, &c->timer, &c->qa);
+}
+
+int mps_bond_update_noalloc(mps_ctx c, const mps_bond_desc* D, const void* xi_m, const void* b_m,
+                            const void* b_n, const void* u, void* b_m_out, void* xi_n_out, void* b_n_out,
+                            int* chi_new_dev, double* trunc_err_dev, mps_stream stream) {
+  if (!c) return set_error(MPS_ERR_ARG, "null context");
+  int rc = check_desc(D);
+  if (rc) return rc;
+  if (!xi_m || !b_m || !b_n || !u || !b_m_out || !xi_n_out || !b_n_out || !chi_new_dev || !trunc_err_dev)
+    return set_error(MPS_ERR_ARG, "null tensor pointer");
+  const BondShape b = shape_of(D);
+  const size_t need = bond_work_bytes(b);
+  if (need > kScratchBytes)
+    return set_error(MPS_ERR_CAPACITY, "bond needs %zu bytes of workspace, the fixed scratch holds %zu", need,
+                     kScratchBytes);
+  if (!c->scratch) return set_error(MPS_ERR_STATE, "context has no scratch address");
+  return bond_update_run(b, c->scratch, c->status, xi_m, b_m, b_n, (const c128*)u, b_m_out, xi_n_out, b_n_out,
+                         chi_new_dev, trunc_err_dev, (hipStream_t)stream, &c->timer, &c->qa);
 }
 
 int mps_profile_enable(mps_ctx c, int on, int max_launches) {

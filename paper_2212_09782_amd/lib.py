@@ -22,7 +22,7 @@ EXPORTS = [
     "mps_ctx_create", "mps_ctx_destroy", "mps_last_error", "mps_sync", "mps_bond_capacity",
     "mps_workspace_query", "mps_bond_update", "mps_clock_gate", "mps_state_create",
     "mps_state_destroy", "mps_state_chis", "mps_sweep", "mps_measure", "mps_zgemm", "mps_qr",
-    "mps_heig", "mps_profile_enable", "mps_profile_read",
+    "mps_heig", "mps_profile_enable", "mps_profile_read", "mps_bond_update_noalloc",
 ]
 
 
@@ -60,6 +60,7 @@ def _declare(lib):
         "mps_bond_capacity": (I, [ctypes.POINTER(mps_bond_desc)]),
         "mps_workspace_query": (I, [P, ctypes.POINTER(mps_bond_desc), ctypes.POINTER(ctypes.c_size_t)]),
         "mps_bond_update": (I, [P, ctypes.POINTER(mps_bond_desc), P, P, P, P, P, P, P, P, P, P]),
+        "mps_bond_update_noalloc": (I, [P, ctypes.POINTER(mps_bond_desc), P, P, P, P, P, P, P, P, P, P]),
         "mps_clock_gate": (I, [I, D, D, D, D, P]),
         "mps_state_create": (I, [P, I, I, I, I, I, ctypes.POINTER(P), ctypes.POINTER(P),
                                  ctypes.POINTER(I), ctypes.POINTER(P)]),
@@ -166,6 +167,14 @@ def mps_bond_update(ctx, desc, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, ch
     _check(ctx.lib.mps_bond_update(ctx.h, ctypes.byref(desc), _ptr(xi_m), _ptr(b_m), _ptr(b_n), _ptr(u),
                                    _ptr(b_m_out), _ptr(xi_n_out), _ptr(b_n_out), _ptr(chi_new),
                                    _ptr(trunc_err), _stream(stream)))
+
+
+def mps_bond_update_noalloc(ctx, desc, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, chi_new, trunc_err,
+                            stream=None):
+    """Direct C-ABI call of the allocation-free variant (fixed per-GPU scratch)."""
+    _check(ctx.lib.mps_bond_update_noalloc(ctx.h, ctypes.byref(desc), _ptr(xi_m), _ptr(b_m), _ptr(b_n), _ptr(u),
+                                           _ptr(b_m_out), _ptr(xi_n_out), _ptr(b_n_out), _ptr(chi_new),
+                                           _ptr(trunc_err), _stream(stream)))
 
 
 def bond_update(ctx, desc, xi_m, b_m, b_n, u, stream=None):
