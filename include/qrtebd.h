@@ -181,6 +181,19 @@ typedef struct {
   int dchi_min;     /* eta = min(chi + max(dchi_min, ceil(dchi_frac*chi)), d chi_l, d chi_r) */
   double dchi_frac;
   int sweeps;       /* QR/LQ sweeps per bond update, as in mps_bond_desc (0 or 1: one) */
+  int exec;         /* 0: every layer reads the new chis back (one host
+                       synchronisation per layer); 1: speculative: while the
+                       chi profile is saturated (no bond update can raise any
+                       chi: chi_m == min(eta, chi_max) on every bond) up to
+                       `chunk` steps are issued with no host synchronisation,
+                       the device checks that every chi~ equals the planned
+                       one, and a chunk with a smaller chi~ is undone (state
+                       restored from a copy) and rerun layer by layer; 2: as 1,
+                       with each step captured once as a hipGraph (keyed by
+                       the chi profile, the buffers and the policy) and
+                       replayed.  Results are the same in all three modes.
+                       Appended field: zero keeps mode 0. */
+  int chunk;        /* steps per speculative chunk (0: 8) */
 } mps_sweep_policy;
 
 /* nsteps Trotter steps on every state.  gates[s] points to the device gates
@@ -191,6 +204,11 @@ typedef struct {
  * the summed truncation error is added to trunc_err_dev[s]. */
 int mps_sweep(mps_ctx ctx, mps_state* states, int nstates, const void* const* gates, int nsteps,
               int order, const mps_sweep_policy* policy, double* trunc_err_dev, mps_stream stream);
+
+/* Counters of mps_sweep since the context was created (6 entries): layers
+ * run with a chi read-back, host synchronisations, speculative chunks,
+ * chunks undone, step graphs captured, step graphs replayed. */
+int mps_sweep_stats(mps_ctx ctx, long long* out6);
 
 /* Observables from the isometric form (Fig. 1c):
  *  site_vals  [L][2] doubles: <op1> at every site from M = Xi^[m] B^[m],

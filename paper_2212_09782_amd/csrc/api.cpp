@@ -71,11 +71,31 @@ int scratch_address(int device, void** out) {
 
 }  // namespace
 
+struct SweepStats {
+  long long layers_eager = 0;   // layers run with a chi read-back
+  long long host_syncs = 0;     // host synchronisations inside mps_sweep
+  long long chunks = 0;         // speculative chunks
+  long long rollbacks = 0;      // speculative chunks undone
+  long long graph_captures = 0;
+  long long graph_replays = 0;
+};
+
+struct GraphEntry {
+  std::vector<long long> key;
+  hipGraphExec_t exec;
+};
+
 struct mps_ctx_s {
   int device = 0;
   void* scratch = nullptr;   // this device's scratch array (device address)
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  unsigned ws_gen = 0;       // bumped whenever ws is reallocated (captured graphs hold its address)
+  void* snap = nullptr;      // state copy of a speculative chunk
+  size_t snap_bytes = 0;
+  hipStream_t cap = nullptr; // stream the step graphs are captured on
+  std::vector<GraphEntry> graphs;
+  SweepStats stats;
   int* status = nullptr;     // device error word
   int* chi_host = nullptr;   // pinned scratch for chi read-back
   double* eps_host = nullptr;
@@ -109,6 +129,14 @@ int ensure(void** p, size_t* have, size_t need, hipStream_t s) {
   }
   *have = bytes;
   return 0;
+}
+
+int ensure_ws(mps_ctx c, size_t need, hipStream_t s) {
+  const void* before = c->ws;
+  const size_t have = c->ws_bytes;
+  int rc = ensure(&c->ws, &c->ws_bytes, need, s);
+  if (c->ws != before || c->ws_bytes != have) ++c->ws_gen;
+  return rc;
 }
 
 int check_desc(const mps_bond_desc* D) {
@@ -220,6 +248,7 @@ int mps_ctx_create(int device, mps_ctx* out) {
     }
   }
   if ((!c->qa.aux && hipStreamCreateWithFlags(&c->qa.aux, hipStreamNonBlocking) != hipSuccess) ||
+      hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->qa.ev_panel, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->qa.ev_trail, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
@@ -234,7 +263,11 @@ int mps_ctx_destroy(mps_ctx c) {
   if (!c) return MPS_OK;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
   if (c->ws) (void)hipFree(c->ws);
+  if (c->snap) (void)hipFree(c->snap);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   if (c->tmp_out) (void)hipFree(c->tmp_out);
   if (c->status) (void)hipFree(c->status);
   if (c->chi_host) (void)hipHostFree(c->chi_host);
@@ -287,7 +320,7 @@ int mps_bond_update(mps_ctx c, const mps_bond_desc* D, const void* xi_m, const v
     return set_error(MPS_ERR_ARG, "null tensor pointer");
   const BondShape b = shape_of(D);
   hipStream_t s = (hipStream_t)stream;
-  if ((rc = ensure(&c->ws, &c->ws_bytes, bond_work_bytes(b), s))) return rc;
+  if ((rc = ensure_ws(c, bond_work_bytes(b), s))) return rc;
   return bond_update_run(b, c->ws, c->status, xi_m, b_m, b_n, (const c128*)u, b_m_out, xi_n_out, b_n_out,
                          chi_new_dev, trunc_err_dev, s, &c->timer, &c->qa);
 }
@@ -445,28 +478,54 @@ std::vector<BondRef> layer_bonds(mps_state st, int parity, const void* gates, in
   return out;
 }
 
+constexpr int kMaxLayerBonds = 512;
+
 struct EpsMap {
   int n;
-  int state[512];
+  int state[kMaxLayerBonds];
 };
 
 __global__ void add_eps_batch_kernel(const double* eps, EpsMap map, double* acc) {
   for (int k = 0; k < map.n; ++k) acc[map.state[k]] += eps[k];
 }
 
-// One layer: every bond of every state in one batched update (per precision),
-// written in place into the state buffers, then one read-back of the new chis.
-int run_layer(mps_ctx c, std::vector<BondRef>& bonds, const mps_sweep_policy* pol, double* eps_acc_base,
-              const std::vector<int>& state_index, hipStream_t s) {
+// Speculative layers: the new chi of every bond must equal the one the host
+// planned the following layers with; a mismatch sets *flag.
+struct ChiExpect {
+  int n;
+  int chi[kMaxLayerBonds];
+};
+
+__global__ void check_chi_kernel(const int* chi_dev, ChiExpect e, int* flag) {
+  for (int k = threadIdx.x; k < e.n; k += blockDim.x)
+    if (chi_dev[k] != e.chi[k]) atomicOr(flag, 1);
+}
+
+// One layer: every bond of every state, shapes from the host copy of chi.
+struct LayerPlan {
+  std::vector<BondRef> bonds;
+  std::vector<int> state_index;
+  std::vector<BondShape> shapes;
+  std::vector<size_t> off;
+  size_t total = 0;
+};
+
+int plan_layer(mps_state* states, int nstates, const void* const* gates, int parity, int slot,
+               const mps_sweep_policy* pol, LayerPlan& lp) {
   int rc;
-  const int nb = (int)bonds.size();
-  if (nb == 0) return 0;
-  if (nb > 512) return set_error(MPS_ERR_CAPACITY, "a layer of %d bonds exceeds 512", nb);
-  std::vector<BondShape> shapes(nb);
-  std::vector<size_t> off(nb);
+  lp = LayerPlan{};
+  for (int si = 0; si < nstates; ++si)
+    for (auto& x : layer_bonds(states[si], parity, gates[si], slot)) {
+      lp.bonds.push_back(x);
+      lp.state_index.push_back(si);
+    }
+  const int nb = (int)lp.bonds.size();
+  if (nb > kMaxLayerBonds) return set_error(MPS_ERR_CAPACITY, "a layer of %d bonds exceeds %d", nb, kMaxLayerBonds);
+  lp.shapes.resize(nb);
+  lp.off.resize(nb);
   size_t total = ((size_t)nb * (sizeof(int) + sizeof(double)) + 4096 + 255) & ~size_t(255);
   for (int k = 0; k < nb; ++k) {
-    BondRef& br = bonds[k];
+    const BondRef& br = lp.bonds[k];
     mps_state st = br.st;
     const int d = st->d;
     const int chiL = st->chi[br.il], chiM = st->chi[br.im], chiR = st->chi[br.ir];
@@ -484,43 +543,204 @@ int run_layer(mps_ctx c, std::vector<BondRef>& bonds, const mps_sweep_policy* po
     D.prec = st->prec;
     D.sweeps = pol->sweeps;
     if ((rc = check_desc(&D))) return rc;
-    shapes[k] = shape_of(&D);
-    off[k] = total;
-    total += (bond_work_bytes(shapes[k]) + 255) & ~size_t(255);
+    lp.shapes[k] = shape_of(&D);
+    lp.off[k] = total;
+    total += (bond_work_bytes(lp.shapes[k]) + 255) & ~size_t(255);
   }
-  if ((rc = ensure(&c->ws, &c->ws_bytes, total, s))) return rc;
+  lp.total = total;
+  return 0;
+}
+
+// Issue a planned layer on s (no host synchronisation).  The workspace must
+// hold lp.total bytes.  expect: if set, the planned chi of the middle bond of
+// every update is checked on the device (speculative layers).
+int launch_layer(mps_ctx c, const LayerPlan& lp, double* eps_acc_base, hipStream_t s, bool helpers,
+                 int* spec_flag) {
+  int rc;
+  const int nb = (int)lp.bonds.size();
+  if (nb == 0) return 0;
   char* base = (char*)c->ws;
   int* chi_dev = (int*)base;
   double* eps_dev = (double*)(base + (((size_t)nb * sizeof(int) + 255) & ~size_t(255)));
   std::vector<BondCall> calls[2];
-  std::vector<int> order[2];
   for (int k = 0; k < nb; ++k) {
-    BondRef& br = bonds[k];
+    const BondRef& br = lp.bonds[k];
     mps_state st = br.st;
-    BondCall bc{shapes[k], base + off[k], c->status, st->Xi[br.m], st->B[br.m], st->B[br.n], br.gate,
+    BondCall bc{lp.shapes[k], base + lp.off[k], c->status, st->Xi[br.m], st->B[br.m], st->B[br.n], br.gate,
                 st->B[br.m], st->Xi[br.n], st->B[br.n], chi_dev + k, eps_dev + k};
     calls[st->prec].push_back(bc);
-    order[st->prec].push_back(k);
   }
   for (int p = 0; p < 2; ++p)
-    if (!calls[p].empty() && (rc = bond_update_batch(calls[p].data(), (int)calls[p].size(), s, &c->timer, &c->qa))) return rc;
+    if (!calls[p].empty() &&
+        (rc = bond_update_batch(calls[p].data(), (int)calls[p].size(), s, helpers ? &c->timer : nullptr,
+                                helpers ? &c->qa : nullptr)))
+      return rc;
   if (eps_acc_base) {
     EpsMap map{};
     map.n = nb;
-    for (int k = 0; k < nb; ++k) map.state[k] = state_index[k];
+    for (int k = 0; k < nb; ++k) map.state[k] = lp.state_index[k];
     hipLaunchKernelGGL(add_eps_batch_kernel, dim3(1), dim3(1), 0, s, eps_dev, map, eps_acc_base);
     QT_HIP_CHECK(hipGetLastError());
   }
-  QT_HIP_CHECK(hipMemcpyAsync(c->chi_host, chi_dev, (size_t)nb * sizeof(int), hipMemcpyDeviceToHost, s));
+  if (spec_flag) {
+    ChiExpect e{};
+    e.n = nb;
+    for (int k = 0; k < nb; ++k) e.chi[k] = lp.bonds[k].st->chi[lp.bonds[k].im];
+    hipLaunchKernelGGL(check_chi_kernel, dim3(1), dim3(256), 0, s, chi_dev, e, spec_flag);
+    QT_HIP_CHECK(hipGetLastError());
+  }
+  return 0;
+}
+
+// Eager layer: issue it, read the new chis back (one host synchronisation)
+// and update the host copies.
+int run_layer_sync(mps_ctx c, LayerPlan& lp, double* eps_acc_base, hipStream_t s) {
+  int rc;
+  const int nb = (int)lp.bonds.size();
+  if (nb == 0) return 0;
+  if ((rc = ensure_ws(c, lp.total, s))) return rc;
+  if ((rc = launch_layer(c, lp, eps_acc_base, s, true, nullptr))) return rc;
+  QT_HIP_CHECK(hipMemcpyAsync(c->chi_host, c->ws, (size_t)nb * sizeof(int), hipMemcpyDeviceToHost, s));
   QT_HIP_CHECK(hipStreamSynchronize(s));
+  c->stats.layers_eager++;
+  c->stats.host_syncs++;
   for (int k = 0; k < nb; ++k) {
-    BondRef& br = bonds[k];
+    BondRef& br = lp.bonds[k];
     const int chiN = c->chi_host[k];
-    if (chiN < 1 || chiN > shapes[k].cap())
-      return set_error(MPS_ERR_NUMERIC, "device returned chi=%d (cap %d)", chiN, shapes[k].cap());
+    if (chiN < 1 || chiN > lp.shapes[k].cap())
+      return set_error(MPS_ERR_NUMERIC, "device returned chi=%d (cap %d)", chiN, lp.shapes[k].cap());
     br.st->chi[br.im] = chiN;
     if (br.st->geometry == 1 && br.im == 0) br.st->chi[2] = chiN;
   }
+  return 0;
+}
+
+struct Layer {
+  int parity, slot;
+};
+
+std::vector<Layer> step_layers(int order) {
+  if (order == 2) return {{0, 0}, {1, 1}, {0, 0}};
+  return {{0, 1}, {1, 1}};
+}
+
+// A profile is saturated when no bond update can raise its middle chi:
+// chi_m == min(eta, chi_max) for every bond, with eta = min(chi_m + dchi,
+// d chi_l, d chi_r).  Then the only possible change is a smaller chi~ (fewer
+// Schmidt values above svd_min), which the device checks.
+bool saturated(mps_state* states, int nstates, const mps_sweep_policy* pol) {
+  for (int si = 0; si < nstates; ++si) {
+    mps_state st = states[si];
+    for (int parity = 0; parity < 2; ++parity)
+      for (const BondRef& br : layer_bonds(st, parity, nullptr, 0)) {
+        const int d = st->d, chiL = st->chi[br.il], chiM = st->chi[br.im], chiR = st->chi[br.ir];
+        const int dchi = std::max(pol->dchi_min, (int)std::ceil(pol->dchi_frac * chiM));
+        const int eta = std::min(std::min(chiM + dchi, d * chiL), d * chiR);
+        const int cap = std::max(1, std::min(eta, std::min(pol->chi_max, st->chi_cap)));
+        if (cap != chiM) return false;
+      }
+  }
+  return true;
+}
+
+int step_eager(mps_ctx c, mps_state* states, int nstates, const void* const* gates, int order,
+               const mps_sweep_policy* pol, double* eps_acc, hipStream_t s) {
+  int rc;
+  for (const Layer& ly : step_layers(order)) {
+    LayerPlan lp;
+    if ((rc = plan_layer(states, nstates, gates, ly.parity, ly.slot, pol, lp))) return rc;
+    if ((rc = run_layer_sync(c, lp, eps_acc, s))) return rc;
+  }
+  return 0;
+}
+
+// Live bytes of every site tensor and bond vector of every state, and of the
+// truncation-error accumulators: what a speculative chunk may overwrite.
+struct SnapItem {
+  void* dev;
+  size_t bytes;
+};
+
+std::vector<SnapItem> snapshot_items(mps_state* states, int nstates, double* eps_acc) {
+  std::vector<SnapItem> v;
+  for (int si = 0; si < nstates; ++si) {
+    mps_state st = states[si];
+    const size_t es = st->prec ? 8 : 16;
+    for (int m = 0; m < st->L; ++m) {
+      const int chiR = st->geometry == 0 ? st->chi[m + 1] : st->chi[1 - m];
+      v.push_back(SnapItem{st->B[m], (size_t)st->chi[m] * st->d * chiR * es});
+      v.push_back(SnapItem{st->Xi[m], (size_t)st->chi[m] * sizeof(double)});
+    }
+  }
+  if (eps_acc) v.push_back(SnapItem{eps_acc, (size_t)nstates * sizeof(double)});
+  return v;
+}
+
+int snapshot_copy(mps_ctx c, const std::vector<SnapItem>& items, bool save, hipStream_t s) {
+  size_t need = 0;
+  for (const SnapItem& it : items) need += (it.bytes + 255) & ~size_t(255);
+  int rc;
+  if (save && (rc = ensure(&c->snap, &c->snap_bytes, need, s))) return rc;
+  char* p = (char*)c->snap;
+  for (const SnapItem& it : items) {
+    if (save) QT_HIP_CHECK(hipMemcpyAsync(p, it.dev, it.bytes, hipMemcpyDeviceToDevice, s));
+    else QT_HIP_CHECK(hipMemcpyAsync(it.dev, p, it.bytes, hipMemcpyDeviceToDevice, s));
+    p += (it.bytes + 255) & ~size_t(255);
+  }
+  return 0;
+}
+
+// Cache key of a captured step: everything the captured launches depend on.
+std::vector<long long> graph_key(mps_ctx c, mps_state* states, int nstates, const void* const* gates, int order,
+                                 const mps_sweep_policy* pol, double* eps_acc) {
+  std::vector<long long> k;
+  k.push_back(nstates);
+  k.push_back(order);
+  k.push_back((long long)(uintptr_t)eps_acc);
+  k.push_back((long long)(uintptr_t)c->ws);
+  k.push_back((long long)c->ws_gen);
+  k.push_back(pol->chi_max);
+  k.push_back(pol->dchi_min);
+  k.push_back(pol->sweeps);
+  long long f;
+  std::memcpy(&f, &pol->dchi_frac, sizeof f);
+  k.push_back(f);
+  std::memcpy(&f, &pol->svd_min, sizeof f);
+  k.push_back(f);
+  for (int si = 0; si < nstates; ++si) {
+    mps_state st = states[si];
+    k.push_back((long long)(uintptr_t)st);
+    k.push_back((long long)(uintptr_t)gates[si]);
+    k.push_back(st->prec);
+    k.push_back(st->chi_cap);
+    for (int x : st->chi) k.push_back(x);
+    for (void* b : st->B) k.push_back((long long)(uintptr_t)b);
+    for (void* x : st->Xi) k.push_back((long long)(uintptr_t)x);
+  }
+  return k;
+}
+
+// One Trotter step of every state captured as a hipGraph on the context's
+// capture stream (QR look-ahead stream and event timing are left out of the
+// capture; cooperative kernels are launched plainly inside it).
+int capture_step(mps_ctx c, const std::vector<LayerPlan>& plans, double* eps_acc, int* spec_flag,
+                 hipGraphExec_t* out) {
+  hipStream_t cs = c->cap;
+  QT_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  int rc = 0;
+  for (const LayerPlan& lp : plans)
+    if ((rc = launch_layer(c, lp, eps_acc, cs, false, spec_flag))) break;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(cs, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return set_hip_error(e, "hipStreamEndCapture", __FILE__, __LINE__);
+  const hipError_t e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) return set_hip_error(e2, "hipGraphInstantiate", __FILE__, __LINE__);
+  c->stats.graph_captures++;
   return 0;
 }
 
@@ -532,25 +752,90 @@ int mps_sweep(mps_ctx c, mps_state* states, int nstates, const void* const* gate
   if (order != 1 && order != 2) return set_error(MPS_ERR_ARG, "order must be 1 or 2");
   if (pol->mode != MPS_TRUNC_CBE)
     return set_error(MPS_ERR_ARG, "mps_sweep keeps diagonal bond matrices: mode must be MPS_TRUNC_CBE");
+  if (pol->exec < 0 || pol->exec > 2) return set_error(MPS_ERR_ARG, "exec must be 0, 1 or 2");
+  for (int si = 0; si < nstates; ++si)
+    if (!states[si] || states[si]->ctx != c) return set_error(MPS_ERR_ARG, "state %d missing or of another context", si);
   hipStream_t s = (hipStream_t)stream;
-  struct Layer { int parity, slot; };
-  std::vector<Layer> layers;
-  if (order == 2) layers = {{0, 0}, {1, 1}, {0, 0}};
-  else layers = {{0, 1}, {1, 1}};
-  for (int step = 0; step < nsteps; ++step)
-    for (const Layer& ly : layers) {
-      std::vector<BondRef> bonds;
-      std::vector<int> idx;
-      for (int si = 0; si < nstates; ++si) {
-        auto b = layer_bonds(states[si], ly.parity, gates[si], ly.slot);
-        for (auto& x : b) {
-          bonds.push_back(x);
-          idx.push_back(si);
-        }
-      }
-      int rc = run_layer(c, bonds, pol, trunc_err_dev, idx, s);
-      if (rc) return rc;
+  int rc;
+  const int chunk_max = pol->chunk > 0 ? pol->chunk : 8;
+  int chunk = chunk_max;
+  int* spec_flag = c->status + 16;
+  int step = 0;
+  while (step < nsteps) {
+    if (pol->exec == 0 || !saturated(states, nstates, pol)) {
+      if ((rc = step_eager(c, states, nstates, gates, order, pol, trunc_err_dev, s))) return rc;
+      ++step;
+      continue;
     }
+    // Speculative chunk: the profile cannot grow, so every layer is planned
+    // with the current chis and issued without reading them back; the device
+    // flags any smaller chi~, and then the chunk is undone and run eagerly.
+    const int K = std::min(chunk, nsteps - step);
+    std::vector<LayerPlan> plans;
+    size_t need = 0;
+    for (const Layer& ly : step_layers(order)) {
+      plans.emplace_back();
+      if ((rc = plan_layer(states, nstates, gates, ly.parity, ly.slot, pol, plans.back()))) return rc;
+      need = std::max(need, plans.back().total);
+    }
+    if ((rc = ensure_ws(c, need, s))) return rc;
+    std::vector<SnapItem> items = snapshot_items(states, nstates, trunc_err_dev);
+    // the error word too: a mis-planned layer may latch errors the eager rerun would not
+    items.push_back(SnapItem{c->status, sizeof(int)});
+    if ((rc = snapshot_copy(c, items, true, s))) return rc;
+    if ((rc = fill_zero(spec_flag, sizeof(int), s))) return rc;
+    hipGraphExec_t gx = nullptr;
+    if (pol->exec == 2) {
+      const std::vector<long long> key = graph_key(c, states, nstates, gates, order, pol, trunc_err_dev);
+      for (auto& g : c->graphs)
+        if (g.key == key) gx = g.exec;
+      if (!gx) {
+        if ((rc = capture_step(c, plans, trunc_err_dev, spec_flag, &gx))) return rc;
+        if (c->graphs.size() >= 8) {
+          (void)hipGraphExecDestroy(c->graphs.front().exec);
+          c->graphs.erase(c->graphs.begin());
+        }
+        c->graphs.push_back(GraphEntry{key, gx});
+      }
+    }
+    for (int k = 0; k < K; ++k) {
+      if (gx) {
+        QT_HIP_CHECK(hipGraphLaunch(gx, s));
+        c->stats.graph_replays++;
+      } else {
+        for (const LayerPlan& lp : plans)
+          if ((rc = launch_layer(c, lp, trunc_err_dev, s, true, spec_flag))) return rc;
+      }
+    }
+    int flag = 0;
+    QT_HIP_CHECK(hipMemcpyAsync(&c->chi_host[kMaxLayerBonds], spec_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    QT_HIP_CHECK(hipStreamSynchronize(s));
+    flag = c->chi_host[kMaxLayerBonds];
+    c->stats.host_syncs++;
+    c->stats.chunks++;
+    if (!flag) {
+      step += K;
+      chunk = std::min(chunk_max, 2 * chunk);
+      continue;
+    }
+    // a bond kept fewer Schmidt values than planned: undo the chunk
+    if ((rc = snapshot_copy(c, items, false, s))) return rc;
+    c->stats.rollbacks++;
+    chunk = std::max(1, chunk / 2);
+    if ((rc = step_eager(c, states, nstates, gates, order, pol, trunc_err_dev, s))) return rc;
+    ++step;
+  }
+  return MPS_OK;
+}
+
+int mps_sweep_stats(mps_ctx c, long long* out) {
+  if (!c || !out) return set_error(MPS_ERR_ARG, "null argument");
+  out[0] = c->stats.layers_eager;
+  out[1] = c->stats.host_syncs;
+  out[2] = c->stats.chunks;
+  out[3] = c->stats.rollbacks;
+  out[4] = c->stats.graph_captures;
+  out[5] = c->stats.graph_replays;
   return MPS_OK;
 }
 
@@ -565,7 +850,7 @@ int mps_measure(mps_ctx c, mps_state st, const void* op1, const void* op2, doubl
     for (int m = 0; m < L; ++m) {
       const int chiL = st->chi[m], chiR = st->chi[m + 1];
       const size_t need = expect_part_doubles(chiL, chiR) * 8 + 256;
-      if ((rc = ensure(&c->ws, &c->ws_bytes, need, s))) return rc;
+      if ((rc = ensure_ws(c, need, s))) return rc;
       if ((rc = expect_run(st->B[m], st->prec, (const double*)st->Xi[m], chiL, d, chiR, (const c128*)op1,
                            (double*)c->ws, site_vals ? site_vals + 2 * m : nullptr, norms ? norms + m : nullptr, s)))
         return rc;
@@ -578,7 +863,7 @@ int mps_measure(mps_ctx c, mps_state st, const void* op1, const void* op2, doubl
       const int chiL = st->chi[m], chiM = st->chi[n], chiR = st->geometry == 0 ? st->chi[n + 1] : st->chi[m];
       const size_t tb = (size_t)chiL * d * d * chiR * es;
       const size_t need = ((tb + 255) & ~size_t(255)) + expect_part_doubles(chiL, chiR) * 8 + 256;
-      if ((rc = ensure(&c->ws, &c->ws_bytes, need, s))) return rc;
+      if ((rc = ensure_ws(c, need, s))) return rc;
       void* th = c->ws;
       double* part = (double*)((char*)c->ws + ((tb + 255) & ~size_t(255)));
       const int dt = st->prec ? DT_C64 : DT_C128;
@@ -619,7 +904,7 @@ int mps_qr(mps_ctx c, int dt, int m, int n, void* A, void* Q, mps_stream stream)
   const int es = dt == DT_C128 ? 16 : 8;
   hipStream_t s = (hipStream_t)stream;
   int rc;
-  if ((rc = ensure(&c->ws, &c->ws_bytes, qr_work_bytes(m, n, es, n), s))) return rc;
+  if ((rc = ensure_ws(c, qr_work_bytes(m, n, es, n), s))) return rc;
   QrWork w = qr_work_carve(c->ws, m, n, es, n, c->status);
   QrJob J{A, n, m, n, A, n, n, &w};
   if ((rc = qr_factor_batch(&J, 1, dt, s, &c->qa))) return rc;
@@ -632,7 +917,7 @@ int mps_heig(mps_ctx c, int n, int k, void* G, double* lam, void* E, mps_stream 
   if (n > kEigMaxN) return set_error(MPS_ERR_CAPACITY, "n=%d > %d", n, kEigMaxN);
   hipStream_t s = (hipStream_t)stream;
   int rc;
-  if ((rc = ensure(&c->ws, &c->ws_bytes, eig_work_bytes(n), s))) return rc;
+  if ((rc = ensure_ws(c, eig_work_bytes(n), s))) return rc;
   EigWork w = eig_work_carve(c->ws, n, c->status);
   return eig_herm_top((c128*)G, n, k, lam, (c128*)E, w, s);
 }

@@ -232,6 +232,14 @@ __device__ inline bool grid_barrier(GridSync gs, unsigned gen, int blk, int nblk
 // Words needed by grid_barrier for nblk blocks.
 inline size_t grid_sync_words(int nblk) { return 16 * (size_t)(nblk + 1); }
 
+// True while s records a graph.  Kernels with grid barriers are then launched
+// plainly (a captured sequence runs its kernels one after another, so a
+// launch of at most one block per CU has all its blocks resident).
+inline bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return s != nullptr && hipStreamIsCapturing(s, &st) == hipSuccess && st == hipStreamCaptureStatusActive;
+}
+
 }  // namespace qrtebd
 
 #define QT_HIP_CHECK(expr)                                                     \

@@ -779,9 +779,14 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
     size_t shmem = 0;
     auto flush = [&]() -> int {
       if (tb.nprob == 0) return 0;
-      void* args[] = {(void*)&tb};
-      QT_HIP_CHECK(hipLaunchCooperativeKernel((const void*)tridiag_kernel, dim3(used), dim3(kTriThreads), args,
-                                              (unsigned)shmem, s));
+      if (stream_capturing(s)) {
+        hipLaunchKernelGGL(tridiag_kernel, dim3(used), dim3(kTriThreads), shmem, s, tb);
+        QT_HIP_CHECK(hipGetLastError());
+      } else {
+        void* args[] = {(void*)&tb};
+        QT_HIP_CHECK(hipLaunchCooperativeKernel((const void*)tridiag_kernel, dim3(used), dim3(kTriThreads), args,
+                                                (unsigned)shmem, s));
+      }
       tb = TriBatch{};
       used = 0;
       shmem = 0;

@@ -815,7 +815,7 @@ int launch_panel(const PanelBatch& pb, int nblk_total, int max_rows, hipStream_t
                                      hipFuncAttributeMaxDynamicSharedMemorySize, kMaxPanelRows * LDP * sizeof(c128)));
     attr_set = true;
   }
-  if (nblk_total <= kPlainPanelBlocks) {
+  if (nblk_total <= kPlainPanelBlocks || stream_capturing(s)) {
     // A plain launch stays on the stream's own queue (a cooperative launch
     // goes through a separate device queue, two cross-queue hops per panel).
     // Its blocks are co-resident: one block per CU, and the CUs that the

@@ -22,7 +22,7 @@ EXPORTS = [
     "mps_ctx_create", "mps_ctx_destroy", "mps_last_error", "mps_sync", "mps_bond_capacity",
     "mps_workspace_query", "mps_bond_update", "mps_clock_gate", "mps_state_create",
     "mps_state_destroy", "mps_state_chis", "mps_sweep", "mps_measure", "mps_zgemm", "mps_qr",
-    "mps_heig", "mps_profile_enable", "mps_profile_read", "mps_bond_update_noalloc",
+    "mps_heig", "mps_profile_enable", "mps_profile_read", "mps_bond_update_noalloc", "mps_sweep_stats",
 ]
 
 
@@ -35,7 +35,11 @@ class mps_bond_desc(ctypes.Structure):
 
 class mps_sweep_policy(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("chi_max", ctypes.c_int), ("svd_min", ctypes.c_double),
-                ("dchi_min", ctypes.c_int), ("dchi_frac", ctypes.c_double), ("sweeps", ctypes.c_int)]
+                ("dchi_min", ctypes.c_int), ("dchi_frac", ctypes.c_double), ("sweeps", ctypes.c_int),
+                ("exec", ctypes.c_int), ("chunk", ctypes.c_int)]
+
+
+EXEC_EAGER, EXEC_SPECULATIVE, EXEC_GRAPH = 0, 1, 2
 
 
 class QrtebdError(RuntimeError):
@@ -69,6 +73,7 @@ def _declare(lib):
         "mps_sweep": (I, [P, ctypes.POINTER(P), I, ctypes.POINTER(P), I, I,
                           ctypes.POINTER(mps_sweep_policy), P, P]),
         "mps_measure": (I, [P, P, P, P, P, P, P, P, P]),
+        "mps_sweep_stats": (I, [P, ctypes.POINTER(ctypes.c_longlong)]),
         "mps_zgemm": (I, [P, I, I, I, I, I, I, P, LL, P, LL, P, LL, D, D, P]),
         "mps_qr": (I, [P, I, I, I, P, P, P]),
         "mps_heig": (I, [P, I, I, P, P, P, P]),
@@ -286,8 +291,19 @@ class State:
             pass
 
 
-def sweep_policy(chi_max, svd_min=1e-14, dchi_min=100, dchi_frac=0.1, mode=CBE, sweeps=1):
-    return mps_sweep_policy(mode, chi_max, svd_min, dchi_min, dchi_frac, sweeps)
+def sweep_policy(chi_max, svd_min=1e-14, dchi_min=100, dchi_frac=0.1, mode=CBE, sweeps=1, exec=EXEC_EAGER,
+                 chunk=0):
+    return mps_sweep_policy(mode, chi_max, svd_min, dchi_min, dchi_frac, sweeps, exec, chunk)
+
+
+SWEEP_STATS = ("layers_eager", "host_syncs", "chunks", "rollbacks", "graph_captures", "graph_replays")
+
+
+def sweep_stats(ctx):
+    """mps_sweep counters of the context (dict with the SWEEP_STATS keys)."""
+    out = (ctypes.c_longlong * 6)()
+    _check(ctx.lib.mps_sweep_stats(ctx.h, out))
+    return dict(zip(SWEEP_STATS, list(out)))
 
 
 def mps_sweep(ctx, states, gates, nsteps, order, policy, trunc_err=None, stream=None):

@@ -74,13 +74,15 @@ def run_oracle(d, g, L, finite, dt, nsteps, chi_max, dchi_min, dchi_frac, sweeps
     return ost, out
 
 
-def run_pair(ctx, d, g, L, finite, dt, nsteps, chi_max, dchi_min=100, dchi_frac=0.1, prec=lib.MPS_C128, sweeps=1):
+def run_pair(ctx, d, g, L, finite, dt, nsteps, chi_max, dchi_min=100, dchi_frac=0.1, prec=lib.MPS_C128, sweeps=1,
+             exec_mode=lib.EXEC_EAGER):
     """Run the GPU sweep and the oracle (plain and with eigensolver backward
     error) side by side; return per-step observables and the bound."""
     B, Xi = product_state_lists(L, d)
     st = lib.State(ctx, B, Xi, finite=finite, chi_cap=chi_max, prec=prec)
     gates = lib.chain_gates(d, g, L, finite, dt)
-    pol = lib.sweep_policy(chi_max, 1e-14 if prec == lib.MPS_C128 else 1e-6, dchi_min, dchi_frac, sweeps=sweeps)
+    pol = lib.sweep_policy(chi_max, 1e-14 if prec == lib.MPS_C128 else 1e-6, dchi_min, dchi_frac, sweeps=sweeps,
+                           exec=exec_mode)
     Z, _ = clock.clock_ops(d)
     zz = torch.from_numpy((Z + Z.conj().T).reshape(-1)).to("cuda")
     site = torch.zeros(2 * L, dtype=torch.float64, device="cuda")
@@ -156,6 +158,21 @@ def test_quench_two_sweeps(ctx):
     step dt = 0.2 (gates further from the identity), chi_max = 16, 6 steps."""
     st, ost, out = run_pair(ctx, 3, 2.0, 10, True, 0.2, 6, 16, dchi_min=4, sweeps=2)
     check_steps(out, "two sweeps")
+
+
+def test_config4_slice_graph(ctx):
+    """The batched finite chain of the Z_4 model (L = 128, g = 2, dt = 0.05)
+    quenched from |0...0> with chi_max = 16 (a profile small enough for the
+    oracle), 12 steps with step graphs: all 64 even bonds form one layer, then
+    the 63 odd ones; once the profile min(4^b, 4^(128-b), 16) is reached the
+    steps run as captured graphs.  <Z + Z^dag> per site against the oracle."""
+    before = lib.sweep_stats(ctx)
+    st, ost, out = run_pair(ctx, 4, 2.0, 128, True, 0.05, 12, 16, dchi_min=4, exec_mode=lib.EXEC_GRAPH)
+    after = lib.sweep_stats(ctx)
+    print({k: after[k] - before[k] for k in after}, flush=True)
+    check_steps(out, "config4 slice")
+    assert out[-1]["chis"] == [1] + inputs.chi_profile_finite(128, 4, 16) + [1]
+    assert after["graph_replays"] > before["graph_replays"]
 
 
 def test_bond_energy_measure(ctx):
