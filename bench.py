@@ -21,6 +21,7 @@ GPU.
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import subprocess
@@ -56,9 +57,9 @@ def gemm_source_hash():
     return h.hexdigest()[:16]
 
 
-def run_precision(lib, torch, prec, chi, d, steps, warmup, sweeps=1):
+def run_precision(lib, torch, prec, chi, d, steps, warmup, sweeps=1, autotune=None):
     from paper_2212_09782_amd import inputs
-    ctx = lib.Context(0)
+    ctx = lib.Context(0, autotune_cache=autotune)
     A, B, lA, lB = inputs.microbench_cell(chi, d, seed=0)
     U = lib.clock_gate(d, 2.0, 0.05)
     eta = chi + -(-chi // 10)
@@ -115,6 +116,58 @@ def run_precision(lib, torch, prec, chi, d, steps, warmup, sweeps=1):
         gemm_ms=gemm_ms, gemm_flops=gemm_flops, gemm_launches=launches,
         chi_new=chi_new, last_eps=eps,
     )
+
+
+def chain_contraction_flops(chis, d, chi_max, dchi_min, dchi_frac, order=2):
+    """Algorithmic flops (8 per complex MAC) of the five contractions of every
+    bond update of one Trotter step on a finite chain with this (saturated)
+    profile: C = B B, X = theta~ Y0^dag, Y^dag = theta~^dag Q, B~[n], B~[m]."""
+    L = len(chis) - 1
+    layers = [0, 1, 0] if order == 2 else [0, 1]
+    total = 0.0
+    for parity in layers:
+        for m in range(parity, L - 1, 2):
+            cl, cm, cr = chis[m], chis[m + 1], chis[m + 2]
+            ml, mr = d * cl, d * cr
+            eta = min(cm + max(dchi_min, math.ceil(dchi_frac * cm)), ml, mr)
+            k = min(eta, chi_max)
+            total += 8.0 * (ml * mr * cm + 2 * ml * eta * mr + k * mr * eta + ml * k * mr)
+    return total
+
+
+def run_chain(lib, torch, prec, L, d, chi_max, steps, warmup, exec_mode, autotune=None):
+    """Steady-state throughput of the batched finite chain: a random
+    right-isometric MPS at the saturated profile min(d^b, d^(L-b), chi_max)
+    (every bond matrix diagonal, random positive, unit norm), the Z_d clock
+    gates (g = 2, dt = 0.05), second-order steps: every even bond in one
+    layer, then every odd bond, then the even bonds again."""
+    from paper_2212_09782_amd import inputs
+    ctx = lib.Context(0, autotune_cache=autotune)
+    mps = inputs.random_finite_mps(L, d, chi_max, seed=4)
+    st = lib.State(ctx, mps["B"], mps["Xi"], finite=True, chi_cap=chi_max, prec=prec)
+    gates = lib.chain_gates(d, 2.0, L, True, 0.05)
+    svd_min = 1e-14 if prec == lib.MPS_C128 else 1e-6
+    pol = lib.sweep_policy(chi_max, svd_min, 0, 0.1, exec=exec_mode, chunk=max(1, steps))
+    stream = torch.cuda.current_stream()
+    lib.mps_sweep(ctx, [st], [gates], warmup, 2, pol, stream=stream)
+    ctx.sync()
+    before = lib.sweep_stats(ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lib.mps_sweep(ctx, [st], [gates], steps, 2, pol, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    after = lib.sweep_stats(ctx)
+    chis = st.chis()
+    st.close()
+    ctx.close()
+    updates = steps * (2 * ((L - 1 + 1) // 2) + (L - 1) // 2)
+    flops = steps * chain_contraction_flops(chis, d, chi_max, 0, 0.1)
+    return dict(updates_per_s=updates / (t1 - t0), ms_per_step=1e3 * (t1 - t0) / steps,
+                ms_per_layer=1e3 * (t1 - t0) / (3 * steps), contraction_tflops=flops / (t1 - t0) / 1e12,
+                chis_saturated=chis == [1] + inputs.chi_profile_finite(L, d, chi_max) + [1],
+                stats={k: after[k] - before[k] for k in after})
 
 
 def roofline(r, key, traffic_ok):
@@ -201,6 +254,14 @@ def main():
     ap.add_argument("--prec", choices=["both", "c128", "mixed"], default="both")
     ap.add_argument("--cpu-budget", type=float, default=24.0, help="seconds of oracle time (0: skip)")
     ap.add_argument("--sweeps", type=int, default=1, help="QR/LQ sweeps per update (1: the paper's single sweep)")
+    ap.add_argument("--workload", choices=["bond", "chain"], default="bond",
+                    help="bond: the single-bond microbenchmark (default); chain: the batched finite chain "
+                         "(L=128, Z_4, chi_max=512 by default), steady state, one JSON line of its own")
+    ap.add_argument("--L", type=int, default=128)
+    ap.add_argument("--chi-max", type=int, default=512)
+    ap.add_argument("--exec", type=int, default=2, help="chain: mps_sweep execution mode (0 eager, 1 speculative, 2 graph)")
+    ap.add_argument("--autotune", default=None,
+                    help="autotune cache file passed to mps_ctx_create (tuned during the warm-up)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB three times (reference run for the HBM byte counters)")
     args = ap.parse_args()
@@ -223,6 +284,27 @@ def main():
     lib.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.workload == "chain":
+        d = 4 if args.d == 5 else args.d
+        res = {}
+        for key, p in [("c128", lib.MPS_C128)] * (args.prec in ("both", "c128")) + \
+                      [("c64", lib.MPS_MIXED_C64)] * (args.prec in ("both", "mixed")):
+            print(f"# chain {key} L={args.L} d={d} chi_max={args.chi_max}", file=sys.stderr, flush=True)
+            res[key] = run_chain(lib, torch, p, args.L, d, args.chi_max, args.steps, args.warmup, args.exec,
+                                 args.autotune)
+        head = "c64" if "c64" in res else "c128"
+        h = res[head]
+        print(json.dumps({
+            "metric": f"bond updates/s, batched finite chain L={args.L} d={d} chi_max={args.chi_max}",
+            "value": round(h["updates_per_s"], 3), "unit": "bond updates/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(h["ms_per_step"], 3), "higher_is_better": True,
+            "dtype": head, "data": "synthetic",
+            "config": {"workload": f"finite chain L={args.L}, Z_{d} clock gates g=2 dt=0.05, random right-isometric "
+                                   f"MPS at the saturated profile min({d}^b, {d}^(L-b), {args.chi_max}), CBE "
+                                   f"eta = chi + ceil(chi/10), second-order steps, exec mode {args.exec}"},
+            "per_precision": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                              for k, v in res.items()}}), flush=True)
+        return
     chis = [args.chi] if args.chi else [int(c) for c in args.chis.split(",") if c.strip()]
     src = gemm_source_hash()
     traffic_ok = {k: (v[0] is not None and v[1] == src and args.d == 5 and chis[0] == 1024) for k, v in TRAFFIC.items()}
@@ -234,7 +316,7 @@ def main():
         for key, p in precs:
             print(f"# timing {key} d={args.d} chi={chi}: {args.warmup} warm-up + {args.steps} updates",
                   file=sys.stderr, flush=True)
-            res[key] = run_precision(lib, torch, p, chi, args.d, args.steps, args.warmup, args.sweeps)
+            res[key] = run_precision(lib, torch, p, chi, args.d, args.steps, args.warmup, args.sweeps, args.autotune)
             res[key]["roofline"] = roofline(res[key], key, traffic_ok if chi == chis[0] else {})
         if "c128" in res and "c64" in res:
             res["mixed_over_c128"] = res["c64"]["updates_per_s"] / res["c128"]["updates_per_s"]

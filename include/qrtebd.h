@@ -97,8 +97,18 @@ typedef struct {
 } mps_bond_desc;
 
 /* Create / destroy a context on HIP device `device`.  Workspace grows on
- * demand and is kept until destruction. */
-int mps_ctx_create(int device, mps_ctx* out);
+ * demand and is kept until destruction.
+ * autotune_cache: NULL (or "") keeps the default launch shapes.  Otherwise
+ * the path of a text file of tuned launch shapes (QR panel blocks, rows per
+ * block of the tridiagonalisation) per workload, read at creation (a missing
+ * file is an empty cache) and appended to: the first mps_bond_update of a
+ * bond shape, and the first speculative chunk of an mps_sweep step shape,
+ * that the cache does not hold times each candidate on the workload itself
+ * (a sweep step is undone after each trial) and keeps the fastest.  Several
+ * contexts may share a file; results depend on the shapes chosen only at
+ * rounding level.  The precision is not a context property: every bond
+ * descriptor and state carries its own, so one context serves both. */
+int mps_ctx_create(int device, const char* autotune_cache, mps_ctx* out);
 int mps_ctx_destroy(mps_ctx ctx);
 
 /* Thread-local text of the last error. */
@@ -205,10 +215,11 @@ typedef struct {
 int mps_sweep(mps_ctx ctx, mps_state* states, int nstates, const void* const* gates, int nsteps,
               int order, const mps_sweep_policy* policy, double* trunc_err_dev, mps_stream stream);
 
-/* Counters of mps_sweep since the context was created (6 entries): layers
- * run with a chi read-back, host synchronisations, speculative chunks,
- * chunks undone, step graphs captured, step graphs replayed. */
-int mps_sweep_stats(mps_ctx ctx, long long* out6);
+/* Counters of the context since its creation (8 entries): layers run with a
+ * chi read-back, host synchronisations inside mps_sweep, speculative chunks,
+ * chunks undone, step graphs captured, step graphs replayed, autotuner trial
+ * runs, workloads whose launch shapes came from the autotune cache. */
+int mps_sweep_stats(mps_ctx ctx, long long* out8);
 
 /* Observables from the isometric form (Fig. 1c):
  *  site_vals  [L][2] doubles: <op1> at every site from M = Xi^[m] B^[m],

@@ -9,7 +9,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <mutex>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "../../include/qrtebd.h"
@@ -28,6 +32,9 @@ int set_error(int code, const char* fmt, ...) {
   va_end(ap);
   return code;
 }
+
+static thread_local TuneParams g_tune;
+TuneParams& tune_params() { return g_tune; }
 
 int set_hip_error(hipError_t e, const char* expr, const char* file, int line) {
   snprintf(g_err, sizeof g_err, "HIP error %s (%d) in %s at %s:%d", hipGetErrorString(e), (int)e, expr, file, line);
@@ -78,6 +85,8 @@ struct SweepStats {
   long long rollbacks = 0;      // speculative chunks undone
   long long graph_captures = 0;
   long long graph_replays = 0;
+  long long tune_trials = 0;    // timed trial runs of the autotuner
+  long long tune_hits = 0;      // workloads whose shapes came from the tuning table
 };
 
 struct GraphEntry {
@@ -96,6 +105,10 @@ struct mps_ctx_s {
   hipStream_t cap = nullptr; // stream the step graphs are captured on
   std::vector<GraphEntry> graphs;
   SweepStats stats;
+  // autotuning: launch shapes per workload key, kept in a text file
+  bool tune_on = false;
+  std::string tune_path;
+  std::map<std::string, TuneParams> tune_table;
   int* status = nullptr;     // device error word
   int* chi_host = nullptr;   // pinned scratch for chi read-back
   double* eps_host = nullptr;
@@ -171,6 +184,60 @@ BondShape shape_of(const mps_bond_desc* D) {
 }
 
 
+// ---- autotuner: candidate launch shapes, timed on the workload itself
+const TuneParams kTuneCandidates[] = {{64, 8}, {48, 8}, {32, 8}, {64, 16}, {48, 16}, {32, 16}};
+
+int tune_load(mps_ctx c) {
+  std::ifstream f(c->tune_path);
+  if (!f) return 0;   // no cache yet
+  std::string line;
+  while (std::getline(f, line)) {
+    if (line.empty() || line[0] == '#') continue;
+    std::istringstream is(line);
+    std::string key;
+    TuneParams t;
+    double ms = 0;
+    if (!(is >> key >> t.panel_blocks >> t.tri_rows >> ms)) continue;
+    if (t.panel_blocks < 1 || t.panel_blocks > 64 || (t.tri_rows != 8 && t.tri_rows != 16)) continue;
+    c->tune_table[key] = t;
+  }
+  return 0;
+}
+
+void tune_store(mps_ctx c, const std::string& key, const TuneParams& t, double ms) {
+  c->tune_table[key] = t;
+  std::ofstream f(c->tune_path, std::ios::app);
+  if (!f) return;   // an unwritable cache only loses the persistence
+  f.seekp(0, std::ios::end);
+  if (f.tellp() == 0) f << "# qrtebd autotune cache: key panel_blocks tri_rows best_ms\n";
+  f << key << ' ' << t.panel_blocks << ' ' << t.tri_rows << ' ' << ms << '\n';
+}
+
+std::string bond_tune_key(const BondShape& b) {
+  std::ostringstream k;
+  k << "bond:" << b.prec << ':' << b.mode << ':' << b.d << ':' << b.chi_l << ':' << b.chi_m << ':' << b.chi_r << ':'
+    << b.eta << ':' << b.chi_max << ':' << b.sweeps << ':' << b.xi_is_diag;
+  return k.str();
+}
+
+// Time one candidate: `run` issues the work on s; returns milliseconds.
+template <typename F>
+int tune_time(hipStream_t s, F run, double* ms) {
+  hipEvent_t e0, e1;
+  QT_HIP_CHECK(hipEventCreate(&e0));
+  QT_HIP_CHECK(hipEventCreate(&e1));
+  QT_HIP_CHECK(hipEventRecord(e0, s));
+  int rc = run();
+  QT_HIP_CHECK(hipEventRecord(e1, s));
+  QT_HIP_CHECK(hipEventSynchronize(e1));
+  float f = 0;
+  QT_HIP_CHECK(hipEventElapsedTime(&f, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = f;
+  return rc;
+}
+
 using cd = std::complex<double>;
 
 // expm by scaling and squaring of a Taylor series (n x n, row-major).
@@ -215,7 +282,7 @@ extern "C" {
 
 const char* mps_last_error(void) { return g_err; }
 
-int mps_ctx_create(int device, mps_ctx* out) {
+int mps_ctx_create(int device, const char* autotune_cache, mps_ctx* out) {
   if (!out) return set_error(MPS_ERR_ARG, "null output");
   *out = nullptr;
   QT_HIP_CHECK(hipSetDevice(device));
@@ -254,6 +321,11 @@ int mps_ctx_create(int device, mps_ctx* out) {
     (void)hipGetLastError();
     mps_ctx_destroy(c);
     return set_error(MPS_ERR_HIP, "context stream creation failed");
+  }
+  if (autotune_cache && autotune_cache[0]) {
+    c->tune_on = true;
+    c->tune_path = autotune_cache;
+    tune_load(c);
   }
   *out = c;
   return MPS_OK;
@@ -321,8 +393,43 @@ int mps_bond_update(mps_ctx c, const mps_bond_desc* D, const void* xi_m, const v
   const BondShape b = shape_of(D);
   hipStream_t s = (hipStream_t)stream;
   if ((rc = ensure_ws(c, bond_work_bytes(b), s))) return rc;
-  return bond_update_run(b, c->ws, c->status, xi_m, b_m, b_n, (const c128*)u, b_m_out, xi_n_out, b_n_out,
-                         chi_new_dev, trunc_err_dev, s, &c->timer, &c->qa);
+  auto run = [&]() {
+    return bond_update_run(b, c->ws, c->status, xi_m, b_m, b_n, (const c128*)u, b_m_out, xi_n_out, b_n_out,
+                           chi_new_dev, trunc_err_dev, s, &c->timer, &c->qa);
+  };
+  g_tune = TuneParams{};
+  if (c->tune_on) {
+    const std::string key = bond_tune_key(b);
+    auto it = c->tune_table.find(key);
+    if (it != c->tune_table.end()) {
+      g_tune = it->second;
+      c->stats.tune_hits++;
+    } else {
+      // inputs are read only and outputs do not alias them: every candidate
+      // runs the whole update on the real data, the best one runs last
+      TuneParams best{};
+      double best_ms = 1e300;
+      const int saved_timer = c->timer.on;
+      c->timer.on = 0;
+      for (const TuneParams& t : kTuneCandidates) {
+        g_tune = t;
+        double ms = 0;
+        if ((rc = tune_time(s, run, &ms))) {
+          c->timer.on = saved_timer;
+          return rc;
+        }
+        c->stats.tune_trials++;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = t;
+        }
+      }
+      c->timer.on = saved_timer;
+      tune_store(c, key, best, best_ms);
+      g_tune = best;
+    }
+  }
+  return run();
 }
 
 int mps_bond_update_noalloc(mps_ctx c, const mps_bond_desc* D, const void* xi_m, const void* b_m,
@@ -339,6 +446,8 @@ int mps_bond_update_noalloc(mps_ctx c, const mps_bond_desc* D, const void* xi_m,
     return set_error(MPS_ERR_CAPACITY, "bond needs %zu bytes of workspace, the fixed scratch holds %zu", need,
                      kScratchBytes);
   if (!c->scratch) return set_error(MPS_ERR_STATE, "context has no scratch address");
+  auto it = c->tune_table.find(bond_tune_key(b));
+  g_tune = it != c->tune_table.end() ? it->second : TuneParams{};
   return bond_update_run(b, c->scratch, c->status, xi_m, b_m, b_n, (const c128*)u, b_m_out, xi_n_out, b_n_out,
                          chi_new_dev, trunc_err_dev, (hipStream_t)stream, &c->timer, &c->qa);
 }
@@ -646,6 +755,7 @@ bool saturated(mps_state* states, int nstates, const mps_sweep_policy* pol) {
 int step_eager(mps_ctx c, mps_state* states, int nstates, const void* const* gates, int order,
                const mps_sweep_policy* pol, double* eps_acc, hipStream_t s) {
   int rc;
+  g_tune = TuneParams{};   // a growing profile changes shape every step: default launch shapes
   for (const Layer& ly : step_layers(order)) {
     LayerPlan lp;
     if ((rc = plan_layer(states, nstates, gates, ly.parity, ly.slot, pol, lp))) return rc;
@@ -690,6 +800,28 @@ int snapshot_copy(mps_ctx c, const std::vector<SnapItem>& items, bool save, hipS
   return 0;
 }
 
+// Tuning key of a step: the shapes of every bond of its layers.
+std::string sweep_tune_key(const std::vector<LayerPlan>& plans) {
+  unsigned long long h = 1469598103934665603ull;   // FNV-1a over the shape fields
+  int nb = 0, chimax = 0, precs = 0;
+  auto mix = [&](long long v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (unsigned long long)((v >> (8 * i)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  for (const LayerPlan& lp : plans)
+    for (const BondShape& b : lp.shapes) {
+      mix(b.d); mix(b.chi_l); mix(b.chi_m); mix(b.chi_r); mix(b.eta); mix(b.chi_max); mix(b.prec); mix(b.sweeps);
+      ++nb;
+      chimax = std::max(chimax, b.chi_m);
+      precs |= 1 << b.prec;
+    }
+  std::ostringstream k;
+  k << "sweep:" << precs << ':' << nb << ':' << chimax << ':' << std::hex << h;
+  return k.str();
+}
+
 // Cache key of a captured step: everything the captured launches depend on.
 std::vector<long long> graph_key(mps_ctx c, mps_state* states, int nstates, const void* const* gates, int order,
                                  const mps_sweep_policy* pol, double* eps_acc) {
@@ -702,6 +834,8 @@ std::vector<long long> graph_key(mps_ctx c, mps_state* states, int nstates, cons
   k.push_back(pol->chi_max);
   k.push_back(pol->dchi_min);
   k.push_back(pol->sweeps);
+  k.push_back(g_tune.panel_blocks);
+  k.push_back(g_tune.tri_rows);
   long long f;
   std::memcpy(&f, &pol->dchi_frac, sizeof f);
   k.push_back(f);
@@ -783,6 +917,37 @@ int mps_sweep(mps_ctx c, mps_state* states, int nstates, const void* const* gate
     // the error word too: a mis-planned layer may latch errors the eager rerun would not
     items.push_back(SnapItem{c->status, sizeof(int)});
     if ((rc = snapshot_copy(c, items, true, s))) return rc;
+    g_tune = TuneParams{};
+    if (c->tune_on) {
+      const std::string key = sweep_tune_key(plans);
+      auto it = c->tune_table.find(key);
+      if (it != c->tune_table.end()) {
+        g_tune = it->second;
+        c->stats.tune_hits++;
+      } else {
+        // time one step per candidate, each from the saved state
+        TuneParams best{};
+        double best_ms = 1e300;
+        for (const TuneParams& t : kTuneCandidates) {
+          g_tune = t;
+          double ms = 0;
+          auto run = [&]() {
+            for (const LayerPlan& lp : plans)
+              if (int r = launch_layer(c, lp, trunc_err_dev, s, false, nullptr)) return r;
+            return 0;
+          };
+          if ((rc = tune_time(s, run, &ms))) return rc;
+          if ((rc = snapshot_copy(c, items, false, s))) return rc;
+          c->stats.tune_trials++;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+          }
+        }
+        tune_store(c, key, best, best_ms);
+        g_tune = best;
+      }
+    }
     if ((rc = fill_zero(spec_flag, sizeof(int), s))) return rc;
     hipGraphExec_t gx = nullptr;
     if (pol->exec == 2) {
@@ -836,6 +1001,8 @@ int mps_sweep_stats(mps_ctx c, long long* out) {
   out[3] = c->stats.rollbacks;
   out[4] = c->stats.graph_captures;
   out[5] = c->stats.graph_replays;
+  out[6] = c->stats.tune_trials;
+  out[7] = c->stats.tune_hits;
   return MPS_OK;
 }
 
@@ -906,6 +1073,7 @@ int mps_qr(mps_ctx c, int dt, int m, int n, void* A, void* Q, mps_stream stream)
   int rc;
   if ((rc = ensure_ws(c, qr_work_bytes(m, n, es, n), s))) return rc;
   QrWork w = qr_work_carve(c->ws, m, n, es, n, c->status);
+  g_tune = TuneParams{};
   QrJob J{A, n, m, n, A, n, n, &w};
   if ((rc = qr_factor_batch(&J, 1, dt, s, &c->qa))) return rc;
   return qr_form_q(Q, n, m, n, dt, w, s);
@@ -919,6 +1087,7 @@ int mps_heig(mps_ctx c, int n, int k, void* G, double* lam, void* E, mps_stream 
   int rc;
   if ((rc = ensure_ws(c, eig_work_bytes(n), s))) return rc;
   EigWork w = eig_work_carve(c->ws, n, c->status);
+  g_tune = TuneParams{};
   return eig_herm_top((c128*)G, n, k, lam, (c128*)E, w, s);
 }
 

@@ -232,6 +232,20 @@ __device__ inline bool grid_barrier(GridSync gs, unsigned gen, int blk, int nblk
 // Words needed by grid_barrier for nblk blocks.
 inline size_t grid_sync_words(int nblk) { return 16 * (size_t)(nblk + 1); }
 
+// Launch shapes chosen per workload by the autotuner (the context's tuning
+// table); the bond-update entry points set them for the calling thread
+// before issuing kernels.
+//  panel_blocks  target number of blocks of a QR panel (rows per block =
+//                ceil(m / panel_blocks), a multiple of 16); at most 64
+//  tri_rows      rows of the matrix per block of the tridiagonalisation (8 or
+//                16, as LDS allows): more rows, fewer blocks per matrix, more
+//                matrices per launch
+struct TuneParams {
+  int panel_blocks = 64;
+  int tri_rows = 8;
+};
+TuneParams& tune_params();   // the calling thread's current parameters
+
 // True while s records a graph.  Kernels with grid barriers are then launched
 // plainly (a captured sequence runs its kernels one after another, so a
 // launch of at most one block per CU has all its blocks resident).

@@ -37,7 +37,8 @@ constexpr int kMaxN = 2048;         // largest matrix
 constexpr int kTriThreads = 512;    // threads of a tridiagonalisation block (two waves per SIMD)
 constexpr int QMAX = kMaxN / kTriThreads;   // register slots per thread
 constexpr size_t kTriLds = 150 * 1024;
-constexpr int kTriRows = 8;           // rows per block at most (register partials of A v)
+constexpr int kTriChunk = 8;          // rows per pass of register partials of A v
+constexpr int kTriRows = 16;          // rows per block at most (two passes)
 static_assert(kEigMaxN <= kMaxN, "eigensolver limit above the register layout");
 static_assert((kEigMaxN + (int)(kTriLds / (16 * (size_t)kEigMaxN)) - 1) / (int)(kTriLds / (16 * (size_t)kEigMaxN)) <= 256,
               "rows of the largest matrix do not fit one block per CU");
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriBatch batch) {
   extern __shared__ c128 rows[];  // rows_loc x n, local row r = global row blk + r * P
   __shared__ double scratch[2][kTriThreads / 64];   // alternating buffers of the block sums
   __shared__ c128 cscr[2][kTriThreads / 64];
-  __shared__ double wred[kTriThreads / 64][16];
+  __shared__ double wred[2][kTriThreads / 64][16];   // alternating by row chunk
   __shared__ c128 vloc[2][kTriRows], wloc[kTriRows];
   __shared__ c128 scal[4];
   __shared__ int flag;
@@ -191,28 +192,37 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriBatch batch) {
     }
   };
 
-  // p = tau A v over the own rows i > kk from the partial sums acc[2r], acc[2r+1]
-  // of this thread; publishes p, this block's p^H v (slot sl) and returns.
-  auto publish_p = [&](double (&acc)[16], int kk, int sl, int vb) {
+  // p = tau A v over the own rows c0 .. c0+7 (i > kk) from the partial sums
+  // acc[2(r-c0)], acc[2(r-c0)+1] of this thread: publishes those p and adds
+  // their p^H v to `part` (wave 0); the last chunk publishes this block's
+  // p^H v (slot sl).  Chunks alternate wred buffers, so one block barrier
+  // per chunk suffices.
+  c128 part = z0();
+  auto publish_p = [&](double (&acc)[16], int kk, int sl, int vb, int c0) {
+    const int cb = (c0 / kTriChunk) & 1;
     const double ws = wave_sum16(acc);   // lane l: wave total of acc[l >> 2]
-    if ((lane & 3) == 0) wred[wid][lane >> 2] = ws;
+    if ((lane & 3) == 0) wred[cb][wid][lane >> 2] = ws;
     __syncthreads();
     if (wid == 0) {
-      c128 part = z0();
-      if (lane < RL) {
-        const int r = lane, gi = blk + r * P;
+      if (c0 == 0) part = z0();
+      if (lane < kTriChunk && c0 + lane < RL) {
+        const int r = c0 + lane, gi = blk + r * P;
         c128 s = z0();
 #pragma unroll
-        for (int g = 0; g < kTriThreads / 64; ++g) s = cadd(s, mk<double>(wred[g][2 * r], wred[g][2 * r + 1]));
+        for (int g = 0; g < kTriThreads / 64; ++g)
+          s = cadd(s, mk<double>(wred[cb][g][2 * lane], wred[cb][g][2 * lane + 1]));
         if (gi > kk && gi < n) {
           const c128 pv = cmul(tau, s);
           pub_store(a.pbuf + (long long)sl * n + gi, pv);
-          part = cmulc(pv, vloc[vb][r]);
+          part = cadd(part, cmulc(pv, vloc[vb][r]));
         }
       }
-      part.re = wave_sum(part.re);
-      part.im = wave_sum(part.im);
-      if (lane == 0) pub_store(a.red + (long long)sl * P + blk, part);
+      if (c0 + kTriChunk >= RL) {
+        c128 t = part;
+        t.re = wave_sum(t.re);
+        t.im = wave_sum(t.im);
+        if (lane == 0) pub_store(a.red + (long long)sl * P + blk, t);
+      }
     }
   };
 
@@ -220,26 +230,29 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriBatch batch) {
   int vb = 0;
   if (n > 1) {
     reflector(0, vb);
-    double acc[16];
+    for (int c0 = 0; c0 < RL; c0 += kTriChunk) {
+      double acc[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+      for (int i = 0; i < 16; ++i) acc[i] = 0.0;
 #pragma unroll
-    for (int r = 0; r < kTriRows; ++r) {
-      if (r < RL) {
-        const int gi = blk + r * P;
-        if (gi > 0 && gi < n) {
-          c128 s = z0();
+      for (int rr = 0; rr < kTriChunk; ++rr) {
+        const int r = c0 + rr;
+        if (r < RL) {
+          const int gi = blk + r * P;
+          if (gi > 0 && gi < n) {
+            c128 s = z0();
 #pragma unroll
-          for (int q = 0; q < QMAX; ++q) {
-            const int j = tid + kTriThreads * q;
-            if (j > 0 && j < n) s = cadd(s, cmul(rows[r * n + j], v[q]));
+            for (int q = 0; q < QMAX; ++q) {
+              const int j = tid + kTriThreads * q;
+              if (j > 0 && j < n) s = cadd(s, cmul(rows[r * n + j], v[q]));
+            }
+            acc[2 * rr] = s.re;
+            acc[2 * rr + 1] = s.im;
           }
-          acc[2 * r] = s.re;
-          acc[2 * r + 1] = s.im;
         }
       }
+      publish_p(acc, 0, 0, vb, c0);
     }
-    publish_p(acc, 0, 0, vb);
     if (!grid_barrier(gs, 1u, blk, P, &flag)) return;
   }
 
@@ -279,34 +292,37 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(TriBatch batch) {
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) vk[q] = v[q];
     reflector(k + 1, vb ^ 1);   // ends with v = v_{k+1}; its block sum orders the LDS writes above
-    // ---- one pass over the own rows i > k+1: rank-2 update of step k and
-    // the partial sums of A v_{k+1} for step k+1
-    double acc[16];
+    // ---- one pass over the own rows i > k+1 (chunks of kTriChunk rows):
+    // rank-2 update of step k and the partial sums of A v_{k+1} for step k+1
+    vb ^= 1;
+    for (int c0 = 0; c0 < RL; c0 += kTriChunk) {
+      double acc[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+      for (int i = 0; i < 16; ++i) acc[i] = 0.0;
 #pragma unroll
-    for (int r = 0; r < kTriRows; ++r) {
-      if (r < RL) {
-        const int gi = blk + r * P;
-        if (gi > k + 1 && gi < n) {
-          const c128 vi = vloc[vb][r], wi = wloc[r];
-          c128 s = z0();
+      for (int rr = 0; rr < kTriChunk; ++rr) {
+        const int r = c0 + rr;
+        if (r < RL) {
+          const int gi = blk + r * P;
+          if (gi > k + 1 && gi < n) {
+            const c128 vi = vloc[vb ^ 1][r], wi = wloc[r];
+            c128 s = z0();
 #pragma unroll
-          for (int q = 0; q < QMAX; ++q) {
-            const int j = tid + kTriThreads * q;
-            if (j > k && j < n) {
-              const c128 x = rank2_sub(rows[r * n + j], vi, w[q], wi, vk[q]);
-              rows[r * n + j] = x;
-              s = cadd(s, cmul(x, v[q]));
+            for (int q = 0; q < QMAX; ++q) {
+              const int j = tid + kTriThreads * q;
+              if (j > k && j < n) {
+                const c128 x = rank2_sub(rows[r * n + j], vi, w[q], wi, vk[q]);
+                rows[r * n + j] = x;
+                s = cadd(s, cmul(x, v[q]));
+              }
             }
+            acc[2 * rr] = s.re;
+            acc[2 * rr + 1] = s.im;
           }
-          acc[2 * r] = s.re;
-          acc[2 * r + 1] = s.im;
         }
       }
+      publish_p(acc, k + 1, slot ^ 1, vb, c0);   // its block barrier orders the row writes above
     }
-    vb ^= 1;
-    publish_p(acc, k + 1, slot ^ 1, vb);   // its block barrier orders the row writes above
     // row k+2, final for step k+1, from its owner
     if ((k + 2) % P == blk) {
       const int r = (k + 2) / P;
@@ -704,9 +720,11 @@ __global__ void eig1_kernel(const c128* G, double* lam, c128* E) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Rows per block: the tuned count (8 or 16), as LDS allows.
 int tri_rows_loc(int n) {
   const int rl = (int)(kTriLds / (16 * (size_t)n));
-  return std::max(1, std::min(std::min(n, kTriRows), rl));
+  const int want = std::max(1, std::min(kTriRows, tune_params().tri_rows));
+  return std::max(1, std::min(std::min(n, want), rl));
 }
 
 }  // namespace

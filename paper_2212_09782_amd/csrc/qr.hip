@@ -791,18 +791,22 @@ __global__ void set_identity_kernel(cpx<S>* Q, long long ldq, int m, int n) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Rows per block of a panel with mp rows: about 64 blocks (rows a multiple
-// of 16, at least 32; at most kMaxPanelRows, which fits the slab in LDS).
-int panel_rows(int mp) {
-  int r = (mp + 63) / 64;
+// Rows per block of a panel with mp rows for about `target` blocks (rows a
+// multiple of 16, at least 32; at most kMaxPanelRows, which fits the slab in
+// LDS).  target <= 64.
+int panel_rows_for(int mp, int target) {
+  target = std::max(1, std::min(64, target));
+  int r = (mp + target - 1) / target;
   r = (r + 15) / 16 * 16;
   return std::min(kMaxPanelRows, std::max(32, r));
 }
+int panel_rows(int mp) { return panel_rows_for(mp, tune_params().panel_blocks); }
 
-// Most blocks any panel of an m-row factorisation uses.
+// Most blocks any panel of an m-row factorisation uses (for any tuned target:
+// 64 blocks gives the fewest rows per block).
 int panel_blocks_max(int m) {
   int mx = 1;
-  for (int mp = m; mp > 0; mp -= NB) mx = std::max(mx, (mp + panel_rows(mp) - 1) / panel_rows(mp));
+  for (int mp = m; mp > 0; mp -= NB) mx = std::max(mx, (mp + panel_rows_for(mp, 64) - 1) / panel_rows_for(mp, 64));
   return mx;
 }
 

@@ -57,7 +57,7 @@ LL = ctypes.c_longlong
 
 def _declare(lib):
     sig = {
-        "mps_ctx_create": (I, [I, ctypes.POINTER(P)]),
+        "mps_ctx_create": (I, [I, ctypes.c_char_p, ctypes.POINTER(P)]),
         "mps_ctx_destroy": (I, [P]),
         "mps_last_error": (ctypes.c_char_p, []),
         "mps_sync": (I, [P, P]),
@@ -121,10 +121,11 @@ def _ptr(t):
 class Context:
     """Owns an mps_ctx (device workspace of the library)."""
 
-    def __init__(self, device=0):
+    def __init__(self, device=0, autotune_cache=None):
         self.lib = load()
         h = P()
-        _check(self.lib.mps_ctx_create(device, ctypes.byref(h)))
+        path = os.fsencode(autotune_cache) if autotune_cache else None
+        _check(self.lib.mps_ctx_create(device, path, ctypes.byref(h)))
         self.h = h
 
     def close(self):
@@ -296,12 +297,13 @@ def sweep_policy(chi_max, svd_min=1e-14, dchi_min=100, dchi_frac=0.1, mode=CBE, 
     return mps_sweep_policy(mode, chi_max, svd_min, dchi_min, dchi_frac, sweeps, exec, chunk)
 
 
-SWEEP_STATS = ("layers_eager", "host_syncs", "chunks", "rollbacks", "graph_captures", "graph_replays")
+SWEEP_STATS = ("layers_eager", "host_syncs", "chunks", "rollbacks", "graph_captures", "graph_replays",
+               "tune_trials", "tune_hits")
 
 
 def sweep_stats(ctx):
-    """mps_sweep counters of the context (dict with the SWEEP_STATS keys)."""
-    out = (ctypes.c_longlong * 6)()
+    """Counters of the context (dict with the SWEEP_STATS keys)."""
+    out = (ctypes.c_longlong * 8)()
     _check(ctx.lib.mps_sweep_stats(ctx.h, out))
     return dict(zip(SWEEP_STATS, list(out)))
 
