@@ -170,6 +170,31 @@ def run_chain(lib, torch, prec, L, d, chi_max, steps, warmup, exec_mode, autotun
                 stats={k: after[k] - before[k] for k in after})
 
 
+def run_serve(lib, torch, nreq, rate, nsteps, prec, slots, max_batch, budget_bytes):
+    """The serving loop on the Poisson request stream (serve.Engine): requests
+    of random d, g, chi_max and geometry, admitted by HBM budget, batched
+    across requests, each run for nsteps second-order steps from |0...0>."""
+    from paper_2212_09782_amd import inputs, serve
+    specs = inputs.serving_requests(n=nreq, rate=rate, seed=5)
+    reqs = serve.requests_from_stream(specs, nsteps=nsteps, prec=prec)
+    execs = [serve.Executor(0) for _ in range(slots)]
+    t0 = time.perf_counter()
+
+    def progress(r, eng):
+        print(f"# request {r.rid} done at {time.perf_counter() - t0:.1f} s "
+              f"({len(eng.finished)}/{nreq}; d={r.d} chi_max={r.chi_max} L={r.L} "
+              f"{'failed: ' + r.result.get('error', '') if r.result and r.result.get('failed') else ''})",
+              file=sys.stderr, flush=True)
+
+    eng = serve.Engine(execs, hbm_budget=budget_bytes, max_batch=max_batch, on_finish=progress)
+    rep = eng.run(reqs)
+    for ex in execs:
+        ex.close()
+    rep["final_chi_max"] = {str(r.rid): max(r.result["chis"]) for r in reqs if r.result and "chis" in r.result}
+    rep["errors"] = eng.errors[:5]
+    return rep
+
+
 def roofline(r, key, traffic_ok):
     achieved = r["gemm_flops"] / (r["gemm_ms"] * 1e-3) if r["gemm_ms"] > 0 else 0.0
     tb = TRAFFIC[key][0] if traffic_ok.get(key) else None
@@ -254,9 +279,15 @@ def main():
     ap.add_argument("--prec", choices=["both", "c128", "mixed"], default="both")
     ap.add_argument("--cpu-budget", type=float, default=24.0, help="seconds of oracle time (0: skip)")
     ap.add_argument("--sweeps", type=int, default=1, help="QR/LQ sweeps per update (1: the paper's single sweep)")
-    ap.add_argument("--workload", choices=["bond", "chain"], default="bond",
+    ap.add_argument("--workload", choices=["bond", "chain", "serve"], default="bond",
                     help="bond: the single-bond microbenchmark (default); chain: the batched finite chain "
                          "(L=128, Z_4, chi_max=512 by default), steady state, one JSON line of its own")
+    ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=4.0, help="serve: Poisson arrival rate (requests/s)")
+    ap.add_argument("--serve-steps", type=int, default=50, help="serve: Trotter steps per request")
+    ap.add_argument("--slots", type=int, default=4, help="serve: executors (contexts and streams)")
+    ap.add_argument("--max-batch", type=int, default=8, help="serve: requests per slot batch")
+    ap.add_argument("--hbm-budget-gb", type=float, default=200.0, help="serve: admission budget")
     ap.add_argument("--L", type=int, default=128)
     ap.add_argument("--chi-max", type=int, default=512)
     ap.add_argument("--exec", type=int, default=2, help="chain: mps_sweep execution mode (0 eager, 1 speculative, 2 graph)")
@@ -284,6 +315,21 @@ def main():
     lib.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.workload == "serve":
+        prec = lib.MPS_C128 if args.prec == "c128" else lib.MPS_MIXED_C64
+        rep = run_serve(lib, torch, args.requests, args.rate, args.serve_steps, prec, args.slots, args.max_batch,
+                        int(args.hbm_budget_gb * 2**30))
+        print(json.dumps({
+            "metric": "serving: aggregate bond updates/s + p50/p99 per-request step latency",
+            "value": round(rep["bond_updates_per_s"], 3), "unit": "bond updates/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "c128" if prec == lib.MPS_C128 else "c64", "data": "synthetic",
+            "p50_step_ms": round(rep["p50_step_ms"], 3), "p99_step_ms": round(rep["p99_step_ms"], 3),
+            "config": {"workload": f"{args.requests} quench requests, Poisson arrivals at {args.rate}/s, d in "
+                                   f"{{2,3,4,5,8}}, g in [0.5,3], chi_max in {{64..1024}}, finite L in {{32,64}} or "
+                                   f"uniform cell, {args.serve_steps} steps dt=0.05 each, {args.slots} slots, "
+                                   f"batch <= {args.max_batch}, HBM budget {args.hbm_budget_gb} GB"},
+            "report": rep}), flush=True)
+        return
     if args.workload == "chain":
         d = 4 if args.d == 5 else args.d
         res = {}

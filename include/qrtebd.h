@@ -210,8 +210,10 @@ typedef struct {
  * of state s: [nbonds][2][(d*d)^2] complex128, index 0 for tau = dt/2 and 1
  * for tau = dt, bond b = the bond starting at site b.  order 2: even(dt/2)
  * odd(dt) even(dt/2); order 1: even(dt) odd(dt).  All even bonds of all states
- * form one batch, then all odd bonds.  trunc_err_dev (nullable): per state,
- * the summed truncation error is added to trunc_err_dev[s]. */
+ * form one batch, then all odd bonds; a batch runs in groups of bonds (in
+ * order) whose workspaces together stay within 16 GiB, one group after the
+ * other (a larger bond forms its own group).  trunc_err_dev (nullable): per
+ * state, the summed truncation error is added to trunc_err_dev[s]. */
 int mps_sweep(mps_ctx ctx, mps_state* states, int nstates, const void* const* gates, int nsteps,
               int order, const mps_sweep_policy* policy, double* trunc_err_dev, mps_stream stream);
 

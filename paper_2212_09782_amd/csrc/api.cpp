@@ -611,11 +611,18 @@ __global__ void check_chi_kernel(const int* chi_dev, ChiExpect e, int* flag) {
 }
 
 // One layer: every bond of every state, shapes from the host copy of chi.
+// Bonds of a layer run in groups, in bond order, whose workspaces together
+// stay within this many bytes (a bond larger than that forms its own group);
+// the groups share one workspace region one after another.
+constexpr size_t kLayerGroupBytes = size_t(16) << 30;
+
 struct LayerPlan {
   std::vector<BondRef> bonds;
   std::vector<int> state_index;
   std::vector<BondShape> shapes;
   std::vector<size_t> off;
+  std::vector<int> group;   // group of each bond (groups run one after another)
+  int ngroups = 0;
   size_t total = 0;
 };
 
@@ -632,7 +639,9 @@ int plan_layer(mps_state* states, int nstates, const void* const* gates, int par
   if (nb > kMaxLayerBonds) return set_error(MPS_ERR_CAPACITY, "a layer of %d bonds exceeds %d", nb, kMaxLayerBonds);
   lp.shapes.resize(nb);
   lp.off.resize(nb);
-  size_t total = ((size_t)nb * (sizeof(int) + sizeof(double)) + 4096 + 255) & ~size_t(255);
+  lp.group.resize(nb);
+  const size_t header = ((size_t)nb * (sizeof(int) + sizeof(double)) + 4096 + 255) & ~size_t(255);
+  size_t gbytes = 0, gmax = 0;
   for (int k = 0; k < nb; ++k) {
     const BondRef& br = lp.bonds[k];
     mps_state st = br.st;
@@ -653,10 +662,17 @@ int plan_layer(mps_state* states, int nstates, const void* const* gates, int par
     D.sweeps = pol->sweeps;
     if ((rc = check_desc(&D))) return rc;
     lp.shapes[k] = shape_of(&D);
-    lp.off[k] = total;
-    total += (bond_work_bytes(lp.shapes[k]) + 255) & ~size_t(255);
+    const size_t wb = (bond_work_bytes(lp.shapes[k]) + 255) & ~size_t(255);
+    if (k == 0 || (gbytes > 0 && gbytes + wb > kLayerGroupBytes)) {
+      ++lp.ngroups;
+      gbytes = 0;
+    }
+    lp.group[k] = lp.ngroups - 1;
+    lp.off[k] = header + gbytes;
+    gbytes += wb;
+    gmax = std::max(gmax, gbytes);
   }
-  lp.total = total;
+  lp.total = header + gmax;
   return 0;
 }
 
@@ -671,19 +687,22 @@ int launch_layer(mps_ctx c, const LayerPlan& lp, double* eps_acc_base, hipStream
   char* base = (char*)c->ws;
   int* chi_dev = (int*)base;
   double* eps_dev = (double*)(base + (((size_t)nb * sizeof(int) + 255) & ~size_t(255)));
-  std::vector<BondCall> calls[2];
-  for (int k = 0; k < nb; ++k) {
-    const BondRef& br = lp.bonds[k];
-    mps_state st = br.st;
-    BondCall bc{lp.shapes[k], base + lp.off[k], c->status, st->Xi[br.m], st->B[br.m], st->B[br.n], br.gate,
-                st->B[br.m], st->Xi[br.n], st->B[br.n], chi_dev + k, eps_dev + k};
-    calls[st->prec].push_back(bc);
+  for (int g = 0; g < lp.ngroups; ++g) {
+    std::vector<BondCall> calls[2];
+    for (int k = 0; k < nb; ++k) {
+      if (lp.group[k] != g) continue;
+      const BondRef& br = lp.bonds[k];
+      mps_state st = br.st;
+      BondCall bc{lp.shapes[k], base + lp.off[k], c->status, st->Xi[br.m], st->B[br.m], st->B[br.n], br.gate,
+                  st->B[br.m], st->Xi[br.n], st->B[br.n], chi_dev + k, eps_dev + k};
+      calls[st->prec].push_back(bc);
+    }
+    for (int p = 0; p < 2; ++p)
+      if (!calls[p].empty() &&
+          (rc = bond_update_batch(calls[p].data(), (int)calls[p].size(), s, helpers ? &c->timer : nullptr,
+                                  helpers ? &c->qa : nullptr)))
+        return rc;
   }
-  for (int p = 0; p < 2; ++p)
-    if (!calls[p].empty() &&
-        (rc = bond_update_batch(calls[p].data(), (int)calls[p].size(), s, helpers ? &c->timer : nullptr,
-                                helpers ? &c->qa : nullptr)))
-      return rc;
   if (eps_acc_base) {
     EpsMap map{};
     map.n = nb;

@@ -85,6 +85,24 @@ def layer_bonds(req, parity):
     return [(ch[m], ch[m + 1], ch[m + 2]) for m in range(parity, req.L - 1, 2)]
 
 
+# mps_sweep runs a layer's bonds in groups (in order) whose workspaces
+# together stay within this many bytes, one group after the other.
+LAYER_GROUP_BYTES = 16 << 30
+
+
+def layer_workspace(bond_bytes):
+    """Workspace one layer needs: the largest group of consecutive bonds
+    (greedy, as mps_sweep forms them) under LAYER_GROUP_BYTES."""
+    best = cur = 0
+    for b in bond_bytes:
+        b = (b + 255) // 256 * 256
+        if cur > 0 and cur + b > LAYER_GROUP_BYTES:
+            cur = 0
+        cur += b
+        best = max(best, cur)
+    return best
+
+
 def eta_of(d, chi_l, chi_m, chi_r, dchi_min=100, dchi_frac=0.1):
     """The sweep's eta rule: min(chi_m + max(dchi_min, ceil(dchi_frac chi_m)), d chi_l, d chi_r)."""
     return min(chi_m + max(dchi_min, math.ceil(dchi_frac * chi_m)), d * chi_l, d * chi_r)
@@ -113,10 +131,10 @@ class Executor:
         return int(n.value)
 
     def workspace_bytes(self, req):
-        """Workspace of this request's larger layer: mps_sweep carves one
-        region per bond of a layer, so a layer needs the sum over its bonds
-        (at the saturated chi profile)."""
-        return max(sum(self.bond_workspace_bytes(req, *b) for b in layer_bonds(req, p)) for p in (0, 1))
+        """Workspace of this request's larger layer at the saturated chi
+        profile (see layer_workspace)."""
+        return max(layer_workspace([self.bond_workspace_bytes(req, *b) for b in layer_bonds(req, p)])
+                   for p in (0, 1))
 
     def admit(self, req):
         lib, torch = self.lib, self.torch
@@ -139,7 +157,8 @@ class Executor:
             group = [r for r in reqs if r.prec == prec]
             sts = [self.states[r.rid][0] for r in group]
             gts = [self.states[r.rid][1] for r in group]
-            pol = lib.sweep_policy(max(r.chi_max for r in group), 1e-14 if prec == 0 else 1e-6)
+            pol = lib.sweep_policy(max(r.chi_max for r in group), 1e-14 if prec == 0 else 1e-6,
+                                   exec=lib.EXEC_SPECULATIVE)
             lib.mps_sweep(self.ctx, sts, gts, 1, 2, pol, stream=self.stream)
         self.stream.synchronize()
         lib._check(lib.load().mps_sync(self.ctx.h, lib._stream(self.stream)))
@@ -177,7 +196,7 @@ class Engine:
     fits the budget.
     """
 
-    def __init__(self, executors, hbm_budget, max_batch=8, clock=time.perf_counter):
+    def __init__(self, executors, hbm_budget, max_batch=8, clock=time.perf_counter, on_finish=None):
         if not 1 <= len(executors) <= MAX_SLOTS:
             raise ValueError(f"1 to {MAX_SLOTS} executors (slots) are supported, got {len(executors)}")
         self.execs = executors
@@ -194,6 +213,7 @@ class Engine:
         self.ws_high = [0 for _ in executors]    # the slot context's workspace (grow-only)
         self.finished = []
         self.errors = []
+        self.on_finish = on_finish   # callback(request, engine) after each finished / failed request
         self.t0 = None
 
     def _try_admit(self, slot):
@@ -253,6 +273,8 @@ class Engine:
             with self.lock:
                 self.finished.append(r)
                 self.errors.append((r.rid, str(err)))
+            if self.on_finish:
+                self.on_finish(r, self)
 
     def _worker(self, slot):
         ex = self.execs[slot]
@@ -287,6 +309,8 @@ class Engine:
                     self._release(slot, r)
                     with self.lock:
                         self.finished.append(r)
+                    if self.on_finish:
+                        self.on_finish(r, self)
                 else:
                     keep.append(r)
             self.batches[slot] = keep

@@ -141,3 +141,11 @@ def test_slot_count_is_capped():
     import pytest
     with pytest.raises(ValueError):
         serve.Engine([StubExecutor([]) for _ in range(serve.MAX_SLOTS + 1)], hbm_budget=1 << 30)
+
+
+def test_layer_workspace_groups():
+    G = serve.LAYER_GROUP_BYTES
+    assert serve.layer_workspace([100, 200, 300]) == 256 + 256 + 512
+    # bonds that do not fit one group run in consecutive groups sharing one region
+    assert serve.layer_workspace([G // 2, G // 2, G // 2]) == G
+    assert serve.layer_workspace([2 * G, 10]) == 2 * G
