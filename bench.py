@@ -195,6 +195,41 @@ def run_serve(lib, torch, nreq, rate, nsteps, prec, slots, max_batch, budget_byt
     return rep
 
 
+def run_quench(lib, torch, prec, d, g, chi_max, steps, dt, dchi_min, exec_mode, autotune=None):
+    """Uniform two-site cell quenched from |0...0> (second-order steps):
+    <Z + Z^dag> on both sites and both bond energies after every step."""
+    ctx = lib.Context(0, autotune_cache=autotune)
+    e0 = np.zeros((1, d, 1), np.complex128)
+    e0[0, 0, 0] = 1
+    st = lib.State(ctx, [e0, e0], [np.ones(1), np.ones(1)], finite=False, chi_cap=chi_max, prec=prec)
+    gates = lib.chain_gates(d, g, 2, False, dt)
+    pol = lib.sweep_policy(chi_max, 1e-14 if prec == lib.MPS_C128 else 1e-6, dchi_min, 0.1, exec=exec_mode)
+    w = np.exp(2j * np.pi * np.arange(d) / d)
+    zz = torch.from_numpy((np.diag(w) + np.diag(w.conj())).reshape(-1)).to("cuda")
+    hb = torch.from_numpy(lib.clock_hamiltonian(d, g).reshape(-1)).to("cuda")
+    site = torch.zeros(4, dtype=torch.float64, device="cuda")
+    bond = torch.zeros(4, dtype=torch.float64, device="cuda")
+    eps = torch.zeros(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    z, e, chis = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lib.mps_sweep(ctx, [st], [gates], 1, 2, pol, trunc_err=eps, stream=stream)
+        lib.mps_measure(ctx, st, op1=zz, op2=hb, site_vals=site, bond_vals=bond, stream=stream)
+        ctx.sync(stream)
+        z.append(site.cpu().numpy().reshape(2, 2)[:, 0].copy())
+        e.append(bond.cpu().numpy().reshape(2, 2)[:, 0].copy())
+        chis.append(max(st.chis()))
+        if len(z) % 10 == 0:
+            print(f"#   step {len(z)}: chi {chis[-1]}, <Z+Z^dag> {z[-1][0]:.6f}, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    eps_sum = float(eps.item())
+    st.close()
+    ctx.close()
+    return dict(z=np.array(z), e=np.array(e), chis=chis, eps_sum=eps_sum, seconds=t1 - t0)
+
+
 def roofline(r, key, traffic_ok):
     achieved = r["gemm_flops"] / (r["gemm_ms"] * 1e-3) if r["gemm_ms"] > 0 else 0.0
     tb = TRAFFIC[key][0] if traffic_ok.get(key) else None
@@ -279,7 +314,7 @@ def main():
     ap.add_argument("--prec", choices=["both", "c128", "mixed"], default="both")
     ap.add_argument("--cpu-budget", type=float, default=24.0, help="seconds of oracle time (0: skip)")
     ap.add_argument("--sweeps", type=int, default=1, help="QR/LQ sweeps per update (1: the paper's single sweep)")
-    ap.add_argument("--workload", choices=["bond", "chain", "serve"], default="bond",
+    ap.add_argument("--workload", choices=["bond", "chain", "serve", "quench"], default="bond",
                     help="bond: the single-bond microbenchmark (default); chain: the batched finite chain "
                          "(L=128, Z_4, chi_max=512 by default), steady state, one JSON line of its own")
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
@@ -289,6 +324,8 @@ def main():
     ap.add_argument("--max-batch", type=int, default=8, help="serve: requests per slot batch")
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0, help="serve: admission budget")
     ap.add_argument("--L", type=int, default=128)
+    ap.add_argument("--g", type=float, default=1.5, help="quench: transverse field")
+    ap.add_argument("--dt", type=float, default=0.02, help="quench: Trotter step")
     ap.add_argument("--chi-max", type=int, default=512)
     ap.add_argument("--exec", type=int, default=2, help="chain: mps_sweep execution mode (0 eager, 1 speculative, 2 graph)")
     ap.add_argument("--autotune", default=None,
@@ -315,6 +352,30 @@ def main():
     lib.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.workload == "quench":
+        d = 10 if args.d == 5 else args.d
+        cm = args.chi_max if args.chi_max != 512 else 1024
+        res = {}
+        for key, p in (("c128", lib.MPS_C128), ("c64", lib.MPS_MIXED_C64)):
+            print(f"# quench {key} d={d} g={args.g} chi_max={cm} {args.steps} steps", file=sys.stderr, flush=True)
+            res[key] = run_quench(lib, torch, p, d, args.g, cm, args.steps, args.dt, 100, args.exec, args.autotune)
+        a, b = res["c128"], res["c64"]
+        dz = np.abs(a["z"] - b["z"]).max(axis=1)
+        de = np.abs(a["e"].mean(axis=1) - b["e"].mean(axis=1))
+        pick = sorted(set([0, 9, 24, 49, 99, 149, args.steps - 1]) & set(range(args.steps)))
+        print(json.dumps({
+            "metric": "mixed vs complex128 error on <Z + Z^dag> and the energy per bond, heavy-d quench",
+            "value": float(dz.max()), "unit": "max_t |d<Z + Z^dag>|", "n_gpus": 1, "higher_is_better": False,
+            "data": "synthetic", "max_abs_dE": float(de.max()),
+            "config": {"workload": f"uniform two-site cell, Z_{d} clock model g={args.g}, quench from |0>, "
+                                   f"chi_max={cm}, dt={args.dt}, {args.steps} second-order steps, CBE dchi = "
+                                   f"max(100, ceil(chi/10)), svd_min 1e-14 (c128) / 1e-6 (mixed)"},
+            "per_step": {str(k + 1): {"dZ": float(dz[k]), "dE": float(de[k]), "z_c128": float(a["z"][k, 0]),
+                                      "e_c128": float(a["e"][k].mean()), "chi_c128": a["chis"][k],
+                                      "chi_mixed": b["chis"][k]} for k in pick},
+            "seconds": {"c128": round(a["seconds"], 2), "c64": round(b["seconds"], 2)},
+            "trunc_err_sum": {"c128": a["eps_sum"], "c64": b["eps_sum"]}}), flush=True)
+        return
     if args.workload == "serve":
         prec = lib.MPS_C128 if args.prec == "c128" else lib.MPS_MIXED_C64
         rep = run_serve(lib, torch, args.requests, args.rate, args.serve_steps, prec, args.slots, args.max_batch,

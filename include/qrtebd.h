@@ -164,6 +164,10 @@ int mps_bond_update_noalloc(mps_ctx ctx, const mps_bond_desc* desc, const void* 
  * Host computation (FP64); u_out: host array of (d*d)^2 complex128. */
 int mps_clock_gate(int d, double g, double tau, double wl, double wr, double* u_out);
 
+/* The bond Hamiltonian h of mps_clock_gate itself (Sec. IV), for energy
+ * measurements with mps_measure; h_out: host array of (d*d)^2 complex128. */
+int mps_clock_hamiltonian(int d, double g, double wl, double wr, double* h_out);
+
 /* ---- device-resident MPS and the even/odd sweep (Fig. 2a) ---------------- */
 
 typedef struct mps_state_s* mps_state;

@@ -489,8 +489,12 @@ int mps_profile_read(mps_ctx c, double* total_ms, double* total_flops, int* laun
   return MPS_OK;
 }
 
-int mps_clock_gate(int d, double g, double tau, double wl, double wr, double* u_out) {
-  if (d < 1 || !u_out) return set_error(MPS_ERR_ARG, "bad gate arguments");
+}  // extern "C"
+
+namespace {
+
+// h = -(Z (x) Z^dag + h.c.) - g (wl (X+X^dag) (x) 1 + wr 1 (x) (X+X^dag)), row i*d+j.
+std::vector<cd> clock_bond_h(int d, double g, double wl, double wr) {
   const int n = d * d;
   const cd w = std::exp(cd(0, 2 * M_PI / d));
   std::vector<cd> Z(d * d, 0.0), X(d * d, 0.0), xs(d * d);
@@ -500,7 +504,7 @@ int mps_clock_gate(int d, double g, double tau, double wl, double wr, double* u_
   }
   for (int i = 0; i < d; ++i)
     for (int j = 0; j < d; ++j) xs[i * d + j] = X[i * d + j] + std::conj(X[j * d + i]);
-  std::vector<cd> A(n * n, 0.0);
+  std::vector<cd> H(n * n, 0.0);
   for (int i = 0; i < d; ++i)
     for (int j = 0; j < d; ++j)
       for (int k = 0; k < d; ++k)
@@ -511,8 +515,30 @@ int mps_clock_gate(int d, double g, double tau, double wl, double wr, double* u_
           const cd zzh = std::conj(Z[k * d + i]) * Z[j * d + l];
           cd h = -(zz + zzh);
           h -= g * (wl * xs[i * d + k] * (j == l ? 1.0 : 0.0) + wr * (i == k ? 1.0 : 0.0) * xs[j * d + l]);
-          A[r * n + c] = cd(0, -tau) * h;
+          H[r * n + c] = h;
         }
+  return H;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mps_clock_hamiltonian(int d, double g, double wl, double wr, double* h_out) {
+  if (d < 1 || !h_out) return set_error(MPS_ERR_ARG, "bad Hamiltonian arguments");
+  const std::vector<cd> H = clock_bond_h(d, g, wl, wr);
+  for (size_t i = 0; i < H.size(); ++i) {
+    h_out[2 * i] = H[i].real();
+    h_out[2 * i + 1] = H[i].imag();
+  }
+  return MPS_OK;
+}
+
+int mps_clock_gate(int d, double g, double tau, double wl, double wr, double* u_out) {
+  if (d < 1 || !u_out) return set_error(MPS_ERR_ARG, "bad gate arguments");
+  const int n = d * d;
+  std::vector<cd> A = clock_bond_h(d, g, wl, wr);
+  for (auto& x : A) x *= cd(0, -tau);
   expm_host(A, n);
   for (int i = 0; i < n * n; ++i) {
     u_out[2 * i] = A[i].real();

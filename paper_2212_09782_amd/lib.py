@@ -23,6 +23,7 @@ EXPORTS = [
     "mps_workspace_query", "mps_bond_update", "mps_clock_gate", "mps_state_create",
     "mps_state_destroy", "mps_state_chis", "mps_sweep", "mps_measure", "mps_zgemm", "mps_qr",
     "mps_heig", "mps_profile_enable", "mps_profile_read", "mps_bond_update_noalloc", "mps_sweep_stats",
+    "mps_clock_hamiltonian",
 ]
 
 
@@ -66,6 +67,7 @@ def _declare(lib):
         "mps_bond_update": (I, [P, ctypes.POINTER(mps_bond_desc), P, P, P, P, P, P, P, P, P, P]),
         "mps_bond_update_noalloc": (I, [P, ctypes.POINTER(mps_bond_desc), P, P, P, P, P, P, P, P, P, P]),
         "mps_clock_gate": (I, [I, D, D, D, D, P]),
+        "mps_clock_hamiltonian": (I, [I, D, D, D, P]),
         "mps_state_create": (I, [P, I, I, I, I, I, ctypes.POINTER(P), ctypes.POINTER(P),
                                  ctypes.POINTER(I), ctypes.POINTER(P)]),
         "mps_state_destroy": (I, [P]),
@@ -156,6 +158,13 @@ def clock_gate(d, g, tau, wl=0.5, wr=0.5):
     """mps_clock_gate: host complex128 (d^2 x d^2) gate of the clock model."""
     out = np.zeros((d * d, d * d), np.complex128)
     _check(load().mps_clock_gate(d, g, tau, wl, wr, out.ctypes.data_as(P)))
+    return out
+
+
+def clock_hamiltonian(d, g, wl=0.5, wr=0.5):
+    """mps_clock_hamiltonian: host complex128 (d^2 x d^2) bond Hamiltonian of the clock model."""
+    out = np.zeros((d * d, d * d), np.complex128)
+    _check(load().mps_clock_hamiltonian(d, g, wl, wr, out.ctypes.data_as(P)))
     return out
 
 

@@ -50,6 +50,12 @@ def test_clock_gate_matches_oracle(d, g, tau, wl, wr):
     assert np.allclose(U @ U.conj().T, np.eye(d * d), atol=1e-13)
 
 
+@pytest.mark.parametrize("d,g,wl,wr", [(2, 1.0, 0.5, 0.5), (3, 2.0, 1.0, 0.5), (10, 1.5, 0.5, 1.0)])
+def test_clock_hamiltonian_matches_oracle(d, g, wl, wr):
+    H = lib.clock_hamiltonian(d, g, wl, wr)
+    assert np.max(np.abs(H - clock.bond_hamiltonian(d, g, wl, wr))) < 1e-14
+
+
 def test_bond_capacity():
     assert lib.bond_capacity(lib.bond_desc(5, 64, 64, 64, eta=71, chi_max=64)) == 64
     assert lib.bond_capacity(lib.bond_desc(5, 64, 64, 64, eta=71, chi_max=100)) == 71
