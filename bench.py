@@ -19,6 +19,9 @@ Prints one JSON line.  --gpus above 1 is refused: the benchmark runs on one
 GPU.
 """
 import argparse
+import collections
+import csv
+import glob
 import hashlib
 import json
 import math
@@ -44,8 +47,8 @@ GEMM_SOURCES = ["paper_2212_09782_amd/csrc/gemm.hip", "paper_2212_09782_amd/csrc
 # Each figure holds only for the kernel sources it was counted on (sha256 of
 # GEMM_SOURCES): after a change to them the bench reports traffic null.
 TRAFFIC = {
-    "c64": (None, None),
-    "c128": (None, None),
+    "c64": (1.3298e9, "aefa09bf25028ea9"),
+    "c128": (2.6978e9, "aefa09bf25028ea9"),
 }
 
 
@@ -303,6 +306,80 @@ def cpu_baseline(chi, d, budget_s):
     return out
 
 
+# ---- rocprofv3 CSV summaries (profiles/ holds their output) ----
+
+def _short(name):
+    name = name.replace("(anonymous namespace)::", "").replace("qrtebd::", "").replace("void ", "")
+    name = re.sub(r"\(.*$", "", name)
+    return name
+
+def trace_summary(d, out):
+    """Per-kernel table of a rocprofv3 --kernel-trace CSV (the default bench):
+    all dispatches, and per update over the 200 timed chi=1024 updates of each
+    precision (found from the contraction launches); removes the raw CSV."""
+    path = os.path.join(d, "run_kernel_trace.csv")
+    rows = list(csv.DictReader(open(path)))
+    ks = [k for k in rows[0].keys()]
+    nk = "Kernel_Name"
+    t0k, t1k = "Start_Timestamp", "End_Timestamp"
+    rows.sort(key=lambda r: int(r[t0k]))
+    by = collections.defaultdict(list)
+    for r in rows:
+        by[_short(r[nk])].append((int(r[t0k]), int(r[t1k])))
+    lines = []
+    tot = sum(b - a for v in by.values() for a, b in v)
+    lines.append(f"all dispatches: {len(rows)}, total kernel time {tot/1e6:.2f} ms")
+    lines.append("")
+    lines.append("| kernel | calls | total ms | avg us |")
+    lines.append("|---|--:|--:|--:|")
+    for k, v in sorted(by.items(), key=lambda kv: -sum(b - a for a, b in kv[1]))[:25]:
+        s = sum(b - a for a, b in v)
+        lines.append(f"| `{k}` | {len(v)} | {s/1e6:.3f} | {s/len(v)/1e3:.2f} |")
+    # the chi=1024 legs: contract launches 25..1024 of each precision's kernel are the timed updates
+    for prec, kname in (("c128", "contract_gemm_kernel<double, double, double>"), ("mixed", "contract_gemm_kernel<float, float, float>")):
+        v = by.get(kname, [])
+        if len(v) < 1025:
+            continue
+        timed = v[25:1025]
+        avg = sum(b - a for a, b in timed) / len(timed)
+        lines.append("")
+        lines.append(f"{prec}, chi=1024, timed updates: {kname} average {avg/1e3:.2f} us over {len(timed)} launches "
+                     f"(launches 26-1025 of the kernel; the first 25 are the 5 warm-up updates)")
+        # window: from the first timed contract launch to the last one, per-kernel time per update
+        w0, w1 = timed[0][0], timed[-1][1]
+        win = collections.defaultdict(lambda: [0, 0])
+        for r in rows:
+            a, b = int(r[t0k]), int(r[t1k])
+            if a >= w0 and b <= w1:
+                e = win[_short(r[nk])]
+                e[0] += 1
+                e[1] += b - a
+        wt = sum(e[1] for e in win.values())
+        lines.append(f"window of the 200 timed updates: {(w1 - w0)/1e6:.1f} ms wall, {wt/1e6:.1f} ms kernel time "
+                     f"(two streams overlap); per update:")
+        lines.append("")
+        lines.append("| kernel | launches per update | ms per update | avg us |")
+        lines.append("|---|--:|--:|--:|")
+        for k, e in sorted(win.items(), key=lambda kv: -kv[1][1])[:16]:
+            lines.append(f"| `{k}` | {e[0]/200:.1f} | {e[1]/200/1e6:.3f} | {e[1]/max(1,e[0])/1e3:.2f} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+    os.remove(path)
+
+def pmc_summary(d, out):
+    """Per-kernel means of a rocprofv3 --pmc CSV; removes the raw CSV."""
+    path = glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+    rows = list(csv.DictReader(open(path)))
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in rows:
+        agg[_short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = ["| kernel | counter | dispatches | mean per dispatch | total |", "|---|---|--:|--:|--:|"]
+    for k in sorted(agg):
+        for c, v in sorted(agg[k].items()):
+            lines.append(f"| `{k}` | {c} | {len(v)} | {sum(v)/len(v):.6g} | {sum(v):.6g} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+    os.remove(path)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,7 +409,13 @@ def main():
                     help="autotune cache file passed to mps_ctx_create (tuned during the warm-up)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB three times (reference run for the HBM byte counters)")
+    ap.add_argument("--rocprof-summary", nargs=3, metavar=("KIND", "DIR", "OUT"),
+                    help="summarise rocprofv3 CSV output: KIND trace (kernel trace of this bench) or pmc")
     args = ap.parse_args()
+    if args.rocprof_summary:
+        kind, d, out = args.rocprof_summary
+        (trace_summary if kind == "trace" else pmc_summary)(d, out)
+        return
     if args.copy_calibration:
         import torch
         x = torch.ones(64 * 2**20, dtype=torch.float32, device="cuda")
