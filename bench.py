@@ -233,6 +233,52 @@ def run_quench(lib, torch, prec, d, g, chi_max, steps, dt, dchi_min, exec_mode, 
     return dict(z=np.array(z), e=np.array(e), chis=chis, eps_sum=eps_sum, seconds=t1 - t0)
 
 
+def run_schemes(lib, torch, chi, ds, reps, budget_s):
+    """Single-gate time of the four truncation schemes of the paper's
+    comparison (Sec. IV) on the GPU, complex128: QR (plain, eta = chi), QR+CBE
+    (eta = chi + ceil(chi/10)), EIG and SVD (rocSOLVER heevd / gesvd), on the
+    microbenchmark cell at each d; a scheme is skipped at larger d once one
+    gate took longer than budget_s."""
+    from paper_2212_09782_amd import inputs
+    ctx = lib.Context(0)
+    out, slow = {}, set()
+    for d in ds:
+        A, B, lA, _ = inputs.microbench_cell(chi, d, seed=0)
+        U = lib.clock_gate(d, 2.0, 0.05)
+        dev = lambda a, t=torch.complex128: torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).to(t).to("cuda")
+        xi, bm, bn, du = dev(lA, torch.float64), dev(A), dev(B), dev(U)
+        row = {}
+        for name in ("qr", "qr_cbe", "eig", "svd"):
+            if name in slow:
+                row[name] = None
+                continue
+            if name in ("qr", "qr_cbe"):
+                eta = chi if name == "qr" else chi + -(-chi // 10)
+                desc = lib.bond_desc(d, chi, chi, chi, eta, chi, 1e-14, True, lib.PLAIN if name == "qr" else lib.CBE)
+                run = lambda: lib.bond_update(ctx, desc, xi, bm, bn, du)
+            else:
+                desc = lib.bond_desc(d, chi, chi, chi, 1, chi, 1e-14, True, lib.CBE)
+                sch = lib.SCHEME_EIG if name == "eig" else lib.SCHEME_SVD
+                run = lambda: lib.reference_update(ctx, desc, sch, xi, bm, bn, du)
+            print(f"# schemes chi={chi} d={d} {name}", file=sys.stderr, flush=True)
+            run()
+            ctx.sync()
+            times = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                run()
+                ctx.sync()
+                times.append(time.perf_counter() - t0)
+                if times[-1] > budget_s:
+                    break
+            row[name] = 1e3 * float(np.median(times))
+            if times[-1] > budget_s:
+                slow.add(name)
+        out[str(d)] = row
+    ctx.close()
+    return out
+
+
 def roofline(r, key, traffic_ok):
     achieved = r["gemm_flops"] / (r["gemm_ms"] * 1e-3) if r["gemm_ms"] > 0 else 0.0
     tb = TRAFFIC[key][0] if traffic_ok.get(key) else None
@@ -391,7 +437,7 @@ def main():
     ap.add_argument("--prec", choices=["both", "c128", "mixed"], default="both")
     ap.add_argument("--cpu-budget", type=float, default=24.0, help="seconds of oracle time (0: skip)")
     ap.add_argument("--sweeps", type=int, default=1, help="QR/LQ sweeps per update (1: the paper's single sweep)")
-    ap.add_argument("--workload", choices=["bond", "chain", "serve", "quench"], default="bond",
+    ap.add_argument("--workload", choices=["bond", "chain", "serve", "quench", "schemes"], default="bond",
                     help="bond: the single-bond microbenchmark (default); chain: the batched finite chain "
                          "(L=128, Z_4, chi_max=512 by default), steady state, one JSON line of its own")
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
@@ -400,6 +446,7 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="serve: executors (contexts and streams)")
     ap.add_argument("--max-batch", type=int, default=8, help="serve: requests per slot batch")
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0, help="serve: admission budget")
+    ap.add_argument("--ds", default="2,3,4,5,6,8,10,12,16,20", help="schemes: physical dimensions")
     ap.add_argument("--L", type=int, default=128)
     ap.add_argument("--g", type=float, default=1.5, help="quench: transverse field")
     ap.add_argument("--dt", type=float, default=0.02, help="quench: Trotter step")
@@ -435,6 +482,18 @@ def main():
     lib.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.workload == "schemes":
+        chi = args.chi or 1024
+        ds = [int(x) for x in args.ds.split(",") if x.strip()]
+        tab = run_schemes(lib, torch, chi, ds, max(1, min(args.steps, 5)), 20.0)
+        ratio = {d: (r["svd"] / r["qr_cbe"] if r.get("svd") and r.get("qr_cbe") else None) for d, r in tab.items()}
+        print(json.dumps({
+            "metric": "single-gate wall time of the truncation schemes (ms), complex128",
+            "unit": "ms per bond update", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+            "config": {"workload": f"microbenchmark cell chi={chi}, clock gate g=2 dt=0.05, schemes: QR (eta=chi), "
+                                   f"QR+CBE (eta=chi+ceil(chi/10)), EIG and SVD (rocSOLVER), median of up to 5"},
+            "ms": tab, "svd_over_qr_cbe": ratio}), flush=True)
+        return
     if args.workload == "quench":
         d = 10 if args.d == 5 else args.d
         cm = args.chi_max if args.chi_max != 512 else 1024

@@ -142,6 +142,19 @@ int mps_bond_update(mps_ctx ctx, const mps_bond_desc* desc, const void* xi_m, co
                     const void* b_n, const void* u, void* b_m_out, void* xi_n_out, void* b_n_out,
                     int* chi_new_dev, double* trunc_err_dev, mps_stream stream);
 
+/* The comparison schemes of Sec. IV on the GPU, complex128 only: the same
+ * two-site contraction, gate and Hastings form as mps_bond_update, with the
+ * truncation of theta~ taken from its SVD (scheme 0: theta~ = U S V^dag,
+ * B~^[n] = V_kept^dag) or from the eigen-decomposition of theta~^dag theta~
+ * (scheme 1, EIG).  Both use the rocSOLVER library (gesvd / heevd): they are
+ * baselines for the QR schemes, not part of them.  desc: mode CBE (chi_max,
+ * svd_min as there), prec MPS_C128; eta and sweeps are ignored.  Outputs as
+ * for CBE with capacity min(chi_max, d chi_l, d chi_r).  MPS_ERR_HIP if the
+ * solver library fails; a failed decomposition (info != 0) is latched. */
+int mps_bond_update_reference(mps_ctx ctx, const mps_bond_desc* desc, int scheme, const void* xi_m, const void* b_m,
+                              const void* b_n, const void* u, void* b_m_out, void* xi_n_out, void* b_n_out,
+                              int* chi_new_dev, double* trunc_err_dev, mps_stream stream);
+
 /* mps_bond_update without any allocation, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, hosts
  * that forbid hipMalloc).  Same arguments, outputs and errors as

@@ -20,6 +20,9 @@
 #include "bond.h"
 #include "gemm.h"
 #include "measure.h"
+#include "reference.h"
+
+#include <rocblas/rocblas.h>
 
 namespace qrtebd {
 
@@ -109,6 +112,7 @@ struct mps_ctx_s {
   bool tune_on = false;
   std::string tune_path;
   std::map<std::string, TuneParams> tune_table;
+  rocblas_handle blas = nullptr;   // solver library handle of the reference schemes (created on first use)
   int* status = nullptr;     // device error word
   int* chi_host = nullptr;   // pinned scratch for chi read-back
   double* eps_host = nullptr;
@@ -165,7 +169,7 @@ int check_desc(const mps_bond_desc* D) {
     return set_error(MPS_ERR_ARG, "eta=%d outside [1, min(d chi_l, d chi_r)=%d]", D->eta, std::min(mL, mR));
   if (D->mode == MPS_TRUNC_CBE && D->chi_max < 1) return set_error(MPS_ERR_ARG, "chi_max must be >= 1");
   if (D->mode == MPS_TRUNC_CBE && !(D->svd_min >= 0)) return set_error(MPS_ERR_ARG, "svd_min must be >= 0");
-  if (D->d * D->d > 160) return set_error(MPS_ERR_CAPACITY, "d=%d too large (d^2 <= 160)", D->d);
+  if (D->d > 25) return set_error(MPS_ERR_CAPACITY, "d=%d too large (d <= 25)", D->d);
   if (std::max(mL, mR) > kMaxQrRows)
     return set_error(MPS_ERR_CAPACITY, "d chi=%d too large", std::max(mL, mR));
   if (D->mode == MPS_TRUNC_CBE && D->eta > kEigMaxN)
@@ -335,6 +339,7 @@ int mps_ctx_destroy(mps_ctx c) {
   if (!c) return MPS_OK;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  if (c->blas) (void)rocblas_destroy_handle(c->blas);
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   c->graphs.clear();
   if (c->ws) (void)hipFree(c->ws);
@@ -430,6 +435,34 @@ int mps_bond_update(mps_ctx c, const mps_bond_desc* D, const void* xi_m, const v
     }
   }
   return run();
+}
+
+int mps_bond_update_reference(mps_ctx c, const mps_bond_desc* D, int scheme, const void* xi_m, const void* b_m,
+                              const void* b_n, const void* u, void* b_m_out, void* xi_n_out, void* b_n_out,
+                              int* chi_new_dev, double* trunc_err_dev, mps_stream stream) {
+  if (!c) return set_error(MPS_ERR_ARG, "null context");
+  if (scheme != MPS_SCHEME_SVD && scheme != MPS_SCHEME_EIG) return set_error(MPS_ERR_ARG, "scheme must be 0 or 1");
+  if (!D) return set_error(MPS_ERR_ARG, "null descriptor");
+  if (D->mode != MPS_TRUNC_CBE || D->prec != MPS_C128)
+    return set_error(MPS_ERR_ARG, "the reference schemes take mode CBE (chi_max, svd_min) and complex128");
+  mps_bond_desc Dr = *D;
+  Dr.eta = std::min(D->d * D->chi_l, D->d * D->chi_r);   // eta is not used: the whole of theta~ is decomposed
+  Dr.sweeps = 0;
+  if (Dr.eta > kEigMaxN) Dr.eta = kEigMaxN;   // only the descriptor check's eigensolver limit; not used here
+  int rc = check_desc(&Dr);
+  if (rc) return rc;
+  if (!xi_m || !b_m || !b_n || !u || !b_m_out || !xi_n_out || !b_n_out || !chi_new_dev || !trunc_err_dev)
+    return set_error(MPS_ERR_ARG, "null tensor pointer");
+  BondShape b = shape_of(&Dr);
+  b.eta = std::min(D->d * D->chi_l, D->d * D->chi_r);
+  hipStream_t s = (hipStream_t)stream;
+  if (!c->blas && rocblas_create_handle(&c->blas) != rocblas_status_success) {
+    c->blas = nullptr;
+    return set_error(MPS_ERR_HIP, "rocblas_create_handle failed");
+  }
+  if ((rc = ensure_ws(c, reference_work_bytes(b, scheme), s))) return rc;
+  return reference_update(b, scheme, c->ws, c->status, c->blas, xi_m, b_m, b_n, (const c128*)u, b_m_out, xi_n_out,
+                          b_n_out, chi_new_dev, trunc_err_dev, s);
 }
 
 int mps_bond_update_noalloc(mps_ctx c, const mps_bond_desc* D, const void* xi_m, const void* b_m,

@@ -58,6 +58,16 @@ int bond_update_run(const BondShape& b, void* ws, int* status, const void* xi_m,
                     int* chi_new, double* eps, hipStream_t s, KernelTimer* timer = nullptr,
                     const QrAsync* as = nullptr);
 
+// ---- pieces shared with the reference truncation schemes (complex128)
+// Sec. II step (i): C~ = U (B^[m] B^[n]) into C, theta~ = Xi^[m] C~ into Th,
+// |theta~|^2 into *norm2 (partial: at least 4096 doubles of scratch).
+int two_site_c128(const BondShape& b, const void* xi_m, const void* b_m, const void* b_n, const c128* u, c128* C,
+                  c128* Th, double* partial, double* norm2, hipStream_t s);
+// Truncation from the descending spectrum lam = S^2 (kmax entries): chi~ (S >=
+// svd_min, at least one), Xi~ = S_kept / |S_kept|, kept weight and eps.
+int select_run(const double* lam, int kmax, double svd_min, const double* norm2, int* chi_new, double* xi,
+               double* kept2, double* eps, int* status, hipStream_t s);
+
 // ---- small kernels shared with the measurement path
 // out[k] = sum over a partial buffer in a fixed order (one block).
 int reduce_partials(const double* part, int n, double* out, hipStream_t s);

@@ -33,37 +33,43 @@ namespace {
 
 inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Gate and Xi over one row alpha of C and W = 64 / R columns delta: the d^2
+// inputs of every column staged in LDS; thread (column t % W, group t / W)
+// forms the outputs o = group, group + R, ... of its column.  R = 1 for d^2 <=
+// 160 (the default), 2 or 4 for larger d, so the staged block fits in LDS.
 template <typename S>
 __global__ __launch_bounds__(64) void gate_kernel(cpx<S>* C, cpx<S>* Th, const c128* __restrict__ U,
-                                                  const double* xi, int d, int chiR, double* partial) {
+                                                  const double* xi, int d, int chiR, int R, double* partial) {
   extern __shared__ unsigned char gate_lds[];
-  cpx<S>* Cs = reinterpret_cast<cpx<S>*>(gate_lds);  // d^2 x 64 in storage precision, one column per thread
+  cpx<S>* Cs = reinterpret_cast<cpx<S>*>(gate_lds);  // d^2 x W in storage precision
   constexpr int G = 5;                                // outputs per pass: G independent FP64 chains per LDS read
-  const int d2 = d * d, t = threadIdx.x;
-  const int alpha = blockIdx.y, delta = blockIdx.x * 64 + t;
+  const int d2 = d * d, t = threadIdx.x, W = 64 / R, col = t % W, grp = t / W;
+  const int alpha = blockIdx.y, delta = blockIdx.x * W + col;
   const long long base = (long long)alpha * d2 * chiR;
   const bool live = delta < chiR;
-  for (int q = 0; q < d2; ++q) Cs[q * 64 + t] = live ? C[base + (long long)q * chiR + delta] : mk<S>(0, 0);
+  for (int q = grp; q < d2; q += R) Cs[q * W + col] = live ? C[base + (long long)q * chiR + delta] : mk<S>(0, 0);
+  if (R > 1) __syncthreads();   // a column's inputs come from R threads
   const double x = xi ? xi[alpha] : 1.0;
+  const int nout = (d2 - grp + R - 1) / R;   // outputs o = grp + R j, j < nout
   double nrm = 0;
   if (live) {
-    for (int o0 = 0; o0 < d2; o0 += G) {
+    for (int j0 = 0; j0 < nout; j0 += G) {
       c128 acc[G];
       int row[G];
 #pragma unroll
       for (int u = 0; u < G; ++u) {
         acc[u] = mk<double>(0, 0);
-        row[u] = min(o0 + u, d2 - 1) * d2;  // rows past d^2 recompute the last one and are not stored
+        row[u] = (grp + R * min(j0 + u, nout - 1)) * d2;  // past the last output: recompute it, not stored
       }
       for (int q = 0; q < d2; ++q) {
-        const c128 c = ccast<double>(Cs[q * 64 + t]);
+        const c128 c = ccast<double>(Cs[q * W + col]);
 #pragma unroll
         for (int u = 0; u < G; ++u) acc[u] = cadd(acc[u], cmul(U[row[u] + q], c));
       }
 #pragma unroll
       for (int u = 0; u < G; ++u) {
-        if (o0 + u >= d2) break;
-        const long long off = base + (long long)(o0 + u) * chiR + delta;
+        if (j0 + u >= nout) break;
+        const long long off = base + (long long)(grp + R * (j0 + u)) * chiR + delta;
         C[off] = ccast<S>(acc[u]);
         if (Th) {
           const cpx<S> th = ccast<S>(cscale(acc[u], x));
@@ -75,6 +81,13 @@ __global__ __launch_bounds__(64) void gate_kernel(cpx<S>* C, cpx<S>* Th, const c
   }
   nrm = wave_sum(nrm);
   if (t == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = nrm;
+}
+
+// Output groups of the gate kernel for physical dimension d (LDS of d^2 x 64 / R elements).
+inline int gate_groups(int d, size_t es) {
+  int R = 1;
+  while (R < 4 && (size_t)d * d * (64 / R) * es > 160 * 1024) R *= 2;
+  return R;
 }
 
 template <typename S>
@@ -243,7 +256,7 @@ BondBufs carve(const BondShape& b, void* base) {
   o.G2 = (c128*)c.take(mixed ? cap * cap * 16 : 0);
   o.Dc = c.take(mixed ? cap * cap * 8 : 0);
   o.tmp = c.take(mixed ? cap * mR * es : 0);
-  const size_t npart = std::max<size_t>((size_t)b.chi_l * ((b.chi_r + 63) / 64), 4096);
+  const size_t npart = std::max<size_t>((size_t)b.chi_l * ((b.chi_r + 15) / 16), 4096);   // gate blocks of >= 16 columns
   o.partial = (double*)c.take(npart * 8);
   o.norm2 = (double*)c.take(8);
   o.kept2 = (double*)c.take(8);
@@ -282,8 +295,9 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
     const BondShape& b = c.b;
     BondBufs& w = W[i];
     const int d = b.d, chiL = b.chi_l, chiR = b.chi_r, mL = d * chiL, mR = d * chiR;
-    const dim3 grid((chiR + 63) / 64, chiL);
-    const size_t shm = (size_t)d * d * 64 * sizeof(cpx<S>);
+    const int R = gate_groups(d, sizeof(cpx<S>)), Wc = 64 / R;
+    const dim3 grid((chiR + Wc - 1) / Wc, chiL);
+    const size_t shm = (size_t)d * d * Wc * sizeof(cpx<S>);
     static bool attr = false;
     if (!attr) {
       QT_HIP_CHECK(hipFuncSetAttribute((const void*)gate_kernel<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -292,7 +306,7 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
     }
     const bool diag = b.xi_is_diag != 0;
     hipLaunchKernelGGL(gate_kernel<S>, grid, dim3(64), shm, s, (cpx<S>*)w.C, diag ? (cpx<S>*)w.Th : nullptr, c.u,
-                       diag ? (const double*)c.xi_m : nullptr, d, chiR, w.partial);
+                       diag ? (const double*)c.xi_m : nullptr, d, chiR, R, w.partial);
     QT_HIP_CHECK(hipGetLastError());
     if (diag) {
       if ((rc = reduce_partials(w.partial, (int)(grid.x * grid.y), w.norm2, s))) return rc;
@@ -554,6 +568,45 @@ int timed_gemm(KernelTimer* t, const GemmProb& p, GemmTypes ty, hipStream_t s) {
   int rc = gemm_one(p, ty, s, true);
   if (rc) return rc;
   QT_HIP_CHECK(hipEventRecord(t->ev[2 * i + 1], s));
+  return 0;
+}
+
+int two_site_c128(const BondShape& b, const void* xi_m, const void* b_m, const void* b_n, const c128* u, c128* C,
+                  c128* Th, double* partial, double* norm2, hipStream_t s) {
+  int rc;
+  const int d = b.d, chiL = b.chi_l, chiR = b.chi_r, mL = d * chiL, mR = d * chiR;
+  if ((rc = gemm_one(gemm_prob(b_m, b.chi_m, OP_N, b_n, mR, OP_N, C, mR, mL, mR, b.chi_m), GemmTypes{DT_C128, DT_C128},
+                     s, true)))
+    return rc;
+  const int R = gate_groups(d, sizeof(c128)), Wc = 64 / R;
+  const dim3 grid((chiR + Wc - 1) / Wc, chiL);
+  const size_t shm = (size_t)d * d * Wc * sizeof(c128);
+  static bool attr = false;
+  if (!attr) {
+    QT_HIP_CHECK(hipFuncSetAttribute((const void*)gate_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     160 * 1024));
+    attr = true;
+  }
+  const bool diag = b.xi_is_diag != 0;
+  hipLaunchKernelGGL(gate_kernel<double>, grid, dim3(64), shm, s, C, diag ? Th : nullptr, u,
+                     diag ? (const double*)xi_m : nullptr, d, chiR, R, partial);
+  QT_HIP_CHECK(hipGetLastError());
+  if (diag) return reduce_partials(partial, (int)(grid.x * grid.y), norm2, s);
+  const int ncol = d * mR;
+  if ((rc = gemm_one(gemm_prob(xi_m, chiL, OP_N, C, ncol, OP_N, Th, ncol, chiL, ncol, chiL), GemmTypes{DT_C128, DT_C128},
+                     s)))
+    return rc;
+  const long long n = (long long)mL * mR;
+  hipLaunchKernelGGL(sumsq_kernel<double>, dim3(1024), dim3(256), 0, s, (const c128*)Th, n, partial);
+  QT_HIP_CHECK(hipGetLastError());
+  return reduce_partials(partial, 1024, norm2, s);
+}
+
+int select_run(const double* lam, int kmax, double svd_min, const double* norm2, int* chi_new, double* xi,
+               double* kept2, double* eps, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, s, lam, kmax, svd_min, norm2, chi_new, xi, kept2, eps,
+                     status);
+  QT_HIP_CHECK(hipGetLastError());
   return 0;
 }
 

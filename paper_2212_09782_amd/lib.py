@@ -23,8 +23,9 @@ EXPORTS = [
     "mps_workspace_query", "mps_bond_update", "mps_clock_gate", "mps_state_create",
     "mps_state_destroy", "mps_state_chis", "mps_sweep", "mps_measure", "mps_zgemm", "mps_qr",
     "mps_heig", "mps_profile_enable", "mps_profile_read", "mps_bond_update_noalloc", "mps_sweep_stats",
-    "mps_clock_hamiltonian",
+    "mps_clock_hamiltonian", "mps_bond_update_reference",
 ]
+SCHEME_SVD, SCHEME_EIG = 0, 1
 
 
 class mps_bond_desc(ctypes.Structure):
@@ -66,6 +67,7 @@ def _declare(lib):
         "mps_workspace_query": (I, [P, ctypes.POINTER(mps_bond_desc), ctypes.POINTER(ctypes.c_size_t)]),
         "mps_bond_update": (I, [P, ctypes.POINTER(mps_bond_desc), P, P, P, P, P, P, P, P, P, P]),
         "mps_bond_update_noalloc": (I, [P, ctypes.POINTER(mps_bond_desc), P, P, P, P, P, P, P, P, P, P]),
+        "mps_bond_update_reference": (I, [P, ctypes.POINTER(mps_bond_desc), I, P, P, P, P, P, P, P, P, P, P]),
         "mps_clock_gate": (I, [I, D, D, D, D, P]),
         "mps_clock_hamiltonian": (I, [I, D, D, D, P]),
         "mps_state_create": (I, [P, I, I, I, I, I, ctypes.POINTER(P), ctypes.POINTER(P),
@@ -190,6 +192,28 @@ def mps_bond_update_noalloc(ctx, desc, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n
     _check(ctx.lib.mps_bond_update_noalloc(ctx.h, ctypes.byref(desc), _ptr(xi_m), _ptr(b_m), _ptr(b_n), _ptr(u),
                                            _ptr(b_m_out), _ptr(xi_n_out), _ptr(b_n_out), _ptr(chi_new),
                                            _ptr(trunc_err), _stream(stream)))
+
+
+def mps_bond_update_reference(ctx, desc, scheme, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, chi_new, trunc_err,
+                              stream=None):
+    """Direct C-ABI call of the SVD / EIG comparison schemes (complex128)."""
+    _check(ctx.lib.mps_bond_update_reference(ctx.h, ctypes.byref(desc), scheme, _ptr(xi_m), _ptr(b_m), _ptr(b_n),
+                                             _ptr(u), _ptr(b_m_out), _ptr(xi_n_out), _ptr(b_n_out), _ptr(chi_new),
+                                             _ptr(trunc_err), _stream(stream)))
+
+
+def reference_update(ctx, desc, scheme, xi_m, b_m, b_n, u, stream=None):
+    """Allocate outputs of capacity min(chi_max, d chi_l, d chi_r) and run a comparison scheme."""
+    import torch
+    dev = b_m.device
+    cap = max(1, min(desc.chi_max, desc.d * desc.chi_l, desc.d * desc.chi_r))
+    b_m_out = torch.empty(desc.chi_l * desc.d * cap, dtype=torch.complex128, device=dev)
+    b_n_out = torch.empty(cap * desc.d * desc.chi_r, dtype=torch.complex128, device=dev)
+    xi_out = torch.empty(cap, dtype=torch.float64, device=dev)
+    chi = torch.zeros(1, dtype=torch.int32, device=dev)
+    eps = torch.zeros(1, dtype=torch.float64, device=dev)
+    mps_bond_update_reference(ctx, desc, scheme, xi_m, b_m, b_n, u, b_m_out, xi_out, b_n_out, chi, eps, stream)
+    return b_m_out, xi_out, b_n_out, chi, eps
 
 
 def bond_update(ctx, desc, xi_m, b_m, b_n, u, stream=None):

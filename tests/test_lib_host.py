@@ -84,7 +84,7 @@ BAD_DESCRIPTORS = [
     ("NaN svd_min", dict(svd_min=float("nan")), lib.MPS_ERR_ARG, "svd_min"),
     ("sweeps > 16", dict(sweeps=17), lib.MPS_ERR_ARG, "sweeps"),
     ("negative sweeps", dict(sweeps=-1), lib.MPS_ERR_ARG, "sweeps"),
-    ("d^2 > 160", dict(d=13, chi_l=1, chi_m=1, chi_r=1, eta=1), lib.MPS_ERR_CAPACITY, "d=13"),
+    ("d > 25", dict(d=26, chi_l=1, chi_m=1, chi_r=1, eta=1), lib.MPS_ERR_CAPACITY, "d=26"),
     ("d chi beyond the QR row limit", dict(d=5, chi_l=8200, chi_m=8200, chi_r=8200, eta=100, chi_max=100),
      lib.MPS_ERR_CAPACITY, "too large"),
     ("CBE eta > 1536", dict(d=4, chi_l=1024, chi_m=1024, chi_r=1024, eta=1537, chi_max=100),
