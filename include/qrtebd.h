@@ -94,6 +94,9 @@ typedef struct {
   int mode;
   int prec;
   int sweeps;
+  int left_iso;   /* PLAIN / GROW only (appended field, zero: Hastings' form):
+                     b_m_out receives the left-isometric A~^[m] = Q^[m],
+                     [chi_l][d][eta], instead of B~^[m] (Sec. II comments) */
 } mps_bond_desc;
 
 /* Create / destroy a context on HIP device `device`.  Workspace grows on
@@ -233,6 +236,29 @@ typedef struct {
  * state, the summed truncation error is added to trunc_err_dev[s]. */
 int mps_sweep(mps_ctx ctx, mps_state* states, int nstates, const void* const* gates, int nsteps,
               int order, const mps_sweep_policy* policy, double* trunc_err_dev, mps_stream stream);
+
+/* Sequential sweeps on a finite chain in the left-isometric form (Sec. II
+ * comments): the QR update hands back A~^[m] = Q^[m] left-isometric, so a
+ * sweep to the right updates bond 0, 1, ..., L-2 in turn, each seeing the bond
+ * matrix the previous update produced.  One second-order step applies the
+ * gates U_b(dt/2) for b = 0 .. L-2 and then for b = L-2 .. 0; the return
+ * sweep is the same update on the mirror image of the chain (site order
+ * reversed, the two virtual legs of every tensor and the two sites of every
+ * gate exchanged), done by transposing the tensors in place.
+ *  sites[m]   device buffer of site m, [chi[m]][d][chi[m+1]], capacity
+ *             chi_cap*d*chi_cap elements (complex128 or complex64 per prec);
+ *             right-isometric on entry and on return
+ *  center     device buffer of chi_cap*chi_cap complex128: the bond matrix
+ *             left of site 0, [[1]] on entry and on return (the norm is kept
+ *             in the sites)
+ *  chi        host array of L+1 bond dimensions (chi[0] = chi[L] = 1), in/out
+ *  gates_half device [L-1][(d*d)^2] complex128: U_b(dt/2) of bond b
+ *  mode       MPS_TRUNC_PLAIN (eta = chi_m: dimensions fixed) or
+ *             MPS_TRUNC_GROW (eta = min(chi_max, chi_cap, d chi_l, d chi_r))
+ * Each bond's new matrix is L / |L|_F.  Bonds run one after another (each
+ * depends on the previous one); no host synchronisation. */
+int mps_sweep_sequential(mps_ctx ctx, int L, int d, int chi_cap, int prec, void* const* sites, void* center,
+                         int* chi, const void* gates_half, int nsteps, int mode, int chi_max, mps_stream stream);
 
 /* Counters of the context since its creation (8 entries): layers run with a
  * chi read-back, host synchronisations inside mps_sweep, speculative chunks,

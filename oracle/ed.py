@@ -98,3 +98,12 @@ def cut_entropy(psi, m, L, d):
     w = np.linalg.eigvalsh(rho / np.trace(rho).real)
     w = w[w > 1e-300]
     return float(-np.sum(w * np.log(w)))
+
+
+def sequential_circuit(psi, gates_half, L, d, nsteps):
+    """The gate order of a second-order sequential sweep on the state vector:
+    per step U_b(dt/2) for b = 0 .. L-2, then b = L-2 .. 0."""
+    for _ in range(nsteps):
+        for m in list(range(L - 1)) + list(range(L - 2, -1, -1)):
+            psi = apply_two_site(psi, gates_half[m], m, L, d)
+    return psi

@@ -148,3 +148,68 @@ def to_statevector(state):
 
 def chi_profile(state):
     return [b.shape[2] for b in state["B"]]
+
+
+# ---- sequential sweeps in the left-isometric form (Sec. II, comments) ----
+#
+# The QR truncation hands back the new left tensor in left-isometric form,
+# A~^[m] = Q^[m], with the bond matrix L (normalised) between m and n and the
+# right-isometric B~^[n] = Q^[n].  Keeping that form instead of Hastings' B~^[m]
+# lets the update run on a finite chain sweeping to the right: the next bond
+# (n, n+1) sees the bond matrix just produced on its left and right-isometric
+# tensors on its right.  Reading taken for the return sweep: it is the same
+# update applied to the mirror image of the chain (site order reversed, each
+# tensor's two virtual legs exchanged, each gate's two sites exchanged), so a
+# step of gates G_b(dt/2) for b = 0 .. L-2 followed by b = L-2 .. 0 is
+# symmetric (second order) and returns the chain to right-isometric form with
+# the bond matrix [[1]] at its left end.
+
+
+def reflect_tensor(t):
+    """Exchange the two virtual legs: [a, i, b] -> [b, i, a]."""
+    return np.ascontiguousarray(t.transpose(2, 1, 0))
+
+
+def reflect_gate(U, d):
+    """The gate with its two sites exchanged: (i j),(i' j') -> (j i),(j' i')."""
+    return np.ascontiguousarray(U.reshape(d, d, d, d).transpose(1, 0, 3, 2).reshape(d * d, d * d))
+
+
+def left_sweep(B, center, gates, mode, eta_rule, chi_max=None):
+    """Update bonds 0 .. L-2 in order with A~^[b] = Q^[b] (returns the new
+    site list; the last site absorbs the final bond matrix from the left).
+
+    B: right-isometric sites, center: dense bond matrix left of site 0.
+    mode PLAIN (eta = chi_m) or GROW (eta = eta_rule(chi_l, chi_m, chi_r)).
+    """
+    B = list(B)
+    L = len(B)
+    xi = center
+    for b in range(L - 1):
+        chiL, d, chiM = B[b].shape
+        chiR = B[b + 1].shape[2]
+        eta = chiM if mode == _bond.PLAIN else eta_rule(chiL, chiM, chiR, d)
+        r = _bond.qr_bond_update(xi, B[b], B[b + 1], gates[b], mode=mode, eta=eta, chi_max=chi_max)
+        B[b] = r["Q"].reshape(chiL, d, r["Q"].shape[1])
+        B[b + 1] = r["bn"]
+        xi = r["xi"]
+    B[L - 1] = np.tensordot(xi, B[L - 1], axes=([1], [0]))
+    return B
+
+
+def sequential_step(state, gates_half, mode=_bond.PLAIN, eta_rule=None, chi_max=None):
+    """One second-order step of sequential sweeps (see the comment above):
+    gates_half[b] = U(dt/2) of bond b.  state: finite chain in right-isometric
+    form with Xi[0] the dense bond matrix [[1]] at the left end; updated in
+    place (afterwards Xi[0] = [[1]] again, other Xi entries are not kept)."""
+    assert state["finite"]
+    B = state["B"]
+    L = len(B)
+    d = B[0].shape[1]
+    B = left_sweep(B, np.atleast_2d(state["Xi"][0]).astype(np.complex128), gates_half, mode, eta_rule, chi_max)
+    R = [reflect_tensor(t) for t in B[::-1]]
+    gr = [reflect_gate(U, d) for U in gates_half[:L - 1][::-1]]
+    R = left_sweep(R, np.ones((1, 1), np.complex128), gr, mode, eta_rule, chi_max)
+    state["B"] = [reflect_tensor(t) for t in R[::-1]]
+    state["Xi"] = [np.ones((1, 1), np.complex128)] + [None] * (L - 1)
+    return state

@@ -175,6 +175,8 @@ int check_desc(const mps_bond_desc* D) {
   if (D->mode == MPS_TRUNC_CBE && D->eta > kEigMaxN)
     return set_error(MPS_ERR_CAPACITY, "eta=%d > %d (CBE eigensolver limit)", D->eta, kEigMaxN);
   if (D->sweeps < 0 || D->sweeps > 16) return set_error(MPS_ERR_ARG, "sweeps=%d outside [0, 16]", D->sweeps);
+  if (D->left_iso && D->mode == MPS_TRUNC_CBE)
+    return set_error(MPS_ERR_ARG, "left-isometric output needs mode PLAIN or GROW (A~ = Q^[m])");
   return 0;
 }
 
@@ -184,6 +186,7 @@ BondShape shape_of(const mps_bond_desc* D) {
   b.eta = D->eta; b.chi_max = D->chi_max; b.svd_min = D->svd_min;
   b.xi_is_diag = D->xi_is_diag; b.mode = D->mode; b.prec = D->prec;
   b.sweeps = std::max(1, D->sweeps);
+  b.left_iso = D->left_iso ? 1 : 0;
   return b;
 }
 
@@ -1068,6 +1071,153 @@ int mps_sweep(mps_ctx c, mps_state* states, int nstates, const void* const* gate
     if ((rc = step_eager(c, states, nstates, gates, order, pol, trunc_err_dev, s))) return rc;
     ++step;
   }
+  return MPS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// out[b][i][a] = in[a][i][b]
+template <typename S>
+__global__ void reflect_site_kernel(const cpx<S>* in, int na, int d, int nb, cpx<S>* out) {
+  const long long n = (long long)na * d * nb;
+  for (long long idx = blockIdx.x * 256ll + threadIdx.x; idx < n; idx += (long long)gridDim.x * 256) {
+    const long long ia = idx / ((long long)d * nb), r = idx % ((long long)d * nb);
+    const int i = (int)(r / nb), ib = (int)(r % nb);
+    out[((long long)ib * d + i) * na + ia] = in[idx];
+  }
+}
+
+// out[k] = in[nb - 1 - k] with the gate's two sites exchanged:
+// out[(j i), (j' i')] = in[(i j), (i' j')]
+__global__ void reflect_gates_kernel(const c128* in, int nb, int d, c128* out) {
+  const int d2 = d * d;
+  const long long per = (long long)d2 * d2, n = per * nb;
+  for (long long idx = blockIdx.x * 256ll + threadIdx.x; idx < n; idx += (long long)gridDim.x * 256) {
+    const int k = (int)(idx / per);
+    const int r = (int)(idx % per), row = r / d2, col = r % d2;
+    const int i = row / d, j = row % d, ip = col / d, jp = col % d;
+    out[idx] = in[(long long)(nb - 1 - k) * per + (long long)(j * d + i) * d2 + (jp * d + ip)];
+  }
+}
+
+__global__ void unit_center_kernel(c128* center) { center[0] = mk<double>(1, 0); }
+
+template <typename D>
+__global__ void cast_center_kernel(const c128* in, long long n, cpx<D>* out) {
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256) out[i] = ccast<D>(in[i]);
+}
+
+inline int grid_of(long long n) { return (int)std::max<long long>(1, std::min<long long>((n + 255) / 256, 4096)); }
+
+}  // namespace
+
+extern "C" {
+
+int mps_sweep_sequential(mps_ctx c, int L, int d, int chi_cap, int prec, void* const* sites, void* center, int* chi,
+                         const void* gates_half, int nsteps, int mode, int chi_max, mps_stream stream) {
+  if (!c || !sites || !center || !chi || !gates_half) return set_error(MPS_ERR_ARG, "null argument");
+  if (L < 2 || L > kMaxSites || d < 1 || chi_cap < 1 || (prec != MPS_C128 && prec != MPS_MIXED_C64))
+    return set_error(MPS_ERR_ARG, "bad L / d / chi_cap / prec");
+  if (mode != MPS_TRUNC_PLAIN && mode != MPS_TRUNC_GROW) return set_error(MPS_ERR_ARG, "mode must be PLAIN or GROW");
+  if (mode == MPS_TRUNC_GROW && chi_max < 1) return set_error(MPS_ERR_ARG, "chi_max must be >= 1");
+  if (chi[0] != 1 || chi[L] != 1) return set_error(MPS_ERR_ARG, "a finite chain has chi = 1 at both ends");
+  for (int m = 0; m <= L; ++m)
+    if (chi[m] < 1 || chi[m] > chi_cap) return set_error(MPS_ERR_ARG, "chi[%d]=%d outside [1, chi_cap]", m, chi[m]);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t es = prec == MPS_C128 ? 16 : 8;
+  const int nb = L - 1;
+  // workspace: one bond update at capacity shape, a site-sized buffer, the
+  // mirrored gates and the bond matrix in storage precision, chi and eps words
+  mps_bond_desc Dc{};
+  Dc.d = d;
+  Dc.chi_l = Dc.chi_m = Dc.chi_r = chi_cap;
+  Dc.eta = mode == MPS_TRUNC_PLAIN ? chi_cap : std::min(std::min(chi_max, chi_cap), d * chi_cap);
+  Dc.chi_max = Dc.eta;
+  Dc.xi_is_diag = 0;
+  Dc.mode = mode;
+  Dc.prec = prec;
+  Dc.left_iso = 1;
+  int rc = check_desc(&Dc);
+  if (rc) return rc;
+  auto a256 = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t bond_ws = a256(bond_work_bytes(shape_of(&Dc)));
+  const size_t site_bytes = a256((size_t)chi_cap * d * chi_cap * es);
+  const size_t gate_bytes = a256((size_t)nb * d * d * d * d * 16);
+  const size_t cen_bytes = a256((size_t)chi_cap * chi_cap * 16);
+  if ((rc = ensure_ws(c, bond_ws + site_bytes + gate_bytes + cen_bytes + 512, s))) return rc;
+  char* p = (char*)c->ws;
+  void* bws = p;
+  void* tmp = p + bond_ws;
+  c128* rgates = (c128*)(p + bond_ws + site_bytes);
+  void* cen_s = p + bond_ws + site_bytes + gate_bytes;
+  int* chi_dev = (int*)(p + bond_ws + site_bytes + gate_bytes + cen_bytes);
+  double* eps_dev = (double*)(chi_dev + 64);
+  hipLaunchKernelGGL(reflect_gates_kernel, dim3(grid_of((long long)nb * d * d * d * d)), dim3(256), 0, s,
+                     (const c128*)gates_half, nb, d, rgates);
+  QT_HIP_CHECK(hipGetLastError());
+  g_tune = TuneParams{};
+  std::vector<void*> site(sites, sites + L);
+  std::vector<int> ch(chi, chi + L + 1);
+  const GemmTypes ty{prec == MPS_C128 ? DT_C128 : DT_C64, prec == MPS_C128 ? DT_C128 : DT_C64};
+  for (int step = 0; step < nsteps; ++step)
+    for (int half = 0; half < 2; ++half) {
+      const c128* g = half == 0 ? (const c128*)gates_half : rgates;
+      // sweep to the right: bond b -> A~^[b] = Q^[b], bond matrix L / |L|, B~^[b+1]
+      // (outputs overwrite inputs: each input is read before its output is written)
+      for (int b = 0; b < nb; ++b) {
+        mps_bond_desc D = Dc;
+        D.chi_l = ch[b];
+        D.chi_m = ch[b + 1];
+        D.chi_r = ch[b + 2];
+        D.eta = mode == MPS_TRUNC_PLAIN ? ch[b + 1]
+                                        : std::min(std::min(chi_max, chi_cap), std::min(d * ch[b], d * ch[b + 2]));
+        D.chi_max = D.eta;
+        if ((rc = check_desc(&D))) return rc;
+        const BondShape bs = shape_of(&D);
+        if ((rc = bond_update_run(bs, bws, c->status, center, site[b], site[b + 1], g + (size_t)b * d * d * d * d,
+                                  site[b], center, site[b + 1], chi_dev, eps_dev, s, nullptr, &c->qa)))
+          return rc;
+        ch[b + 1] = D.eta;
+      }
+      // the last site absorbs the bond matrix: M = Xi B^[L-1]
+      const int cl = ch[L - 1];
+      const void* xiA = center;
+      if (prec != MPS_C128) {
+        hipLaunchKernelGGL(cast_center_kernel<float>, dim3(grid_of((long long)cl * cl)), dim3(256), 0, s,
+                           (const c128*)center, (long long)cl * cl, (c64*)cen_s);
+        QT_HIP_CHECK(hipGetLastError());
+        xiA = cen_s;
+      }
+      const int ncol = d * ch[L];
+      if ((rc = gemm_one(gemm_prob(xiA, cl, OP_N, site[L - 1], ncol, OP_N, tmp, ncol, cl, ncol, cl), ty, s))) return rc;
+      QT_HIP_CHECK(hipMemcpyAsync(site[L - 1], tmp, (size_t)cl * ncol * es, hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(unit_center_kernel, dim3(1), dim3(1), 0, s, (c128*)center);
+      QT_HIP_CHECK(hipGetLastError());
+      // mirror the chain: site m <- reflect(site L-1-m), chi reversed
+      for (int m = 0; m <= (L - 1) / 2; ++m) {
+        const int k = L - 1 - m;
+        const long long nm = (long long)ch[m] * d * ch[m + 1], nk = (long long)ch[k] * d * ch[k + 1];
+        if (prec == MPS_C128) {
+          hipLaunchKernelGGL(reflect_site_kernel<double>, dim3(grid_of(nk)), dim3(256), 0, s, (const c128*)site[k],
+                             ch[k], d, ch[k + 1], (c128*)tmp);
+          if (k != m)
+            hipLaunchKernelGGL(reflect_site_kernel<double>, dim3(grid_of(nm)), dim3(256), 0, s, (const c128*)site[m],
+                               ch[m], d, ch[m + 1], (c128*)site[k]);
+        } else {
+          hipLaunchKernelGGL(reflect_site_kernel<float>, dim3(grid_of(nk)), dim3(256), 0, s, (const c64*)site[k],
+                             ch[k], d, ch[k + 1], (c64*)tmp);
+          if (k != m)
+            hipLaunchKernelGGL(reflect_site_kernel<float>, dim3(grid_of(nm)), dim3(256), 0, s, (const c64*)site[m],
+                               ch[m], d, ch[m + 1], (c64*)site[k]);
+        }
+        QT_HIP_CHECK(hipGetLastError());
+        QT_HIP_CHECK(hipMemcpyAsync(site[m], tmp, (size_t)nk * es, hipMemcpyDeviceToDevice, s));
+      }
+      std::reverse(ch.begin(), ch.end());
+    }
+  std::copy(ch.begin(), ch.end(), chi);
   return MPS_OK;
 }
 

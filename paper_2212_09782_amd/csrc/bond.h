@@ -22,6 +22,7 @@ struct BondShape {
   double svd_min;
   int xi_is_diag, mode, prec;
   int sweeps = 1;      // QR/LQ sweeps (>= 1)
+  int left_iso = 0;    // PLAIN / GROW: b_m_out = Q^[m] (left-isometric) instead of Hastings' B~^[m]
   int cap() const;     // capacity of the new bond
 };
 

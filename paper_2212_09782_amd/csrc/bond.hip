@@ -532,17 +532,26 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
     }
     if ((rc = gemm_run(g.data(), nc, ty, s))) return rc;
   }
+  // left-isometric output (Sec. II comments): A~^[m] = Q^[m], the explicit Q
+  // of the (last) QR of X, (chi_l d) x eta
+  for (int i = 0; i < nc; ++i) {
+    const BondCall& c = calls[i];
+    if (!c.b.left_iso) continue;
+    const size_t bytes = (size_t)c.b.d * c.b.chi_l * c.b.eta * sizeof(cpx<S>);
+    QT_HIP_CHECK(hipMemcpyAsync(c.b_m_out, W[i].X, bytes, hipMemcpyDeviceToDevice, s));
+  }
   // B~^[m] = C~ B~^[n]^dag  (chi_l d x chi~, compact with the live chi~)
   g.clear();
   for (int i = 0; i < nc; ++i) {
     const BondCall& c = calls[i];
+    if (c.b.left_iso) continue;
     const int cap = c.b.cap(), mL = c.b.d * c.b.chi_l, mR = c.b.d * c.b.chi_r;
     GemmProb gp = gemm_prob(W[i].C, mR, OP_N, c.b_n_out, mR, OP_C, c.b_m_out, cap, mL, cap, mR);
     gp.dN = c.chi_new;
     gp.ldc_live_N = 1;
     g.push_back(gp);
   }
-  return timed_gemm_batch(tm, g.data(), nc, ty, s);
+  return g.empty() ? 0 : timed_gemm_batch(tm, g.data(), (int)g.size(), ty, s);
 }
 
 }  // namespace

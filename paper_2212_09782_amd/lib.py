@@ -23,7 +23,7 @@ EXPORTS = [
     "mps_workspace_query", "mps_bond_update", "mps_clock_gate", "mps_state_create",
     "mps_state_destroy", "mps_state_chis", "mps_sweep", "mps_measure", "mps_zgemm", "mps_qr",
     "mps_heig", "mps_profile_enable", "mps_profile_read", "mps_bond_update_noalloc", "mps_sweep_stats",
-    "mps_clock_hamiltonian", "mps_bond_update_reference",
+    "mps_clock_hamiltonian", "mps_bond_update_reference", "mps_sweep_sequential",
 ]
 SCHEME_SVD, SCHEME_EIG = 0, 1
 
@@ -32,7 +32,7 @@ class mps_bond_desc(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int), ("chi_l", ctypes.c_int), ("chi_m", ctypes.c_int),
                 ("chi_r", ctypes.c_int), ("eta", ctypes.c_int), ("chi_max", ctypes.c_int),
                 ("svd_min", ctypes.c_double), ("xi_is_diag", ctypes.c_int), ("mode", ctypes.c_int),
-                ("prec", ctypes.c_int), ("sweeps", ctypes.c_int)]
+                ("prec", ctypes.c_int), ("sweeps", ctypes.c_int), ("left_iso", ctypes.c_int)]
 
 
 class mps_sweep_policy(ctypes.Structure):
@@ -78,6 +78,7 @@ def _declare(lib):
                           ctypes.POINTER(mps_sweep_policy), P, P]),
         "mps_measure": (I, [P, P, P, P, P, P, P, P, P]),
         "mps_sweep_stats": (I, [P, ctypes.POINTER(ctypes.c_longlong)]),
+        "mps_sweep_sequential": (I, [P, I, I, I, I, ctypes.POINTER(P), P, ctypes.POINTER(I), P, I, I, I, P]),
         "mps_zgemm": (I, [P, I, I, I, I, I, I, P, LL, P, LL, P, LL, D, D, P]),
         "mps_qr": (I, [P, I, I, I, P, P, P]),
         "mps_heig": (I, [P, I, I, P, P, P, P]),
@@ -171,8 +172,9 @@ def clock_hamiltonian(d, g, wl=0.5, wr=0.5):
 
 
 def bond_desc(d, chi_l, chi_m, chi_r, eta, chi_max, svd_min=1e-14, xi_is_diag=True, mode=CBE, prec=MPS_C128,
-              sweeps=1):
-    return mps_bond_desc(d, chi_l, chi_m, chi_r, eta, chi_max, svd_min, int(bool(xi_is_diag)), mode, prec, sweeps)
+              sweeps=1, left_iso=False):
+    return mps_bond_desc(d, chi_l, chi_m, chi_r, eta, chi_max, svd_min, int(bool(xi_is_diag)), mode, prec, sweeps,
+                         int(bool(left_iso)))
 
 
 def bond_capacity(desc):
@@ -370,3 +372,44 @@ def chain_gates(d, g, L, finite, dt):
         out[b, 0] = clock_gate(d, g, dt / 2, wl, wr)
         out[b, 1] = clock_gate(d, g, dt, wl, wr)
     return torch.from_numpy(out).to("cuda")
+
+
+class SequentialState:
+    """Finite chain for mps_sweep_sequential: site buffers of capacity
+    chi_cap*d*chi_cap and the bond matrix at the left end (torch buffers)."""
+
+    def __init__(self, ctx, B, chi_cap, prec=MPS_C128):
+        """B: list of numpy [chi_l, d, chi_r] in right-isometric form."""
+        import torch
+        self.ctx = ctx
+        self.L = len(B)
+        self.d = B[0].shape[1]
+        self.prec = prec
+        self.chi_cap = int(chi_cap)
+        cdt = torch.complex128 if prec == MPS_C128 else torch.complex64
+        self.sites = [torch.zeros(self.chi_cap * self.d * self.chi_cap, dtype=cdt, device="cuda") for _ in B]
+        for m in range(self.L):
+            flat = torch.from_numpy(np.ascontiguousarray(B[m]).reshape(-1)).to(cdt)
+            self.sites[m][: flat.numel()].copy_(flat)
+        self.center = torch.zeros(self.chi_cap * self.chi_cap, dtype=torch.complex128, device="cuda")
+        self.center[0] = 1
+        self.chi = [b.shape[0] for b in B] + [B[-1].shape[2]]
+
+    def sweep(self, gates_half, nsteps, mode=PLAIN, chi_max=0, stream=None):
+        """nsteps second-order sequential steps (gates_half: device [L-1, d^2, d^2] complex128)."""
+        sp = (P * self.L)(*[P(t.data_ptr()) for t in self.sites])
+        ch = (I * (self.L + 1))(*self.chi)
+        _check(self.ctx.lib.mps_sweep_sequential(self.ctx.h, self.L, self.d, self.chi_cap, self.prec, sp,
+                                                 _ptr(self.center), ch, _ptr(gates_half), nsteps, mode, chi_max,
+                                                 _stream(stream)))
+        self.chi = list(ch)
+
+    def to_numpy(self):
+        import torch
+        torch.cuda.synchronize()
+        out = []
+        for m in range(self.L):
+            n = self.chi[m] * self.d * self.chi[m + 1]
+            out.append(self.sites[m][:n].cpu().numpy().astype(np.complex128).reshape(self.chi[m], self.d,
+                                                                                     self.chi[m + 1]))
+        return out

@@ -429,3 +429,82 @@ def test_uniform_cell_matches_finite_chain_bulk():
         assert np.max(np.abs(z[20:22] - zc[k])) < 1e-8, k
         assert np.max(np.abs(e[20:22] - ec[k])) < 1e-8, k
     assert abs(zc[-1][0] - 1.0) > 0.3                            # the quench has moved <Z>
+
+
+# ---- sequential sweeps in the left-isometric form (Sec. II comments) ----
+
+def _grow_full(cl, cm, cr, d):
+    return min(d * cl, d * cr)
+
+
+def _seq_gates(d, g, L, dt):
+    return [clock.gate(h, dt / 2) for h in clock.chain_hamiltonians(d, g, L, True)]
+
+
+def test_sequential_sweep_equals_its_circuit():
+    """Untruncated sequential steps (growth to eta = min(d chi_l, d chi_r)) from
+    |0...0> reproduce the state-vector circuit of the same gate order (U_b(dt/2)
+    for b = 0..L-2, then L-2..0): the left-isometric update with Xi~ = L/|L|
+    loses nothing without truncation."""
+    d, g, L, dt, n = 3, 2.0, 6, 0.1, 4
+    gh = _seq_gates(d, g, L, dt)
+    st = mps.product_state(L, d)
+    psi = ed.product_vector(L, d)
+    for _ in range(n):
+        mps.sequential_step(st, gh, mode=bond.GROW, eta_rule=_grow_full)
+        psi = ed.sequential_circuit(psi, gh, L, d, 1)
+        v = mps.to_statevector(st)
+        assert abs(np.vdot(v, psi) - 1.0) < 1e-12   # same state, same global phase
+    # back in right-isometric form with the bond matrix [[1]] at the left end
+    for t in st["B"]:
+        M = t.reshape(t.shape[0], -1)
+        assert np.max(np.abs(M @ M.conj().T - np.eye(t.shape[0]))) < 1e-12
+    assert np.allclose(st["Xi"][0], 1.0)
+
+
+def test_sequential_plain_full_rank_is_exact():
+    """Plain mode keeps chi fixed; on a full-rank profile min(d^b, d^(L-b)) no
+    truncation happens, so the sweep again equals its circuit (c.2 (gamma))."""
+    d, g, L, dt = 2, 1.5, 6, 0.1
+    r = inputs.rng(3)
+    chis = [1] + [min(d ** b, d ** (L - b)) for b in range(1, L)] + [1]
+    B = [inputs.right_isometric(chis[m], d, chis[m + 1], r) for m in range(L)]
+    st = dict(B=[b.copy() for b in B], Xi=[np.ones((1, 1))] + [None] * (L - 1), finite=True)
+    psi = mps.to_statevector(dict(B=B, Xi=[np.ones(1)], finite=True))
+    gh = _seq_gates(d, g, L, dt)
+    for _ in range(3):
+        mps.sequential_step(st, gh, mode=bond.PLAIN)
+        psi = ed.sequential_circuit(psi, gh, L, d, 1)
+    assert abs(np.vdot(mps.to_statevector(st), psi) - 1.0) < 1e-12
+    assert [t.shape[0] for t in st["B"]] == chis[:-1]
+
+
+def test_left_sweep_produces_left_isometries():
+    """Within a sweep to the right every updated site is A~ = Q^[m] with
+    sum_{a,i} A[a,i,b] conj(A[a,i,b']) = delta, and the last site carries the norm."""
+    d, g, L, dt = 3, 2.0, 5, 0.2
+    gh = _seq_gates(d, g, L, dt)
+    st = mps.product_state(L, d)
+    mps.sequential_step(st, gh, mode=bond.GROW, eta_rule=_grow_full)   # entangled start
+    out = mps.left_sweep(st["B"], np.ones((1, 1), np.complex128), gh, bond.GROW, _grow_full)
+    for t in out[:-1]:
+        M = t.reshape(-1, t.shape[2])
+        assert np.max(np.abs(M.conj().T @ M - np.eye(t.shape[2]))) < 1e-12
+    assert abs(np.linalg.norm(out[-1]) - 1.0) < 1e-12
+
+
+def test_sequential_sweep_is_second_order():
+    """The symmetric sweep order is a second-order product formula: the
+    error against exp(-iHt) drops about 4x when dt halves."""
+    d, g, L, T = 3, 2.0, 5, 0.4
+    H = ed.sparse_hamiltonian(d, g, L)
+    exact = ed.exact_evolve(ed.product_vector(L, d), H, T)
+    errs = []
+    for dt in (0.1, 0.05):
+        st = mps.product_state(L, d)
+        gh = _seq_gates(d, g, L, dt)
+        for _ in range(int(round(T / dt))):
+            mps.sequential_step(st, gh, mode=bond.GROW, eta_rule=_grow_full)
+        errs.append(np.linalg.norm(mps.to_statevector(st) - exact))
+    ratio = errs[0] / errs[1]
+    assert 3.3 < ratio < 4.7, ratio
