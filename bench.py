@@ -498,9 +498,16 @@ def main():
         d = 10 if args.d == 5 else args.d
         cm = args.chi_max if args.chi_max != 512 else 1024
         res = {}
-        for key, p in (("c128", lib.MPS_C128), ("c64", lib.MPS_MIXED_C64)):
+        legs = [("c128", lib.MPS_C128)] * (args.prec in ("both", "c128")) + \
+               [("c64", lib.MPS_MIXED_C64)] * (args.prec in ("both", "mixed"))
+        for key, p in legs:
             print(f"# quench {key} d={d} g={args.g} chi_max={cm} {args.steps} steps", file=sys.stderr, flush=True)
             res[key] = run_quench(lib, torch, p, d, args.g, cm, args.steps, args.dt, 100, args.exec, args.autotune)
+        if len(res) < 2:
+            r = next(iter(res.values()))
+            print(json.dumps({"quench": next(iter(res)), "seconds": r["seconds"], "final_chi": r["chis"][-1],
+                              "z_last": r["z"][-1].tolist(), "trunc_err_sum": r["eps_sum"]}), flush=True)
+            return
         a, b = res["c128"], res["c64"]
         dz = np.abs(a["z"] - b["z"]).max(axis=1)
         de = np.abs(a["e"].mean(axis=1) - b["e"].mean(axis=1))

@@ -8,6 +8,7 @@ namespace qrtebd {
 // keeps every row in LDS (at most 150 KiB per block, one block per CU), so
 // ceil(n / floor(150 KiB / (16 n))) blocks must fit the 256 CUs.
 constexpr int kEigMaxN = 1536;
+constexpr int kNsMaxSteps = 5;
 
 struct EigWork {
   double* d;        // n   diagonal of the tridiagonal matrix
@@ -19,7 +20,8 @@ struct EigWork {
   QrWork qtri;      // reflectors of the tridiagonalisation, (n-1) x (n-1) problem with n work columns
   c128* gz;         // n x n Gram matrix of the eigenvector block (Newton-Schulz polish)
   c128* ztmp;       // n x n copy of the eigenvector block
-  c128* tpart;      // split-K partials of V_p^H V_p for every reflector panel (8 x 32 x 32 each)
+  c128* tpart;      // split-K partials of V_p^H V_p for every panel p (8 x 32 x 32 each)
+  int* ns_live;     // [0] live K of Z^H Z (n or 0), [1] live K of the update (kwant or 0), [2..3] max |Z^H Z - 1| bits
   int* status;
 };
 
@@ -39,7 +41,9 @@ struct EigJob {
   double* lam;
   c128* E;
   const EigWork* w;
-  int ns_steps = 2;   // Newton-Schulz re-orthonormalisation steps of the eigenvectors (0..2)
+  int ns_steps = 2;   // Newton-Schulz steps of the eigenvectors always taken (0..2); up to
+                      // kNsMaxSteps in all until max |Z^H Z - 1| before a step is below 1e-7
+                      // (vectors of close, unclustered eigenvalues overlap more)
 };
 int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s);
 

@@ -16,9 +16,10 @@
 //     partial pivoting, two solves from a fixed pseudo-random start), one
 //     thread per vector.
 //  4. Re-orthogonalisation: modified Gram-Schmidt (two passes) inside each
-//     cluster of eigenvalues closer than 1e-9 |T| (where independent inverse
-//     iterations can return nearly parallel vectors), then two Newton-Schulz
-//     steps Z <- Z - Z (Z^H Z - 1)/2 on the MFMA GEMM.  Mixing two vectors by
+//     cluster of eigenvalues closer than 1e-11 |T| (where independent inverse
+//     iterations can return nearly parallel vectors), then Newton-Schulz
+//     steps Z <- Z - Z (Z^H Z - 1)/2 on the MFMA GEMM (two, and up to five
+//     while the overlaps left by close unclustered eigenvalues remain).  Mixing two vectors by
 //     their overlap, which is ~u|T|/gap, moves their residuals by ~u|T|
 //     whatever the gap, so the polish keeps the eigenvectors accurate.
 //  5. Back-transformation E = Q Z with the compact-WY blocks of step 1 on
@@ -37,6 +38,11 @@ constexpr int kMaxN = 2048;         // largest matrix
 constexpr int kTriThreads = 512;    // threads of a tridiagonalisation block (two waves per SIMD)
 constexpr int QMAX = kMaxN / kTriThreads;   // register slots per thread
 constexpr size_t kTriLds = 150 * 1024;
+// Eigenvalues closer than this times max |lambda| form a cluster whose
+// inverse-iteration vectors are orthogonalised by Gram-Schmidt (below it they
+// may come out nearly parallel); wider gaps leave overlaps of about u / rtol
+// that the Newton-Schulz steps remove.
+constexpr double kClusterRtol = 1e-11;
 constexpr int kTriChunk = 8;          // rows per pass of register partials of A v
 constexpr int kTriRows = 16;          // rows per block at most (two passes)
 static_assert(kEigMaxN <= kMaxN, "eigensolver limit above the register layout");
@@ -706,6 +712,41 @@ __global__ __launch_bounds__(256) void cluster_mgs_kernel(SmallBatch sb, double 
     }
 }
 
+// Adaptive Newton-Schulz steps.  live[0]: K extent of the next Z^H Z (n, or 0
+// once stopped); live[1]: K extent of this step's update (kwant or 0);
+// live[2..3]: bits of max |Z^H Z - 1| of this step (non-negative doubles order
+// as their bit patterns); live[4]: stopped; live[5]: kwant.
+__global__ void ns_init_kernel(int* live, int n, int kwant) {
+  live[0] = n;
+  live[1] = kwant;
+  live[4] = 0;
+  live[5] = kwant;
+}
+
+__global__ void ns_max_kernel(const c128* D, long long tot, int* live) {
+  double mx = 0;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < tot; i += (long long)gridDim.x * 256)
+    mx = fmax(mx, fmax(fabs(D[i].re), fabs(D[i].im)));
+  mx = wave_max(mx);
+  if ((threadIdx.x & 63) == 0)
+    atomicMax((unsigned long long*)(live + 2), (unsigned long long)__double_as_longlong(mx));
+}
+
+// From this step's max |Z^H Z - 1| (measured before its update, which squares
+// it): skip the update of an optional step already orthonormal to tol_skip;
+// stop all later steps once the error is below tol_stop (the update then
+// leaves about tol_stop^2).
+__global__ void ns_decide_kernel(int* live, int optional, double tol_skip, double tol_stop) {
+  const double mx = __longlong_as_double((long long)*(unsigned long long*)(live + 2));
+  const bool stopped = live[4] != 0;
+  live[1] = (stopped || (optional && !(mx >= tol_skip))) ? 0 : live[5];
+  if (!(mx >= tol_stop)) {
+    live[4] = 1;
+    live[0] = 0;
+  }
+  *(unsigned long long*)(live + 2) = 0ull;
+}
+
 // D = G - 1 on a k x k block (in place).
 __global__ void sub_identity_kernel(c128* G, int k) {
   const long long tot = (long long)k * k;
@@ -739,6 +780,7 @@ size_t eig_work_bytes(int n) {
   b += align256(qr_work_bytes(std::max(n - 1, 1), std::max(n - 1, 1), 16, n));
   b += 2 * align256((size_t)n * n * 16);
   b += align256((size_t)((n - 1 + NB - 1) / NB + 1) * kLarftParts * NB * NB * 16);
+  b += 256;   // ns_live
   return b;
 }
 
@@ -757,6 +799,7 @@ EigWork eig_work_carve(void* base, int n, int* status) {
   w.gz = (c128*)p; p += align256((size_t)n * n * 16);
   w.ztmp = (c128*)p; p += align256((size_t)n * n * 16);
   w.tpart = (c128*)p; p += align256((size_t)((n - 1 + NB - 1) / NB + 1) * kLarftParts * NB * NB * 16);
+  w.ns_live = (int*)p; p += 256;
   w.status = status;
   return w;
 }
@@ -882,26 +925,38 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
     hipLaunchKernelGGL(invit_kernel, dim3((maxk + ig - 1) / ig, sb.njobs), dim3(64), invit_lds_bytes(maxn, ig), s, sb,
                        ig);
     QT_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(cluster_mgs_kernel, dim3(maxk, sb.njobs), dim3(256), 0, s, sb, 1e-9);
+    hipLaunchKernelGGL(cluster_mgs_kernel, dim3(maxk, sb.njobs), dim3(256), 0, s, sb, kClusterRtol);
     QT_HIP_CHECK(hipGetLastError());
   }
   // 6. Newton-Schulz steps Z <- Z - Z (Z^H Z - 1)/2 (each squares the
-  // orthogonality error of Z), grouped over the jobs
+  // orthogonality error of Z), grouped over the jobs: the job's ns_steps
+  // always, then further ones (up to kNsMaxSteps) until max |Z^H Z - 1| before
+  // a step is below 1e-7 (that step leaves ~1e-14), decided on the device: a
+  // finished job's products run with live extent 0.  Vectors of eigenvalues closer than the cluster tolerance
+  // were orthogonalised by Gram-Schmidt above; the rest overlap by at most
+  // about u / rtol, which these steps remove.
   const GemmTypes ty{DT_C128, DT_C128};
   std::vector<GemmProb> gs;
-  for (int it = 0; it < 2; ++it) {
+  for (int j : big) {
+    hipLaunchKernelGGL(ns_init_kernel, dim3(1), dim3(1), 0, s, jobs[j].w->ns_live, jobs[j].n, jobs[j].kwant);
+    QT_HIP_CHECK(hipGetLastError());
+    if ((rc = fill_zero(jobs[j].w->ns_live + 2, 8, s))) return rc;
+  }
+  for (int it = 0; it < kNsMaxSteps; ++it) {
     std::vector<int> ns;
     for (int j : big)
-      if (it < jobs[j].ns_steps) ns.push_back(j);
+      if (jobs[j].ns_steps > 0) ns.push_back(j);
     if (ns.empty()) break;
     gs.clear();
     for (int j : ns) {
       const EigJob& J = jobs[j];
+      const bool gated = it >= J.ns_steps;
       // the inverse-iteration factors are dead: their buffer holds split-K partials
       GemmProb g1 = gemm_prob(J.E, J.kwant, OP_C, J.E, J.kwant, OP_N, J.w->gz, J.kwant, J.kwant, J.kwant, J.n);
       g1.ksplit = splitk_auto(J.kwant, J.kwant, J.n, 4 * (size_t)J.n * J.n * 8, sizeof(c128), true);
       g1.work = J.w->lu;
       g1.herm = 1;
+      if (gated) g1.dK = J.w->ns_live;
       gs.push_back(g1);
     }
     if ((rc = gemm_run(gs.data(), (int)gs.size(), ty, s))) return rc;
@@ -910,14 +965,24 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
     gs.clear();
     for (int j : ns) {
       const EigJob& J = jobs[j];
+      const bool gated = it >= J.ns_steps;
+      const long long kk = (long long)J.kwant * J.kwant;
       hipLaunchKernelGGL(sub_identity_kernel, dim3(std::min(4096, (J.kwant * J.kwant + 255) / 256)), dim3(256), 0, s,
                          J.w->gz, J.kwant);
       QT_HIP_CHECK(hipGetLastError());
+      if (it + 1 >= J.ns_steps) {   // from the last fixed step on: decide the optional ones
+        hipLaunchKernelGGL(ns_max_kernel, dim3((int)std::min<long long>(1024, (kk + 255) / 256)), dim3(256), 0, s,
+                           (const c128*)J.w->gz, kk, J.w->ns_live);
+        QT_HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(ns_decide_kernel, dim3(1), dim3(1), 0, s, J.w->ns_live, gated ? 1 : 0, 1e-13, 1e-7);
+        QT_HIP_CHECK(hipGetLastError());
+      }
       QT_HIP_CHECK(hipMemcpyAsync(J.w->ztmp, J.E, (size_t)J.n * J.kwant * sizeof(c128), hipMemcpyDeviceToDevice, s));
       GemmProb g2 = gemm_prob(J.w->ztmp, J.kwant, OP_N, J.w->gz, J.kwant, OP_N, J.E, J.kwant, J.n, J.kwant, J.kwant,
                               -0.5f, 1.f);
       g2.ksplit = splitk_auto(J.n, J.kwant, J.kwant, 4 * (size_t)J.n * J.n * 8, sizeof(c128));
       g2.work = J.w->lu;
+      if (gated) g2.dK = J.w->ns_live + 1;
       gs.push_back(g2);
     }
     if ((rc = gemm_run(gs.data(), (int)gs.size(), ty, s))) return rc;
