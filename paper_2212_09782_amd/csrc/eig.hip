@@ -15,9 +15,13 @@
 //  3. Their eigenvectors by inverse iteration on T (tridiagonal LU with
 //     partial pivoting, two solves from a fixed pseudo-random start), one
 //     thread per vector.
-//  4. Re-orthogonalisation: modified Gram-Schmidt (two passes) inside each
-//     cluster of eigenvalues closer than 1e-11 |T| (where independent inverse
-//     iterations can return nearly parallel vectors), then Newton-Schulz
+//  4. Re-orthogonalisation inside each cluster of eigenvalues closer than
+//     1e-11 |T| (where independent inverse iterations can return nearly
+//     parallel vectors): modified Gram-Schmidt (two passes) for clusters of
+//     up to 16 vectors; larger ones by blocked Gram-Schmidt in one workgroup,
+//     one inverse-iteration step of the whole block with a shift just outside
+//     the cluster (which removes the rounding that the first
+//     orthogonalisation magnified) and blocked Gram-Schmidt again.  Then Newton-Schulz
 //     steps Z <- Z - Z (Z^H Z - 1)/2 on the MFMA GEMM (two, and up to five
 //     while the overlaps left by close unclustered eigenvalues remain).  Mixing two vectors by
 //     their overlap, which is ~u|T|/gap, moves their residuals by ~u|T|
@@ -43,6 +47,8 @@ constexpr size_t kTriLds = 150 * 1024;
 // may come out nearly parallel); wider gaps leave overlaps of about u / rtol
 // that the Newton-Schulz steps remove.
 constexpr double kClusterRtol = 1e-11;
+constexpr int kBigCluster = 16;   // larger clusters take the blocked Gram-Schmidt
+constexpr int kPan = 16;          // its panel width
 constexpr int kTriChunk = 8;          // rows per pass of register partials of A v
 constexpr int kTriRows = 16;          // rows per block at most (two passes)
 static_assert(kEigMaxN <= kMaxN, "eigensolver limit above the register layout");
@@ -395,6 +401,9 @@ struct SmallJob {
   c128* T;
   const c128* tau;
   const c128* tpart;
+  double* zr;   // blocked Gram-Schmidt: row-major cluster copies (n x m at n j)
+  double* zc;   // column-major cluster copies (n x m at n j)
+  double* wb;   // projection coefficients (m x kPan at kPan j)
   int n, kwant;
 };
 constexpr int kMaxSmallJobs = 24;
@@ -680,7 +689,8 @@ __global__ __launch_bounds__(256) void larft_kernel(SmallBatch sb) {
 
 // Two-pass modified Gram-Schmidt over each cluster of close eigenvalues
 // (lam descending; a cluster starts where the gap to the previous value
-// exceeds rtol * max|lam|).  Block b handles the cluster starting at column b, if any.
+// exceeds rtol * max|lam|) of at most kBigCluster columns.  Block b handles
+// the cluster starting at column b, if any.
 __global__ __launch_bounds__(256) void cluster_mgs_kernel(SmallBatch sb, double rtol) {
   __shared__ double scr[8];
   const SmallJob& J = sb.j[blockIdx.y];
@@ -693,7 +703,7 @@ __global__ __launch_bounds__(256) void cluster_mgs_kernel(SmallBatch sb, double 
   if (j > 0 && lam[j - 1] - lam[j] <= ctol) return;
   int e = j;
   while (e + 1 < kw && lam[e] - lam[e + 1] <= ctol) ++e;
-  if (e == j) return;
+  if (e == j || e - j + 1 > kBigCluster) return;
   for (int pass = 0; pass < 2; ++pass)
     for (int v = j; v <= e; ++v) {
       for (int u = j; u < v; ++u) {
@@ -710,6 +720,430 @@ __global__ __launch_bounds__(256) void cluster_mgs_kernel(SmallBatch sb, double 
       for (int i = threadIdx.x; i < n; i += 256) Z[(long long)i * kw + v].re *= f;
       __syncthreads();
     }
+}
+
+// ---- blocked Gram-Schmidt for clusters of more than kBigCluster columns
+// (one workgroup per cluster).  The cluster's m columns are copied twice,
+// row-major (Zr) and column-major (Zc), so that both products below read
+// memory contiguously.  Panels of kPan columns, each taken twice:
+//   W = Zr[:, :p0]^T Zr[:, p0:p0+P]     (lanes own columns u, loop over rows)
+//   Zc[:, p0:p0+P] -= Zc[:, :p0] W      (lanes own rows, loop over u)
+//   classical Gram-Schmidt inside the panel, column by column, and
+//   normalisation (the panel lives in registers, one block sum per step).
+// Two passes of the whole sequence give every column two projections
+// against all earlier columns of the cluster, as the two-pass MGS does.
+constexpr int kBcgsThreads = 512;
+constexpr int kBcgsRows = 3;    // matrix rows per thread in the row-owned phases
+constexpr int kBcgsChunk = 64;  // rows (or u) per LDS chunk
+static_assert(kEigMaxN <= kBcgsThreads * kBcgsRows, "blocked Gram-Schmidt row slots");
+constexpr int kBcgsLds = 2 * kBcgsChunk * kPan + 4 * kBcgsThreads;
+// LU factors of T - sigma: four n-vectors and n interchange flags
+constexpr int kFilterLds = 4 * kEigMaxN + kEigMaxN / 8;
+// distance of the cluster filter's shift from the cluster, relative to max |lam|
+constexpr double kFilterRel = 1e-8;
+
+// Start and size of the g-th cluster of more than kBigCluster columns
+// (out[0] = -1 if there is none); lam staged in lds (kw doubles).
+__device__ inline void find_big_cluster(const double* lam, int kw, double rtol, int g, double* lds, int* out) {
+  for (int c = threadIdx.x; c < kw; c += blockDim.x) lds[c] = lam[c];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double ctol = rtol * fmax(fabs(lds[0]), fabs(lds[kw - 1]));
+    int cnt = 0, j = 0;
+    out[0] = -1;
+    out[1] = 0;
+    while (j < kw) {
+      int e = j;
+      while (e + 1 < kw && lds[e] - lds[e + 1] <= ctol) ++e;
+      if (e - j + 1 > kBigCluster) {
+        if (cnt == g) {
+          out[0] = j;
+          out[1] = e - j + 1;
+          break;
+        }
+        ++cnt;
+      }
+      j = e + 1;
+    }
+  }
+  __syncthreads();
+}
+
+// Block sum of 16 values (every thread gets all 16), fixed order; sc holds
+// 8 * 16 + 16 doubles and must not be read by any thread since the block's
+// previous barrier.
+__device__ inline void block_sum16(double (&x)[kPan], double* sc) {
+  static_assert(kPan == 16, "block_sum16 reduces 16 values");
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const double t = wave_sum16(x);   // lane l: wave total of x[l >> 2]
+  if ((lane & 3) == 0) sc[wid * kPan + (lane >> 2)] = t;
+  __syncthreads();
+  if (threadIdx.x < kPan) {
+    double a = 0;
+    for (int w = 0; w < kBcgsThreads / 64; ++w) a += sc[w * kPan + threadIdx.x];
+    sc[(kBcgsThreads / 64) * kPan + threadIdx.x] = a;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kPan; ++u) x[u] = sc[(kBcgsThreads / 64) * kPan + u];
+}
+
+// W[u][v] = sum_i Zr[i][u] Zr[i][p0 + v] for u < p0, v < kPan (zero for v >= P).
+__device__ inline void bcgs_dots(const double* Zr, int n, int m, int p0, int P, double* Wb, double* lds) {
+  const int tid = threadIdx.x;
+  const int Gp = (((p0 + 3) / 4) + 63) & ~63;   // lanes over u, whole waves
+  const int R = kBcgsThreads / Gp;             // row slices (>= 1)
+  const int ug = tid % Gp, r = tid / Gp;
+  const bool act = r < R;
+  double acc[4][kPan];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int v = 0; v < kPan; ++v) acc[k][v] = 0;
+  double* pan = lds;   // kBcgsChunk x kPan
+  for (int i0 = 0; i0 < n; i0 += kBcgsChunk) {
+    const int ie = min(kBcgsChunk, n - i0);
+    for (int q = tid; q < kBcgsChunk * kPan; q += kBcgsThreads) {
+      const int ii = q / kPan, v = q % kPan;
+      pan[q] = (ii < ie && v < P) ? Zr[(size_t)(i0 + ii) * m + p0 + v] : 0.0;
+    }
+    __syncthreads();
+    if (act) {
+      for (int ii = r; ii < ie; ii += R) {
+        const double* row = Zr + (size_t)(i0 + ii) * m;
+        double a[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int u = ug + k * Gp;
+          a[k] = u < p0 ? row[u] : 0.0;
+        }
+        const double2* pr = (const double2*)(pan + ii * kPan);
+#pragma unroll
+        for (int v2 = 0; v2 < kPan / 2; ++v2) {
+          const double2 pv = pr[v2];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            acc[k][2 * v2] = fma(a[k], pv.x, acc[k][2 * v2]);
+            acc[k][2 * v2 + 1] = fma(a[k], pv.y, acc[k][2 * v2 + 1]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // sum over the row slices in slice order, four values a round
+  double* red = lds;   // (R - 1) x Gp x 4
+#pragma unroll
+  for (int q = 0; q < 4 * kPan; q += 4) {
+    if (act && r > 0)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) red[((r - 1) * Gp + ug) * 4 + t] = acc[(q + t) / kPan][(q + t) % kPan];
+    __syncthreads();
+    if (r == 0) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        double sum = acc[(q + t) / kPan][(q + t) % kPan];
+        for (int rr = 1; rr < R; ++rr) sum += red[((rr - 1) * Gp + ug) * 4 + t];
+        const int u = ug + ((q + t) / kPan) * Gp;
+        if (u < p0) Wb[(size_t)u * kPan + (q + t) % kPan] = sum;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Zc[:, p0 + v] -= sum_{u < p0} Zc[:, u] W[u][v], v < P.
+__device__ inline void bcgs_update(double* Zc, int n, int p0, int P, const double* Wb, double* lds) {
+  const int tid = threadIdx.x;
+  double acc[kBcgsRows][kPan];
+#pragma unroll
+  for (int q = 0; q < kBcgsRows; ++q)
+#pragma unroll
+    for (int v = 0; v < kPan; ++v) acc[q][v] = 0;
+  double* wch = lds;   // kBcgsChunk x kPan
+  for (int u0 = 0; u0 < p0; u0 += kBcgsChunk) {
+    const int ue = min(kBcgsChunk, p0 - u0);
+    for (int q = tid; q < kBcgsChunk * kPan; q += kBcgsThreads)
+      wch[q] = q / kPan < ue ? Wb[(size_t)u0 * kPan + q] : 0.0;
+    __syncthreads();
+#pragma unroll 2
+    for (int uu = 0; uu < ue; ++uu) {
+      const double* col = Zc + (size_t)(u0 + uu) * n;
+      double z[kBcgsRows];
+#pragma unroll
+      for (int q = 0; q < kBcgsRows; ++q) {
+        const int i = tid + q * kBcgsThreads;
+        z[q] = i < n ? col[i] : 0.0;
+      }
+      const double2* wr = (const double2*)(wch + uu * kPan);
+#pragma unroll
+      for (int v2 = 0; v2 < kPan / 2; ++v2) {
+        const double2 w = wr[v2];
+#pragma unroll
+        for (int q = 0; q < kBcgsRows; ++q) {
+          acc[q][2 * v2] = fma(z[q], w.x, acc[q][2 * v2]);
+          acc[q][2 * v2 + 1] = fma(z[q], w.y, acc[q][2 * v2 + 1]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < kBcgsRows; ++q) {
+    const int i = tid + q * kBcgsThreads;
+    if (i < n)
+#pragma unroll
+      for (int v = 0; v < kPan; ++v)
+        if (v < P) Zc[(size_t)(p0 + v) * n + i] -= acc[q][v];
+  }
+}
+
+// Classical Gram-Schmidt and normalisation inside the panel (columns p0 ..
+// p0 + P of Zc); the result is written to both copies.
+__device__ inline void bcgs_panel(double* Zc, double* Zr, int n, int m, int p0, int P, double* lds) {
+  const int tid = threadIdx.x;
+  double x[kBcgsRows][kPan];
+#pragma unroll
+  for (int q = 0; q < kBcgsRows; ++q) {
+    const int i = tid + q * kBcgsThreads;
+#pragma unroll
+    for (int v = 0; v < kPan; ++v) x[q][v] = (i < n && v < P) ? Zc[(size_t)(p0 + v) * n + i] : 0.0;
+  }
+  int buf = 0;
+#pragma unroll
+  for (int v = 0; v < kPan; ++v) {
+    if (v >= P) continue;   // uniform over the block
+    if (v > 0) {
+      double dp[kPan];
+#pragma unroll
+      for (int u = 0; u < kPan; ++u) {
+        double a = 0;
+        if (u < v)
+#pragma unroll
+          for (int q = 0; q < kBcgsRows; ++q) a = fma(x[q][u], x[q][v], a);
+        dp[u] = a;
+      }
+      block_sum16(dp, lds + buf * 160);
+      buf ^= 1;
+#pragma unroll
+      for (int q = 0; q < kBcgsRows; ++q) {
+        double y = x[q][v];
+#pragma unroll
+        for (int u = 0; u < kPan; ++u)
+          if (u < v) y = fma(-dp[u], x[q][u], y);
+        x[q][v] = y;
+      }
+    }
+    double nn = 0;
+#pragma unroll
+    for (int q = 0; q < kBcgsRows; ++q) nn = fma(x[q][v], x[q][v], nn);
+    nn = block_sum1(nn, lds + 320 + buf * 8);
+    buf ^= 1;
+    const double f = nn > 0 ? 1.0 / sqrt(nn) : 0.0;
+#pragma unroll
+    for (int q = 0; q < kBcgsRows; ++q) x[q][v] *= f;
+  }
+#pragma unroll
+  for (int q = 0; q < kBcgsRows; ++q) {
+    const int i = tid + q * kBcgsThreads;
+    if (i < n)
+#pragma unroll
+      for (int v = 0; v < kPan; ++v)
+        if (v < P) {
+          Zc[(size_t)(p0 + v) * n + i] = x[q][v];
+          Zr[(size_t)i * m + p0 + v] = x[q][v];
+        }
+  }
+  __syncthreads();
+}
+
+// Zc = Zr (n x m row-major to column-major) through 32 x 32 LDS tiles.
+__device__ inline void rows_to_cols(const double* Zr, int n, int m, double* Zc, double* tile) {
+  for (int i0 = 0; i0 < n; i0 += 32)
+    for (int c0 = 0; c0 < m; c0 += 32) {
+      for (int q = threadIdx.x; q < 1024; q += kBcgsThreads) {
+        const int a = q >> 5, b = q & 31, i = i0 + a, c = c0 + b;
+        tile[a * 33 + b] = (i < n && c < m) ? Zr[(size_t)i * m + c] : 0.0;
+      }
+      __syncthreads();
+      for (int q = threadIdx.x; q < 1024; q += kBcgsThreads) {
+        const int a = q >> 5, b = q & 31, c = c0 + a, i = i0 + b;
+        if (i < n && c < m) Zc[(size_t)c * n + i] = tile[b * 33 + a];
+      }
+      __syncthreads();
+    }
+}
+
+// Both passes over all panels of the cluster.
+__device__ __attribute__((noinline)) void bcgs_all(double* Zr, double* Zc, int n, int m, double* Wb, double* lds) {
+  for (int p0 = 0; p0 < m; p0 += kPan) {
+    const int P = min(kPan, m - p0);
+    for (int pass = 0; pass < 2; ++pass) {
+      if (p0 > 0) {
+        bcgs_dots(Zr, n, m, p0, P, Wb, lds);
+        bcgs_update(Zc, n, p0, P, Wb, lds);
+      }
+      bcgs_panel(Zc, Zr, n, m, p0, P, lds);
+    }
+  }
+}
+
+// Gaussian elimination with partial pivoting of the tridiagonal T - sigma
+// (one thread; LAPACK dgttrf layout): multipliers dl, reciprocal pivots rp,
+// first and second superdiagonals du, du2 of U, interchange flags sw.  A
+// zero pivot becomes tiny.
+__device__ inline void tri_lu(const double* d, const double* e, int n, double sigma, double tiny, double* dl,
+                              double* rp, double* du, double* du2, unsigned char* sw) {
+  double piv = d[0] - sigma, up = n > 1 ? e[0] : 0.0;
+  for (int k = 0; k < n - 1; ++k) {
+    const double sub = e[k], dn = d[k + 1] - sigma, upn = k + 1 < n - 1 ? e[k + 1] : 0.0;
+    if (fabs(piv) >= fabs(sub)) {   // rows stay: pivot row (piv, up, 0)
+      const double p = piv != 0.0 ? piv : tiny;
+      const double l = sub / p;
+      rp[k] = 1.0 / p;
+      du[k] = up;
+      du2[k] = 0.0;
+      dl[k] = l;
+      sw[k] = 0;
+      piv = dn - l * up;
+      up = upn;
+    } else {                        // interchange: pivot row (sub, dn, upn)
+      const double l = piv / sub;
+      rp[k] = 1.0 / sub;
+      du[k] = dn;
+      du2[k] = upn;
+      dl[k] = l;
+      sw[k] = 1;
+      piv = up - l * dn;
+      up = -l * upn;
+    }
+  }
+  rp[n - 1] = 1.0 / (piv != 0.0 ? piv : tiny);
+  du[n - 1] = 0.0;
+  du2[n - 1] = 0.0;
+  sw[n - 1] = 0;
+}
+
+// x <- (T - sigma)^-1 x for column c of the row-major n x m block X (in place).
+__device__ inline void tri_solve_col(double* X, int n, int m, int c, const double* dl, const double* rp,
+                                     const double* du, const double* du2, const unsigned char* sw) {
+  constexpr int CH = 8;
+  double* x = X + c;
+  double b = x[0];   // running row k of the eliminated right-hand side
+  for (int k0 = 0; k0 < n - 1; k0 += CH) {
+    double nx[CH], out[CH];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) nx[t] = k0 + t < n - 1 ? x[(size_t)(k0 + t + 1) * m] : 0.0;
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int k = k0 + t;
+      if (k < n - 1) {
+        const double l = dl[k];
+        if (sw[k]) {
+          out[t] = nx[t];
+          b = b - l * nx[t];
+        } else {
+          out[t] = b;
+          b = nx[t] - l * b;
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < CH; ++t)
+      if (k0 + t < n - 1) x[(size_t)(k0 + t) * m] = out[t];
+  }
+  x[(size_t)(n - 1) * m] = b;
+  double z1 = 0.0, z2 = 0.0;
+  for (int k0 = n - 1; k0 >= 0; k0 -= CH) {
+    double bb[CH];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) bb[t] = k0 - t >= 0 ? x[(size_t)(k0 - t) * m] : 0.0;
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int k = k0 - t;
+      if (k >= 0) {
+        const double z = (bb[t] - du[k] * z1 - du2[k] * z2) * rp[k];
+        bb[t] = z;
+        z2 = z1;
+        z1 = z;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < CH; ++t)
+      if (k0 - t >= 0) x[(size_t)(k0 - t) * m] = bb[t];
+  }
+}
+
+// Block (g, job): the g-th cluster of more than kBigCluster columns of the
+// job, if there is one.
+//  1. Blocked Gram-Schmidt (two passes) of its inverse-iteration vectors.
+//     These come out nearly parallel (every shift lies inside the cluster),
+//     so the remainders are small and their rounding, which has components
+//     outside the cluster's invariant subspace, is magnified by the
+//     normalisation.
+//  2. One inverse-iteration step with a single shift sigma just outside the
+//     cluster (at c = min(kFilterRel |lam|max, gap / 2) from its edge, on the
+//     side of the larger known gap): the cluster's directions are amplified
+//     by 1/c to within a factor (c + width) / c of each other, a direction
+//     at distance D by 1/D, so the magnified rounding shrinks by c / D while
+//     the block stays well conditioned.
+//  3. Blocked Gram-Schmidt again; its remainders are no longer small.
+__global__ __launch_bounds__(kBcgsThreads) void cluster_bcgs_kernel(SmallBatch sb, double rtol) {
+  __shared__ double lds[kBcgsLds > kFilterLds ? kBcgsLds : kFilterLds];
+  __shared__ int cl[2];
+  __shared__ double red[kBcgsThreads / 64];
+  const SmallJob& J = sb.j[blockIdx.y];
+  const int n = J.n, kw = J.kwant, tid = threadIdx.x;
+  find_big_cluster(J.lam, kw, rtol, blockIdx.x, lds, cl);
+  const int j0 = cl[0], m = cl[1];
+  if (j0 < 0) return;
+  c128* Z = J.E;
+  double* Zr = J.zr + (size_t)n * j0;
+  double* Zc = J.zc + (size_t)n * j0;
+  double* Wb = J.wb + (size_t)kPan * j0;
+  for (long long q = tid; q < (long long)n * m; q += kBcgsThreads) {
+    const long long i = q / m, c = q % m;
+    Zr[q] = Z[i * kw + j0 + c].re;
+  }
+  __syncthreads();
+  rows_to_cols(Zr, n, m, Zc, lds);
+  bcgs_all(Zr, Zc, n, m, Wb, lds);
+  // 2. the shift
+  const double* lam = J.lam;
+  const double lmax = fmax(fabs(lam[0]), fabs(lam[kw - 1]));
+  double tn = 0;
+  for (int i = tid; i < n; i += kBcgsThreads)
+    tn = fmax(tn, fabs(J.d[i]) + (i > 0 ? fabs(J.e[i - 1]) : 0.0) + (i < n - 1 ? fabs(J.e[i]) : 0.0));
+  tn = wave_max(tn);
+  if ((tid & 63) == 0) red[tid >> 6] = tn;
+  __syncthreads();
+  tn = 0;
+  for (int w = 0; w < kBcgsThreads / 64; ++w) tn = fmax(tn, red[w]);
+  if (lmax > 0) {
+    const double inf = HUGE_VAL;
+    const double gap_up = j0 > 0 ? lam[j0 - 1] - lam[j0] : inf;
+    // below the wanted eigenvalues the next one is unknown unless all are wanted
+    const double gap_dn = j0 + m < kw ? lam[j0 + m - 1] - lam[j0 + m] : (kw == n ? inf : 0.0);
+    const bool up = gap_up >= gap_dn;
+    const double c = fmin(kFilterRel * lmax, 0.5 * (up ? gap_up : gap_dn));
+    const double sigma = up ? lam[j0] + c : lam[j0 + m - 1] - c;
+    double* dl = lds;
+    double* rp = lds + n;
+    double* du = lds + 2 * (size_t)n;
+    double* du2 = lds + 3 * (size_t)n;
+    unsigned char* sw = (unsigned char*)(lds + 4 * (size_t)n);
+    if (tid == 0) tri_lu(J.d, J.e, n, sigma, fmax(tn, 1e-300) * 2.2e-16, dl, rp, du, du2, sw);
+    __syncthreads();
+    for (int c0 = tid; c0 < m; c0 += kBcgsThreads) tri_solve_col(Zr, n, m, c0, dl, rp, du, du2, sw);
+    __syncthreads();
+    // 3.
+    rows_to_cols(Zr, n, m, Zc, lds);
+    bcgs_all(Zr, Zc, n, m, Wb, lds);
+  }
+  for (long long q = tid; q < (long long)n * m; q += kBcgsThreads) {
+    const long long i = q / m, c = q % m;
+    Z[i * kw + j0 + c].re = Zr[q];
+  }
 }
 
 // Adaptive Newton-Schulz steps.  live[0]: K extent of the next Z^H Z (n, or 0
@@ -896,6 +1330,9 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
       S.T = J.w->qtri.T;
       S.tau = J.w->tau;
       S.tpart = J.w->tpart;
+      S.zr = (double*)J.w->gz;
+      S.zc = (double*)J.w->ztmp;
+      S.wb = J.w->lu;
       S.n = J.n;
       S.kwant = J.kwant;
       maxn = std::max(maxn, J.n);
@@ -927,6 +1364,11 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
     QT_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(cluster_mgs_kernel, dim3(maxk, sb.njobs), dim3(256), 0, s, sb, kClusterRtol);
     QT_HIP_CHECK(hipGetLastError());
+    if (maxk > kBigCluster) {
+      hipLaunchKernelGGL(cluster_bcgs_kernel, dim3(maxk / (kBigCluster + 1), sb.njobs), dim3(kBcgsThreads), 0, s, sb,
+                         kClusterRtol);
+      QT_HIP_CHECK(hipGetLastError());
+    }
   }
   // 6. Newton-Schulz steps Z <- Z - Z (Z^H Z - 1)/2 (each squares the
   // orthogonality error of Z), grouped over the jobs: the job's ns_steps

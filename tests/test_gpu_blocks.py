@@ -134,12 +134,21 @@ def _herm(n, kind, r):
         w = np.repeat(np.sort(r.uniform(0, 1, (n + 1) // 2))[::-1], 2)[:n]
         U = inputs.random_unitary(n, r)
         return (U * w[None, :]) @ U.conj().T
+    if kind == "cluster":  # two large clusters (one at the top, ragged panel tail) among distinct values
+        w = np.sort(r.uniform(0.1, 1, n))[::-1]
+        c1, c2 = min(97, n // 4), min(300, n // 3)
+        w[:c1] = 1.0 + 1e-14 * r.standard_normal(c1)
+        w[n // 2:n // 2 + c2] = 0.5 + 1e-15 * r.standard_normal(c2)
+        w = np.sort(w)[::-1]
+        U = inputs.random_unitary(n, r)
+        return (U * w[None, :]) @ U.conj().T
     raise ValueError(kind)
 
 
 HEIG = [(n, kind, n if n < 10 else (n * 3) // 4) for n in (1, 2, 3, 17, 64, 100, 257, 600)
         for kind in ("random", "gram", "degenerate")]
 HEIG += [(1127, "gram", 1024), (1127, "random", 1127), (1536, "gram", 1536), (1536, "degenerate", 1152)]
+HEIG += [(200, "cluster", 200), (600, "cluster", 450), (1127, "cluster", 1024), (1536, "cluster", 1536)]
 
 
 @pytest.mark.parametrize("n,kind,k", HEIG, ids=[f"n{n}-{kind}-k{k}" for n, kind, k in HEIG])
