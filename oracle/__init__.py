@@ -19,6 +19,9 @@ Everything is plain numpy/scipy in complex128, written from the paper:
               observables of Fig. 4 (local Z, entanglement entropy, truncation
               error).
 - ``ed``      exact state-vector evolution used to pin the above.
+- ``sym``     the Z_d block structure of the clock model in its charge basis
+              and the CBE update block by block with one truncation over all
+              blocks (Sec. III, closing paragraph; Sec. IV).
 
 Parity status of each function is stated in its docstring; a function whose
 result no test ties to something outside the oracle says "parity unpinned".

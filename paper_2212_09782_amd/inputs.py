@@ -124,3 +124,62 @@ def serving_requests(n=64, rate=4.0, seed=5):
             L=[32, 64, 2][geo],
         ))
     return reqs
+
+
+# ---- Z_d block structure (charge basis: eigenbasis of the clock model's shift X)
+
+def sym_sectors(chi, d):
+    """chi split into d charge sectors as evenly as possible (lower charges first)."""
+    return [chi // d + (1 if a < chi % d else 0) for a in range(d)]
+
+
+def sym_offsets(sec):
+    return np.concatenate([[0], np.cumsum(sec)]).astype(int)
+
+
+def random_sym_tensor(sec_l, sec_r, d, r):
+    """Right-isometric tensor [chi_l, d, chi_r] with the Z_d block structure.
+
+    Virtual indices run over the charge sectors in order; B[alpha, q, beta] is
+    nonzero only where charge(beta) = charge(alpha) + q mod d.  For every left
+    sector a the rows restricted to their allowed columns are Gaussian, then
+    orthonormalised (Q of a QR of the conjugate transpose); needs
+    sec_l[a] <= chi_r.
+    """
+    oL, oR = sym_offsets(sec_l), sym_offsets(sec_r)
+    chiL, chiR = int(oL[-1]), int(oR[-1])
+    B = np.zeros((chiL, d, chiR), np.complex128)
+    for a in range(d):
+        if sec_l[a] == 0:
+            continue
+        cols = [(q, beta) for q in range(d) for beta in range(oR[(a + q) % d], oR[(a + q) % d + 1])]
+        assert sec_l[a] <= len(cols)
+        G = gaussian_complex((sec_l[a], len(cols)), r)
+        Q, _ = np.linalg.qr(G.conj().T, mode="reduced")
+        rows = Q.conj().T
+        for k, (q, beta) in enumerate(cols):
+            B[oL[a]:oL[a + 1], q, beta] = rows[:, k]
+    return B
+
+
+def random_sym_bond(sec_l, sec_m, sec_r, d, seed):
+    """(Xi^[m], B^[m], B^[n]) of one bond with the Z_d block structure: Xi a
+    positive diagonal (unit 2-norm, descending inside every sector), B^[m] and
+    B^[n] right-isometric block-sparse tensors."""
+    r = rng(seed)
+    xi = np.concatenate([np.sort(r.uniform(0.0, 1.0, n))[::-1] for n in sec_l])
+    xi = xi / np.linalg.norm(xi)
+    bm = random_sym_tensor(sec_l, sec_m, d, r)
+    bn = random_sym_tensor(sec_m, sec_r, d, r)
+    return xi, bm, bn
+
+
+def charge_product_cell(d):
+    """Uniform two-site cell in the product state with charge 0 on every site
+    (|q=0> in the charge basis, the uniform superposition of the clock states):
+    tensors [1, d, 1] and unit bond weights, one sector of size 1 (charge 0)
+    on both bonds."""
+    e0 = np.zeros((1, d, 1), np.complex128)
+    e0[0, 0, 0] = 1.0
+    sec = [1] + [0] * (d - 1)
+    return [e0, e0.copy()], [np.ones(1), np.ones(1)], [sec, list(sec)]
