@@ -233,6 +233,43 @@ def run_quench(lib, torch, prec, d, g, chi_max, steps, dt, dchi_min, exec_mode, 
     return dict(z=np.array(z), e=np.array(e), chis=chis, eps_sum=eps_sum, seconds=t1 - t0)
 
 
+def run_sym(lib, torch, prec, chi, d, steps, warmup):
+    """The microbenchmark cell with the Z_d block structure (charge basis):
+    random symmetric right-isometric A, B with chi split evenly over the d
+    charge sectors of both bonds, the clock gate (g = 2, dt = 0.05) in the
+    charge basis, every sector expanded by ceil(sec/10) (at least 1), chi_max
+    = chi.  Updates alternate between the bonds (A,B) and (B,A) on the evolving
+    state; each reads its new sector sizes back (one synchronisation per
+    update, inside the timed region)."""
+    from paper_2212_09782_amd import inputs
+    ctx = lib.Context(0)
+    sec = inputs.sym_sectors(chi, d)
+    _, A, B = inputs.random_sym_bond(sec, sec, sec, d, seed=0)
+    r = inputs.rng(2)
+    lam = [np.concatenate([np.sort(r.uniform(0, 1, n))[::-1] for n in sec]) for _ in range(2)]
+    lam = [x / np.linalg.norm(x) for x in lam]
+    cell = lib.SymCell(ctx, [A, B], lam, [sec, sec], chi_cap=chi + d, prec=prec)
+    du = torch.from_numpy(lib.clock_gate_charge(d, 2.0, 0.05).reshape(-1)).to("cuda")
+    svd_min = 1e-14 if prec == lib.MPS_C128 else 1e-6
+    stream = torch.cuda.current_stream()
+    for k in range(warmup):
+        cell.update(k % 2, du, 1, 0.1, chi, svd_min, stream)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        a = time.perf_counter()
+        cell.update((warmup + k) % 2, du, 1, 0.1, chi, svd_min, stream)
+        lat.append(time.perf_counter() - a)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out = dict(updates_per_s=steps / (t1 - t0), ms_per_step=1e3 * (t1 - t0) / steps,
+               p50_ms=1e3 * float(np.percentile(lat, 50)), p99_ms=1e3 * float(np.percentile(lat, 99)),
+               sectors=cell.secs, chi=cell.chis())
+    ctx.close()
+    return out
+
+
 def run_schemes(lib, torch, chi, ds, reps, budget_s):
     """Single-gate time of the four truncation schemes of the paper's
     comparison (Sec. IV) on the GPU, complex128: QR (plain, eta = chi), QR+CBE
@@ -437,7 +474,7 @@ def main():
     ap.add_argument("--prec", choices=["both", "c128", "mixed"], default="both")
     ap.add_argument("--cpu-budget", type=float, default=24.0, help="seconds of oracle time (0: skip)")
     ap.add_argument("--sweeps", type=int, default=1, help="QR/LQ sweeps per update (1: the paper's single sweep)")
-    ap.add_argument("--workload", choices=["bond", "chain", "serve", "quench", "schemes"], default="bond",
+    ap.add_argument("--workload", choices=["bond", "chain", "serve", "quench", "schemes", "sym"], default="bond",
                     help="bond: the single-bond microbenchmark (default); chain: the batched finite chain "
                          "(L=128, Z_4, chi_max=512 by default), steady state, one JSON line of its own")
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
@@ -493,6 +530,24 @@ def main():
             "config": {"workload": f"microbenchmark cell chi={chi}, clock gate g=2 dt=0.05, schemes: QR (eta=chi), "
                                    f"QR+CBE (eta=chi+ceil(chi/10)), EIG and SVD (rocSOLVER), median of up to 5"},
             "ms": tab, "svd_over_qr_cbe": ratio}), flush=True)
+        return
+    if args.workload == "sym":
+        chi = args.chi or 1024
+        res = {}
+        for key, p in (("c128", lib.MPS_C128), ("c64", lib.MPS_MIXED_C64)):
+            if args.prec not in ("both", "c128" if key == "c128" else "mixed"):
+                continue
+            print(f"# sym {key} d={args.d} chi={chi}", file=sys.stderr, flush=True)
+            res[key] = run_sym(lib, torch, p, chi, args.d, args.steps, args.warmup)
+        first = res.get("c128") or res.get("c64")
+        print(json.dumps({
+            "metric": "bond updates/s, Z_d block-structured QR+CBE update (charge basis)", "value": first["updates_per_s"],
+            "unit": "bond updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": f"microbenchmark cell with Z_{args.d} blocks, chi={chi} in {args.d} equal sectors "
+                                   f"on both bonds, eta_c = sec + ceil(sec/10), chi_max = chi, clock gate g=2 dt=0.05 "
+                                   f"in the charge basis, one sector read-back per update"},
+            "per_precision": res}), flush=True)
         return
     if args.workload == "quench":
         d = 10 if args.d == 5 else args.d

@@ -184,6 +184,75 @@ int mps_clock_gate(int d, double g, double tau, double wl, double wr, double* u_
  * measurements with mps_measure; h_out: host array of (d*d)^2 complex128. */
 int mps_clock_hamiltonian(int d, double g, double wl, double wr, double* h_out);
 
+/* ---- Z_d block structure (Sec. III, closing paragraph; Sec. IV) -----------
+ * The clock model conserves the Z_d charge generated by prod_i X_i.  In the
+ * eigenbasis of X (charge basis: |q> = d^-1/2 sum_k w^(q k) |k>, X|q> = w^q |q>,
+ * Z|q> = |q+1>) the bond gate conserves q_i + q_j mod d and an MPS of definite
+ * charge is block sparse: every bond splits into d charge sectors, and
+ * B[alpha, q, beta] vanishes unless charge(beta) = charge(alpha) + q mod d.
+ * Controlled bond expansion then sets the sector sizes dynamically: each
+ * block is expanded and one truncation over all blocks keeps the largest
+ * Schmidt values. */
+
+/* The gate and bond Hamiltonian of mps_clock_gate / mps_clock_hamiltonian in
+ * the charge basis (same arguments; host arrays of (d*d)^2 complex128). */
+int mps_clock_gate_charge(int d, double g, double tau, double wl, double wr, double* u_out);
+int mps_clock_hamiltonian_charge(int d, double g, double wl, double wr, double* h_out);
+
+#define MPS_SYM_MAX_D 16
+/* One bond (m, n) with the block structure.  sec_l / sec_m / sec_r: sector
+ * sizes (charge 0 .. d-1) of the bond left of m, of the bond (m, n) and of
+ * the bond right of n; each bond's index runs over its sectors in charge
+ * order.  Sector c of the bond (m, n) is expanded to
+ *   eta_c = min(sec_m[c] + max(dchi_min, ceil(dchi_frac sec_m[c])), chi_l, chi_r)
+ * (chi_l, chi_r: the outer bonds' total sizes, which bound every block; a
+ * sector with eta_c = 0 stays empty); the update then keeps the Schmidt
+ * values S >= svd_min, at most chi_max of them over all sectors, at least
+ * one, ranked by S^2 with ties to the lower charge. */
+typedef struct {
+  int d;                      /* 2 .. MPS_SYM_MAX_D */
+  int sec_l[MPS_SYM_MAX_D];
+  int sec_m[MPS_SYM_MAX_D];
+  int sec_r[MPS_SYM_MAX_D];
+  int dchi_min;
+  double dchi_frac;
+  int chi_max;
+  double svd_min;
+  int prec;                   /* mps_precision */
+} mps_sym_desc;
+
+/* Capacity of the new bond: min(chi_max, sum_c min(eta_c, chi_max)) (>= 1),
+ * or a negative error code for an invalid descriptor. */
+int mps_sym_capacity(const mps_sym_desc* desc);
+/* Workspace the library allocates (and keeps in the context) for this update. */
+int mps_sym_workspace_query(mps_ctx ctx, const mps_sym_desc* desc, size_t* bytes);
+
+/* The CBE update (Sec. III, steps (i)-(v)) block by block: theta~ splits into
+ * d blocks of middle charge c (rows (q, alpha) with charge(alpha) = c - q,
+ * columns (q', beta) with charge(beta) = c + q'); each block takes steps
+ * (i)-(iv) with the first eta_c of its rows as the slice of step (i); one
+ * truncation over all blocks, then step (v) and Hastings' B~^[m] = C~ B~^[n]^dag
+ * per block.  Tensors are dense and charge-ordered, as in mps_bond_update:
+ *   xi_m      chi_l doubles: the (diagonal) bond matrix left of m
+ *   b_m       [chi_l][d][chi_m], b_n [chi_m][d][chi_r] (storage precision
+ *             per prec), zero outside the blocks
+ *   u         (d*d)^2 complex128 gate in the charge basis (entries that
+ *             change q_i + q_j are not read)
+ *   b_m_out   [chi_l][d][chi~], b_n_out [chi~][d][chi_r], xi_n_out chi~
+ *             doubles (unit 2-norm): compact with the new chi~, the new bond
+ *             in charge order (inside a sector by descending S); capacity
+ *             mps_sym_capacity elements along the new bond.  They may alias
+ *             b_m / b_n (the inputs are read into blocks first).
+ *   sec_out   d ints: the new sector sizes; chi_new: their sum; trunc_err:
+ *             (|theta~|^2 - sum_kept S^2) / |theta~|^2
+ * All pointers are device pointers owned by the caller; the call is
+ * asynchronous on stream.  MPS_ERR_ARG for an invalid descriptor or a null
+ * pointer, MPS_ERR_CAPACITY when a block exceeds the dense update's limits
+ * (eta_c <= 1536), MPS_ERR_OOM if the workspace cannot be allocated. */
+int mps_bond_update_sym(mps_ctx ctx, const mps_sym_desc* desc, const double* xi_m, const void* b_m, const void* b_n,
+                        const void* u, void* b_m_out, double* xi_n_out, void* b_n_out, int* sec_out, int* chi_new,
+                        double* trunc_err, mps_stream stream);
+
 /* ---- device-resident MPS and the even/odd sweep (Fig. 2a) ---------------- */
 
 typedef struct mps_state_s* mps_state;

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(CSRC, "_build")
 LIB = os.path.join(HERE, "libqrtebd.so")
-SOURCES = ["gemm.hip", "qr.hip", "eig.hip", "bond.hip", "measure.hip", "reference.cpp", "api.cpp"]
+SOURCES = ["gemm.hip", "qr.hip", "eig.hip", "bond.hip", "sym.hip", "measure.hip", "reference.cpp", "api.cpp"]
 # the reference (comparison) truncation schemes use the solver library
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 

@@ -21,6 +21,7 @@
 #include "gemm.h"
 #include "measure.h"
 #include "reference.h"
+#include "sym.h"
 
 #include <rocblas/rocblas.h>
 
@@ -530,13 +531,21 @@ int mps_profile_read(mps_ctx c, double* total_ms, double* total_flops, int* laun
 namespace {
 
 // h = -(Z (x) Z^dag + h.c.) - g (wl (X+X^dag) (x) 1 + wr 1 (x) (X+X^dag)), row i*d+j.
-std::vector<cd> clock_bond_h(int d, double g, double wl, double wr) {
+// Bond term of the clock model (Sec. IV).  charge = false: clock basis, Z =
+// diag(w^k), X the cyclic shift; charge = true: eigenbasis of X (charge q,
+// X|q> = w^q |q>), where X = diag(w^q) and Z raises the charge by one.
+std::vector<cd> clock_bond_h(int d, double g, double wl, double wr, bool charge = false) {
   const int n = d * d;
   const cd w = std::exp(cd(0, 2 * M_PI / d));
   std::vector<cd> Z(d * d, 0.0), X(d * d, 0.0), xs(d * d);
   for (int k = 0; k < d; ++k) {
-    Z[k * d + k] = std::pow(w, k);
-    X[k * d + (k + 1) % d] = 1.0;
+    if (charge) {
+      Z[((k + 1) % d) * d + k] = 1.0;
+      X[k * d + k] = std::pow(w, k);
+    } else {
+      Z[k * d + k] = std::pow(w, k);
+      X[k * d + (k + 1) % d] = 1.0;
+    }
   }
   for (int i = 0; i < d; ++i)
     for (int j = 0; j < d; ++j) xs[i * d + j] = X[i * d + j] + std::conj(X[j * d + i]);
@@ -581,6 +590,82 @@ int mps_clock_gate(int d, double g, double tau, double wl, double wr, double* u_
     u_out[2 * i + 1] = A[i].imag();
   }
   return MPS_OK;
+}
+
+int mps_clock_hamiltonian_charge(int d, double g, double wl, double wr, double* h_out) {
+  if (d < 1 || !h_out) return set_error(MPS_ERR_ARG, "bad Hamiltonian arguments");
+  const std::vector<cd> H = clock_bond_h(d, g, wl, wr, true);
+  for (size_t i = 0; i < H.size(); ++i) {
+    h_out[2 * i] = H[i].real();
+    h_out[2 * i + 1] = H[i].imag();
+  }
+  return MPS_OK;
+}
+
+int mps_clock_gate_charge(int d, double g, double tau, double wl, double wr, double* u_out) {
+  if (d < 1 || !u_out) return set_error(MPS_ERR_ARG, "bad gate arguments");
+  const int n = d * d;
+  std::vector<cd> A = clock_bond_h(d, g, wl, wr, true);
+  for (auto& x : A) x *= cd(0, -tau);
+  expm_host(A, n);
+  for (int i = 0; i < n * n; ++i) {
+    u_out[2 * i] = A[i].real();
+    u_out[2 * i + 1] = A[i].imag();
+  }
+  return MPS_OK;
+}
+
+// ---------------------------------------------------------------- Z_d blocks
+
+int sym_plan_of(const mps_sym_desc* D, SymPlan* p) {
+  if (!D) return set_error(MPS_ERR_ARG, "null descriptor");
+  if (D->d < 2 || D->d > MPS_SYM_MAX_D) return set_error(MPS_ERR_ARG, "d=%d outside [2, %d]", D->d, MPS_SYM_MAX_D);
+  SymShape sh{};
+  sh.d = D->d;
+  for (int a = 0; a < D->d; ++a) {
+    sh.sec_l[a] = D->sec_l[a];
+    sh.sec_m[a] = D->sec_m[a];
+    sh.sec_r[a] = D->sec_r[a];
+  }
+  sh.dchi_min = D->dchi_min;
+  sh.dchi_frac = D->dchi_frac;
+  sh.chi_max = D->chi_max;
+  sh.svd_min = D->svd_min;
+  sh.prec = D->prec;
+  return sym_plan(sh, p);
+}
+
+int mps_sym_capacity(const mps_sym_desc* D) {
+  SymPlan p;
+  const int rc = sym_plan_of(D, &p);
+  return rc ? rc : p.cap;
+}
+
+int mps_sym_workspace_query(mps_ctx c, const mps_sym_desc* D, size_t* bytes) {
+  (void)c;
+  if (!bytes) return set_error(MPS_ERR_ARG, "null argument");
+  SymPlan p;
+  const int rc = sym_plan_of(D, &p);
+  if (rc) return rc;
+  *bytes = sym_work_bytes(p);
+  return MPS_OK;
+}
+
+int mps_bond_update_sym(mps_ctx c, const mps_sym_desc* D, const double* xi_m, const void* b_m, const void* b_n,
+                        const void* u, void* b_m_out, double* xi_n_out, void* b_n_out, int* sec_out_dev,
+                        int* chi_new_dev, double* trunc_err_dev, mps_stream stream) {
+  if (!c) return set_error(MPS_ERR_ARG, "null context");
+  SymPlan p;
+  int rc = sym_plan_of(D, &p);
+  if (rc) return rc;
+  if (!xi_m || !b_m || !b_n || !u || !b_m_out || !xi_n_out || !b_n_out || !sec_out_dev || !chi_new_dev ||
+      !trunc_err_dev)
+    return set_error(MPS_ERR_ARG, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = ensure_ws(c, sym_work_bytes(p), s))) return rc;
+  g_tune = TuneParams{};
+  return sym_update_run(p, c->ws, c->status, xi_m, b_m, b_n, (const c128*)u, b_m_out, xi_n_out, b_n_out,
+                        sec_out_dev, chi_new_dev, trunc_err_dev, s, &c->qa);
 }
 
 // ---------------------------------------------------------------- states

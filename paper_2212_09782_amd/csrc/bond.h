@@ -23,7 +23,31 @@ struct BondShape {
   int xi_is_diag, mode, prec;
   int sweeps = 1;      // QR/LQ sweeps (>= 1)
   int left_iso = 0;    // PLAIN / GROW: b_m_out = Q^[m] (left-isometric) instead of Hastings' B~^[m]
+  int pre = 0;         // C~ and theta~ already in the workspace (bond_pre_views): skip step (i) and the gate
   int cap() const;     // capacity of the new bond
+};
+
+// One truncation over the blocks of a bond with a Z_d block structure (Sec.
+// III, closing paragraph): block k hands over its eigenvalues lam[k] (kw[k]
+// of them, descending; kw = 0 for an absent block), and the largest ones over
+// all blocks are kept (sqrt(max(lam, 0)) >= svd_min, at most chi_max, at
+// least one), ranked by max(lam, 0) with ties to the lower block index.
+// Outputs: chi[k] kept per block, offs[0..n] their prefix sums, *chi_tot,
+// xi (chi_tot values: block after block, S / |S_kept|), *eps.
+constexpr int kSymMaxD = 16;
+struct SymSelect {
+  int n;
+  const double* lam[kSymMaxD];
+  int kw[kSymMaxD];
+  int* chi;                 // n entries
+  int* offs;                // n + 1 entries
+  int* chi_tot;
+  double* xi;
+  const double* norm2;      // |theta~|^2 over all blocks
+  double* eps;
+  int* status;
+  double svd_min;
+  int chi_max;
 };
 
 // Workspace bytes of one bond update of this shape.
@@ -45,7 +69,12 @@ struct BondCall {
   void* b_n_out;
   int* chi_new;
   double* eps;
+  const SymSelect* sym = nullptr;   // CBE blocks of one symmetric bond: joint truncation instead of select_kernel
 };
+
+// Where a bond of this shape keeps C~ and theta~ (for pre = 1) and, in CBE
+// mode, the eigenvalues of step (iv) in its workspace.
+void bond_pre_views(const BondShape& b, void* ws, void** C, void** Th, double** lam);
 // All bonds of a batch must share the precision; modes and shapes may differ.
 // as: optional look-ahead resources for the QR factorisations.
 int bond_update_batch(const BondCall* calls, int n, hipStream_t s, KernelTimer* timer = nullptr,

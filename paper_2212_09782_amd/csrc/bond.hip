@@ -177,6 +177,85 @@ __global__ __launch_bounds__(256) void select_kernel(const double* lam, int kmax
   }
 }
 
+// Entries of a non-increasing list (max(lam, 0)) ranked before value v: those
+// above it, and those equal to it when ties go to the list.
+__device__ inline int ranked_before(const double* lam, int n, double v, bool ties) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const double x = fmax(lam[mid], 0.0);
+    if (ties ? x >= v : x > v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// One truncation over the blocks of a symmetric bond (see SymSelect).
+// Within a block the kept entries form a prefix: ranks grow along a list.
+__global__ __launch_bounds__(256) void select_sym_kernel(SymSelect S) {
+  __shared__ int first_bad[kSymMaxD];
+  __shared__ int offs[kSymMaxD + 1];
+  __shared__ double scr[4];
+  __shared__ double k2s;
+  const int tid = threadIdx.x;
+  if (tid < kSymMaxD) first_bad[tid] = tid < S.n ? S.kw[tid] : 0;
+  __syncthreads();
+  for (int k = 0; k < S.n; ++k)
+    for (int j = tid; j < S.kw[k]; j += 256) {
+      const double l = S.lam[k][j];
+      if (!isfinite(l)) latch_error(S.status, ERRBIT_NONFINITE);
+      const double v = fmax(l, 0.0);
+      long long rank = j;
+      for (int k2 = 0; k2 < S.n; ++k2)
+        if (k2 != k && S.kw[k2] > 0) rank += ranked_before(S.lam[k2], S.kw[k2], v, k2 < k);
+      if (!(rank < S.chi_max && sqrt(v) >= S.svd_min)) atomicMin(&first_bad[k], j);
+    }
+  __syncthreads();
+  if (tid == 0) {
+    int tot = 0;
+    for (int k = 0; k < S.n; ++k) tot += first_bad[k];
+    if (tot == 0) {   // keep the largest value (lowest block on a tie)
+      int best = -1;
+      double bv = -1.0;
+      for (int k = 0; k < S.n; ++k)
+        if (S.kw[k] > 0 && fmax(S.lam[k][0], 0.0) > bv) {
+          bv = fmax(S.lam[k][0], 0.0);
+          best = k;
+        }
+      if (best >= 0) first_bad[best] = 1;
+    }
+    offs[0] = 0;
+    for (int k = 0; k < S.n; ++k) offs[k + 1] = offs[k] + first_bad[k];
+  }
+  __syncthreads();
+  const int tot = offs[S.n];
+  double s = 0;
+  for (int g = tid; g < tot; g += 256) {
+    int k = 0;
+    while (offs[k + 1] <= g) ++k;
+    s += fmax(S.lam[k][g - offs[k]], 0.0);
+  }
+  s = block_sum(s, scr);
+  if (tid == 0) k2s = s;
+  __syncthreads();
+  const double inv = k2s > 0 ? 1.0 / sqrt(k2s) : 0.0;
+  for (int g = tid; g < tot; g += 256) {
+    int k = 0;
+    while (offs[k + 1] <= g) ++k;
+    S.xi[g] = sqrt(fmax(S.lam[k][g - offs[k]], 0.0)) * inv;
+  }
+  if (tid < S.n) S.chi[tid] = first_bad[tid];
+  if (tid <= S.n) S.offs[tid] = offs[tid];
+  if (tid == 0) {
+    const double n2 = *S.norm2;
+    if (!(n2 > 0) || !isfinite(n2)) latch_error(S.status, n2 == 0 ? ERRBIT_ZERONORM : ERRBIT_NONFINITE);
+    *S.chi_tot = tot;
+    *S.eps = n2 > 0 ? fmax(0.0, n2 - k2s) / n2 : 0.0;
+  }
+}
+
 // out (cols x rows) = conj(in (rows x cols))^T
 template <typename S>
 __global__ __launch_bounds__(256) void transpose_conj_kernel(const cpx<S>* in, int rows, int cols, cpx<S>* out) {
@@ -281,18 +360,20 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
     QW[i] = qr_work_carve(W[i].qrw, std::max(b.d * b.chi_l, b.d * b.chi_r), b.eta, (int)sizeof(cpx<S>), b.eta,
                           calls[i].status);
   }
-  // (i) C = B^[m] B^[n]
+  // (i) C = B^[m] B^[n] (bonds whose C~ and theta~ were formed by the caller skip this and the gate)
   g.clear();
   for (int i = 0; i < nc; ++i) {
     const BondShape& b = calls[i].b;
+    if (b.pre) continue;
     const int mL = b.d * b.chi_l, mR = b.d * b.chi_r;
     g.push_back(gemm_prob(calls[i].b_m, b.chi_m, OP_N, calls[i].b_n, mR, OP_N, W[i].C, mR, mL, mR, b.chi_m));
   }
-  if ((rc = timed_gemm_batch(tm, g.data(), nc, ty, s))) return rc;
+  if (!g.empty() && (rc = timed_gemm_batch(tm, g.data(), (int)g.size(), ty, s))) return rc;
   // C~ = U C (in place) and theta~ = Xi C~, |theta~|^2
   for (int i = 0; i < nc; ++i) {
     const BondCall& c = calls[i];
     const BondShape& b = c.b;
+    if (b.pre) continue;
     BondBufs& w = W[i];
     const int d = b.d, chiL = b.chi_l, chiR = b.chi_r, mL = d * chiL, mR = d * chiR;
     const int R = gate_groups(d, sizeof(cpx<S>)), Wc = 64 / R;
@@ -461,12 +542,21 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
       QT_HIP_CHECK(hipEventRecord(as->ev_trail, as->aux));
     }
     g.clear();
+    std::vector<const SymSelect*> joint;
     for (int i : cb) {
       const BondCall& c = calls[i];
       const int kw = kwant_of(c.b), eta = c.b.eta, mR = c.b.d * c.b.chi_r;
-      hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, s, W[i].lam, kw, c.b.svd_min, W[i].norm2, c.chi_new,
-                         (double*)c.xi_n_out, W[i].kept2, c.eps, c.status);
-      QT_HIP_CHECK(hipGetLastError());
+      if (c.sym) {
+        if (std::find(joint.begin(), joint.end(), c.sym) == joint.end()) {
+          joint.push_back(c.sym);
+          hipLaunchKernelGGL(select_sym_kernel, dim3(1), dim3(256), 0, s, *c.sym);
+          QT_HIP_CHECK(hipGetLastError());
+        }
+      } else {
+        hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), 0, s, W[i].lam, kw, c.b.svd_min, W[i].norm2,
+                           c.chi_new, (double*)c.xi_n_out, W[i].kept2, c.eps, c.status);
+        QT_HIP_CHECK(hipGetLastError());
+      }
       const void* Eu = W[i].E;
       if (mixed) {
         const long long n = (long long)eta * kw;
@@ -626,6 +716,13 @@ int reduce_partials(const double* part, int n, double* out, hipStream_t s) {
 }
 
 size_t bond_work_bytes(const BondShape& b) { return carve(b, nullptr).total + 256; }
+
+void bond_pre_views(const BondShape& b, void* ws, void** C, void** Th, double** lam) {
+  const BondBufs w = carve(b, ws);
+  *C = w.C;
+  *Th = w.Th;
+  *lam = w.lam;
+}
 
 int bond_update_batch(const BondCall* calls, int n, hipStream_t s, KernelTimer* timer, const QrAsync* as) {
   if (n <= 0) return 0;

@@ -183,3 +183,16 @@ def charge_product_cell(d):
     e0[0, 0, 0] = 1.0
     sec = [1] + [0] * (d - 1)
     return [e0, e0.copy()], [np.ones(1), np.ones(1)], [sec, list(sec)]
+
+
+def random_charge_gate(d, r, scale=0.1):
+    """exp(-i s H) for a random Hermitian two-site H that conserves q_i + q_j
+    mod d (block diagonal over the total charge, row index q_i d + q_j): a
+    charge-conserving gate close to 1 in the charge basis."""
+    H = np.zeros((d * d, d * d), np.complex128)
+    for s in range(d):
+        idx = [q * d + (s - q) % d for q in range(d)]
+        G = gaussian_complex((d, d), r)
+        H[np.ix_(idx, idx)] = (G + G.conj().T) / (2 * np.sqrt(d))
+    w, V = np.linalg.eigh(H)
+    return (V * np.exp(-1j * scale * w)[None, :]) @ V.conj().T

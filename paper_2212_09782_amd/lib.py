@@ -24,7 +24,10 @@ EXPORTS = [
     "mps_state_destroy", "mps_state_chis", "mps_sweep", "mps_measure", "mps_zgemm", "mps_qr",
     "mps_heig", "mps_profile_enable", "mps_profile_read", "mps_bond_update_noalloc", "mps_sweep_stats",
     "mps_clock_hamiltonian", "mps_bond_update_reference", "mps_sweep_sequential",
+    "mps_clock_gate_charge", "mps_clock_hamiltonian_charge", "mps_sym_capacity", "mps_sym_workspace_query",
+    "mps_bond_update_sym",
 ]
+MPS_SYM_MAX_D = 16
 SCHEME_SVD, SCHEME_EIG = 0, 1
 
 
@@ -42,6 +45,13 @@ class mps_sweep_policy(ctypes.Structure):
 
 
 EXEC_EAGER, EXEC_SPECULATIVE, EXEC_GRAPH = 0, 1, 2
+
+
+class mps_sym_desc(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("sec_l", ctypes.c_int * MPS_SYM_MAX_D),
+                ("sec_m", ctypes.c_int * MPS_SYM_MAX_D), ("sec_r", ctypes.c_int * MPS_SYM_MAX_D),
+                ("dchi_min", ctypes.c_int), ("dchi_frac", ctypes.c_double), ("chi_max", ctypes.c_int),
+                ("svd_min", ctypes.c_double), ("prec", ctypes.c_int)]
 
 
 class QrtebdError(RuntimeError):
@@ -70,6 +80,11 @@ def _declare(lib):
         "mps_bond_update_reference": (I, [P, ctypes.POINTER(mps_bond_desc), I, P, P, P, P, P, P, P, P, P, P]),
         "mps_clock_gate": (I, [I, D, D, D, D, P]),
         "mps_clock_hamiltonian": (I, [I, D, D, D, P]),
+        "mps_clock_gate_charge": (I, [I, D, D, D, D, P]),
+        "mps_clock_hamiltonian_charge": (I, [I, D, D, D, P]),
+        "mps_sym_capacity": (I, [ctypes.POINTER(mps_sym_desc)]),
+        "mps_sym_workspace_query": (I, [P, ctypes.POINTER(mps_sym_desc), ctypes.POINTER(ctypes.c_size_t)]),
+        "mps_bond_update_sym": (I, [P, ctypes.POINTER(mps_sym_desc), P, P, P, P, P, P, P, P, P, P, P]),
         "mps_state_create": (I, [P, I, I, I, I, I, ctypes.POINTER(P), ctypes.POINTER(P),
                                  ctypes.POINTER(I), ctypes.POINTER(P)]),
         "mps_state_destroy": (I, [P]),
@@ -169,6 +184,73 @@ def clock_hamiltonian(d, g, wl=0.5, wr=0.5):
     out = np.zeros((d * d, d * d), np.complex128)
     _check(load().mps_clock_hamiltonian(d, g, wl, wr, out.ctypes.data_as(P)))
     return out
+
+
+def clock_gate_charge(d, g, tau, wl=0.5, wr=0.5):
+    """mps_clock_gate_charge: the clock gate in the charge basis (eigenbasis of X)."""
+    out = np.zeros((d * d, d * d), np.complex128)
+    _check(load().mps_clock_gate_charge(d, g, tau, wl, wr, out.ctypes.data_as(P)))
+    return out
+
+
+def clock_hamiltonian_charge(d, g, wl=0.5, wr=0.5):
+    """mps_clock_hamiltonian_charge: the bond Hamiltonian in the charge basis."""
+    out = np.zeros((d * d, d * d), np.complex128)
+    _check(load().mps_clock_hamiltonian_charge(d, g, wl, wr, out.ctypes.data_as(P)))
+    return out
+
+
+def sym_desc(d, sec_l, sec_m, sec_r, dchi_min, dchi_frac, chi_max, svd_min=1e-14, prec=MPS_C128):
+    arr = lambda v: (ctypes.c_int * MPS_SYM_MAX_D)(*(list(v) + [0] * (MPS_SYM_MAX_D - len(v))))
+    return mps_sym_desc(d, arr(sec_l), arr(sec_m), arr(sec_r), dchi_min, dchi_frac, chi_max, svd_min, prec)
+
+
+def sym_capacity(desc):
+    return _check_cap(load().mps_sym_capacity(ctypes.byref(desc)))
+
+
+def _check_cap(v):
+    if v < 0:
+        raise QrtebdError(v, load().mps_last_error().decode())
+    return v
+
+
+def mps_bond_update_sym(ctx, desc, xi_m, b_m, b_n, u, b_m_out, xi_n_out, b_n_out, sec_out, chi_new, trunc_err,
+                        stream=None):
+    """Direct C-ABI call; every argument a torch tensor on the GPU."""
+    _check(ctx.lib.mps_bond_update_sym(ctx.h, ctypes.byref(desc), _ptr(xi_m), _ptr(b_m), _ptr(b_n), _ptr(u),
+                                       _ptr(b_m_out), _ptr(xi_n_out), _ptr(b_n_out), _ptr(sec_out), _ptr(chi_new),
+                                       _ptr(trunc_err), _stream(stream)))
+
+
+def bond_update_sym(ctx, desc, xi_m, b_m, b_n, u, stream=None):
+    """Allocate capacity-sized outputs, run mps_bond_update_sym, return device
+    tensors (b_m_out, xi_n_out, b_n_out, sec_out, chi_new, trunc_err)."""
+    import torch
+    dev = b_m.device
+    cap = sym_capacity(desc)
+    d = desc.d
+    chi_l, chi_r = sum(desc.sec_l[:d]), sum(desc.sec_r[:d])
+    cdt = torch.complex128 if desc.prec == MPS_C128 else torch.complex64
+    b_m_out = torch.empty(chi_l * d * cap, dtype=cdt, device=dev)
+    b_n_out = torch.empty(cap * d * chi_r, dtype=cdt, device=dev)
+    xi_out = torch.empty(cap, dtype=torch.float64, device=dev)
+    sec = torch.zeros(d, dtype=torch.int32, device=dev)
+    chi = torch.zeros(1, dtype=torch.int32, device=dev)
+    eps = torch.zeros(1, dtype=torch.float64, device=dev)
+    mps_bond_update_sym(ctx, desc, xi_m, b_m, b_n, u, b_m_out, xi_out, b_n_out, sec, chi, eps, stream)
+    return b_m_out, xi_out, b_n_out, sec, chi, eps
+
+
+def unpack_sym(desc, b_m_out, xi_out, b_n_out, sec, chi):
+    """Host numpy views of a finished symmetric update (synchronises):
+    (bm, xi, bn, sector sizes, chi~)."""
+    d = desc.d
+    chi_l, chi_r = sum(desc.sec_l[:d]), sum(desc.sec_r[:d])
+    k = int(chi.item())
+    bm = b_m_out[: chi_l * d * k].cpu().numpy().reshape(chi_l, d, k)
+    bn = b_n_out[: k * d * chi_r].cpu().numpy().reshape(k, d, chi_r)
+    return bm, xi_out[:k].cpu().numpy(), bn, [int(x) for x in sec.cpu().numpy()], k
 
 
 def bond_desc(d, chi_l, chi_m, chi_r, eta, chi_max, svd_min=1e-14, xi_is_diag=True, mode=CBE, prec=MPS_C128,
@@ -325,6 +407,80 @@ class State:
             self.close()
         except Exception:
             pass
+
+
+class SymCell:
+    """Uniform two-site cell (sites A = 0, B = 1; bond 0 = (A,B), bond 1 =
+    (B,A)) with the Z_d block structure, in the charge basis: dense
+    charge-ordered device tensors with room for chi_cap, the sector sizes of
+    every bond (secs[m]: the bond left of site m) kept on the host and read
+    back after every update (one synchronisation per update)."""
+
+    def __init__(self, ctx, B, Xi, secs, chi_cap, prec=MPS_C128):
+        import torch
+        self.ctx, self.prec, self.chi_cap = ctx, prec, int(chi_cap)
+        self.d = B[0].shape[1]
+        cdt = torch.complex128 if prec == MPS_C128 else torch.complex64
+        self.B = [torch.zeros(self.chi_cap * self.d * self.chi_cap, dtype=cdt, device="cuda") for _ in range(2)]
+        self.Xi = [torch.zeros(self.chi_cap, dtype=torch.float64, device="cuda") for _ in range(2)]
+        for m in range(2):
+            flat = torch.from_numpy(np.ascontiguousarray(B[m]).reshape(-1)).to(cdt)
+            self.B[m][: flat.numel()].copy_(flat)
+            x = torch.from_numpy(np.asarray(Xi[m], dtype=np.float64).reshape(-1))
+            self.Xi[m][: x.numel()].copy_(x)
+        self.secs = [list(secs[0]), list(secs[1])]
+        self.sec_dev = torch.zeros(self.d, dtype=torch.int32, device="cuda")
+        self.chi_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.eps_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        self.eps_sum = 0.0
+
+    def chis(self):
+        return [sum(self.secs[0]), sum(self.secs[1])]
+
+    def update(self, bond, u, dchi_min, dchi_frac, chi_max, svd_min=1e-14, stream=None):
+        """mps_bond_update_sym on bond 0 (A,B) or 1 (B,A) with the device gate
+        u (charge basis); the new tensors replace the old ones in place."""
+        m, n = bond, 1 - bond
+        desc = sym_desc(self.d, self.secs[m], self.secs[n], self.secs[m], dchi_min, dchi_frac, chi_max, svd_min,
+                        self.prec)
+        if sym_capacity(desc) > self.chi_cap:
+            raise QrtebdError(MPS_ERR_CAPACITY, f"new bond may reach {sym_capacity(desc)} > chi_cap {self.chi_cap}")
+        mps_bond_update_sym(self.ctx, desc, self.Xi[m], self.B[m], self.B[n], u, self.B[m], self.Xi[n], self.B[n],
+                            self.sec_dev, self.chi_dev, self.eps_dev, stream)
+        self.ctx.sync(stream)
+        self.secs[n] = [int(x) for x in self.sec_dev.cpu().numpy()]
+        self.eps_sum += float(self.eps_dev.item())
+
+    def step(self, u_half, u_full, dchi_min, dchi_frac, chi_max, svd_min=1e-14, stream=None):
+        """Second-order step: (A,B) for dt/2, (B,A) for dt, (A,B) for dt/2."""
+        for bond, u in ((0, u_half), (1, u_full), (0, u_half)):
+            self.update(bond, u, dchi_min, dchi_frac, chi_max, svd_min, stream)
+
+    def measure(self, op1=None, op2=None, site_vals=None, norms=None, bond_vals=None, entropies=None, stream=None):
+        """mps_measure on the cell (operators in the charge basis)."""
+        ch = self.chis()
+        bp = (P * 2)(*[P(t.data_ptr()) for t in self.B])
+        xp = (P * 2)(*[P(t.data_ptr()) for t in self.Xi])
+        h = P()
+        _check(self.ctx.lib.mps_state_create(self.ctx.h, 1, 2, self.d, self.chi_cap, self.prec, bp, xp,
+                                             (I * 3)(ch[0], ch[1], ch[0]), ctypes.byref(h)))
+        try:
+            _check(self.ctx.lib.mps_measure(self.ctx.h, h, _ptr(op1), _ptr(op2), _ptr(site_vals), _ptr(norms),
+                                            _ptr(bond_vals), _ptr(entropies), _stream(stream)))
+        finally:
+            self.ctx.lib.mps_state_destroy(h)
+
+    def to_numpy(self):
+        """(B list, Xi list, secs) with live dimensions (synchronises)."""
+        import torch
+        torch.cuda.synchronize()
+        ch = self.chis()
+        B, Xi = [], []
+        for m in range(2):
+            k = ch[m] * self.d * ch[1 - m]
+            B.append(self.B[m][:k].cpu().numpy().astype(np.complex128).reshape(ch[m], self.d, ch[1 - m]))
+            Xi.append(self.Xi[m][: ch[m]].cpu().numpy())
+        return B, Xi, [list(self.secs[0]), list(self.secs[1])]
 
 
 def sweep_policy(chi_max, svd_min=1e-14, dchi_min=100, dchi_frac=0.1, mode=CBE, sweeps=1, exec=EXEC_EAGER,

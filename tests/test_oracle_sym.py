@@ -151,3 +151,39 @@ def test_at_least_one_value_and_ties_go_to_the_lower_charge():
     r = sym.sym_bond_update(xi, bm, bn, U, sec, sec, sec, 10, 0.0, 3, 1e-14)
     assert np.allclose(r["S"][0], r["S"][1], rtol=1e-14) and r["S"][0][1] > 1e-3
     assert r["sec"] == [2, 1]
+
+
+def test_charge_basis_quench_matches_the_dense_clock_basis_quench():
+    """The uniform cell of the Z_3 clock model (g = 1, dt = 0.05, 12
+    second-order steps, chi_max = 16, eta at its maximum) from the charge-0
+    product state: block by block in the charge basis and densely (oracle/
+    bond.py through oracle/mps.py) in the clock basis from |+>|+>...  Both
+    keep the chi_max largest Schmidt values of every update above svd_min =
+    1e-6 (clear of the ~1e-8 |S| rounding floor of S from L^dag L, whose
+    count depends on the block sizes), so the bond dimensions, <X + X^dag>
+    and the bond energies agree to rounding."""
+    from oracle import mps
+    d, g, dt, steps, chi_max = 3, 1.0, 0.05, 12, 16
+    plus = np.full((1, d, 1), 1 / np.sqrt(d), np.complex128)
+    st = dict(B=[plus, plus.copy()], Xi=[np.ones(1), np.ones(1)], finite=False)
+    _, Xc = clock.clock_ops(d)
+    hb = clock.bond_hamiltonian(d, g)
+    gh, gf = [clock.gate(hb, dt / 2)] * 2, [clock.gate(hb, dt)] * 2
+    B, Xi, secs = inputs.charge_product_cell(d)
+    S = dict(B=list(B), Xi=list(Xi), secs=[list(secs[0]), list(secs[1])], finite=False)
+    Uh, Uf = sym.to_charge_basis_gate(gh[0], d), sym.to_charge_basis_gate(gf[0], d)
+    hc = sym.to_charge_basis_gate(hb, d)
+    w = np.exp(2j * np.pi * np.arange(d) / d)
+    for _ in range(steps):
+        mps.trotter_step(st, gh, gf, dchi_rule=lambda c: 1000, chi_max=chi_max, svd_min=1e-6)
+        for bnd, U in ((0, Uh), (1, Uf), (0, Uh)):
+            m, n = bnd, 1 - bnd
+            r = sym.sym_bond_update(S["Xi"][m], S["B"][m], S["B"][n], U, S["secs"][m], S["secs"][n], S["secs"][m],
+                                    1000, 0.0, chi_max, 1e-6)
+            S["B"][m], S["B"][n], S["Xi"][n], S["secs"][n] = r["bm"], r["bn"], r["xi"], r["sec"]
+        assert [sum(s) for s in S["secs"]] == [b.shape[0] for b in st["B"]]
+        xd, _ = mps.site_expectation(st, Xc + Xc.conj().T)
+        xs, _ = mps.site_expectation(S, np.diag(w + w.conj()))
+        assert np.max(np.abs(xd - xs)) < 1e-12
+        assert np.max(np.abs(mps.bond_expectation(st, [hb, hb]) - mps.bond_expectation(S, [hc, hc]))) < 1e-12
+    assert max(b.shape[0] for b in st["B"]) == chi_max   # the cut was reached
