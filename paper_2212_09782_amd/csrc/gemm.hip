@@ -2,18 +2,18 @@
 //
 // Every contraction of the bond update (theta, X, Y, L^dag L, the new tensors,
 // the compact-WY trailing updates of the Householder QR) is a complex matrix
-// product.  With FP64 arithmetic a complex product is four real MFMA
-// products (Re C += Re A Re B - Im A Im B, Im C += Re A Im B + Im A Re B); with
-// FP32 arithmetic it is three (Gauss' form: P1 = Re A Re B, P2 = Im A Im B,
-// P3 = (Re A + Im A)(Re B + Im B), Re C = P1 - P2, Im C = P3 - P1 - P2).
-// FP64 runs on v_mfma_f64_16x16x4f64, FP32 on v_mfma_f32_16x16x4f32, both with
-// their native accumulator.
+// product, formed from three real MFMA products (Gauss' form: P1 = Re A Re B,
+// P2 = Im A Im B, P3 = (Re A + Im A)(Re B + Im B), Re C = P1 - P2,
+// Im C = P3 - P1 - P2) instead of four.  FP64 runs on v_mfma_f64_16x16x4f64,
+// FP32 on v_mfma_f32_16x16x4f32, both with their native accumulator.  The
+// rounding of the form is that of the four-product one up to a constant
+// (|err Im C| <= ~3 u sum |Re A + Im A| |Re B + Im B| per term).
 //
 // Tiling: a 256-thread workgroup owns a 64x64 output tile, each wave a 32x32
 // quadrant (2x2 MFMA blocks, one accumulator set per real product).  Operand
-// tiles of depth 16 are staged through LDS in planar k-major form (re, im and,
-// for the 3-product form, re + im) so that each MFMA operand is one
-// conflict-light LDS read per lane.  LDS is
+// tiles of depth 16 are staged through LDS as re and im planes, [m][k] rows
+// with k contiguous, so that a lane reads the four k values of its MFMA steps
+// with one vector read per plane and forms re + im in registers.  LDS is
 // double-buffered: the next tile is loaded from global memory into registers
 // and stored into the other buffer while the current one is consumed, so each
 // K stage needs one workgroup barrier.  Workgroup ids are remapped so that the
@@ -57,27 +57,23 @@ template <> struct Mfma<float> {
   __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
+constexpr int BM = 64, BN = 64, BK = 16;
 
 template <typename Tin, typename Tout, typename Tc>
 __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   using MF = Mfma<Tc>;
   using v4 = typename MF::v4;
-  // FP32 products take the 3-product form (P1 = Re A Re B, P2 = Im A Im B,
-  // P3 = (Re A + Im A)(Re B + Im B); Re C = P1 - P2, Im C = P3 - P1 - P2),
-  // a quarter fewer MFMAs; FP64 keeps the 4-product form, whose smaller
-  // accumulator set fits two waves per SIMD (the 3-product form does not).
-  constexpr bool k3 = sizeof(Tc) == 4;
-  constexpr int NPL = k3 ? 3 : 2;            // accumulator sets (real products)
-  // LDS holds the re and im planes of each operand tile, double-buffered.
-  // 3-product form: [m][k] rows with k contiguous (stride BK + 4), so a lane
-  // reads the four k values of its four MFMA steps with one 16-byte read (the
-  // steps take k = 4 (lane / 16) + s, the same for A and B), re + im is
-  // formed in registers.  4-product form: [k][m] rows (stride BM + 1).
+  // Three accumulator sets (P1, P2, P3).  FP64 fits two waves per SIMD with
+  // them (205 registers; 80 KiB of LDS per workgroup, two workgroups per CU).
+  constexpr int NPL = 3;
+  // LDS holds the re and im planes of each operand tile, double-buffered, as
+  // [m][k] rows with k contiguous (stride BK + 4), so a lane reads the four k
+  // values of its four MFMA steps with one vector read per plane (the steps
+  // take k = 4 (lane / 16) + s, the same for A and B); re + im is formed in
+  // registers.
   constexpr int KS = BK + 4;
-  constexpr int D1 = k3 ? BM : BK, D2 = k3 ? KS : BM + PAD;
-  __shared__ __attribute__((aligned(16))) Tc As[2][2][D1][D2];
-  __shared__ __attribute__((aligned(16))) Tc Bs[2][2][D1][D2];
+  __shared__ __attribute__((aligned(16))) Tc As[2][2][BM][KS];
+  __shared__ __attribute__((aligned(16))) Tc Bs[2][2][BN][KS];
 
   // XCD-aware remap: hardware workgroup g runs on XCD g % 8; give XCD x the
   // contiguous logical range [start_x, start_x + count_x)
@@ -120,8 +116,7 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = (wid & 1) * 32, wn = (wid >> 1) * 32;
 
-  // 3-product form: P1, P2, P3; 4-product form: Re C in acc[0], Im C in acc[1]
-  v4 acc[NPL][2][2];
+  v4 acc[NPL][2][2];   // P1, P2, P3
 #pragma unroll
   for (int pl = 0; pl < NPL; ++pl)
 #pragma unroll
@@ -129,40 +124,33 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[pl][i][j] = v4{0, 0, 0, 0};
 
-  // thread -> tile element mapping for the two storage orientations; each
-  // thread stages EPT elements of each operand per stage in groups of 4
-  constexpr int EPT = BM * BK / 256, KG = BK / 16;
+  // thread -> tile element mapping: each thread stages EPT = 4 consecutive k
+  // of one row of each operand per stage.  Operands stored m-major (A as
+  // stored, B^T / B^H): 64 rows x BK k.  Operands stored k-major (A^T / A^H,
+  // B as stored): lane -> m (or n), wave -> four consecutive k, so the global
+  // loads stay coalesced (64 consecutive elements per load) and each lane
+  // writes one row segment per plane, the conflict-free pattern of the reads.
+  constexpr int EPT = BM * BK / 256;
+  static_assert(EPT == 4, "one LDS row segment holds the four k values of a thread");
   cpx<Tin> ra[EPT], rb[EPT];
-  const int rowq = tid >> 2, colq = (tid & 3) * (BK / 4);   // 64 rows x BK cols (k contiguous)
-  const int rowk = tid >> 4, colk = (tid & 15) * 4;         // BK k-rows (16 per group) x 64 cols
-  // 3-product form, operands stored k-major (A^T / A^H, B as stored): lane ->
-  // m (or n), wave -> four consecutive k, so the global loads stay coalesced
-  // (64 consecutive elements per load) and each lane writes one 16-byte LDS
-  // row segment per plane, the conflict-free pattern of the reads
+  const int rowq = tid >> 2, colq = (tid & 3) * (BK / 4);
   const int kml = tid & 63, kmk = 4 * (tid >> 6);
 
   auto load = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      const int g = e >> 2, e4 = e & 3;
       cpx<Tin> z = mk<Tin>(0, 0);
       if (opA == OP_N) {
         const int m = m0 + rowq, k = k0 + colq + e;
         if (m < M && k < kend) z = A[(long long)m * lda + k];
-      } else if (k3) {
-        const int k = k0 + kmk + e, m = m0 + kml;
-        if (m < M && k < kend) z = A[(long long)k * lda + m];
       } else {
-        const int k = k0 + rowk + 16 * g, m = m0 + colk + e4;
+        const int k = k0 + kmk + e, m = m0 + kml;
         if (m < M && k < kend) z = A[(long long)k * lda + m];
       }
       ra[e] = z;
       cpx<Tin> w = mk<Tin>(0, 0);
-      if (opB == OP_N && k3) {
+      if (opB == OP_N) {
         const int k = k0 + kmk + e, n = n0 + kml;
-        if (n < N && k < kend) w = B[(long long)k * ldb + n];
-      } else if (opB == OP_N) {
-        const int k = k0 + rowk + 16 * g, n = n0 + colk + e4;
         if (n < N && k < kend) w = B[(long long)k * ldb + n];
       } else {
         const int n = n0 + rowq, k = k0 + colq + e;
@@ -171,40 +159,15 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
       rb[e] = w;
     }
   };
+  typedef Tc f4 __attribute__((ext_vector_type(4)));
   auto store = [&](int buf) {
-    if constexpr (k3) {
-      static_assert(EPT == 4, "16-byte LDS rows need four k values per thread");
-      typedef float f4 __attribute__((ext_vector_type(4)));
-      if (opA == OP_N) {   // four consecutive k of row rowq: one 16-byte write per plane
-        *(f4*)&As[buf][0][rowq][colq] = f4{(Tc)ra[0].re, (Tc)ra[1].re, (Tc)ra[2].re, (Tc)ra[3].re};
-        *(f4*)&As[buf][1][rowq][colq] =
-            f4{sa * (Tc)ra[0].im, sa * (Tc)ra[1].im, sa * (Tc)ra[2].im, sa * (Tc)ra[3].im};
-      } else {   // four consecutive k of row kml
-        *(f4*)&As[buf][0][kml][kmk] = f4{(Tc)ra[0].re, (Tc)ra[1].re, (Tc)ra[2].re, (Tc)ra[3].re};
-        *(f4*)&As[buf][1][kml][kmk] =
-            f4{sa * (Tc)ra[0].im, sa * (Tc)ra[1].im, sa * (Tc)ra[2].im, sa * (Tc)ra[3].im};
-      }
-      if (opB != OP_N) {
-        *(f4*)&Bs[buf][0][rowq][colq] = f4{(Tc)rb[0].re, (Tc)rb[1].re, (Tc)rb[2].re, (Tc)rb[3].re};
-        *(f4*)&Bs[buf][1][rowq][colq] =
-            f4{sb * (Tc)rb[0].im, sb * (Tc)rb[1].im, sb * (Tc)rb[2].im, sb * (Tc)rb[3].im};
-      } else {
-        *(f4*)&Bs[buf][0][kml][kmk] = f4{(Tc)rb[0].re, (Tc)rb[1].re, (Tc)rb[2].re, (Tc)rb[3].re};
-        *(f4*)&Bs[buf][1][kml][kmk] =
-            f4{sb * (Tc)rb[0].im, sb * (Tc)rb[1].im, sb * (Tc)rb[2].im, sb * (Tc)rb[3].im};
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int g = e >> 2, e4 = e & 3;
-        const int ak = opA == OP_N ? colq + e : rowk + 16 * g, am = opA == OP_N ? rowq : colk + e4;
-        const int bk = opB == OP_N ? rowk + 16 * g : colq + e, bn = opB == OP_N ? colk + e4 : rowq;
-        As[buf][0][ak][am] = (Tc)ra[e].re;
-        As[buf][1][ak][am] = sa * (Tc)ra[e].im;
-        Bs[buf][0][bk][bn] = (Tc)rb[e].re;
-        Bs[buf][1][bk][bn] = sb * (Tc)rb[e].im;
-      }
-    }
+    // four consecutive k of one row: one vector write per plane
+    const int ar = opA == OP_N ? rowq : kml, ac = opA == OP_N ? colq : kmk;
+    const int br = opB == OP_N ? kml : rowq, bc = opB == OP_N ? kmk : colq;
+    *(f4*)&As[buf][0][ar][ac] = f4{(Tc)ra[0].re, (Tc)ra[1].re, (Tc)ra[2].re, (Tc)ra[3].re};
+    *(f4*)&As[buf][1][ar][ac] = f4{sa * (Tc)ra[0].im, sa * (Tc)ra[1].im, sa * (Tc)ra[2].im, sa * (Tc)ra[3].im};
+    *(f4*)&Bs[buf][0][br][bc] = f4{(Tc)rb[0].re, (Tc)rb[1].re, (Tc)rb[2].re, (Tc)rb[3].re};
+    *(f4*)&Bs[buf][1][br][bc] = f4{sb * (Tc)rb[0].im, sb * (Tc)rb[1].im, sb * (Tc)rb[2].im, sb * (Tc)rb[3].im};
   };
 
   if (kbeg < kend) {
@@ -216,8 +179,7 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
     const bool more = k0 + BK < kend;
     if (more) load(k0 + BK);     // global -> registers, overlapping the MFMAs below
-    if constexpr (k3) {
-      typedef float f4 __attribute__((ext_vector_type(4)));
+    {
       const int kq = 4 * (lane >> 4);
       f4 a2[2][2], b2[2][2];   // [re / im][block]: k = kq .. kq + 3
 #pragma unroll
@@ -238,28 +200,6 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
             acc[1][i][j] = MF::op(ai, bi, acc[1][i][j]);
             acc[2][i][j] = MF::op(ar + ai, br + bi, acc[2][i][j]);
           }
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        const int kr = kk + (lane >> 4);
-        Tc a3[2][2], b3[2][2];
-#pragma unroll
-        for (int pl = 0; pl < 2; ++pl)
-#pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            a3[pl][i] = As[buf][pl][kr][wm + i * 16 + (lane & 15)];
-            b3[pl][i] = Bs[buf][pl][kr][wn + i * 16 + (lane & 15)];
-          }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            acc[0][i][j] = MF::op(a3[0][i], b3[0][j], acc[0][i][j]);
-            acc[0][i][j] = MF::op(-a3[1][i], b3[1][j], acc[0][i][j]);
-            acc[1][i][j] = MF::op(a3[0][i], b3[1][j], acc[1][i][j]);
-            acc[1][i][j] = MF::op(a3[1][i], b3[0][j], acc[1][i][j]);
-          }
-      }
     }
     if (more) store(buf ^ 1);    // the other buffer was released by the previous barrier
     __syncthreads();
@@ -272,13 +212,8 @@ __device__ __forceinline__ void gemm_body(const GemmBatch& b) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      if constexpr (k3) {
-        acc_re[i][j] = acc[0][i][j] - acc[1][i][j];
-        acc_im[i][j] = acc[NPL - 1][i][j] - acc[0][i][j] - acc[1][i][j];
-      } else {
-        acc_re[i][j] = acc[0][i][j];
-        acc_im[i][j] = acc[1][i][j];
-      }
+      acc_re[i][j] = acc[0][i][j] - acc[1][i][j];
+      acc_im[i][j] = acc[2][i][j] - acc[0][i][j] - acc[1][i][j];
     }
   if (ks > 1) {
     cpx<Tc>* W = (cpx<Tc>*)P.work + (long long)split * P.M * P.N;
