@@ -33,22 +33,25 @@ namespace {
 
 inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Gate and Xi over one row alpha of C and W = 64 / R columns delta: the d^2
-// inputs of every column staged in LDS; thread (column t % W, group t / W)
-// forms the outputs o = group, group + R, ... of its column.  R = 1 for d^2 <=
-// 160 (the default), 2 or 4 for larger d, so the staged block fits in LDS.
+// Gate and Xi over one row alpha of C and W columns delta: the d^2 inputs
+// of every column staged in LDS; 256 threads in R = 256 / W groups, thread
+// (column t % W, group t / W) forms the outputs o = group, group + R, ... of
+// its column.  W is 64, 32 or 16, the widest whose staged block (d^2 W
+// elements) leaves room for three workgroups per CU, so that twelve or more
+// waves per CU keep loads in flight.
 template <typename S>
-__global__ __launch_bounds__(64) void gate_kernel(cpx<S>* C, cpx<S>* Th, const c128* __restrict__ U,
-                                                  const double* xi, int d, int chiR, int R, double* partial) {
+__global__ __launch_bounds__(256) void gate_kernel(cpx<S>* C, cpx<S>* Th, const c128* __restrict__ U,
+                                                   const double* xi, int d, int chiR, int W, double* partial) {
   extern __shared__ unsigned char gate_lds[];
+  __shared__ double scr[4];
   cpx<S>* Cs = reinterpret_cast<cpx<S>*>(gate_lds);  // d^2 x W in storage precision
   constexpr int G = 5;                                // outputs per pass: G independent FP64 chains per LDS read
-  const int d2 = d * d, t = threadIdx.x, W = 64 / R, col = t % W, grp = t / W;
+  const int d2 = d * d, t = threadIdx.x, R = 256 / W, col = t % W, grp = t / W;
   const int alpha = blockIdx.y, delta = blockIdx.x * W + col;
   const long long base = (long long)alpha * d2 * chiR;
   const bool live = delta < chiR;
   for (int q = grp; q < d2; q += R) Cs[q * W + col] = live ? C[base + (long long)q * chiR + delta] : mk<S>(0, 0);
-  if (R > 1) __syncthreads();   // a column's inputs come from R threads
+  __syncthreads();   // a column's inputs come from R threads
   const double x = xi ? xi[alpha] : 1.0;
   const int nout = (d2 - grp + R - 1) / R;   // outputs o = grp + R j, j < nout
   double nrm = 0;
@@ -79,15 +82,18 @@ __global__ __launch_bounds__(64) void gate_kernel(cpx<S>* C, cpx<S>* Th, const c
       }
     }
   }
-  nrm = wave_sum(nrm);
+  nrm = block_sum(nrm, scr);
   if (t == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = nrm;
 }
 
-// Output groups of the gate kernel for physical dimension d (LDS of d^2 x 64 / R elements).
-inline int gate_groups(int d, size_t es) {
-  int R = 1;
-  while (R < 4 && (size_t)d * d * (64 / R) * es > 160 * 1024) R *= 2;
-  return R;
+// Dynamic LDS the gate kernel may take (160 KiB less its static block sums).
+constexpr int kGateMaxLds = 160 * 1024 - 256;
+
+// Columns per workgroup of the gate kernel for physical dimension d.
+inline int gate_width(int d, size_t es) {
+  int W = 64;
+  while (W > 16 && (size_t)d * d * W * es > 48 * 1024) W /= 2;
+  return W;
 }
 
 template <typename S>
@@ -376,18 +382,18 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
     if (b.pre) continue;
     BondBufs& w = W[i];
     const int d = b.d, chiL = b.chi_l, chiR = b.chi_r, mL = d * chiL, mR = d * chiR;
-    const int R = gate_groups(d, sizeof(cpx<S>)), Wc = 64 / R;
+    const int Wc = gate_width(d, sizeof(cpx<S>));
     const dim3 grid((chiR + Wc - 1) / Wc, chiL);
     const size_t shm = (size_t)d * d * Wc * sizeof(cpx<S>);
     static bool attr = false;
     if (!attr) {
       QT_HIP_CHECK(hipFuncSetAttribute((const void*)gate_kernel<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024));
+                                       kGateMaxLds));
       attr = true;
     }
     const bool diag = b.xi_is_diag != 0;
-    hipLaunchKernelGGL(gate_kernel<S>, grid, dim3(64), shm, s, (cpx<S>*)w.C, diag ? (cpx<S>*)w.Th : nullptr, c.u,
-                       diag ? (const double*)c.xi_m : nullptr, d, chiR, R, w.partial);
+    hipLaunchKernelGGL(gate_kernel<S>, grid, dim3(256), shm, s, (cpx<S>*)w.C, diag ? (cpx<S>*)w.Th : nullptr, c.u,
+                       diag ? (const double*)c.xi_m : nullptr, d, chiR, Wc, w.partial);
     QT_HIP_CHECK(hipGetLastError());
     if (diag) {
       if ((rc = reduce_partials(w.partial, (int)(grid.x * grid.y), w.norm2, s))) return rc;
@@ -677,18 +683,18 @@ int two_site_c128(const BondShape& b, const void* xi_m, const void* b_m, const v
   if ((rc = gemm_one(gemm_prob(b_m, b.chi_m, OP_N, b_n, mR, OP_N, C, mR, mL, mR, b.chi_m), GemmTypes{DT_C128, DT_C128},
                      s, true)))
     return rc;
-  const int R = gate_groups(d, sizeof(c128)), Wc = 64 / R;
+  const int Wc = gate_width(d, sizeof(c128));
   const dim3 grid((chiR + Wc - 1) / Wc, chiL);
   const size_t shm = (size_t)d * d * Wc * sizeof(c128);
   static bool attr = false;
   if (!attr) {
     QT_HIP_CHECK(hipFuncSetAttribute((const void*)gate_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     160 * 1024));
+                                     kGateMaxLds));
     attr = true;
   }
   const bool diag = b.xi_is_diag != 0;
-  hipLaunchKernelGGL(gate_kernel<double>, grid, dim3(64), shm, s, C, diag ? Th : nullptr, u,
-                     diag ? (const double*)xi_m : nullptr, d, chiR, R, partial);
+  hipLaunchKernelGGL(gate_kernel<double>, grid, dim3(256), shm, s, C, diag ? Th : nullptr, u,
+                     diag ? (const double*)xi_m : nullptr, d, chiR, Wc, partial);
   QT_HIP_CHECK(hipGetLastError());
   if (diag) return reduce_partials(partial, (int)(grid.x * grid.y), norm2, s);
   const int ncol = d * mR;

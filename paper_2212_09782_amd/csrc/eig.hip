@@ -702,7 +702,7 @@ __global__ __launch_bounds__(256) void cluster_mgs_kernel(SmallBatch sb, double 
   const double ctol = rtol * fmax(fabs(lam[0]), fabs(lam[kw - 1]));
   if (j > 0 && lam[j - 1] - lam[j] <= ctol) return;
   int e = j;
-  while (e + 1 < kw && lam[e] - lam[e + 1] <= ctol) ++e;
+  while (e + 1 < kw && lam[e] - lam[e + 1] <= ctol && e - j < kBigCluster) ++e;   // larger: cluster_bcgs_kernel
   if (e == j || e - j + 1 > kBigCluster) return;
   for (int pass = 0; pass < 2; ++pass)
     for (int v = j; v <= e; ++v) {
@@ -743,27 +743,38 @@ constexpr int kFilterLds = 4 * kEigMaxN + kEigMaxN / 8;
 constexpr double kFilterRel = 1e-8;
 
 // Start and size of the g-th cluster of more than kBigCluster columns
-// (out[0] = -1 if there is none); lam staged in lds (kw doubles).
+// (out[0] = -1 if there is none); lam staged in lds (kw doubles).  Every
+// thread looks at its own columns: a cluster start walks to its end (at
+// most the cluster's size in steps), a large cluster enters a list, and its
+// rank in the list (by column) decides which block takes it.
+constexpr int kMaxBigClusters = kEigMaxN / (kBigCluster + 1) + 1;
 __device__ inline void find_big_cluster(const double* lam, int kw, double rtol, int g, double* lds, int* out) {
+  __shared__ int nbig;
+  __shared__ int big[kMaxBigClusters];
   for (int c = threadIdx.x; c < kw; c += blockDim.x) lds[c] = lam[c];
-  __syncthreads();
   if (threadIdx.x == 0) {
-    const double ctol = rtol * fmax(fabs(lds[0]), fabs(lds[kw - 1]));
-    int cnt = 0, j = 0;
+    nbig = 0;
     out[0] = -1;
     out[1] = 0;
-    while (j < kw) {
-      int e = j;
+  }
+  __syncthreads();
+  const double ctol = rtol * fmax(fabs(lds[0]), fabs(lds[kw - 1]));
+  for (int c = threadIdx.x; c < kw; c += blockDim.x) {
+    if (c > 0 && lds[c - 1] - lds[c] <= ctol) continue;   // not a cluster start
+    int e = c;
+    while (e + 1 < kw && lds[e] - lds[e + 1] <= ctol) ++e;
+    if (e - c + 1 > kBigCluster) big[atomicAdd(&nbig, 1)] = c;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nbig; i += blockDim.x) {
+    const int c = big[i];
+    int rank = 0;
+    for (int k = 0; k < nbig; ++k) rank += big[k] < c;
+    if (rank == g) {
+      int e = c;
       while (e + 1 < kw && lds[e] - lds[e + 1] <= ctol) ++e;
-      if (e - j + 1 > kBigCluster) {
-        if (cnt == g) {
-          out[0] = j;
-          out[1] = e - j + 1;
-          break;
-        }
-        ++cnt;
-      }
-      j = e + 1;
+      out[0] = c;
+      out[1] = e - c + 1;
     }
   }
   __syncthreads();
