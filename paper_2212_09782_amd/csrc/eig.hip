@@ -1157,24 +1157,52 @@ __global__ __launch_bounds__(kBcgsThreads) void cluster_bcgs_kernel(SmallBatch s
   }
 }
 
-// Adaptive Newton-Schulz steps.  live[0]: K extent of the next Z^H Z (n, or 0
-// once stopped); live[1]: K extent of this step's update (kwant or 0);
-// live[2..3]: bits of max |Z^H Z - 1| of this step (non-negative doubles order
-// as their bit patterns); live[4]: stopped; live[5]: kwant.
+// Adaptive Newton-Schulz steps.  live[0]: live size of the next Z^H Z
+// (kwant, or 0 once stopped); live[1]: live rows of this step's update (n, or
+// 0 when it is skipped); live[2..3]: bits of max |Z^H Z - 1| of this step
+// (non-negative doubles order as their bit patterns); live[4]: stopped;
+// live[5]: n.  Every kernel of a step that Z^H Z feeds returns at once when
+// live[0] is 0, so a finished job costs only the launches.
 __global__ void ns_init_kernel(int* live, int n, int kwant) {
-  live[0] = n;
-  live[1] = kwant;
+  live[0] = kwant;
+  live[1] = n;
   live[4] = 0;
-  live[5] = kwant;
+  live[5] = n;
 }
 
-__global__ void ns_max_kernel(const c128* D, long long tot, int* live) {
+// Z^H Z - 1 from the upper triangle the Hermitian product forms: the lower
+// triangle filled by conjugation (32 x 32 blocks read transposed through
+// LDS), 1 subtracted on the diagonal, and, with want_max, max |Z^H Z - 1| over
+// the upper triangle into live[2..3].  Nothing while the step is off.
+__global__ __launch_bounds__(256) void ns_gram_fix_kernel(c128* G, int k, int* live, int want_max) {
+  if (live[0] == 0) return;
+  __shared__ c128 tile[32][33];
+  const int bi = blockIdx.y, bj = blockIdx.x;   // destination block (bi >= bj)
+  if (bj > bi) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   double mx = 0;
-  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < tot; i += (long long)gridDim.x * 256)
-    mx = fmax(mx, fmax(fabs(D[i].re), fabs(D[i].im)));
-  mx = wave_max(mx);
-  if ((threadIdx.x & 63) == 0)
-    atomicMax((unsigned long long*)(live + 2), (unsigned long long)__double_as_longlong(mx));
+  for (int r = ty; r < 32; r += 8) {   // source block (bj, bi): rows bj*32 + r
+    const int i = bj * 32 + r, j = bi * 32 + tx;
+    if (i < k && j < k) {
+      c128 v = G[(long long)i * k + j];
+      if (i == j) v.re -= 1.0;
+      tile[r][tx] = v;
+      if (i <= j) mx = fmax(mx, fmax(fabs(v.re), fabs(v.im)));
+    }
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bi * 32 + r, j = bj * 32 + tx;
+    if (i < k && j < k && i >= j) {
+      const c128 v = tile[tx][r];
+      G[(long long)i * k + j] = i == j ? v : cconj(v);
+    }
+  }
+  if (want_max) {
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0)
+      atomicMax((unsigned long long*)(live + 2), (unsigned long long)__double_as_longlong(mx));
+  }
 }
 
 // From this step's max |Z^H Z - 1| (measured before its update, which squares
@@ -1192,11 +1220,10 @@ __global__ void ns_decide_kernel(int* live, int optional, double tol_skip, doubl
   *(unsigned long long*)(live + 2) = 0ull;
 }
 
-// D = G - 1 on a k x k block (in place).
-__global__ void sub_identity_kernel(c128* G, int k) {
-  const long long tot = (long long)k * k;
-  for (long long idx = blockIdx.x * 256ll + threadIdx.x; idx < tot; idx += (long long)gridDim.x * 256)
-    if (idx / k == idx % k) G[idx].re -= 1.0;
+// The operand copy of the update (tot elements), unless the update is skipped.
+__global__ void ns_copy_kernel(const c128* __restrict__ src, c128* __restrict__ dst, long long tot, const int* live) {
+  if (live[1] == 0) return;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < tot; i += (long long)gridDim.x * 256) dst[i] = src[i];
 }
 
 __global__ void eig1_kernel(const c128* G, double* lam, c128* E) {
@@ -1385,9 +1412,10 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
   // orthogonality error of Z), grouped over the jobs: the job's ns_steps
   // always, then further ones (up to kNsMaxSteps) until max |Z^H Z - 1| before
   // a step is below 1e-7 (that step leaves ~1e-14), decided on the device: a
-  // finished job's products run with live extent 0.  Vectors of eigenvalues closer than the cluster tolerance
-  // were orthogonalised by Gram-Schmidt above; the rest overlap by at most
-  // about u / rtol, which these steps remove.
+  // finished job's products run with live size 0 and its other kernels return
+  // at once.  Vectors of eigenvalues closer than the cluster tolerance were
+  // orthogonalised by Gram-Schmidt above; the rest overlap by at most about
+  // u / rtol, which these steps remove.
   const GemmTypes ty{DT_C128, DT_C128};
   std::vector<GemmProb> gs;
   for (int j : big) {
@@ -1409,33 +1437,38 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
       g1.ksplit = splitk_auto(J.kwant, J.kwant, J.n, 4 * (size_t)J.n * J.n * 8, sizeof(c128), true);
       g1.work = J.w->lu;
       g1.herm = 1;
-      if (gated) g1.dK = J.w->ns_live;
+      if (gated) g1.dM = g1.dN = J.w->ns_live;
       gs.push_back(g1);
     }
     if ((rc = gemm_run(gs.data(), (int)gs.size(), ty, s))) return rc;
-    for (int j : ns)
-      if ((rc = herm_fill_lower(jobs[j].w->gz, jobs[j].kwant, jobs[j].kwant, s))) return rc;
     gs.clear();
     for (int j : ns) {
       const EigJob& J = jobs[j];
       const bool gated = it >= J.ns_steps;
-      const long long kk = (long long)J.kwant * J.kwant;
-      hipLaunchKernelGGL(sub_identity_kernel, dim3(std::min(4096, (J.kwant * J.kwant + 255) / 256)), dim3(256), 0, s,
-                         J.w->gz, J.kwant);
+      const bool decide = it + 1 >= J.ns_steps;   // from the last fixed step on: decide the optional ones
+      const int nb = (J.kwant + 31) / 32;
+      hipLaunchKernelGGL(ns_gram_fix_kernel, dim3(nb, nb), dim3(256), 0, s, J.w->gz, J.kwant, J.w->ns_live,
+                         decide ? 1 : 0);
       QT_HIP_CHECK(hipGetLastError());
-      if (it + 1 >= J.ns_steps) {   // from the last fixed step on: decide the optional ones
-        hipLaunchKernelGGL(ns_max_kernel, dim3((int)std::min<long long>(1024, (kk + 255) / 256)), dim3(256), 0, s,
-                           (const c128*)J.w->gz, kk, J.w->ns_live);
-        QT_HIP_CHECK(hipGetLastError());
+      if (decide) {
         hipLaunchKernelGGL(ns_decide_kernel, dim3(1), dim3(1), 0, s, J.w->ns_live, gated ? 1 : 0, 1e-13, 1e-7);
         QT_HIP_CHECK(hipGetLastError());
       }
-      QT_HIP_CHECK(hipMemcpyAsync(J.w->ztmp, J.E, (size_t)J.n * J.kwant * sizeof(c128), hipMemcpyDeviceToDevice, s));
-      GemmProb g2 = gemm_prob(J.w->ztmp, J.kwant, OP_N, J.w->gz, J.kwant, OP_N, J.E, J.kwant, J.n, J.kwant, J.kwant,
+      GemmProb g2 = gemm_prob(J.E, J.kwant, OP_N, J.w->gz, J.kwant, OP_N, J.E, J.kwant, J.n, J.kwant, J.kwant,
                               -0.5f, 1.f);
       g2.ksplit = splitk_auto(J.n, J.kwant, J.kwant, 4 * (size_t)J.n * J.n * 8, sizeof(c128));
       g2.work = J.w->lu;
-      if (gated) g2.dK = J.w->ns_live + 1;
+      if (g2.ksplit <= 1) {
+        // one pass writes E while other tiles of its rows still read it: the
+        // left operand is a copy (split K writes only the partials, and the
+        // reduction after the product is the one that updates E)
+        const long long tot = (long long)J.n * J.kwant;
+        hipLaunchKernelGGL(ns_copy_kernel, dim3((int)std::min<long long>(2048, (tot + 255) / 256)), dim3(256), 0, s,
+                           (const c128*)J.E, J.w->ztmp, tot, (const int*)J.w->ns_live);
+        QT_HIP_CHECK(hipGetLastError());
+        g2.A = J.w->ztmp;
+      }
+      if (gated) g2.dM = J.w->ns_live + 1;
       gs.push_back(g2);
     }
     if ((rc = gemm_run(gs.data(), (int)gs.size(), ty, s))) return rc;

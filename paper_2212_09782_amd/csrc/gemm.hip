@@ -265,9 +265,15 @@ __global__ __launch_bounds__(256, sizeof(Tc) == 8 ? 2 : 3) void contract_gemm_ke
   gemm_body<Tin, Tout, Tc>(b);
 }
 
-// C = alpha * sum_s work[s] + beta * C over the live M x N.
+// C = alpha * sum_s work[s] + beta * C over the live M x N, for every problem
+// of a batch at once: problem p owns workgroups [tile_start[p], tile_start[p+1]).
 template <typename Tout, typename Tc>
-__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmProb P) {
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmBatch b) {
+  const int bid = blockIdx.x;
+  int p = 0;
+  while (p + 1 < b.nprob && bid >= b.tile_start[p + 1]) ++p;
+  const GemmProb& P = b.p[p];
+  const int nblk = b.tile_start[p + 1] - b.tile_start[p];
   int M = P.M, N = P.N;
   if (P.dM) M = min(M, *P.dM);
   if (P.dN) N = min(N, *P.dN);
@@ -276,8 +282,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmProb P) {
   const cpx<Tc>* W = (const cpx<Tc>*)P.work;
   cpx<Tout>* C = (cpx<Tout>*)P.C;
   const Tc alpha = (Tc)P.alpha, beta = (Tc)P.beta;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
+  for (long long idx = (bid - b.tile_start[p]) * 256ll + threadIdx.x; idx < total; idx += nblk * 256ll) {
     const int row = (int)(idx / N), col = (int)(idx % N);
     Tc sr = 0, si = 0;
     for (int s = 0; s < P.ksplit; ++s) {
@@ -323,14 +328,22 @@ int launch_typed(const GemmProb* probs, int nprob, hipStream_t stream, bool cont
     else
       hipLaunchKernelGGL((gemm_kernel<Tin, Tout, Tc>), dim3(total), dim3(256), 0, stream, b);
     QT_HIP_CHECK(hipGetLastError());
+    // one launch reduces the split-K partials of every problem of the batch
+    GemmBatch r{};
+    int nblk = 0;
     for (int q = 0; q < b.nprob; ++q) {
       const GemmProb& pr = b.p[q];
       if (pr.ksplit > 1 && !pr.skip_reduce) {
         const long long tot = (long long)pr.M * pr.N;
-        const int grid = (int)std::min<long long>((tot + 255) / 256, 4096);
-        hipLaunchKernelGGL((splitk_reduce_kernel<Tout, Tc>), dim3(grid), dim3(256), 0, stream, pr);
-        QT_HIP_CHECK(hipGetLastError());
+        r.p[r.nprob] = pr;
+        r.tile_start[r.nprob++] = nblk;
+        nblk += (int)std::min<long long>((tot + 255) / 256, 4096);
       }
+    }
+    if (r.nprob) {
+      r.tile_start[r.nprob] = nblk;
+      hipLaunchKernelGGL((splitk_reduce_kernel<Tout, Tc>), dim3(nblk), dim3(256), 0, stream, r);
+      QT_HIP_CHECK(hipGetLastError());
     }
   }
   return 0;
