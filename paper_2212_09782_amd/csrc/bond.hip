@@ -36,17 +36,19 @@ inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 // Gate and Xi over one row alpha of C and W columns delta: the d^2 inputs
 // of every column staged in LDS; 256 threads in R = 256 / W groups, thread
 // (column t % W, group t / W) forms the outputs o = group, group + R, ... of
-// its column.  W is 64, 32 or 16, the widest whose staged block (d^2 W
-// elements) leaves room for three workgroups per CU, so that twelve or more
-// waves per CU keep loads in flight.
-template <typename S>
+// its column, G of them per pass (G independent FP64 chains per LDS read).
+// kWave (W = 64): a group is one wave, so the gate entries a thread reads are
+// the same across its wave and come through scalar loads.  Each complex
+// product-accumulate is four FP64 FMAs.
+template <typename S, bool kWave, int G>
 __global__ __launch_bounds__(256) void gate_kernel(cpx<S>* C, cpx<S>* Th, const c128* __restrict__ U,
-                                                   const double* xi, int d, int chiR, int W, double* partial) {
+                                                   const double* xi, int d, int chiR, int Wa, double* partial) {
   extern __shared__ unsigned char gate_lds[];
   __shared__ double scr[4];
   cpx<S>* Cs = reinterpret_cast<cpx<S>*>(gate_lds);  // d^2 x W in storage precision
-  constexpr int G = 5;                                // outputs per pass: G independent FP64 chains per LDS read
-  const int d2 = d * d, t = threadIdx.x, R = 256 / W, col = t % W, grp = t / W;
+  const int W = kWave ? 64 : Wa;
+  const int d2 = d * d, t = threadIdx.x, R = 256 / W, col = t % W;
+  const int grp = kWave ? __builtin_amdgcn_readfirstlane(t >> 6) : t / W;
   const int alpha = blockIdx.y, delta = blockIdx.x * W + col;
   const long long base = (long long)alpha * d2 * chiR;
   const bool live = delta < chiR;
@@ -67,7 +69,13 @@ __global__ __launch_bounds__(256) void gate_kernel(cpx<S>* C, cpx<S>* Th, const 
       for (int q = 0; q < d2; ++q) {
         const c128 c = ccast<double>(Cs[q * W + col]);
 #pragma unroll
-        for (int u = 0; u < G; ++u) acc[u] = cadd(acc[u], cmul(U[row[u] + q], c));
+        for (int u = 0; u < G; ++u) {
+          const c128 g = U[row[u] + q];
+          acc[u].re = fma(g.re, c.re, acc[u].re);
+          acc[u].im = fma(g.re, c.im, acc[u].im);
+          acc[u].re = fma(-g.im, c.im, acc[u].re);
+          acc[u].im = fma(g.im, c.re, acc[u].im);
+        }
       }
 #pragma unroll
       for (int u = 0; u < G; ++u) {
@@ -89,11 +97,40 @@ __global__ __launch_bounds__(256) void gate_kernel(cpx<S>* C, cpx<S>* Th, const 
 // Dynamic LDS the gate kernel may take (160 KiB less its static block sums).
 constexpr int kGateMaxLds = 160 * 1024 - 256;
 
-// Columns per workgroup of the gate kernel for physical dimension d.
+// Columns per workgroup of the gate kernel for physical dimension d: 64 (one
+// wave per output group) whenever the staged block fits the LDS of a CU;
+// else 32 or 16, the widest whose block (d^2 W elements) leaves room for
+// three workgroups per CU.
 inline int gate_width(int d, size_t es) {
-  int W = 64;
+  if ((size_t)d * d * 64 * es <= (size_t)kGateMaxLds) return 64;
+  int W = 32;
   while (W > 16 && (size_t)d * d * W * es > 48 * 1024) W /= 2;
   return W;
+}
+
+// Dynamic LDS limits are set once per instantiation.
+template <typename S>
+int launch_gate(cpx<S>* C, cpx<S>* Th, const c128* U, const double* xi, int d, int chiL, int chiR, int W,
+                double* partial, size_t shm, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    QT_HIP_CHECK(hipFuncSetAttribute((const void*)gate_kernel<S, true, 7>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     kGateMaxLds));
+    QT_HIP_CHECK(hipFuncSetAttribute((const void*)gate_kernel<S, true, 5>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     kGateMaxLds));
+    QT_HIP_CHECK(hipFuncSetAttribute((const void*)gate_kernel<S, false, 5>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kGateMaxLds));
+    attr = true;
+  }
+  const dim3 grid((chiR + W - 1) / W, chiL);
+  if (W == 64 && d * d <= 28)   // at most 7 outputs per group: one pass
+    hipLaunchKernelGGL((gate_kernel<S, true, 7>), grid, dim3(256), shm, s, C, Th, U, xi, d, chiR, W, partial);
+  else if (W == 64)
+    hipLaunchKernelGGL((gate_kernel<S, true, 5>), grid, dim3(256), shm, s, C, Th, U, xi, d, chiR, W, partial);
+  else
+    hipLaunchKernelGGL((gate_kernel<S, false, 5>), grid, dim3(256), shm, s, C, Th, U, xi, d, chiR, W, partial);
+  QT_HIP_CHECK(hipGetLastError());
+  return 0;
 }
 
 template <typename S>
@@ -385,16 +422,10 @@ int run_batch(const BondCall* calls, int nc, hipStream_t s, KernelTimer* tm, con
     const int Wc = gate_width(d, sizeof(cpx<S>));
     const dim3 grid((chiR + Wc - 1) / Wc, chiL);
     const size_t shm = (size_t)d * d * Wc * sizeof(cpx<S>);
-    static bool attr = false;
-    if (!attr) {
-      QT_HIP_CHECK(hipFuncSetAttribute((const void*)gate_kernel<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       kGateMaxLds));
-      attr = true;
-    }
     const bool diag = b.xi_is_diag != 0;
-    hipLaunchKernelGGL(gate_kernel<S>, grid, dim3(256), shm, s, (cpx<S>*)w.C, diag ? (cpx<S>*)w.Th : nullptr, c.u,
-                       diag ? (const double*)c.xi_m : nullptr, d, chiR, Wc, w.partial);
-    QT_HIP_CHECK(hipGetLastError());
+    if ((rc = launch_gate<S>((cpx<S>*)w.C, diag ? (cpx<S>*)w.Th : nullptr, c.u,
+                             diag ? (const double*)c.xi_m : nullptr, d, chiL, chiR, Wc, w.partial, shm, s)))
+      return rc;
     if (diag) {
       if ((rc = reduce_partials(w.partial, (int)(grid.x * grid.y), w.norm2, s))) return rc;
     } else {
@@ -686,16 +717,10 @@ int two_site_c128(const BondShape& b, const void* xi_m, const void* b_m, const v
   const int Wc = gate_width(d, sizeof(c128));
   const dim3 grid((chiR + Wc - 1) / Wc, chiL);
   const size_t shm = (size_t)d * d * Wc * sizeof(c128);
-  static bool attr = false;
-  if (!attr) {
-    QT_HIP_CHECK(hipFuncSetAttribute((const void*)gate_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     kGateMaxLds));
-    attr = true;
-  }
   const bool diag = b.xi_is_diag != 0;
-  hipLaunchKernelGGL(gate_kernel<double>, grid, dim3(256), shm, s, C, diag ? Th : nullptr, u,
-                     diag ? (const double*)xi_m : nullptr, d, chiR, Wc, partial);
-  QT_HIP_CHECK(hipGetLastError());
+  if ((rc = launch_gate<double>(C, diag ? Th : nullptr, u, diag ? (const double*)xi_m : nullptr, d, chiL, chiR, Wc,
+                                partial, shm, s)))
+    return rc;
   if (diag) return reduce_partials(partial, (int)(grid.x * grid.y), norm2, s);
   const int ncol = d * mR;
   if ((rc = gemm_one(gemm_prob(xi_m, chiL, OP_N, C, ncol, OP_N, Th, ncol, chiL, ncol, chiL), GemmTypes{DT_C128, DT_C128},

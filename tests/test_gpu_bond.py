@@ -83,7 +83,10 @@ CASES = [
     (37, 41, 33, 5, obond.CBE, 45, 200, False),
     (200, 200, 200, 5, obond.CBE, 220, 200, True),
     (130, 130, 130, 4, obond.PLAIN, 130, 130, True),
-    # large d: the gate stages 32 (d = 13) or 16 (d = 20) columns per block
+    # the gate's one-wave groups at d = 8 and 12 (64 columns, five outputs per pass)
+    (6, 7, 70, 8, obond.CBE, 40, 50, True),
+    (4, 3, 5, 12, obond.CBE, 20, 30, True),
+    # large d: the gate stages 16 columns per block (d = 13, 20)
     (3, 4, 5, 13, obond.CBE, 20, 30, True),
     (4, 5, 3, 20, obond.CBE, 30, 40, False),
 ]
