@@ -94,6 +94,75 @@ __global__ __launch_bounds__(256) void gate_kernel(cpx<S>* C, cpx<S>* Th, const 
   if (t == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = nrm;
 }
 
+// The gate at 7 <= d <= 10 (64 columns, one wave per output group): every
+// output of a group stays in registers (NP passes of G complex FP64
+// accumulators, NP G >= ceil(d^2 / 4)) while the inputs pass through LDS in
+// chunks of QC rows, so the staged block is QC x 64 elements (about 48 KiB)
+// and three workgroups share a CU.  Inside a chunk the passes run one after
+// another, each over the chunk's rows with G gate rows (scalar loads
+// streaming along q).  A group with fewer outputs recomputes its last one
+// (not stored).  All inputs of the columns are read before the first output
+// is written in place.
+template <typename S, int NP, int G, int QC>
+__global__ __launch_bounds__(256) void gate_regs_kernel(cpx<S>* C, cpx<S>* Th, const c128* __restrict__ U,
+                                                        const double* xi, int d, int chiR, double* partial) {
+  constexpr int NO = NP * G;
+  extern __shared__ unsigned char gate_lds[];
+  __shared__ double scr[4];
+  cpx<S>* Cs = reinterpret_cast<cpx<S>*>(gate_lds);  // QC x 64 in storage precision
+  const int d2 = d * d, t = threadIdx.x, col = t & 63;
+  const int grp = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int alpha = blockIdx.y, delta = blockIdx.x * 64 + col;
+  const long long base = (long long)alpha * d2 * chiR;
+  const bool live = delta < chiR;
+  const int nout = (d2 - grp + 3) / 4;   // outputs o = grp + 4 j, j < nout
+  c128 acc[NO];
+#pragma unroll
+  for (int j = 0; j < NO; ++j) acc[j] = mk<double>(0, 0);
+  for (int q0 = 0; q0 < d2; q0 += QC) {
+    const int nq = min(QC, d2 - q0);
+    __syncthreads();   // the previous chunk is consumed
+    for (int q = grp; q < nq; q += 4) Cs[q * 64 + col] = live ? C[base + (long long)(q0 + q) * chiR + delta] : mk<S>(0, 0);
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const c128* Ur[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) Ur[u] = U + (long long)(grp + 4 * min(p * G + u, nout - 1)) * d2 + q0;
+      for (int q = 0; q < nq; ++q) {
+        const c128 c = ccast<double>(Cs[q * 64 + col]);
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+          const c128 g = Ur[u][q];
+          c128& a = acc[p * G + u];
+          a.re = fma(g.re, c.re, a.re);
+          a.im = fma(g.re, c.im, a.im);
+          a.re = fma(-g.im, c.im, a.re);
+          a.im = fma(g.im, c.re, a.im);
+        }
+      }
+    }
+  }
+  const double x = xi ? xi[alpha] : 1.0;
+  double nrm = 0;
+  if (live) {
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      if (j < nout) {
+        const long long off = base + (long long)(grp + 4 * j) * chiR + delta;
+        C[off] = ccast<S>(acc[j]);
+        if (Th) {
+          const cpx<S> th = ccast<S>(cscale(acc[j], x));
+          Th[off] = th;
+          nrm += (double)th.re * th.re + (double)th.im * th.im;
+        }
+      }
+    }
+  }
+  nrm = block_sum(nrm, scr);
+  if (t == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = nrm;
+}
+
 // Dynamic LDS the gate kernel may take (160 KiB less its static block sums).
 constexpr int kGateMaxLds = 160 * 1024 - 256;
 
@@ -112,6 +181,9 @@ inline int gate_width(int d, size_t es) {
 template <typename S>
 int launch_gate(cpx<S>* C, cpx<S>* Th, const c128* U, const double* xi, int d, int chiL, int chiR, int W,
                 double* partial, size_t shm, hipStream_t s) {
+  // rows per LDS chunk of the register-resident gate (about 50 KiB, three
+  // workgroups per CU; d = 10 in two chunks of complex128, one of complex64)
+  constexpr int QC = sizeof(S) == 8 ? 50 : 100;
   static bool attr = false;
   if (!attr) {
     QT_HIP_CHECK(hipFuncSetAttribute((const void*)gate_kernel<S, true, 7>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -123,12 +195,28 @@ int launch_gate(cpx<S>* C, cpx<S>* Th, const c128* U, const double* xi, int d, i
     attr = true;
   }
   const dim3 grid((chiR + W - 1) / W, chiL);
-  if (W == 64 && d * d <= 28)   // at most 7 outputs per group: one pass
+  const size_t shq = (size_t)std::min(QC, d * d) * 64 * sizeof(cpx<S>);
+  // the register-resident form where the whole staged block would hold a
+  // CU to fewer than three workgroups (complex128 from d = 7, complex64
+  // storage from d = 9; measured faster there, slower below)
+  const bool regs = W == 64 && d <= 10 && d >= (sizeof(S) == 8 ? 7 : 9);
+  if (W == 64 && d * d <= 28) {   // at most 7 outputs per group: one pass
     hipLaunchKernelGGL((gate_kernel<S, true, 7>), grid, dim3(256), shm, s, C, Th, U, xi, d, chiR, W, partial);
-  else if (W == 64)
+  } else if (regs) {   // ceil(d^2 / 4) outputs per group, all in registers
+#define QT_GATE_REGS(NP, G)                                                                                  \
+  hipLaunchKernelGGL((gate_regs_kernel<S, NP, G, QC>), grid, dim3(256), shq, s, C, Th, U, xi, d, chiR, partial)
+    switch (d) {
+      case 7: QT_GATE_REGS(3, 5); break;
+      case 8: QT_GATE_REGS(4, 4); break;
+      case 9: QT_GATE_REGS(3, 7); break;
+      default: QT_GATE_REGS(5, 5); break;
+    }
+#undef QT_GATE_REGS
+  } else if (W == 64) {
     hipLaunchKernelGGL((gate_kernel<S, true, 5>), grid, dim3(256), shm, s, C, Th, U, xi, d, chiR, W, partial);
-  else
+  } else {
     hipLaunchKernelGGL((gate_kernel<S, false, 5>), grid, dim3(256), shm, s, C, Th, U, xi, d, chiR, W, partial);
+  }
   QT_HIP_CHECK(hipGetLastError());
   return 0;
 }

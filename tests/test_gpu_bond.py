@@ -83,8 +83,11 @@ CASES = [
     (37, 41, 33, 5, obond.CBE, 45, 200, False),
     (200, 200, 200, 5, obond.CBE, 220, 200, True),
     (130, 130, 130, 4, obond.PLAIN, 130, 130, True),
-    # the gate's one-wave groups at d = 8 and 12 (64 columns, five outputs per pass)
+    # the gate's one-wave groups: all outputs in registers at d = 7, 8, 9 (odd d:
+    # groups with fewer outputs), five outputs per pass at d = 12
+    (3, 5, 20, 7, obond.CBE, 20, 40, True),
     (6, 7, 70, 8, obond.CBE, 40, 50, True),
+    (2, 4, 6, 9, obond.CBE, 18, 20, False),
     (4, 3, 5, 12, obond.CBE, 20, 30, True),
     # large d: the gate stages 16 columns per block (d = 13, 20)
     (3, 4, 5, 13, obond.CBE, 20, 30, True),
@@ -239,6 +242,9 @@ MIXED = [
     (64, 64, 64, 3, obond.CBE, 71, 64),
     (120, 100, 90, 4, obond.CBE, 110, 100),
     (64, 64, 64, 3, obond.PLAIN, 64, 64),
+    # the gate on complex64 storage: five outputs per pass (d = 7), all in registers (d = 9)
+    (10, 12, 30, 7, obond.CBE, 30, 30),
+    (20, 24, 70, 9, obond.CBE, 40, 40),
 ]
 
 
