@@ -1162,23 +1162,42 @@ __global__ __launch_bounds__(kBcgsThreads) void cluster_bcgs_kernel(SmallBatch s
 // 0 when it is skipped); live[2..3]: bits of max |Z^H Z - 1| of this step
 // (non-negative doubles order as their bit patterns); live[4]: stopped;
 // live[5]: n.  Every kernel of a step that Z^H Z feeds returns at once when
-// live[0] is 0, so a finished job costs only the launches.
-__global__ void ns_init_kernel(int* live, int n, int kwant) {
-  live[0] = kwant;
-  live[1] = n;
-  live[4] = 0;
-  live[5] = n;
+// live[0] is 0, so a finished job costs only its share of the launches.  The
+// small kernels of a step take all jobs of the batch in one launch.
+struct NsEntry {
+  c128* G;          // Z^H Z (k x k)
+  const c128* src;  // operand copy of the update: E ...
+  c128* dst;        // ... into this buffer (tot elements)
+  long long tot;
+  int* live;
+  int n, k;
+  int flag;         // init: -; fix: form the max; decide: optional step
+};
+constexpr int kMaxNsJobs = 32;
+struct NsBatch {
+  int n;
+  NsEntry e[kMaxNsJobs];
+};
+
+__global__ void ns_init_kernel(NsBatch b) {
+  const NsEntry& e = b.e[blockIdx.x];
+  e.live[0] = e.k;
+  e.live[1] = e.n;
+  e.live[4] = 0;
+  e.live[5] = e.n;
 }
 
 // Z^H Z - 1 from the upper triangle the Hermitian product forms: the lower
 // triangle filled by conjugation (32 x 32 blocks read transposed through
-// LDS), 1 subtracted on the diagonal, and, with want_max, max |Z^H Z - 1| over
+// LDS), 1 subtracted on the diagonal, and, with flag, max |Z^H Z - 1| over
 // the upper triangle into live[2..3].  Nothing while the step is off.
-__global__ __launch_bounds__(256) void ns_gram_fix_kernel(c128* G, int k, int* live, int want_max) {
-  if (live[0] == 0) return;
+// blockIdx.z: job.
+__global__ __launch_bounds__(256) void ns_gram_fix_kernel(NsBatch b) {
+  const NsEntry& e = b.e[blockIdx.z];
+  const int k = e.k, bi = blockIdx.y, bj = blockIdx.x;   // destination block (bi >= bj)
+  if (bj > bi || bi * 32 >= k || e.live[0] == 0) return;
   __shared__ c128 tile[32][33];
-  const int bi = blockIdx.y, bj = blockIdx.x;   // destination block (bi >= bj)
-  if (bj > bi) return;
+  c128* G = e.G;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   double mx = 0;
   for (int r = ty; r < 32; r += 8) {   // source block (bj, bi): rows bj*32 + r
@@ -1198,21 +1217,22 @@ __global__ __launch_bounds__(256) void ns_gram_fix_kernel(c128* G, int k, int* l
       G[(long long)i * k + j] = i == j ? v : cconj(v);
     }
   }
-  if (want_max) {
+  if (e.flag) {
     mx = wave_max(mx);
     if ((threadIdx.x & 63) == 0)
-      atomicMax((unsigned long long*)(live + 2), (unsigned long long)__double_as_longlong(mx));
+      atomicMax((unsigned long long*)(e.live + 2), (unsigned long long)__double_as_longlong(mx));
   }
 }
 
 // From this step's max |Z^H Z - 1| (measured before its update, which squares
-// it): skip the update of an optional step already orthonormal to tol_skip;
-// stop all later steps once the error is below tol_stop (the update then
-// leaves about tol_stop^2).
-__global__ void ns_decide_kernel(int* live, int optional, double tol_skip, double tol_stop) {
+// it): skip the update of an optional step (flag) already orthonormal to
+// tol_skip; stop all later steps once the error is below tol_stop (the update
+// then leaves about tol_stop^2).  blockIdx.x: job.
+__global__ void ns_decide_kernel(NsBatch b, double tol_skip, double tol_stop) {
+  int* live = b.e[blockIdx.x].live;
   const double mx = __longlong_as_double((long long)*(unsigned long long*)(live + 2));
   const bool stopped = live[4] != 0;
-  live[1] = (stopped || (optional && !(mx >= tol_skip))) ? 0 : live[5];
+  live[1] = (stopped || (b.e[blockIdx.x].flag && !(mx >= tol_skip))) ? 0 : live[5];
   if (!(mx >= tol_stop)) {
     live[4] = 1;
     live[0] = 0;
@@ -1220,10 +1240,24 @@ __global__ void ns_decide_kernel(int* live, int optional, double tol_skip, doubl
   *(unsigned long long*)(live + 2) = 0ull;
 }
 
-// The operand copy of the update (tot elements), unless the update is skipped.
-__global__ void ns_copy_kernel(const c128* __restrict__ src, c128* __restrict__ dst, long long tot, const int* live) {
-  if (live[1] == 0) return;
-  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < tot; i += (long long)gridDim.x * 256) dst[i] = src[i];
+// The operand copy of the update, unless the update is skipped.  blockIdx.y:
+// job.
+__global__ void ns_copy_kernel(NsBatch b) {
+  const NsEntry& e = b.e[blockIdx.y];
+  if (e.live[1] == 0) return;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < e.tot; i += (long long)gridDim.x * 256) e.dst[i] = e.src[i];
+}
+
+// launch(batch) for the entries, in groups of kMaxNsJobs.
+template <typename Launch>
+int ns_launch(const std::vector<NsEntry>& es, Launch&& launch) {
+  for (size_t i0 = 0; i0 < es.size(); i0 += kMaxNsJobs) {
+    NsBatch b{};
+    for (size_t i = i0; i < es.size() && b.n < kMaxNsJobs; ++i) b.e[b.n++] = es[i];
+    launch(b);
+    QT_HIP_CHECK(hipGetLastError());
+  }
+  return 0;
 }
 
 __global__ void eig1_kernel(const c128* G, double* lam, c128* E) {
@@ -1288,6 +1322,7 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
   }
   // validation, 1 x 1 problems, barrier words and reflector buffers
   std::vector<int> big;
+  std::vector<ZeroSpan> zs;
   for (int j = 0; j < njobs; ++j) {
     const EigJob& J = jobs[j];
     if (J.n < 1 || J.kwant < 1 || J.kwant > J.n) return set_error(-1, "eig: bad sizes n=%d kwant=%d", J.n, J.kwant);
@@ -1299,12 +1334,21 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
     }
     const int RL = tri_rows_loc(J.n), P = (J.n + RL - 1) / RL;
     if (P > 256) return set_error(-2, "eig: n=%d needs %d blocks", J.n, P);
-    if ((rc = fill_zero(J.w->sync, grid_sync_words(P) * 4, s))) return rc;
-    const int mqr = J.n - 1, npan = (mqr + NB - 1) / NB;
-    if ((rc = fill_zero(J.w->qtri.V, (size_t)((npan + 1) / 2) * mqr * kQrLdv * 16, s))) return rc;
+    // cleared before the tridiagonalisation: its barrier words, the Newton-
+    // Schulz error word, and the reflector entries it does not write that
+    // later products read: the top 32 rows of every odd panel of a pair
+    // block, and the whole last pair block (its last panel may be partial)
+    zs.push_back(ZeroSpan{J.w->sync, (long long)grid_sync_words(P) * 4, 0, 0, 1, 1});
+    zs.push_back(ZeroSpan{J.w->ns_live + 2, 8, 0, 0, 1, 1});
+    const int mqr = J.n - 1, npan = (mqr + NB - 1) / NB, npair = (npan + 1) / 2;
+    const long long pair_bytes = (long long)mqr * kQrLdv * 16, row_bytes = (long long)kQrLdv * 16;
+    char* V = (char*)J.w->qtri.V;
+    if (npair > 1) zs.push_back(ZeroSpan{V + NB * 16, NB * 16, row_bytes, pair_bytes, NB, npair - 1});
+    zs.push_back(ZeroSpan{V + (npair - 1) * pair_bytes, row_bytes, row_bytes, 0, mqr - 2 * NB * (npair - 1), 1});
     big.push_back(j);
   }
   if (big.empty()) return 0;
+  if ((rc = zero_spans(zs.data(), (int)zs.size(), s))) return rc;
   // 1. tridiagonalisations, packed into cooperative launches of <= 256 blocks
   {
     TriBatch tb{};
@@ -1418,11 +1462,13 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
   // u / rtol, which these steps remove.
   const GemmTypes ty{DT_C128, DT_C128};
   std::vector<GemmProb> gs;
-  for (int j : big) {
-    hipLaunchKernelGGL(ns_init_kernel, dim3(1), dim3(1), 0, s, jobs[j].w->ns_live, jobs[j].n, jobs[j].kwant);
-    QT_HIP_CHECK(hipGetLastError());
-    if ((rc = fill_zero(jobs[j].w->ns_live + 2, 8, s))) return rc;
-  }
+  std::vector<NsEntry> ne;
+  auto entry = [&](const EigJob& J, int flag) {
+    return NsEntry{J.w->gz, J.E, J.w->ztmp, (long long)J.n * J.kwant, J.w->ns_live, J.n, J.kwant, flag};
+  };
+  for (int j : big) ne.push_back(entry(jobs[j], 0));
+  if ((rc = ns_launch(ne, [&](const NsBatch& b) { hipLaunchKernelGGL(ns_init_kernel, dim3(b.n), dim3(1), 0, s, b); })))
+    return rc;
   for (int it = 0; it < kNsMaxSteps; ++it) {
     std::vector<int> ns;
     for (int j : big)
@@ -1441,19 +1487,19 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
       gs.push_back(g1);
     }
     if ((rc = gemm_run(gs.data(), (int)gs.size(), ty, s))) return rc;
+    // fill and shift of Z^H Z (with its max from the last fixed step on), the
+    // decision on the optional steps, and the operand copies, each one launch
+    std::vector<NsEntry> fix, dec, cpy;
+    int maxnb = 0;
+    long long maxtot = 0;
     gs.clear();
     for (int j : ns) {
       const EigJob& J = jobs[j];
       const bool gated = it >= J.ns_steps;
       const bool decide = it + 1 >= J.ns_steps;   // from the last fixed step on: decide the optional ones
-      const int nb = (J.kwant + 31) / 32;
-      hipLaunchKernelGGL(ns_gram_fix_kernel, dim3(nb, nb), dim3(256), 0, s, J.w->gz, J.kwant, J.w->ns_live,
-                         decide ? 1 : 0);
-      QT_HIP_CHECK(hipGetLastError());
-      if (decide) {
-        hipLaunchKernelGGL(ns_decide_kernel, dim3(1), dim3(1), 0, s, J.w->ns_live, gated ? 1 : 0, 1e-13, 1e-7);
-        QT_HIP_CHECK(hipGetLastError());
-      }
+      fix.push_back(entry(J, decide ? 1 : 0));
+      maxnb = std::max(maxnb, (J.kwant + 31) / 32);
+      if (decide) dec.push_back(entry(J, gated ? 1 : 0));
       GemmProb g2 = gemm_prob(J.E, J.kwant, OP_N, J.w->gz, J.kwant, OP_N, J.E, J.kwant, J.n, J.kwant, J.kwant,
                               -0.5f, 1.f);
       g2.ksplit = splitk_auto(J.n, J.kwant, J.kwant, 4 * (size_t)J.n * J.n * 8, sizeof(c128));
@@ -1462,15 +1508,26 @@ int eig_herm_top_batch(const EigJob* jobs, int njobs, hipStream_t s) {
         // one pass writes E while other tiles of its rows still read it: the
         // left operand is a copy (split K writes only the partials, and the
         // reduction after the product is the one that updates E)
-        const long long tot = (long long)J.n * J.kwant;
-        hipLaunchKernelGGL(ns_copy_kernel, dim3((int)std::min<long long>(2048, (tot + 255) / 256)), dim3(256), 0, s,
-                           (const c128*)J.E, J.w->ztmp, tot, (const int*)J.w->ns_live);
-        QT_HIP_CHECK(hipGetLastError());
+        cpy.push_back(entry(J, 0));
+        maxtot = std::max(maxtot, (long long)J.n * J.kwant);
         g2.A = J.w->ztmp;
       }
       if (gated) g2.dM = J.w->ns_live + 1;
       gs.push_back(g2);
     }
+    if ((rc = ns_launch(fix, [&](const NsBatch& b) {
+           hipLaunchKernelGGL(ns_gram_fix_kernel, dim3(maxnb, maxnb, b.n), dim3(256), 0, s, b);
+         })))
+      return rc;
+    if ((rc = ns_launch(dec, [&](const NsBatch& b) {
+           hipLaunchKernelGGL(ns_decide_kernel, dim3(b.n), dim3(1), 0, s, b, 1e-13, 1e-7);
+         })))
+      return rc;
+    const int cgrid = (int)std::min<long long>(2048, (maxtot + 255) / 256);
+    if ((rc = ns_launch(cpy, [&](const NsBatch& b) {
+           hipLaunchKernelGGL(ns_copy_kernel, dim3(cgrid, b.n), dim3(256), 0, s, b);
+         })))
+      return rc;
     if ((rc = gemm_run(gs.data(), (int)gs.size(), ty, s))) return rc;
   }
   // 7. back-transformation E = Q Z (rows 1.. of each E)

@@ -81,6 +81,16 @@ int qr_apply_q_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s);
 
 // Helpers shared by the bond update.
 int fill_zero(void* p, size_t bytes, hipStream_t s);
+// A region to clear: nrep repetitions (rep_stride bytes apart) of rows rows
+// (row_stride bytes apart) of row_bytes bytes each; pointers and sizes are
+// multiples of 4 bytes.
+struct ZeroSpan {
+  void* p;
+  long long row_bytes, row_stride, rep_stride;
+  int rows, nrep;
+};
+// Clears every span with one launch per 32 spans.
+int zero_spans(const ZeroSpan* spans, int n, hipStream_t s);
 int set_identity(void* Q, long long ldq, int m, int n, int dt, hipStream_t s);
 
 }  // namespace qrtebd

@@ -844,6 +844,38 @@ int splitk_for(int M, int N, int K) {
   return std::max(1, std::min(ks, kMaxSplit));
 }
 
+constexpr int kMaxZeroSpans = 32;
+struct ZeroBatch {
+  int n;
+  ZeroSpan sp[kMaxZeroSpans];
+};
+// blockIdx.y: span; the blocks along x share its rows, a thread one word at
+// a time.
+__global__ void zero_spans_kernel(ZeroBatch b) {
+  const ZeroSpan& z = b.sp[blockIdx.y];
+  const long long wpr = z.row_bytes / 4, tot = wpr * z.rows * (long long)z.nrep;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < tot; i += (long long)gridDim.x * 256) {
+    const long long row = i / wpr, w = i - row * wpr, rep = row / z.rows, r = row - rep * z.rows;
+    *(unsigned*)((char*)z.p + rep * z.rep_stride + r * z.row_stride + w * 4) = 0u;
+  }
+}
+
+int zero_spans(const ZeroSpan* spans, int n, hipStream_t s) {
+  for (int i0 = 0; i0 < n; i0 += kMaxZeroSpans) {
+    ZeroBatch b{};
+    long long most = 0;
+    for (int i = i0; i < n && b.n < kMaxZeroSpans; ++i) {
+      b.sp[b.n++] = spans[i];
+      most = std::max(most, spans[i].row_bytes / 4 * spans[i].rows * (long long)spans[i].nrep);
+    }
+    if (most == 0) continue;
+    const int gx = (int)std::min<long long>((most + 255) / 256, 256);
+    hipLaunchKernelGGL(zero_spans_kernel, dim3(gx, b.n), dim3(256), 0, s, b);
+    QT_HIP_CHECK(hipGetLastError());
+  }
+  return 0;
+}
+
 int fill_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t n = bytes / 4;
   if (n == 0) return 0;
@@ -1141,14 +1173,16 @@ static int update_columns(const QrJob* jobs, int njobs, int p, int dt, int b0, i
 
 int qr_factor_batch(const QrJob* jobs, int njobs, int dt, hipStream_t s, const QrAsync* as) {
   int maxp = 0, rc;
+  std::vector<ZeroSpan> zs;
   for (int j = 0; j < njobs; ++j) {
     const QrJob& J = jobs[j];
     if (J.n > J.m || J.n <= 0) return set_error(-1, "qr_factor: need 0 < n <= m (m=%d n=%d)", J.m, J.n);
     if (J.m > kMaxQrRows) return set_error(-2, "qr_factor: m=%d too large", J.m);
     // barrier words are zeroed once per factorisation; generations increase over its panels
-    if ((rc = fill_zero(J.w->sync, grid_sync_words(kMaxPanelBlocks) * 4, s))) return rc;
+    zs.push_back(ZeroSpan{J.w->sync, (long long)grid_sync_words(kMaxPanelBlocks) * 4, 0, 0, 1, 1});
     maxp = std::max(maxp, (J.n + NB - 1) / NB);
   }
+  if ((rc = zero_spans(zs.data(), (int)zs.size(), s))) return rc;
   if (!as || !as->aux) {
     // in order on one stream: panel p (which first applies panel p-1 to its
     // own columns), then the columns from panel p+2 on
