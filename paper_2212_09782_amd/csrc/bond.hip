@@ -242,11 +242,13 @@ __global__ __launch_bounds__(256) void reduce_kernel(const double* part, int n, 
 }
 
 // R (upper triangle of the first eta rows of the factored Y^dag) with zeros below.
+// (Element loops of these small kernels index with 32 bits: a 64-bit division
+// per element would cost more than the element's memory traffic.)
 template <typename S>
 __global__ void extract_r_kernel(const cpx<S>* YH, int eta, cpx<S>* R) {
-  const long long n = (long long)eta * eta;
-  for (long long idx = blockIdx.x * 256ll + threadIdx.x; idx < n; idx += (long long)gridDim.x * 256) {
-    const int i = (int)(idx / eta), j = (int)(idx % eta);
+  const unsigned n = (unsigned)eta * eta, m = eta;
+  for (unsigned idx = blockIdx.x * 256u + threadIdx.x; idx < n; idx += gridDim.x * 256u) {
+    const unsigned i = idx / m, j = idx - i * m;
     R[idx] = j >= i ? YH[idx] : mk<S>(0, 0);
   }
 }
@@ -255,9 +257,9 @@ __global__ void extract_r_kernel(const cpx<S>* YH, int eta, cpx<S>* R) {
 template <typename S>
 __global__ void plain_xi_kernel(const cpx<S>* R, int eta, const double* kept2, c128* xi) {
   const double inv = 1.0 / sqrt(*kept2);
-  const long long n = (long long)eta * eta;
-  for (long long idx = blockIdx.x * 256ll + threadIdx.x; idx < n; idx += (long long)gridDim.x * 256) {
-    const int i = (int)(idx / eta), j = (int)(idx % eta);
+  const unsigned n = (unsigned)eta * eta, m = eta;
+  for (unsigned idx = blockIdx.x * 256u + threadIdx.x; idx < n; idx += gridDim.x * 256u) {
+    const int i = (int)(idx / m), j = (int)(idx - (unsigned)i * m);
     c128 v = mk<double>(0, 0);
     if (j <= i) {
       const cpx<S> r = R[(long long)j * eta + i];
@@ -415,9 +417,9 @@ __global__ void cast_kernel(const cpx<S>* in, long long n, cpx<D>* out) {
 // Dc = (G - 1)/2 on the live chi~ x chi~ block (G complex128, Dc complex64, ld cap).
 __global__ void reorth_prep_kernel(const c128* G, int cap, const int* chi_new, c64* Dc) {
   const int k = *chi_new;
-  const long long n = (long long)k * k;
-  for (long long idx = blockIdx.x * 256ll + threadIdx.x; idx < n; idx += (long long)gridDim.x * 256) {
-    const int i = (int)(idx / k), j = (int)(idx % k);
+  const unsigned n = (unsigned)k * k, uk = k;
+  for (unsigned idx = blockIdx.x * 256u + threadIdx.x; idx < n; idx += gridDim.x * 256u) {
+    const int i = (int)(idx / uk), j = (int)(idx - (unsigned)i * uk);
     // G is Hermitian and only its upper triangle was formed
     const c128 g = i <= j ? G[(long long)i * cap + j] : cconj(G[(long long)j * cap + i]);
     Dc[(long long)i * cap + j] = mk<float>((float)(0.5 * (g.re - (i == j ? 1.0 : 0.0))), (float)(0.5 * g.im));

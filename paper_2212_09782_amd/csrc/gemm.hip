@@ -277,13 +277,15 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmBatch b) {
   int M = P.M, N = P.N;
   if (P.dM) M = min(M, *P.dM);
   if (P.dN) N = min(N, *P.dN);
-  const long long total = (long long)M * N;
+  // 32-bit element index (M N < 2^31 for every product here): a 64-bit
+  // division per element would cost more than its memory traffic
+  const unsigned total = (unsigned)M * (unsigned)N, un = N;
   const long long ldc = P.ldc_live_N ? (long long)N : P.ldc;
   const cpx<Tc>* W = (const cpx<Tc>*)P.work;
   cpx<Tout>* C = (cpx<Tout>*)P.C;
   const Tc alpha = (Tc)P.alpha, beta = (Tc)P.beta;
-  for (long long idx = (bid - b.tile_start[p]) * 256ll + threadIdx.x; idx < total; idx += nblk * 256ll) {
-    const int row = (int)(idx / N), col = (int)(idx % N);
+  for (unsigned idx = (bid - b.tile_start[p]) * 256u + threadIdx.x; idx < total; idx += nblk * 256u) {
+    const int row = (int)(idx / un), col = (int)(idx - (unsigned)row * un);
     Tc sr = 0, si = 0;
     for (int s = 0; s < P.ksplit; ++s) {
       const cpx<Tc> w = W[((long long)s * P.M + row) * P.N + col];

@@ -780,11 +780,11 @@ __global__ void fill_zero_kernel(unsigned* p, size_t n) {
 }
 
 template <typename S>
+// (32-bit element index: m n < 2^32 for every workspace this library sizes.)
 __global__ void set_identity_kernel(cpx<S>* Q, long long ldq, int m, int n) {
-  const long long total = (long long)m * n;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(idx / n), j = (int)(idx % n);
+  const unsigned total = (unsigned)m * (unsigned)n, un = n;
+  for (unsigned idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+    const unsigned i = idx / un, j = idx - i * un;
     Q[(long long)i * ldq + j] = mk<S>(i == j ? S(1) : S(0), S(0));
   }
 }
