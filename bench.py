@@ -640,7 +640,7 @@ def main():
     rnd = lambda v: {k: (round(x, 6) if isinstance(x, float) else rnd(x) if isinstance(x, dict) else x)
                      for k, x in v.items()}
     line = {
-        "metric": f"bond updates/s at d={args.d} chi={chi} (mixed vs FP64) + p50/p99 step latency",
+        "metric": f"bond updates/s at d={args.d} \u03c7={chi} (mixed vs FP64) + p50/p99 step latency",
         "value": round(h["updates_per_s"], 4),
         "unit": "bond updates/s",
         "n_gpus": 1,
