@@ -173,6 +173,8 @@ ORACLE_FULL = [
     # chi, d, precision
     (1024, 5, lib.MPS_C128),          # the headline shape, eta = 1127
     (600, 10, lib.MPS_C128),          # d chi = 6000 rows: QR panels beyond two LDS slabs (column loop)
+    (512, 8, lib.MPS_C128),           # the register-resident gate (complex128 from d = 7)
+    (256, 10, lib.MPS_MIXED_C64),     # the register-resident gate on complex64 storage (from d = 9)
     (256, 5, lib.MPS_MIXED_C64),
     (512, 5, lib.MPS_MIXED_C64),
     (1024, 5, lib.MPS_MIXED_C64),
