@@ -21,7 +21,8 @@ struct EigWork {
   c128* gz;         // n x n Gram matrix of the eigenvector block (Newton-Schulz polish)
   c128* ztmp;       // n x n copy of the eigenvector block
   c128* tpart;      // split-K partials of V_p^H V_p for every panel p (8 x 32 x 32 each)
-  int* ns_live;     // [0] live K of Z^H Z (n or 0), [1] live K of the update (kwant or 0), [2..3] max |Z^H Z - 1| bits
+  int* ns_live;     // Newton-Schulz step state: [0] live size of Z^H Z (kwant or 0), [1] live rows of the
+                    // update (n or 0), [2..3] max |Z^H Z - 1| bits, [4] stopped, [5] n
   int* status;
 };
 
